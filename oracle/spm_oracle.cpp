@@ -1,0 +1,199 @@
+// spm oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, deliberately unoptimised CPU reference for what the sparse path computes:
+// bulk assembly of coordinate (COO) triplets into compressed sparse column (CSC) form, the CSC
+// sparse x dense product Y = A.X, and its adjoint (dX = A^T.G, dvalues = G.X sampled on A's
+// pattern).  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
+// so every '+' and '*' below is one correctly rounded binary64 operation, in the order written.
+//
+// Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may load this
+// library.  It shares no code, header, table or helper with the GPU implementation.
+//
+// Paper: C. Sanderson, R. Curtin, "A User-Friendly Hybrid Sparse Matrix Class in C++", LNCS 10931
+// (2018), arXiv:1805.03380.
+//
+// Status codes returned here match the public ones by value only (0 ok, 1 invalid argument,
+// 2 triplet out of range); the numbers are retyped, not shared.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+// Section 3.1: zero-based row / column indices; a triplet whose location lies outside the
+// n_rows x n_cols matrix has no place in the CSC arrays and is rejected.
+bool in_range(int64_t n_rows, int64_t n_cols, int32_t r, int32_t c) {
+  return r >= 0 && c >= 0 && (int64_t)r < n_rows && (int64_t)c < n_cols;
+}
+
+// Section 3.1: column offsets.  c[0] = 0, c[n_cols] = N, and column i holds c[i+1] - c[i]
+// elements.  Built from the column of each emitted element, in emission order.
+void offsets_from_columns(int64_t n_cols, const std::vector<int64_t>& emitted_cols,
+                          int32_t* col_ptr) {
+  std::vector<int64_t> count(n_cols + 1, 0);
+  for (int64_t c : emitted_cols) count[c + 1] += 1;
+  col_ptr[0] = 0;
+  for (int64_t i = 0; i < n_cols; ++i) col_ptr[i + 1] = (int32_t)(col_ptr[i] + count[i + 1]);
+}
+
+}  // namespace
+
+extern "C" {
+
+// Assembly, read 1 (the paper's own route, Section 3.3 and Section 3.4):
+//   every triplet is an element insertion into a red-black tree (std::map is one) keyed by the
+//   location index  index = row + column * n_rows  (column-major encoding, Section 3.3);
+//   repeated locations accumulate, like X(r,c) += v in Fig. 1, in input order;
+//   the sync to CSC is an in-order traversal (smallest to largest index == column-major order),
+//   decoding row = index mod n_rows and column = floor(index / n_rows).
+// Exact zeros are not stored: a location whose accumulated value compares equal to 0.0 (this
+// includes -0.0 and cancelled sums) is skipped during the traversal.  NaN and Inf are stored.
+// Output arrays: col_ptr[n_cols+1]; row_idx and val_out have capacity nnz_in.
+// Returns 0, 1 (bad sizes / null pointers) or 2 (some triplet out of range; outputs untouched).
+int oracle_coo_to_csc_rbt(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
+                          const int32_t* col, const double* val, int32_t* col_ptr,
+                          int32_t* row_idx, double* val_out, int64_t* nnz_out) {
+  if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || !col_ptr || !nnz_out) return 1;
+  if (nnz_in > 0 && (!row || !col || !val || !row_idx || !val_out)) return 1;
+  for (int64_t t = 0; t < nnz_in; ++t)
+    if (!in_range(n_rows, n_cols, row[t], col[t])) return 2;
+
+  std::map<uint64_t, double> tree;  // a red-black tree of (index, value)
+  for (int64_t t = 0; t < nnz_in; ++t) {
+    uint64_t index = (uint64_t)row[t] + (uint64_t)col[t] * (uint64_t)n_rows;
+    auto it = tree.find(index);
+    if (it == tree.end())
+      tree.emplace(index, val[t]);
+    else
+      it->second = it->second + val[t];
+  }
+
+  std::vector<int64_t> emitted_cols;
+  int64_t n = 0;
+  for (const auto& kv : tree) {
+    if (kv.second == 0.0) continue;  // exact zero: not stored
+    int64_t r = (int64_t)(kv.first % (uint64_t)n_rows);
+    int64_t c = (int64_t)(kv.first / (uint64_t)n_rows);
+    row_idx[n] = (int32_t)r;
+    val_out[n] = kv.second;
+    emitted_cols.push_back(c);
+    ++n;
+  }
+  offsets_from_columns(n_cols, emitted_cols, col_ptr);
+  *nnz_out = n;
+  return 0;
+}
+
+// Assembly, read 2 (batch form of the same definition, Section 3.1 "sort, then merge"):
+//   stable sort of the triplets by (column, row) -- column-major order -- so that triplets at
+//   one location stay in input order; then each run of equal locations is folded left to right,
+//   s = ((v_t1 + v_t2) + v_t3) + ...; the location is stored iff s != 0.0.
+// Same contract and outputs as oracle_coo_to_csc_rbt; the two must agree bit for bit.
+int oracle_coo_to_csc_sort(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
+                           const int32_t* col, const double* val, int32_t* col_ptr,
+                           int32_t* row_idx, double* val_out, int64_t* nnz_out) {
+  if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || !col_ptr || !nnz_out) return 1;
+  if (nnz_in > 0 && (!row || !col || !val || !row_idx || !val_out)) return 1;
+  for (int64_t t = 0; t < nnz_in; ++t)
+    if (!in_range(n_rows, n_cols, row[t], col[t])) return 2;
+
+  std::vector<int64_t> order(nnz_in);
+  for (int64_t t = 0; t < nnz_in; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (col[a] != col[b]) return col[a] < col[b];
+    return row[a] < row[b];
+  });
+
+  std::vector<int64_t> emitted_cols;
+  int64_t n = 0;
+  int64_t i = 0;
+  while (i < nnz_in) {
+    int64_t j = i;
+    double s = val[order[i]];
+    ++j;
+    while (j < nnz_in && col[order[j]] == col[order[i]] && row[order[j]] == row[order[i]]) {
+      s = s + val[order[j]];
+      ++j;
+    }
+    if (s != 0.0) {
+      row_idx[n] = row[order[i]];
+      val_out[n] = s;
+      emitted_cols.push_back(col[order[i]]);
+      ++n;
+    }
+    i = j;
+  }
+  offsets_from_columns(n_cols, emitted_cols, col_ptr);
+  *nnz_out = n;
+  return 0;
+}
+
+// Sparse x dense product, Section 3 use case (iv) and the CSC traversal of Section 3.1:
+//   Y[r, j] = sum over stored (r, c) of  v * X[c, j],   X is n_cols x k, Y is n_rows x k,
+// both dense row-major.  The loop walks columns in ascending order and, within a column, the
+// stored elements in CSC order; each output therefore accumulates its terms in ascending
+// column order, starting from 0.0.
+// Alongside each output it accumulates the error scale S[r, j] = sum |v| * |X[c, j]| and the
+// number of terms M[r] (the length of row r); a fixed-order binary64 sum of M terms is within
+// gamma_M * S of the exact value (Higham, Accuracy and Stability of Numerical Algorithms, 3.1).
+void oracle_spmm(int64_t n_rows, int64_t n_cols, int64_t k, const int32_t* col_ptr,
+                 const int32_t* row_idx, const double* val, const double* X, double* Y,
+                 double* S, int64_t* M) {
+  for (int64_t i = 0; i < n_rows * k; ++i) { Y[i] = 0.0; S[i] = 0.0; }
+  for (int64_t r = 0; r < n_rows; ++r) M[r] = 0;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    for (int64_t p = col_ptr[c]; p < col_ptr[c + 1]; ++p) {
+      int64_t r = row_idx[p];
+      double v = val[p];
+      for (int64_t j = 0; j < k; ++j) {
+        Y[r * k + j] = Y[r * k + j] + v * X[c * k + j];
+        S[r * k + j] = S[r * k + j] + std::fabs(v) * std::fabs(X[c * k + j]);
+      }
+      M[r] += 1;
+    }
+  }
+}
+
+// Adjoint of Y = A.X for the loss L = sum(Y * G), i.e. dL/dY = G:
+//   dX[c, j]   = sum over stored (r, c) of v * G[r, j]        (A^T . G: a walk down column c,
+//                 the same traversal as the row-vector times CSC product of Fig. 1)
+//   dval[p]    = sum_j G[r_p, j] * X[c_p, j]                   (dense.dense product sampled at
+//                 the stored location p of A)
+// dX accumulates in CSC order within each column, dval in ascending j.  SdX / Sdv are the
+// matching error scales (sum of |terms|); the term counts are the column length for dX and k
+// for dval, so they are not returned.
+void oracle_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t k, const int32_t* col_ptr,
+                          const int32_t* row_idx, const double* val, const double* G,
+                          const double* X, double* dX, double* dval, double* SdX, double* Sdv) {
+  (void)n_rows;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    for (int64_t j = 0; j < k; ++j) { dX[c * k + j] = 0.0; SdX[c * k + j] = 0.0; }
+    for (int64_t p = col_ptr[c]; p < col_ptr[c + 1]; ++p) {
+      int64_t r = row_idx[p];
+      double v = val[p];
+      double d = 0.0, sd = 0.0;
+      for (int64_t j = 0; j < k; ++j) {
+        dX[c * k + j] = dX[c * k + j] + v * G[r * k + j];
+        SdX[c * k + j] = SdX[c * k + j] + std::fabs(v) * std::fabs(G[r * k + j]);
+        d = d + G[r * k + j] * X[c * k + j];
+        sd = sd + std::fabs(G[r * k + j]) * std::fabs(X[c * k + j]);
+      }
+      dval[p] = d;
+      Sdv[p] = sd;
+    }
+  }
+}
+
+// Row sums through the CSC arrays, for the sum(X, dim) special case of Table 1.
+void oracle_column_sums(int64_t n_cols, const int32_t* col_ptr, const double* val, double* out) {
+  for (int64_t c = 0; c < n_cols; ++c) {
+    double s = 0.0;
+    for (int64_t p = col_ptr[c]; p < col_ptr[c + 1]; ++p) s = s + val[p];
+    out[c] = s;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,376 @@
+"""Checks that pin the oracle to something other than itself.
+
+Each ``pin_*`` function raises AssertionError when the oracle disagrees with a definition,
+closed form, invariant, brute force or hand-computed fixture.  They are run as ordinary tests
+(test_oracle_pins.py) and against deliberately broken copies of the oracle
+(test_oracle_mutants.py), to show that a plausible mistake in the oracle fails at least one.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+from paper_1805_03380_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def brute_force_csc(n_rows, n_cols, row, col, val):
+    """Dense brute force: D[r, c] += v in input order (Python floats are binary64), then every
+    location whose total is not 0.0, in column-major order (Sections 3.1, 3.3)."""
+    acc = {}
+    for r, c, v in zip(row.tolist(), col.tolist(), np.asarray(val, dtype=np.float64).tolist()):
+        acc[(c, r)] = acc.get((c, r), 0.0) + v
+    items = sorted((key, s) for key, s in acc.items() if s != 0.0)
+    col_ptr = np.zeros(n_cols + 1, dtype=np.int64)
+    for (c, _r), _s in items:
+        col_ptr[c + 1] += 1
+    col_ptr = np.cumsum(col_ptr)
+    rows = np.array([r for (_c, r), _s in items], dtype=np.int64)
+    vals = np.array([s for _k, s in items], dtype=np.float64)
+    return col_ptr, rows, vals
+
+
+def same_floats(a, b) -> bool:
+    """Bitwise equality of binary64 arrays, treating any NaN as equal to any NaN."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.shape != b.shape:
+        return False
+    na, nb = np.isnan(a), np.isnan(b)
+    if not np.array_equal(na, nb):
+        return False
+    return bool(np.all(a.view(np.int64)[~na] == b.view(np.int64)[~nb]))
+
+
+def dense_of(A: oracle.CSC) -> np.ndarray:
+    D = np.zeros((A.n_rows, A.n_cols), dtype=np.float64)
+    for c in range(A.n_cols):
+        for p in range(A.col_ptr[c], A.col_ptr[c + 1]):
+            D[A.row_idx[p], c] = A.values[p]
+    return D
+
+
+def csc_from_dense(D: np.ndarray) -> oracle.CSC:
+    n_rows, n_cols = D.shape
+    cols, rows, vals = [], [], []
+    cp = [0]
+    for c in range(n_cols):
+        for r in range(n_rows):
+            if D[r, c] != 0.0:
+                rows.append(r)
+                vals.append(D[r, c])
+        cp.append(len(rows))
+    return oracle.CSC(n_rows, n_cols, np.array(cp, np.int32), np.array(rows, np.int32),
+                      np.array(vals, np.float64))
+
+
+# ------------------------------------------------------------------------------ assembly pins
+
+def pin_golden_assembly():
+    for name in ("assembly_small.json", "fold_order.json"):
+        g = load_golden(name)
+        row = np.array(g["row"], np.int32)
+        col = np.array(g["col"], np.int32)
+        val = np.array(g["val"], np.float64)
+        if "expect_val_hex" in g:
+            expect = np.array([float.fromhex(h) for h in g["expect_val_hex"]])
+        else:
+            expect = np.array(g["expect_val"], np.float64)
+        for method in ("sort", "rbt"):
+            st, A = oracle.coo_to_csc(g["n_rows"], g["n_cols"], row, col, val, method=method)
+            assert st == oracle.OK
+            assert A.col_ptr.tolist() == g["expect_col_ptr"], (name, method)
+            assert A.row_idx.tolist() == g["expect_row_idx"], (name, method)
+            assert same_floats(A.values, expect), (name, method, A.values, expect)
+
+
+def pin_brute_force(seeds=range(12)):
+    """Both oracle reads equal dense brute force bit for bit on small random inputs with many
+    duplicates, exact zeros and cancelling pairs."""
+    for seed in seeds:
+        rng = np.random.Generator(np.random.PCG64(5000 + seed))
+        n_rows = int(rng.integers(1, 9))
+        n_cols = int(rng.integers(1, 9))
+        nnz = int(rng.integers(0, 60))
+        row = rng.integers(0, n_rows, nnz).astype(np.int32)
+        col = rng.integers(0, n_cols, nnz).astype(np.int32)
+        val = rng.choice(np.array([-1.5, -1.0, -0.5, -0.0, 0.0, 0.25, 0.5, 1.0, 3.0]), nnz)
+        val = val + rng.standard_normal(nnz) * (rng.random(nnz) < 0.3)
+        ecp, er, ev = brute_force_csc(n_rows, n_cols, row, col, val)
+        for method in ("sort", "rbt"):
+            st, A = oracle.coo_to_csc(n_rows, n_cols, row, col, val, method=method)
+            assert st == oracle.OK
+            assert np.array_equal(A.col_ptr, ecp), (seed, method)
+            assert np.array_equal(A.row_idx, er), (seed, method)
+            assert same_floats(A.values, ev), (seed, method)
+
+
+def pin_scipy_dyadic():
+    """scipy.sparse COO->CSC with duplicates summed and zeros eliminated; dyadic values make
+    every summation order exact, so structure and values must match exactly."""
+    import scipy.sparse as sp
+    for seed in range(4):
+        rng = np.random.Generator(np.random.PCG64(7000 + seed))
+        n_rows, n_cols, nnz = 300, 200, 4000
+        row = rng.integers(0, n_rows, nnz).astype(np.int32)
+        col = rng.integers(0, n_cols, nnz).astype(np.int32)
+        val = rng.integers(-16, 17, nnz).astype(np.float64) / 8.0
+        M = sp.coo_matrix((val, (row, col)), shape=(n_rows, n_cols)).tocsc()
+        M.sum_duplicates()
+        M.eliminate_zeros()
+        M.sort_indices()
+        st, A = oracle.coo_to_csc(n_rows, n_cols, row, col, val)
+        assert st == oracle.OK
+        assert np.array_equal(A.col_ptr, M.indptr)
+        assert np.array_equal(A.row_idx, M.indices)
+        assert np.array_equal(A.values, M.data)
+
+
+def pin_invariants_and_totals():
+    """Section 3.1 invariants on the 1000 x 1000 workload; the total of the stored values equals
+    the total of the inputs up to the rounding of the per-location folds."""
+    p = synth.tiny_spmv()
+    st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    assert st == oracle.OK
+    oracle.check_csc_invariants(A)
+    assert A.nnz <= p.nnz_in
+    exact_in = math.fsum(p.val.tolist())
+    exact_out = math.fsum(A.values.tolist())
+    bound = 2.0 ** -52 * float(np.abs(p.val).sum())
+    assert abs(exact_out - exact_in) <= bound
+    # sum(X, 0) of Table 1: per-column totals equal brute-force per-column sums of the inputs
+    cs = oracle.column_sums(A)
+    ref = np.zeros(p.n_cols)
+    np.add.at(ref, p.col, p.val)
+    assert np.allclose(cs, ref, rtol=0, atol=1e-12)
+
+
+def pin_index_encoding():
+    """Section 3.3: index = row + column * n_rows; decoding with mod / floor-div is the inverse,
+    and sorting by index is column-major order, the same order as the key (col << b) | row for
+    any b with 2^b >= n_rows."""
+    for n_rows, n_cols in ((1, 1), (3, 5), (7, 2), (16, 16), (17, 9)):
+        rr, cc = np.meshgrid(np.arange(n_rows), np.arange(n_cols), indexing="ij")
+        rr, cc = rr.ravel(), cc.ravel()
+        idx = rr + cc * n_rows
+        assert np.array_equal(idx % n_rows, rr) and np.array_equal(idx // n_rows, cc)
+        b = max(1, int(math.ceil(math.log2(max(n_rows, 2)))))
+        shift = (cc << b) | rr
+        assert np.array_equal(np.argsort(idx, kind="stable"), np.argsort(shift, kind="stable"))
+        lex = np.lexsort((rr, cc))
+        assert np.array_equal(np.argsort(idx, kind="stable"), lex)
+    # and the oracle emits in that order for a full dense pattern given in reverse order
+    n_rows, n_cols = 5, 4
+    rr, cc = np.meshgrid(np.arange(n_rows), np.arange(n_cols), indexing="ij")
+    rr, cc = rr.ravel()[::-1].astype(np.int32), cc.ravel()[::-1].astype(np.int32)
+    val = np.arange(1, rr.size + 1, dtype=np.float64)
+    for method in ("sort", "rbt"):
+        st, A = oracle.coo_to_csc(n_rows, n_cols, rr, cc, val, method=method)
+        assert A.col_ptr.tolist() == [0, 5, 10, 15, 20]
+        assert A.row_idx.tolist() == [0, 1, 2, 3, 4] * 4
+
+
+def pin_special_cases():
+    # empty input, zero columns, out-of-range rejection
+    st, A = oracle.coo_to_csc(3, 4, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert st == oracle.OK and A.col_ptr.tolist() == [0] * 5 and A.nnz == 0
+    st, A = oracle.coo_to_csc(3, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert st == oracle.OK and A.col_ptr.tolist() == [0]
+    for r, c in ((3, 0), (0, 4), (-1, 0), (0, -1)):
+        st, _ = oracle.coo_to_csc(3, 4, np.array([0, r], np.int32), np.array([0, c], np.int32),
+                                  np.array([1.0, 1.0]))
+        assert st == oracle.EBOUNDS
+    # every triplet on one location: one left fold in input order
+    rng = np.random.Generator(np.random.PCG64(99))
+    v = rng.standard_normal(1000)
+    s = 0.0
+    for x in v.tolist():
+        s = s + x
+    st, A = oracle.coo_to_csc(2, 2, np.ones(1000, np.int32), np.zeros(1000, np.int32), v)
+    assert A.col_ptr.tolist() == [0, 1, 1] and A.row_idx.tolist() == [1]
+    assert same_floats(A.values, [s])
+    # NaN and Inf are stored; Inf + -Inf is NaN and stored; (a, -a, b) stores b
+    st, A = oracle.coo_to_csc(4, 1, np.array([0, 1, 2, 2, 3, 3, 3], np.int32),
+                              np.zeros(7, np.int32),
+                              np.array([np.nan, np.inf, np.inf, -np.inf, 0.7, -0.7, 0.125]))
+    assert A.row_idx.tolist() == [0, 1, 2, 3]
+    assert np.isnan(A.values[0]) and A.values[1] == np.inf and np.isnan(A.values[2])
+    assert A.values[3] == 0.125
+
+
+# ---------------------------------------------------------------------------------- SpMM pins
+
+def pin_golden_spmm():
+    g = load_golden("assembly_small.json")
+    st, A = oracle.coo_to_csc(g["n_rows"], g["n_cols"], np.array(g["row"], np.int32),
+                              np.array(g["col"], np.int32), np.array(g["val"]))
+    s = g["spmm"]
+    Y, _S, M = oracle.spmm(A, np.array(s["X"]))
+    assert np.array_equal(Y, np.array(s["expect_Y"]))
+    assert M.tolist() == [1, 1, 1, 0]
+    dX, dval, _a, _b = oracle.spmm_backward(A, np.array(s["G"]), np.array(s["X"]))
+    assert np.array_equal(dX, np.array(s["expect_dX"]))
+    assert np.array_equal(dval, np.array(s["expect_dval"]))
+
+
+def pin_fraction_exact():
+    """Exact rational arithmetic on tiny random inputs: every oracle output is within
+    gamma_m * S of the exact value (m terms, S = sum of |terms|)."""
+    for seed in range(5):
+        rng = np.random.Generator(np.random.PCG64(8100 + seed))
+        n_rows, n_cols, k = 7, 6, 3
+        p = synth.random_coo(8100 + seed, n_rows, n_cols, 25, dup_frac=0.2, dist="normal")
+        st, A = oracle.coo_to_csc(n_rows, n_cols, p.row, p.col, p.val)
+        X = rng.standard_normal((n_cols, k))
+        G = rng.standard_normal((n_rows, k))
+        D = dense_of(A)
+        Y, S, M = oracle.spmm(A, X)
+        dX, dval, SdX, Sdv = oracle.spmm_backward(A, G, X)
+        Fr = lambda x: Fraction(float(x))
+        for r in range(n_rows):
+            for j in range(k):
+                exact = sum((Fr(D[r, c]) * Fr(X[c, j]) for c in range(n_cols)), Fraction(0))
+                assert abs(Fraction(float(Y[r, j])) - exact) <= Fr(oracle.gamma(M[r]) * S[r, j])
+        for c in range(n_cols):
+            m = A.col_ptr[c + 1] - A.col_ptr[c]
+            for j in range(k):
+                exact = sum((Fr(D[r, c]) * Fr(G[r, j]) for r in range(n_rows)), Fraction(0))
+                assert abs(Fraction(float(dX[c, j])) - exact) <= Fr(oracle.gamma(m) * SdX[c, j])
+            for q in range(A.col_ptr[c], A.col_ptr[c + 1]):
+                r = A.row_idx[q]
+                exact = sum((Fr(G[r, j]) * Fr(X[c, j]) for j in range(k)), Fraction(0))
+                assert abs(Fraction(float(dval[q])) - exact) <= Fr(oracle.gamma(k) * Sdv[q])
+
+
+def pin_identity_and_permutation():
+    """speye (Table 1) gives Y = X and dX = G exactly; a permutation matrix permutes rows
+    exactly; one stored value per row is a single product, hence exact."""
+    rng = np.random.Generator(np.random.PCG64(8200))
+    n, k = 50, 5
+    X = rng.standard_normal((n, k))
+    G = rng.standard_normal((n, k))
+    idx = np.arange(n, dtype=np.int32)
+    st, I = oracle.coo_to_csc(n, n, idx, idx, np.ones(n))
+    Y, _, _ = oracle.spmm(I, X)
+    assert np.array_equal(Y, X)
+    dX, dval, _, _ = oracle.spmm_backward(I, G, X)
+    assert np.array_equal(dX, G)
+    assert np.array_equal(dval, np.einsum("ij,ij->i", G, X)) or np.allclose(
+        dval, (G * X).sum(1), rtol=1e-14, atol=0)
+    perm = rng.permutation(n).astype(np.int32)
+    st, P = oracle.coo_to_csc(n, n, perm, idx, np.ones(n))  # P[perm[c], c] = 1
+    Y, _, _ = oracle.spmm(P, X)
+    expect = np.zeros_like(X)
+    expect[perm] = X
+    assert np.array_equal(Y, expect)
+    scale = rng.standard_normal(n)
+    st, D = oracle.coo_to_csc(n, n, perm, idx, scale)
+    Y, _, _ = oracle.spmm(D, X)
+    expect = np.zeros_like(X)
+    expect[perm] = scale[:, None] * X
+    assert np.array_equal(Y, expect)
+    # transposed operand mistake detector: non-symmetric 2x3 case by hand
+    st, A = oracle.coo_to_csc(2, 3, np.array([0, 1], np.int32), np.array([2, 0], np.int32),
+                              np.array([2.0, 5.0]))
+    Y, _, _ = oracle.spmm(A, np.array([[1.0], [10.0], [100.0]]))
+    assert Y.ravel().tolist() == [200.0, 5.0]
+
+
+def pin_ones_closed_form():
+    """All-ones n_rows x n_cols matrix times integer X: every output row is the column sum of X,
+    exact in binary64 for small integers."""
+    rng = np.random.Generator(np.random.PCG64(8300))
+    n_rows, n_cols, k = 9, 13, 4
+    rr, cc = np.meshgrid(np.arange(n_rows), np.arange(n_cols), indexing="ij")
+    st, A = oracle.coo_to_csc(n_rows, n_cols, rr.ravel().astype(np.int32),
+                              cc.ravel().astype(np.int32), np.ones(n_rows * n_cols))
+    X = rng.integers(-50, 50, (n_cols, k)).astype(np.float64)
+    Y, _, M = oracle.spmm(A, X)
+    assert np.array_equal(Y, np.tile(X.sum(0), (n_rows, 1)))
+    assert np.all(M == n_cols)
+    G = rng.integers(-50, 50, (n_rows, k)).astype(np.float64)
+    dX, dval, _, _ = oracle.spmm_backward(A, G, X)
+    assert np.array_equal(dX, np.tile(G.sum(0), (n_cols, 1)))
+    # dval at stored (r, c) is G[r] . X[c]
+    expect = np.array([G[r] @ X[c] for c in range(n_cols) for r in range(n_rows)])
+    assert np.array_equal(dval, expect)
+
+
+def pin_dense_crosscheck():
+    """numpy dense products on a 2000 x 2000 instance agree within the a-priori bound."""
+    p = synth.diff_fd()
+    st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    D = np.zeros((p.n_rows, p.n_cols))
+    D[A.row_idx, np.repeat(np.arange(p.n_cols), np.diff(A.col_ptr))] = A.values
+    Y, S, M = oracle.spmm(A, p.X)
+    Yd = D @ p.X
+    assert np.all(np.abs(Y - Yd) <= 2 * oracle.gamma(p.n_cols) * (np.abs(D) @ np.abs(p.X)))
+    dX, dval, SdX, Sdv = oracle.spmm_backward(A, p.G, p.X)
+    dXd = D.T @ p.G
+    assert np.all(np.abs(dX - dXd) <= 2 * oracle.gamma(p.n_rows) * (np.abs(D).T @ np.abs(p.G)))
+    cols = np.repeat(np.arange(p.n_cols), np.diff(A.col_ptr))
+    dvd = np.einsum("ij,ij->i", p.G[A.row_idx], p.X[cols])
+    assert np.all(np.abs(dval - dvd) <= 2 * oracle.gamma(p.k) * Sdv)
+
+
+def pin_adjoint_identity():
+    """<A.X, G> = <X, A^T.G> = <values, dvalues> up to binary64 rounding."""
+    p = synth.diff_fd()
+    st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    Y, S, _ = oracle.spmm(A, p.X)
+    dX, dval, SdX, Sdv = oracle.spmm_backward(A, p.G, p.X)
+    a = math.fsum((Y * p.G).ravel().tolist())
+    b = math.fsum((p.X * dX).ravel().tolist())
+    c = math.fsum((A.values * dval).tolist())
+    scale = float((S * np.abs(p.G)).sum())
+    tol = 4 * oracle.gamma(max(p.n_cols, p.k)) * scale
+    assert abs(a - b) <= tol and abs(a - c) <= tol and abs(b - c) <= tol
+
+
+def pin_central_fd(samples: int = 24):
+    """Central differences of L = sum(A.X * G) in binary64.  L is bilinear in (values, X), so
+    the difference quotient with h = 2^-4 has no truncation error; only the rounding of L
+    remains (tolerance 1e-8 relative + 1e-10 absolute)."""
+    p = synth.diff_fd()
+    st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    dX, dval, _, _ = oracle.spmm_backward(A, p.G, p.X)
+    h = 2.0 ** -4
+
+    def L(values, X):
+        Y, _, _ = oracle.spmm(A, X, values=values)
+        return math.fsum((Y * p.G).ravel().tolist())
+
+    rng = np.random.Generator(np.random.PCG64(8400))
+    for q in rng.choice(A.nnz, samples, replace=False):
+        vp = A.values.copy()
+        vp[q] += h
+        vm = A.values.copy()
+        vm[q] -= h
+        fd = (L(vp, p.X) - L(vm, p.X)) / (2 * h)
+        assert abs(fd - dval[q]) <= 1e-8 * abs(dval[q]) + 1e-10, (q, fd, dval[q])
+    for _ in range(samples):
+        c, j = int(rng.integers(p.n_cols)), int(rng.integers(p.k))
+        Xp = p.X.copy()
+        Xp[c, j] += h
+        Xm = p.X.copy()
+        Xm[c, j] -= h
+        fd = (L(A.values, Xp) - L(A.values, Xm)) / (2 * h)
+        assert abs(fd - dX[c, j]) <= 1e-8 * abs(dX[c, j]) + 1e-10, (c, j, fd, dX[c, j])
+
+
+ASSEMBLY_PINS = [pin_golden_assembly, pin_brute_force, pin_scipy_dyadic, pin_invariants_and_totals,
+                 pin_index_encoding, pin_special_cases]
+SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
+             pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
+ALL_PINS = ASSEMBLY_PINS + SPMM_PINS

@@ -1,0 +1,68 @@
+"""Planted mistakes in copies of the oracle (on the CPU) must each fail at least one pin.
+
+Each mutant is the oracle source with one plausible slip -- a dropped or sign-flipped term, a
+wrong or swapped index, a transposed operand, a wrong ordering or a skipped rule -- compiled to
+a temporary library and swapped in for the real one while the pins run.  All mutations keep
+every memory access in bounds.
+"""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+import pins
+
+MUTANTS = {
+    "fold_sign_sort": ("s = s + val[order[j]];", "s = s - val[order[j]];"),
+    "fold_last_wins_rbt": ("it->second = it->second + val[t];", "it->second = val[t];"),
+    "keep_zero_sort": ("if (s != 0.0) {", "if (true) {"),
+    "keep_zero_rbt": ("if (kv.second == 0.0) continue;", ""),
+    "row_order_reversed": ("return row[a] < row[b];", "return row[a] > row[b];"),
+    "decode_swapped": ("int64_t r = (int64_t)(kv.first % (uint64_t)n_rows);",
+                       "int64_t r = (int64_t)(kv.first / (uint64_t)n_rows) % n_rows;"),
+    "offsets_shifted": ("for (int64_t c : emitted_cols) count[c + 1] += 1;",
+                        "for (int64_t c : emitted_cols) count[c] += 1;"),
+    "spmm_wrong_j": ("Y[r * k + j] = Y[r * k + j] + v * X[c * k + j];",
+                     "Y[r * k + j] = Y[r * k + j] + v * X[c * k + (k - 1 - j)];"),
+    "spmm_sign": ("Y[r * k + j] = Y[r * k + j] + v * X[c * k + j];",
+                  "Y[r * k + j] = Y[r * k + j] - v * X[c * k + j];"),
+    "spmm_count": ("M[r] += 1;", "M[r] += 2;"),
+    "dx_wrong_operand": ("dX[c * k + j] = dX[c * k + j] + v * G[r * k + j];",
+                         "dX[c * k + j] = dX[c * k + j] + v * X[c * k + j];"),
+    "dval_sign": ("d = d + G[r * k + j] * X[c * k + j];", "d = d - G[r * k + j] * X[c * k + j];"),
+    "dval_dropped_term": ("d = d + G[r * k + j] * X[c * k + j];",
+                          "if (j) d = d + G[r * k + j] * X[c * k + j];"),
+}
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(oracle._SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, source, tmp_path):
+    old, new = MUTANTS[name]
+    assert source.count(old) == 1, "mutation site must be unique: %r" % old
+    src = tmp_path / "mutant.cpp"
+    src.write_text(source.replace(old, new))
+    so = tmp_path / ("lib_%s.so" % name)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", str(src),
+                    "-o", str(so)], check=True)
+    saved = oracle._load()
+    oracle._lib = oracle.configure(ctypes.CDLL(str(so)))
+    caught = []
+    try:
+        for pin in pins.ALL_PINS:
+            try:
+                pin()
+            except AssertionError:
+                caught.append(pin.__name__)
+                break
+    finally:
+        oracle._lib = saved
+    assert caught, "planted mistake %s passed every pin" % name
