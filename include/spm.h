@@ -1,0 +1,214 @@
+/*
+ * spm.h -- C ABI of the MI355X (gfx950) sparse assembly + CSC SpMM library (libspm.so).
+ *
+ * The operations follow Sanderson & Curtin, "A User-Friendly Hybrid Sparse Matrix Class in C++"
+ * (LNCS 10931, 2018; arXiv:1805.03380):
+ *   - COO (Section 3.2): an unordered list of (row, column, value) triplets held as three
+ *     arrays; duplicates of one location are allowed and accumulate (the += element update of
+ *     Fig. 1), in input order.
+ *   - CSC (Section 3.1): values[N], row_indices[N] and column offsets c[n_cols+1] with c[0] = 0,
+ *     c[n_cols] = N, zero-based indices; column i holds c[i+1] - c[i] elements, stored in
+ *     increasing row order (the ordered traversal of Section 3.3 emits column-major order).
+ *   - the product of a dense operand with the sparse matrix (Section 3, use case (iv)).
+ *
+ * Conventions shared by every entry point
+ *   Memory.   Every array argument is DEVICE memory owned by the caller, except where marked
+ *             "host".  The library never allocates, frees or keeps a pointer after returning;
+ *             scratch memory comes in through a caller-provided workspace (ws, ws_bytes) whose
+ *             size the matching *_workspace / *_size call reports.  Device buffers must be
+ *             256-byte aligned where noted (PyTorch allocations are).
+ *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every
+ *             call only enqueues work on that stream; none synchronizes it.
+ *   Errors.   Arguments that can be checked on the host are checked before anything is
+ *             enqueued; on failure the call returns that status and enqueues nothing.
+ *             Conditions only the device can see (an out-of-range triplet, a malformed CSC)
+ *             are written to the device status word info[1]; outputs are then unspecified,
+ *             but no kernel ever reads or writes outside the buffers described here.
+ *             A failed HIP launch returns SPM_EHIP.
+ *   Sizes.    Dimensions and counts are int64_t on the ABI; n_rows, n_cols, nnz and every
+ *             offset must fit in int32 (SPM_EOVERFLOW otherwise).
+ *   Dense.    Dense operands are row-major with a leading dimension (elements between rows):
+ *             X is n_cols x k (row c of X multiplies column c of A), Y and G are n_rows x k.
+ *   Numerics. Assembly folds duplicates left to right in input order in binary64 and rounds
+ *             once to the output type; a location whose fold compares equal to 0.0 is not
+ *             stored (so -0.0 and cancelled sums are dropped; NaN and Inf are kept).  SpMM
+ *             accumulates every output sequentially in a fixed order (ascending column for Y,
+ *             ascending row for dX) in binary64, or in binary32 when an operand is bfloat16
+ *             and none is binary64, and rounds once.  Results do not depend on tuning,
+ *             launch shape or batching: the batched entry point is bitwise equal to the
+ *             per-matrix entry points.
+ */
+#ifndef SPM_H
+#define SPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spm_status {
+  SPM_OK = 0,
+  SPM_EINVAL = 1,     /* null pointer, negative size, k < 1, bad leading dimension, bad CSC */
+  SPM_EBOUNDS = 2,    /* (device) a triplet's row or column is outside the matrix */
+  SPM_EOVERFLOW = 3,  /* a size or offset does not fit in int32 */
+  SPM_EWORKSPACE = 4, /* workspace / plan buffer smaller than reported */
+  SPM_EDTYPE = 5,     /* unsupported element-type combination */
+  SPM_EHIP = 6        /* a HIP runtime call or kernel launch failed */
+} spm_status;
+
+typedef enum spm_dtype {
+  SPM_F64 = 0,  /* IEEE binary64 */
+  SPM_F32 = 1,  /* IEEE binary32 */
+  SPM_BF16 = 2  /* bfloat16, stored as uint16 */
+} spm_dtype;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *spm_status_string(int status);
+
+/* Library version string, e.g. "0.1.0 gfx950". */
+const char *spm_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * COO -> CSC bulk assembly  (Section 3.2 -> Section 3.1; duplicates accumulate as in Fig. 1,
+ * location order is the column-major index order row + col * n_rows of Section 3.3).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Bytes of workspace spm_coo_to_csc needs for these sizes (*ws_bytes, host).
+ * Returns SPM_EINVAL / SPM_EOVERFLOW for sizes spm_coo_to_csc would reject. */
+spm_status spm_coo_to_csc_workspace(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                    size_t *ws_bytes);
+
+/* Assemble nnz_in triplets (row[t], col[t], val[t]) of an n_rows x n_cols matrix into CSC.
+ *   row, col  int32[nnz_in]; val[nnz_in] of type val_type (F64, F32 or BF16).
+ *   col_ptr   int32[n_cols + 1], fully written: col_ptr[0] = 0, col_ptr[n_cols] = nnz_out.
+ *   row_idx   int32[nnz_in] capacity; the first nnz_out entries are written.
+ *   val_out   capacity nnz_in elements of out_type (F64 or F32); first nnz_out written.
+ *   info      int32[2], written on the stream: info[0] = nnz_out, info[1] = device status
+ *             (0, or SPM_EBOUNDS when some triplet lies outside the matrix; out-of-range
+ *             triplets are then skipped and the outputs describe the remaining ones).
+ *   ws        workspace of at least spm_coo_to_csc_workspace() bytes, 256-byte aligned.
+ * nnz_in = 0 is legal (all-zero col_ptr); n_cols = 0 gives col_ptr = {0}. */
+spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t *row,
+                          const int32_t *col, const void *val, spm_dtype val_type,
+                          int32_t *col_ptr, int32_t *row_idx, void *val_out,
+                          spm_dtype out_type, int32_t *info, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Row index ("plan") of a CSC pattern: the structural transpose the forward product walks.
+ * Deriving the layout an operation needs from the canonical CSC and keeping it alongside is
+ * the hybrid-storage idea of Section 3.4; the transpose itself is X.t() of Table 1.
+ * Plan layout (int32, each part starting on a 256-byte boundary):
+ *   row_ptr[n_rows + 1] | col_t[nnz_cap] | perm[nnz_cap]
+ * where for q in [row_ptr[r], row_ptr[r+1]) the stored element (r, col_t[q]) sits at CSC
+ * slot perm[q], and columns increase with q inside each row.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Plan size and plan-build workspace size for a CSC with capacity nnz_cap. */
+spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                             size_t *plan_bytes, size_t *ws_bytes);
+
+/* Build the plan of the CSC pattern (col_ptr[n_cols+1], row_idx[nnz]) where nnz =
+ * col_ptr[n_cols] is read on the device and must not exceed nnz_cap.
+ *   info  int32[2]: info[0] = nnz seen, info[1] = 0, SPM_EINVAL (col_ptr not monotone,
+ *         col_ptr[0] != 0 or nnz > nnz_cap) or SPM_EBOUNDS (a row index out of range). */
+spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                              const int32_t *col_ptr, const int32_t *row_idx, void *plan,
+                              size_t plan_bytes, int32_t *info, void *ws, size_t ws_bytes,
+                              void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Forward product Y = A . X  (Section 3 use case (iv), through the plan of A's pattern).
+ *   val      CSC values of A, val_type F64 or F32 (indexed through plan.perm).
+ *   X        n_cols x k, x_type F64, F32 or BF16, leading dimension ldx >= k.
+ *   Y        n_rows x k, y_type F64 or F32, leading dimension ldy >= k; fully written
+ *            (rows with no stored element are 0).
+ * Y[r, j] = sum over q in row r, ascending column, of val[perm[q]] * X[col_t[q], j].
+ * ------------------------------------------------------------------------------------------ */
+spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                        const void *plan, const void *val, spm_dtype val_type, const void *X,
+                        int64_t ldx, spm_dtype x_type, void *Y, int64_t ldy, spm_dtype y_type,
+                        void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Adjoint of Y = A . X for a loss with dL/dY = G (n_rows x k):
+ *   dX[c, j]  = sum over p in column c (ascending row) of val[p] * G[row_idx[p], j]
+ *               -- A^T . G by a walk down each CSC column, the traversal of the row-vector
+ *               times CSC product of Fig. 1;
+ *   dval[p]   = sum_j G[row_idx[p], j] * X[c, j]  -- G . X^T sampled on A's pattern.
+ * G and X share g_type = x_type (F64, F32 or BF16).  dX (n_cols x k, ld lddx, dx_type F64 or
+ * F32) and dval (nnz elements, dval_type F64 or F32) may each be NULL to skip that output;
+ * nnz = col_ptr[n_cols] is read on the device and clamped to nnz_cap.
+ * ------------------------------------------------------------------------------------------ */
+spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                                 const int32_t *col_ptr, const int32_t *row_idx,
+                                 const void *val, spm_dtype val_type, const void *G,
+                                 int64_t ldg, const void *X, int64_t ldx, spm_dtype x_type,
+                                 void *dX, int64_t lddx, spm_dtype dx_type, void *dval,
+                                 spm_dtype dval_type, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Batched path: many independent matrices assembled, planned, multiplied forward and
+ * backward in ONE persistent launch (one workgroup per matrix at a time, matrices taken
+ * from a device queue in the order given, largest first recommended).
+ * All per-matrix arrays are packed; item b describes where matrix b lives.  Element offsets
+ * are in elements of the respective array.  For matrix b with nnz_in triplets:
+ *   triplets       row/col/val[trip_off .. trip_off + nnz_in)
+ *   CSC            col_ptr[colptr_off .. + n_cols + 1), row_idx/val_out[trip_off .. + nnz_in)
+ *   plan           row_ptr[rowptr_off .. + n_rows + 1), col_t/perm[trip_off .. + nnz_in)
+ *   dense          X and dX at x_off (n_cols x k, ld k), G and Y at g_off (n_rows x k, ld k)
+ *   dval           dval[trip_off .. + nnz_in)
+ *   info           info[2b] = nnz_out, info[2b + 1] = status of matrix b
+ * Types: val_type F32 or BF16 (values assembled into F32), x_type (X and G) F32 or BF16;
+ * val_out, Y, dX and dval are F32.  Each matrix's results are bitwise equal to what
+ * spm_coo_to_csc + spm_csc_plan_build + spm_csc_spmm + spm_csc_spmm_backward give for it.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct spm_batch_item {
+  int32_t n_rows, n_cols, nnz_in, reserved;
+  int64_t trip_off, colptr_off, rowptr_off, x_off, g_off;
+} spm_batch_item;
+
+/* Host only.  Workspace for a batch whose matrices all have n_rows, n_cols <= max_dim and
+ * nnz_in <= max_nnz_in, run with `workers` persistent workgroups (0 = the library's choice,
+ * which is also what spm_batch_run uses for 0). */
+spm_status spm_batch_workspace(int64_t max_dim, int64_t max_nnz_in, int32_t workers,
+                               size_t *ws_bytes);
+
+/* Host only.  Longest-processing-time-first order of the items (host arrays): order[i] is
+ * the index of the i-th matrix to start; cost is estimated from nnz_in, n and k. */
+spm_status spm_batch_schedule(const spm_batch_item *items_host, int32_t batch, int64_t k,
+                              int32_t *order_host);
+
+/* Run the whole batch.  items and order are device copies (batch entries each); items whose
+ * sizes exceed max_dim / max_nnz_in get info status SPM_EINVAL and are skipped. */
+spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item *items,
+                         const int32_t *order, const int32_t *row, const int32_t *col,
+                         const void *val, spm_dtype val_type, const void *X, const void *G,
+                         spm_dtype x_type, int32_t *col_ptr, int32_t *row_idx, float *val_out,
+                         int32_t *row_ptr, int32_t *col_t, int32_t *perm, float *Y, float *dX,
+                         float *dval, int32_t *info, int64_t max_dim, int64_t max_nnz_in,
+                         int32_t workers, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Tuning.  Launch-shape parameters that never change results (see Numerics above).  The
+ * values are process-wide; spm_tuning_set validates and copies them (host only).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct spm_tuning {
+  int32_t spmm_block;       /* threads per workgroup of the forward / backward kernels */
+  int32_t spmm_unroll;      /* stored elements loaded ahead per group (1, 2, 4 or 8) */
+  int32_t spmm_waves_per_cu;/* forward / backward grid = CUs * this * (64 / block) groups */
+  int32_t batch_block;      /* threads per workgroup of the batched kernel (256 or 512) */
+  int32_t batch_wg_per_cu;  /* persistent batched workgroups per compute unit */
+  int32_t reserved[3];
+} spm_tuning;
+
+spm_status spm_tuning_get(spm_tuning *out);
+spm_status spm_tuning_set(const spm_tuning *in);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPM_H */

@@ -1,0 +1,104 @@
+"""ctypes binding of libspm.so (the C ABI in include/spm.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP kernels.  There
+is no fallback -- if the library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libspm.so")
+
+# spm_status
+OK, EINVAL, EBOUNDS, EOVERFLOW, EWORKSPACE, EDTYPE, EHIP = range(7)
+# spm_dtype
+F64, F32, BF16 = 0, 1, 2
+
+_lib = None
+
+c_i64 = ctypes.c_int64
+c_i32 = ctypes.c_int32
+c_p = ctypes.c_void_p
+c_size_p = ctypes.POINTER(ctypes.c_size_t)
+
+
+class BatchItem(ctypes.Structure):
+    """spm_batch_item."""
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("nnz_in", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("trip_off", ctypes.c_int64), ("colptr_off", ctypes.c_int64),
+                ("rowptr_off", ctypes.c_int64), ("x_off", ctypes.c_int64),
+                ("g_off", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    """spm_tuning."""
+    _fields_ = [("spmm_block", ctypes.c_int32), ("spmm_unroll", ctypes.c_int32),
+                ("spmm_waves_per_cu", ctypes.c_int32), ("batch_block", ctypes.c_int32),
+                ("batch_wg_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "spm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "spm_version": (ctypes.c_char_p, []),
+    "spm_coo_to_csc_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p]),
+    "spm_coo_to_csc": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
+                                      c_p, ctypes.c_int, c_p, c_p, ctypes.c_size_t, c_p]),
+    "spm_csc_plan_size": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p, c_size_p]),
+    "spm_csc_plan_build": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_size_t,
+                                          c_p, c_p, ctypes.c_size_t, c_p]),
+    "spm_csc_spmm": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int, c_p,
+                                    c_i64, ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p]),
+    "spm_csc_spmm_backward": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, c_p,
+                                             ctypes.c_int, c_p, c_i64, c_p, c_i64, ctypes.c_int,
+                                             c_p, c_i64, ctypes.c_int, c_p, ctypes.c_int, c_p]),
+    "spm_batch_workspace": (ctypes.c_int, [c_i64, c_i64, c_i32, c_size_p]),
+    "spm_batch_schedule": (ctypes.c_int, [c_p, c_i32, c_i64, c_p]),
+    "spm_batch_run": (ctypes.c_int, [c_i32, c_i64, c_p, c_p, c_p, c_p, c_p, ctypes.c_int, c_p,
+                                     c_p, ctypes.c_int, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
+                                     c_p, c_p, c_i64, c_i64, c_i32, c_p, ctypes.c_size_t, c_p]),
+    "spm_tuning_get": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+    "spm_tuning_set": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+}
+
+
+class SpmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, status_string(status), status))
+
+
+def load():
+    """Load libspm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libspm.so is not built (%s); run `python -m paper_1805_03380_amd.build`"
+                           % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().spm_status_string(int(status)).decode()
+
+
+def check(status: int, where: str) -> None:
+    if status == OK:
+        return
+    if status == EBOUNDS:
+        raise IndexError(SpmError(status, where))
+    if status in (EINVAL, EDTYPE, EWORKSPACE):
+        raise ValueError(SpmError(status, where))
+    if status == EOVERFLOW:
+        raise OverflowError(SpmError(status, where))
+    raise SpmError(status, where)

@@ -1,0 +1,484 @@
+// Host side of libspm.so: argument validation, workspace layout, launch sequencing.
+// Every entry point is declared (and documented) in include/spm.h.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "spm.h"
+#include "spm_assemble.h"
+#include "spm_spmm.h"
+
+
+namespace {
+
+using namespace spm;
+
+constexpr int kNT = 256;          // threads per workgroup of the assembly / plan kernels
+constexpr int kScanIPT = 8;       // scan tile = 2048 counts
+constexpr int kFoldIPT = 8;       // fold tile = 2048 keys
+constexpr int kSortT = 2048;      // segment-sort tile (segments starting in a tile)
+constexpr int kSortCap = 4096;    // LDS capacity of one sort chunk (keys)
+constexpr int kUnroll = 4;
+
+constexpr int64_t kScanTile = (int64_t)kNT * kScanIPT;
+constexpr int64_t kFoldTile = (int64_t)kNT * kFoldIPT;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Sequential carving of a 256-byte aligned workspace.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  }
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+spm_tuning g_tuning = {256, 4, 8, 256, 2, {0, 0, 0}};
+std::mutex g_tuning_mu;
+
+spm_tuning tuning() {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return g_tuning;
+}
+
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+int grid_for(int64_t work_items, int64_t per_block, int cap) {
+  int64_t g = ceil_div(work_items, per_block);
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+bool fits_i32(int64_t x) { return x >= 0 && x <= INT32_MAX; }
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+spm_status launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPM_OK : SPM_EHIP;
+}
+
+// ------------------------------------------------------------------------------------------
+// Assembly workspace layout.  The first region (counts, look-back states, tickets) is zeroed
+// by one kernel at the start of every call.
+// ------------------------------------------------------------------------------------------
+struct AsmLayout {
+  size_t colcnt, scan_state, fold_state, tickets, zero_bytes;
+  size_t colstart, bucket, scratch, total;
+  int64_t scan_tiles, fold_tiles;
+};
+
+AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
+  AsmLayout L;
+  Carve c;
+  L.scan_tiles = n_cols > 0 ? ceil_div(n_cols, kScanTile) : 1;
+  L.fold_tiles = nnz_in > 0 ? ceil_div(nnz_in, kFoldTile) : 1;
+  L.colcnt = c.take(sizeof(uint32_t) * (size_t)n_cols);
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)L.scan_tiles);
+  L.fold_state = c.take(sizeof(uint64_t) * (size_t)L.fold_tiles);
+  L.tickets = c.take(sizeof(uint32_t) * 4);
+  L.zero_bytes = c.off;
+  L.colstart = c.take(sizeof(int32_t) * (size_t)(n_cols + 1));
+  L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_in);
+  L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_in);
+  L.total = c.off;
+  return L;
+}
+
+struct PlanLayout {
+  size_t rowcnt, scan_state, tickets, zero_bytes, bucket, scratch, total;
+  int64_t scan_tiles;
+};
+
+PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
+  PlanLayout L;
+  Carve c;
+  L.scan_tiles = n_rows > 0 ? ceil_div(n_rows, kScanTile) : 1;
+  L.rowcnt = c.take(sizeof(uint32_t) * (size_t)n_rows);
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)L.scan_tiles);
+  L.tickets = c.take(sizeof(uint32_t) * 4);
+  L.zero_bytes = c.off;
+  L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
+  L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
+  L.total = c.off;
+  return L;
+}
+
+struct PlanParts {
+  size_t row_ptr, col_t, perm, total;
+};
+
+PlanParts plan_parts(int64_t n_rows, int64_t nnz_cap) {
+  PlanParts P;
+  Carve c;
+  P.row_ptr = c.take(sizeof(int32_t) * (size_t)(n_rows + 1));
+  P.col_t = c.take(sizeof(int32_t) * (size_t)nnz_cap);
+  P.perm = c.take(sizeof(int32_t) * (size_t)nnz_cap);
+  P.total = c.off;
+  return P;
+}
+
+spm_status check_dims(int64_t n_rows, int64_t n_cols, int64_t nnz) {
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return SPM_EINVAL;
+  if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz) || n_cols == INT32_MAX ||
+      n_rows == INT32_MAX)
+    return SPM_EOVERFLOW;
+  return SPM_OK;
+}
+
+template <int NT, int IPT>
+void launch_scan(const uint32_t* in, int64_t n, int32_t* out, uint64_t* state, uint32_t* ticket,
+                 hipStream_t s) {
+  const int64_t tiles = n > 0 ? ceil_div(n, (int64_t)NT * IPT) : 1;
+  hipLaunchKernelGGL((k_scan_excl<NT, IPT>), dim3((unsigned)tiles), dim3(NT), 0, s, in, n, out,
+                     state, ticket);
+}
+
+template <typename VT>
+void launch_fold(const uint64_t* keys, const int32_t* colstart, int64_t n_cols, const VT* val,
+                 int32_t* col_ptr, int32_t* row_idx, void* val_out, int out_f64, int32_t* info,
+                 uint64_t* state, uint32_t* ticket, int64_t tiles, hipStream_t s) {
+  hipLaunchKernelGGL((k_fold<kNT, kFoldIPT, VT>), dim3((unsigned)tiles), dim3(kNT), 0, s, keys,
+                     colstart, n_cols, val, col_ptr, row_idx, val_out, out_f64, info, state,
+                     ticket);
+}
+
+// ------------------------------------------------------------------------------------------
+// SpMM dispatch over element types.
+// ------------------------------------------------------------------------------------------
+template <typename VT, typename XT, typename ACC>
+void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G,
+                  const int32_t* row_ptr, const int32_t* col_t,
+                  const int32_t* perm, const void* val, const void* X, int64_t ldx, int xal,
+                  void* Y, int64_t ldy, int y_f64, int yal, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL((k_spmm_fwd<VT, XT, ACC, kUnroll>), dim3(grid), dim3(block), 0, s, n_rows,
+                     n_cols, nnz_cap, k, G, row_ptr, col_t, perm, static_cast<const VT*>(val),
+                     static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal);
+}
+
+template <typename VT, typename XT, typename ACC>
+void launch_bwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G,
+                  const int32_t* col_ptr, const int32_t* row_idx, const void* val, const void* Gm,
+                  int64_t ldg, int gal, const void* X, int64_t ldx, int xal, void* dX,
+                  int64_t lddx, int dx_f64, int dxal, void* dval, int dv_f64, int grid,
+                  int block, hipStream_t s) {
+  hipLaunchKernelGGL((k_spmm_bwd<VT, XT, ACC, kUnroll>), dim3(grid), dim3(block), 0, s, n_rows,
+                     n_cols, nnz_cap, k, G, col_ptr, row_idx, static_cast<const VT*>(val),
+                     static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal,
+                     dX, lddx, dx_f64, dxal, dval, dv_f64);
+}
+
+size_t dsize(spm_dtype t) { return t == SPM_F64 ? 8 : (t == SPM_F32 ? 4 : 2); }
+
+// binary32 accumulation only when bfloat16 is involved and binary64 is not.
+bool acc_is_f32(spm_dtype vt, spm_dtype xt) { return xt == SPM_BF16 && vt != SPM_F64; }
+
+int spmm_grid(int64_t groups, int G, int block) {
+  const spm_tuning tu = tuning();
+  const int64_t per_block = block / G;
+  int64_t want = ceil_div(groups, per_block);
+  int64_t cap = (int64_t)cu_count() * tu.spmm_waves_per_cu * 16;
+  if (want > cap) want = cap;
+  if (want < 1) want = 1;
+  return (int)want;
+}
+
+}  // namespace
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+extern "C" {
+
+const char* spm_status_string(int status) {
+  switch (status) {
+    case SPM_OK: return "ok";
+    case SPM_EINVAL: return "invalid argument";
+    case SPM_EBOUNDS: return "triplet index out of range";
+    case SPM_EOVERFLOW: return "size does not fit in int32";
+    case SPM_EWORKSPACE: return "workspace too small";
+    case SPM_EDTYPE: return "unsupported element type";
+    case SPM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* spm_version(void) { return "0.1.0 gfx950"; }
+
+spm_status spm_coo_to_csc_workspace(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                    size_t* ws_bytes) {
+  if (!ws_bytes) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, nnz_in);
+  if (st != SPM_OK) return st;
+  *ws_bytes = asm_layout(n_cols, nnz_in).total;
+  return SPM_OK;
+}
+
+spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
+                          const int32_t* col, const void* val, spm_dtype val_type,
+                          int32_t* col_ptr, int32_t* row_idx, void* val_out, spm_dtype out_type,
+                          int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_in);
+  if (st != SPM_OK) return st;
+  if (val_type != SPM_F64 && val_type != SPM_F32 && val_type != SPM_BF16) return SPM_EDTYPE;
+  if (out_type != SPM_F64 && out_type != SPM_F32) return SPM_EDTYPE;
+  if (!col_ptr || !info || !ws) return SPM_EINVAL;
+  if (nnz_in > 0 && (!row || !col || !val || !row_idx || !val_out)) return SPM_EINVAL;
+  if (!aligned(ws, 256)) return SPM_EINVAL;
+  const AsmLayout L = asm_layout(n_cols, nnz_in);
+  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  uint32_t* colcnt = reinterpret_cast<uint32_t*>(w + L.colcnt);
+  uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
+  uint64_t* fold_state = reinterpret_cast<uint64_t*>(w + L.fold_state);
+  uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
+  int32_t* colstart = reinterpret_cast<int32_t*>(w + L.colstart);
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
+  uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
+
+  (void)hipGetLastError();
+  const int cap = cu_count() * 16;
+  hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
+                     dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
+                     (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
+  if (nnz_in > 0)
+    hipLaunchKernelGGL((k_col_hist<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0, s,
+                       row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
+  launch_scan<kNT, kScanIPT>(colcnt, n_cols, colstart, scan_state, tickets + 0, s);
+  if (nnz_in > 0) {
+    hipLaunchKernelGGL((k_col_scatter<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0,
+                       s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colstart, colcnt,
+                       bucket);
+    hipLaunchKernelGGL((k_segsort<kNT, kSortCap, false>),
+                       dim3((unsigned)ceil_div(nnz_in, kSortT)), dim3(kNT), 0, s, bucket,
+                       colstart, n_cols, (int64_t)kSortT, scratch, (int32_t*)nullptr,
+                       (int32_t*)nullptr);
+  }
+  const int out_f64 = out_type == SPM_F64 ? 1 : 0;
+  switch (val_type) {
+    case SPM_F64:
+      launch_fold<double>(bucket, colstart, n_cols, static_cast<const double*>(val), col_ptr,
+                          row_idx, val_out, out_f64, info, fold_state, tickets + 1, L.fold_tiles,
+                          s);
+      break;
+    case SPM_F32:
+      launch_fold<float>(bucket, colstart, n_cols, static_cast<const float*>(val), col_ptr,
+                         row_idx, val_out, out_f64, info, fold_state, tickets + 1, L.fold_tiles,
+                         s);
+      break;
+    default:
+      launch_fold<bf16_t>(bucket, colstart, n_cols, static_cast<const bf16_t*>(val), col_ptr,
+                          row_idx, val_out, out_f64, info, fold_state, tickets + 1,
+                          L.fold_tiles, s);
+      break;
+  }
+  return launch_status();
+}
+
+spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_t* plan_bytes,
+                             size_t* ws_bytes) {
+  if (!plan_bytes || !ws_bytes) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  *plan_bytes = plan_parts(n_rows, nnz_cap).total;
+  *ws_bytes = plan_ws_layout(n_rows, nnz_cap).total;
+  return SPM_OK;
+}
+
+spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                              const int32_t* col_ptr, const int32_t* row_idx, void* plan,
+                              size_t plan_bytes, int32_t* info, void* ws, size_t ws_bytes,
+                              void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  if (!col_ptr || !plan || !info || !ws) return SPM_EINVAL;
+  if (nnz_cap > 0 && !row_idx) return SPM_EINVAL;
+  if (!aligned(ws, 256) || !aligned(plan, 256)) return SPM_EINVAL;
+  const PlanParts P = plan_parts(n_rows, nnz_cap);
+  const PlanLayout L = plan_ws_layout(n_rows, nnz_cap);
+  if (plan_bytes < P.total || ws_bytes < L.total) return SPM_EWORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  char* pl = static_cast<char*>(plan);
+  uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
+  uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
+  uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
+  uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
+  int32_t* row_ptr = reinterpret_cast<int32_t*>(pl + P.row_ptr);
+  int32_t* col_t = reinterpret_cast<int32_t*>(pl + P.col_t);
+  int32_t* perm = reinterpret_cast<int32_t*>(pl + P.perm);
+
+  (void)hipGetLastError();
+  const int cap = cu_count() * 16;
+  hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
+                     dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
+                     (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
+  hipLaunchKernelGGL((k_plan_hist<kNT>),
+                     dim3(grid_for(nnz_cap > n_cols ? nnz_cap : n_cols, kNT, cap)), dim3(kNT), 0,
+                     s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, rowcnt, info);
+  launch_scan<kNT, kScanIPT>(rowcnt, n_rows, row_ptr, scan_state, tickets, s);
+  if (nnz_cap > 0 && n_cols > 0) {
+    hipLaunchKernelGGL((k_row_scatter<kNT>), dim3(grid_for(nnz_cap, kNT * 4, cap)), dim3(kNT), 0,
+                       s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, row_ptr, rowcnt, bucket);
+    hipLaunchKernelGGL((k_segsort<kNT, kSortCap, true>),
+                       dim3((unsigned)ceil_div(nnz_cap, kSortT)), dim3(kNT), 0, s, bucket,
+                       row_ptr, n_rows, (int64_t)kSortT, scratch, col_t, perm);
+  }
+  return launch_status();
+}
+
+spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                        const void* plan, const void* val, spm_dtype val_type, const void* X,
+                        int64_t ldx, spm_dtype x_type, void* Y, int64_t ldy, spm_dtype y_type,
+                        void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  if (k < 1 || ldx < k || ldy < k) return SPM_EINVAL;
+  if (!fits_i32(k) || (n_cols > 0 && ldx > INT64_MAX / n_cols) ||
+      (n_rows > 0 && ldy > INT64_MAX / n_rows))
+    return SPM_EOVERFLOW;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
+  if (y_type != SPM_F64 && y_type != SPM_F32) return SPM_EDTYPE;
+  if (!plan || !Y || (nnz_cap > 0 && !val) || (n_cols > 0 && !X)) return SPM_EINVAL;
+  if (!aligned(plan, 256)) return SPM_EINVAL;
+  if (n_rows == 0) return SPM_OK;
+  const PlanParts P = plan_parts(n_rows, nnz_cap);
+  const char* pl = static_cast<const char*>(plan);
+  const int32_t* row_ptr = reinterpret_cast<const int32_t*>(pl + P.row_ptr);
+  const int32_t* col_t = reinterpret_cast<const int32_t*>(pl + P.col_t);
+  const int32_t* perm = reinterpret_cast<const int32_t*>(pl + P.perm);
+  const int G = group_width(k);
+  const spm_tuning tu = tuning();
+  const int block = tu.spmm_block;
+  const int grid = spmm_grid(n_rows, G, block);
+  const int xal = (aligned(X, 4 * dsize(x_type)) && (ldx % 4) == 0) ? 1 : 0;
+  const int yal = (aligned(Y, 4 * dsize(y_type)) && (ldy % 4) == 0) ? 1 : 0;
+  const int y_f64 = y_type == SPM_F64;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const bool f32acc = acc_is_f32(val_type, x_type);
+#define SPM_FWD(VT, XT, ACC)                                                                   \
+  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, \
+                            yal, grid, block, s)
+  if (val_type == SPM_F64) {
+    if (x_type == SPM_F64) SPM_FWD(double, double, double);
+    else if (x_type == SPM_F32) SPM_FWD(double, float, double);
+    else SPM_FWD(double, bf16_t, double);
+  } else {
+    if (x_type == SPM_F64) SPM_FWD(float, double, double);
+    else if (x_type == SPM_F32) SPM_FWD(float, float, double);
+    else if (f32acc) SPM_FWD(float, bf16_t, float);
+    else SPM_FWD(float, bf16_t, double);
+  }
+#undef SPM_FWD
+  return launch_status();
+}
+
+spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                                 const int32_t* col_ptr, const int32_t* row_idx, const void* val,
+                                 spm_dtype val_type, const void* Gm, int64_t ldg, const void* X,
+                                 int64_t ldx, spm_dtype x_type, void* dX, int64_t lddx,
+                                 spm_dtype dx_type, void* dval, spm_dtype dval_type,
+                                 void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  if (k < 1 || ldg < k || ldx < k || (dX && lddx < k)) return SPM_EINVAL;
+  if (!fits_i32(k)) return SPM_EOVERFLOW;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
+  if (dX && dx_type != SPM_F64 && dx_type != SPM_F32) return SPM_EDTYPE;
+  if (dval && dval_type != SPM_F64 && dval_type != SPM_F32) return SPM_EDTYPE;
+  if (!col_ptr || (nnz_cap > 0 && (!row_idx || !val)) || (n_rows > 0 && !Gm) ||
+      (n_cols > 0 && !X))
+    return SPM_EINVAL;
+  if (!dX && !dval) return SPM_OK;
+  if (n_cols == 0) return SPM_OK;
+  const int G = group_width(k);
+  const spm_tuning tu = tuning();
+  const int block = tu.spmm_block;
+  const int grid = spmm_grid(n_cols, G, block);
+  const int gal = (aligned(Gm, 4 * dsize(x_type)) && (ldg % 4) == 0) ? 1 : 0;
+  const int xal = (aligned(X, 4 * dsize(x_type)) && (ldx % 4) == 0) ? 1 : 0;
+  const int dxal = dX ? ((aligned(dX, 4 * dsize(dx_type)) && (lddx % 4) == 0) ? 1 : 0) : 0;
+  const int dx_f64 = dx_type == SPM_F64;
+  const int dv_f64 = dval_type == SPM_F64;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const bool f32acc = acc_is_f32(val_type, x_type);
+#define SPM_BWD(VT, XT, ACC)                                                                   \
+  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, col_ptr, row_idx, val, Gm, ldg, gal, X, \
+                            ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, block, s)
+  if (val_type == SPM_F64) {
+    if (x_type == SPM_F64) SPM_BWD(double, double, double);
+    else if (x_type == SPM_F32) SPM_BWD(double, float, double);
+    else SPM_BWD(double, bf16_t, double);
+  } else {
+    if (x_type == SPM_F64) SPM_BWD(float, double, double);
+    else if (x_type == SPM_F32) SPM_BWD(float, float, double);
+    else if (f32acc) SPM_BWD(float, bf16_t, float);
+    else SPM_BWD(float, bf16_t, double);
+  }
+#undef SPM_BWD
+  return launch_status();
+}
+
+spm_status spm_tuning_get(spm_tuning* out) {
+  if (!out) return SPM_EINVAL;
+  *out = tuning();
+  return SPM_OK;
+}
+
+spm_status spm_tuning_set(const spm_tuning* in) {
+  if (!in) return SPM_EINVAL;
+  if (in->spmm_block != 64 && in->spmm_block != 128 && in->spmm_block != 256) return SPM_EINVAL;
+  if (in->spmm_unroll != 1 && in->spmm_unroll != 2 && in->spmm_unroll != 4 &&
+      in->spmm_unroll != 8)
+    return SPM_EINVAL;
+  if (in->spmm_waves_per_cu < 1 || in->spmm_waves_per_cu > 64) return SPM_EINVAL;
+  if (in->batch_block != 256 && in->batch_block != 512) return SPM_EINVAL;
+  if (in->batch_wg_per_cu < 1 || in->batch_wg_per_cu > 8) return SPM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning = *in;
+  return SPM_OK;
+}
+
+}  // extern "C"
+
+// Batched entry points: not built yet in this revision.
+extern "C" {
+spm_status spm_batch_workspace(int64_t, int64_t, int32_t, size_t*) { return SPM_EINVAL; }
+spm_status spm_batch_schedule(const spm_batch_item*, int32_t, int64_t, int32_t*) {
+  return SPM_EINVAL;
+}
+spm_status spm_batch_run(int32_t, int64_t, const spm_batch_item*, const int32_t*, const int32_t*,
+                         const int32_t*, const void*, spm_dtype, const void*, const void*,
+                         spm_dtype, int32_t*, int32_t*, float*, int32_t*, int32_t*, int32_t*,
+                         float*, float*, float*, int32_t*, int64_t, int64_t, int32_t, void*,
+                         size_t, void*) {
+  return SPM_EINVAL;
+}
+}

@@ -1,0 +1,251 @@
+// CSC sparse x dense products on gfx950: the forward product Y = A.X through the plan (row
+// index) of A's pattern, and the fused adjoint (dX = A^T.G, dval = G.X^T on A's pattern) by a
+// walk down each CSC column.  Bandwidth-bound (about 0.5 flop per byte): no matrix cores;
+// every nonzero's dense row is read as coalesced 16-byte vectors by a group of lanes.
+//
+// Result ordering does not depend on the launch shape:
+//   * a group of G lanes serves one output row (forward) or one column (adjoint), each lane
+//     owning 4 consecutive dense columns; G depends on k alone (group_width);
+//   * every Y / dX element is ONE accumulator updated with fma in ascending column (forward)
+//     or ascending row (adjoint) order, starting from 0;
+//   * dval[p]: each lane folds its 4-element pieces with fma in ascending j, then the G lane
+//     partials are combined by a fixed xor butterfly.
+// The batched kernel calls the same device functions, so its results are bitwise equal.
+#pragma once
+
+#include "spm_device.h"
+
+namespace spm {
+
+// Lanes per row: next power of two >= ceil(k/4), capped at one wavefront.
+__host__ __device__ inline int group_width(int64_t k) {
+  int64_t need = (k + 3) / 4;
+  int g = 1;
+  while (g < need && g < kWave) g <<= 1;
+  return g;
+}
+
+template <typename ACC>
+__device__ __forceinline__ ACC fma_acc(ACC a, ACC b, ACC c);
+template <>
+__device__ __forceinline__ double fma_acc<double>(double a, double b, double c) {
+  return __fma_rn(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_acc<float>(float a, float b, float c) {
+  return __fmaf_rn(a, b, c);
+}
+
+// Forward: Y[r, :] for one row r, by the G lanes of a group (lane lg in [0, G)).
+// A plan entry whose column or slot is out of range (only possible for a plan that was not
+// built from a valid CSC) contributes nothing and is never dereferenced.
+template <typename VT, typename XT, typename ACC, int U>
+__device__ __forceinline__ void spmm_row(int64_t r, int lg, int G, int64_t k, int64_t n_cols,
+                                         int64_t nnz_cap,
+                                         const int32_t* __restrict__ row_ptr,
+                                         const int32_t* __restrict__ col_t,
+                                         const int32_t* __restrict__ perm,
+                                         const VT* __restrict__ val, const XT* __restrict__ X,
+                                         int64_t ldx, bool xal, void* __restrict__ Y,
+                                         int64_t ldy, bool y_f64, bool yal) {
+  int64_t q0 = row_ptr[r], q1 = row_ptr[r + 1];
+  q0 = q0 < 0 ? 0 : (q0 > nnz_cap ? nnz_cap : q0);
+  q1 = q1 < q0 ? q0 : (q1 > nnz_cap ? nnz_cap : q1);
+  for (int64_t j0 = (int64_t)lg * 4; j0 < k; j0 += (int64_t)G * 4) {
+    const int avail = (int)((k - j0) < 4 ? (k - j0) : 4);
+    ACC acc[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
+    int64_t q = q0;
+    for (; q + U <= q1; q += U) {
+      int32_t c[U], pp[U];
+      bool ok[U];
+      ACC v[U];
+      ACC x[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        c[u] = col_t[q + u];
+        pp[u] = perm[q + u];
+        ok[u] = (uint32_t)c[u] < (uint64_t)n_cols && (uint32_t)pp[u] < (uint64_t)nnz_cap;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ok[u] ? to_acc<ACC>(val[pp[u]]) : (ACC)0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        load4<ACC>(X + (int64_t)(ok[u] ? c[u] : 0) * ldx + j0, ok[u] ? avail : 0, xal, x[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fma_acc<ACC>(v[u], x[u][e], acc[e]);
+    }
+    for (; q < q1; ++q) {
+      const int32_t c = col_t[q], pq = perm[q];
+      const bool ok = (uint32_t)c < (uint64_t)n_cols && (uint32_t)pq < (uint64_t)nnz_cap;
+      const ACC v = ok ? to_acc<ACC>(val[pq]) : (ACC)0;
+      ACC x[4];
+      load4<ACC>(X + (int64_t)(ok ? c : 0) * ldx + j0, ok ? avail : 0, xal, x);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = fma_acc<ACC>(v, x[e], acc[e]);
+    }
+    store_n<ACC>(Y, r * ldy + j0, avail, y_f64, yal, acc);
+  }
+}
+
+// Adjoint for one column c, by the G lanes of a group.  p range already clamped.
+template <typename VT, typename XT, typename ACC, int U>
+__device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, int lg, int G,
+                                             int64_t k, int64_t n_rows,
+                                             const int32_t* __restrict__ row_idx,
+                                             const VT* __restrict__ val,
+                                             const XT* __restrict__ Gm, int64_t ldg, bool gal,
+                                             const XT* __restrict__ X, int64_t ldx, bool xal,
+                                             void* __restrict__ dX, int64_t lddx, bool dx_f64,
+                                             bool dxal, void* __restrict__ dval, bool dv_f64) {
+  const int64_t span = (int64_t)G * 4;
+  const int nch = (int)((k + span - 1) / span);
+  if (nch <= 1) {
+    const int64_t j0 = (int64_t)lg * 4;
+    const int avail = (int)((k - j0) < 0 ? 0 : ((k - j0) < 4 ? (k - j0) : 4));
+    ACC x[4];
+    load4<ACC>(X + c * ldx + j0, avail, xal, x);
+    ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
+    int64_t p = p0;
+    for (; p + U <= p1; p += U) {
+      int32_t r[U];
+      ACC v[U];
+      ACC g[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        r[u] = row_idx[p + u];
+        if (r[u] < 0 || (int64_t)r[u] >= n_rows) r[u] = -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = to_acc<ACC>(val[p + u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        load4<ACC>(Gm + (int64_t)(r[u] < 0 ? 0 : r[u]) * ldg + j0, r[u] < 0 ? 0 : avail, gal,
+                   g[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dx[e] = fma_acc<ACC>(v[u], g[u][e], dx[e]);
+        if (dval) {
+          ACC d = (ACC)0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[u][e], x[e], d);
+          for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+          if (lg == 0) {
+            if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d;
+            else static_cast<float*>(dval)[p + u] = (float)d;
+          }
+        }
+      }
+    }
+    for (; p < p1; ++p) {
+      int32_t r = row_idx[p];
+      if (r < 0 || (int64_t)r >= n_rows) r = -1;
+      const ACC v = to_acc<ACC>(val[p]);
+      ACC g[4];
+      load4<ACC>(Gm + (int64_t)(r < 0 ? 0 : r) * ldg + j0, r < 0 ? 0 : avail, gal, g);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dx[e] = fma_acc<ACC>(v, g[e], dx[e]);
+      if (dval) {
+        ACC d = (ACC)0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
+        for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+        if (lg == 0) {
+          if (dv_f64) static_cast<double*>(dval)[p] = (double)d;
+          else static_cast<float*>(dval)[p] = (float)d;
+        }
+      }
+    }
+    if (dX && avail > 0) store_n<ACC>(dX, c * lddx + j0, avail, dx_f64, dxal, dx);
+    return;
+  }
+  // k wider than one wavefront's 4-element pieces: several pieces per lane.
+  if (dX) {
+    for (int m = 0; m < nch; ++m) {
+      const int64_t j0 = ((int64_t)m * G + lg) * 4;
+      if (j0 >= k) break;
+      const int avail = (int)((k - j0) < 4 ? (k - j0) : 4);
+      ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
+      for (int64_t p = p0; p < p1; ++p) {
+        const int32_t r = row_idx[p];
+        if (r < 0 || (int64_t)r >= n_rows) continue;
+        const ACC v = to_acc<ACC>(val[p]);
+        ACC g[4];
+        load4<ACC>(Gm + (int64_t)r * ldg + j0, avail, gal, g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dx[e] = fma_acc<ACC>(v, g[e], dx[e]);
+      }
+      store_n<ACC>(dX, c * lddx + j0, avail, dx_f64, dxal, dx);
+    }
+  }
+  if (dval) {
+    for (int64_t p = p0; p < p1; ++p) {
+      int32_t r = row_idx[p];
+      if (r < 0 || (int64_t)r >= n_rows) r = -1;
+      ACC d = (ACC)0;
+      for (int m = 0; m < nch; ++m) {
+        const int64_t j0 = ((int64_t)m * G + lg) * 4;
+        const int avail = (r < 0 || j0 >= k) ? 0 : (int)((k - j0) < 4 ? (k - j0) : 4);
+        ACC g[4], x[4];
+        load4<ACC>(Gm + (int64_t)(r < 0 ? 0 : r) * ldg + (avail ? j0 : 0), avail, gal, g);
+        load4<ACC>(X + c * ldx + (avail ? j0 : 0), avail, xal, x);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
+      }
+      for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+      if (lg == 0) {
+        if (dv_f64) static_cast<double*>(dval)[p] = (double)d;
+        else static_cast<float*>(dval)[p] = (float)d;
+      }
+    }
+  }
+}
+
+template <typename VT, typename XT, typename ACC, int U>
+__global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                                                  int64_t k, int G,
+                                                  const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_t,
+                                                  const int32_t* __restrict__ perm,
+                                                  const VT* __restrict__ val,
+                                                  const XT* __restrict__ X, int64_t ldx,
+                                                  int xal, void* __restrict__ Y, int64_t ldy,
+                                                  int y_f64, int yal) {
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t groups_per_block = blockDim.x / G;
+  const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
+  for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; r < n_rows;
+       r += ngroups)
+    spmm_row<VT, XT, ACC, U>(r, lg, G, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X, ldx,
+                             xal != 0, Y, ldy, y_f64 != 0, yal != 0);
+}
+
+template <typename VT, typename XT, typename ACC, int U>
+__global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                                                  int64_t k, int G,
+                                                  const int32_t* __restrict__ col_ptr,
+                                                  const int32_t* __restrict__ row_idx,
+                                                  const VT* __restrict__ val,
+                                                  const XT* __restrict__ Gm, int64_t ldg, int gal,
+                                                  const XT* __restrict__ X, int64_t ldx, int xal,
+                                                  void* __restrict__ dX, int64_t lddx, int dx_f64,
+                                                  int dxal, void* __restrict__ dval, int dv_f64) {
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t groups_per_block = blockDim.x / G;
+  const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
+  const int64_t raw = col_ptr[n_cols];
+  const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
+  for (int64_t c = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; c < n_cols;
+       c += ngroups) {
+    int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
+    p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
+    p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
+    spmm_col_bwd<VT, XT, ACC, U>(c, p0, p1, lg, G, k, n_rows, row_idx, val, Gm, ldg, gal != 0,
+                                 X, ldx, xal != 0, dX, lddx, dx_f64 != 0, dxal != 0, dval,
+                                 dv_f64 != 0);
+  }
+}
+
+}  // namespace spm

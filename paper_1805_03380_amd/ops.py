@@ -1,0 +1,242 @@
+"""Torch-facing wrappers of the C ABI: device tensors in, device tensors out.
+
+PyTorch supplies device memory and the current HIP stream; every computation is a libspm.so
+kernel.  Functions raise if the library is missing, if no GPU is present, or when the library
+reports an error (IndexError for out-of-range triplets, ValueError for bad arguments).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+
+_DT = {torch.float64: _lib.F64, torch.float32: _lib.F32, torch.bfloat16: _lib.BF16}
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t not in _DT:
+        raise ValueError("unsupported element type %s" % t)
+    return _DT[t]
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_cuda(*tensors):
+    if not torch.cuda.is_available():
+        raise RuntimeError("libspm needs a GPU: torch.cuda.is_available() is False")
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("expected a device tensor, got one on %s" % t.device)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class CSCMatrix:
+    """CSC arrays of Section 3.1 on the device.  ``row_idx`` / ``values`` have capacity
+    ``nnz_cap``; the first ``nnz`` entries are the matrix."""
+    n_rows: int
+    n_cols: int
+    col_ptr: torch.Tensor
+    row_idx_buf: torch.Tensor
+    values_buf: torch.Tensor
+    info: torch.Tensor
+    _nnz: int | None = None
+    _plan: torch.Tensor | None = field(default=None, repr=False)
+
+    @property
+    def nnz_cap(self) -> int:
+        return int(self.row_idx_buf.shape[0])
+
+    @property
+    def device(self):
+        return self.col_ptr.device
+
+    def sync(self) -> "CSCMatrix":
+        """Read the device info words once (the only host synchronisation of assembly)."""
+        if self._nnz is None:
+            info = self.info.cpu()
+            _lib.check(int(info[1]), "spm_coo_to_csc (device)")
+            self._nnz = int(info[0])
+        return self
+
+    @property
+    def nnz(self) -> int:
+        return self.sync()._nnz
+
+    @property
+    def row_idx(self) -> torch.Tensor:
+        return self.row_idx_buf[: self.nnz]
+
+    @property
+    def values(self) -> torch.Tensor:
+        return self.values_buf[: self.nnz]
+
+    def plan(self) -> torch.Tensor:
+        """Row index of the pattern (built once, cached)."""
+        if self._plan is None:
+            self._plan = build_plan(self)
+        return self._plan
+
+
+def coo_to_csc(row: torch.Tensor, col: torch.Tensor, val: torch.Tensor, shape,
+               out_dtype: torch.dtype | None = None, sync: bool = True) -> CSCMatrix:
+    """Assemble COO triplets into CSC on the current stream (spm_coo_to_csc)."""
+    _require_cuda(row, col, val)
+    n_rows, n_cols = int(shape[0]), int(shape[1])
+    row = row.contiguous()
+    col = col.contiguous()
+    val = val.contiguous()
+    if row.dtype != torch.int32 or col.dtype != torch.int32:
+        raise ValueError("row and col must be int32")
+    nnz_in = int(row.numel())
+    if col.numel() != nnz_in or val.numel() != nnz_in:
+        raise ValueError("row, col and val must have the same length")
+    if out_dtype is None:
+        out_dtype = torch.float64 if val.dtype == torch.float64 else torch.float32
+    lib = _lib.load()
+    dev = row.device
+    ws_bytes = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_coo_to_csc_workspace(n_rows, n_cols, nnz_in, _lib.ctypes.byref(ws_bytes)),
+               "spm_coo_to_csc_workspace")
+    ws = _workspace(ws_bytes.value, dev)
+    col_ptr = torch.empty(n_cols + 1, dtype=torch.int32, device=dev)
+    row_idx = torch.empty(max(nnz_in, 1), dtype=torch.int32, device=dev)
+    vout = torch.empty(max(nnz_in, 1), dtype=out_dtype, device=dev)
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.spm_coo_to_csc(n_rows, n_cols, nnz_in, _ptr(row), _ptr(col), _ptr(val),
+                            _dtype_code(val.dtype), _ptr(col_ptr), _ptr(row_idx), _ptr(vout),
+                            _dtype_code(out_dtype), _ptr(info), _ptr(ws), ws.numel(),
+                            _stream(dev))
+    _lib.check(st, "spm_coo_to_csc")
+    A = CSCMatrix(n_rows, n_cols, col_ptr, row_idx[:nnz_in] if nnz_in else row_idx[:0],
+                  vout[:nnz_in] if nnz_in else vout[:0], info)
+    A._ws = ws  # keep the workspace alive until the stream has consumed it
+    if sync:
+        A.sync()
+    return A
+
+
+def plan_size(n_rows: int, n_cols: int, nnz_cap: int):
+    lib = _lib.load()
+    pb = _lib.ctypes.c_size_t(0)
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_csc_plan_size(n_rows, n_cols, nnz_cap, _lib.ctypes.byref(pb),
+                                     _lib.ctypes.byref(wb)), "spm_csc_plan_size")
+    return pb.value, wb.value
+
+
+def build_plan(A: CSCMatrix, check: bool = True) -> torch.Tensor:
+    """Row index of A's pattern (spm_csc_plan_build), as a uint8 device buffer."""
+    _require_cuda(A.col_ptr)
+    lib = _lib.load()
+    cap = A.nnz_cap
+    pb, wb = plan_size(A.n_rows, A.n_cols, cap)
+    plan = torch.empty(max(pb, 256), dtype=torch.uint8, device=A.device)
+    ws = _workspace(wb, A.device)
+    info = torch.empty(2, dtype=torch.int32, device=A.device)
+    st = lib.spm_csc_plan_build(A.n_rows, A.n_cols, cap, _ptr(A.col_ptr),
+                                _ptr(A.row_idx_buf) if cap else None, _ptr(plan), plan.numel(),
+                                _ptr(info), _ptr(ws), ws.numel(), _stream(A.device))
+    _lib.check(st, "spm_csc_plan_build")
+    plan._ws = ws
+    if check:
+        h = info.cpu()
+        _lib.check(int(h[1]), "spm_csc_plan_build (device)")
+    return plan
+
+
+def plan_arrays(plan: torch.Tensor, n_rows: int, nnz_cap: int):
+    """(row_ptr, col_t, perm) int32 views of a plan buffer (layout of include/spm.h)."""
+    def a256(x):
+        return (x + 255) & ~255
+    rp_bytes = a256(4 * (n_rows + 1))
+    ct_bytes = a256(4 * nnz_cap)
+    row_ptr = plan[:4 * (n_rows + 1)].view(torch.int32)
+    col_t = plan[rp_bytes:rp_bytes + 4 * nnz_cap].view(torch.int32)
+    perm = plan[rp_bytes + ct_bytes:rp_bytes + ct_bytes + 4 * nnz_cap].view(torch.int32)
+    return row_ptr, col_t, perm
+
+
+def _out_type(vt: torch.dtype, xt: torch.dtype) -> torch.dtype:
+    return torch.float64 if torch.float64 in (vt, xt) else torch.float32
+
+
+def spmm(A: CSCMatrix, X: torch.Tensor, values: torch.Tensor | None = None,
+         out_dtype: torch.dtype | None = None, plan: torch.Tensor | None = None,
+         out: torch.Tensor | None = None) -> torch.Tensor:
+    """Y = A.X (spm_csc_spmm).  X is n_cols x k (or a vector of length n_cols)."""
+    vec = X.dim() == 1
+    X2 = X.reshape(-1, 1) if vec else X
+    _require_cuda(X2, A.col_ptr)
+    if X2.shape[0] != A.n_cols:
+        raise ValueError("X has %d rows, A has %d columns" % (X2.shape[0], A.n_cols))
+    if X2.stride(1) != 1:
+        X2 = X2.contiguous()
+    v = A.values_buf if values is None else values
+    k = int(X2.shape[1])
+    if out_dtype is None:
+        out_dtype = _out_type(v.dtype, X2.dtype)
+    if plan is None:
+        plan = A.plan()
+    Y = out if out is not None else torch.empty(A.n_rows, k, dtype=out_dtype, device=X2.device)
+    lib = _lib.load()
+    st = lib.spm_csc_spmm(A.n_rows, A.n_cols, A.nnz_cap, k, _ptr(plan), _ptr(v),
+                          _dtype_code(v.dtype), _ptr(X2), X2.stride(0), _dtype_code(X2.dtype),
+                          _ptr(Y), Y.stride(0), _dtype_code(Y.dtype), _stream(X2.device))
+    _lib.check(st, "spm_csc_spmm")
+    return Y.reshape(-1) if vec else Y
+
+
+def spmm_backward(A: CSCMatrix, G: torch.Tensor, X: torch.Tensor,
+                  values: torch.Tensor | None = None, need_dX: bool = True,
+                  need_dval: bool = True, dx_dtype: torch.dtype | None = None,
+                  dval_dtype: torch.dtype | None = None):
+    """(dX, dval) of Y = A.X for dL/dY = G (spm_csc_spmm_backward); None where not needed."""
+    vec = X.dim() == 1
+    X2 = X.reshape(-1, 1) if vec else X
+    G2 = G.reshape(-1, 1) if G.dim() == 1 else G
+    _require_cuda(X2, G2, A.col_ptr)
+    if G2.dtype != X2.dtype:
+        raise ValueError("G and X must share one element type")
+    if X2.stride(1) != 1:
+        X2 = X2.contiguous()
+    if G2.stride(1) != 1:
+        G2 = G2.contiguous()
+    v = A.values_buf if values is None else values
+    k = int(X2.shape[1])
+    if G2.shape != (A.n_rows, k) or X2.shape[0] != A.n_cols:
+        raise ValueError("shape mismatch: G %s, X %s, A %dx%d" % (tuple(G2.shape),
+                         tuple(X2.shape), A.n_rows, A.n_cols))
+    if dx_dtype is None:
+        dx_dtype = X2.dtype if X2.dtype != torch.bfloat16 else torch.float32
+    if dval_dtype is None:
+        dval_dtype = v.dtype
+    dev = X2.device
+    dX = torch.empty(A.n_cols, k, dtype=dx_dtype, device=dev) if need_dX else None
+    dval = torch.empty(max(A.nnz_cap, 1), dtype=dval_dtype, device=dev) if need_dval else None
+    lib = _lib.load()
+    st = lib.spm_csc_spmm_backward(A.n_rows, A.n_cols, A.nnz_cap, k, _ptr(A.col_ptr),
+                                   _ptr(A.row_idx_buf) if A.nnz_cap else None,
+                                   _ptr(v) if A.nnz_cap else None, _dtype_code(v.dtype),
+                                   _ptr(G2), G2.stride(0), _ptr(X2), X2.stride(0),
+                                   _dtype_code(X2.dtype), _ptr(dX),
+                                   dX.stride(0) if dX is not None else k,
+                                   _dtype_code(dx_dtype), _ptr(dval), _dtype_code(dval_dtype),
+                                   _stream(dev))
+    _lib.check(st, "spm_csc_spmm_backward")
+    if dval is not None:
+        dval = dval[: A.nnz]
+    if vec and dX is not None:
+        dX = dX.reshape(-1)
+    return dX, dval

@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every function include/spm.h declares,
+and rejects bad arguments on the host (before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1805_03380_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_build():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1805_03380_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "spm.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib_or_build()
+    names = _declared()
+    assert "spm_coo_to_csc" in names and "spm_csc_spmm_backward" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings_and_version():
+    lib = _lib_or_build()
+    assert lib.spm_status_string(0) == b"ok"
+    assert lib.spm_status_string(2) == b"triplet index out of range"
+    assert lib.spm_version().startswith(b"0.")
+
+
+def test_workspace_sizes():
+    lib = _lib_or_build()
+    ws = ctypes.c_size_t(0)
+    assert lib.spm_coo_to_csc_workspace(10, 10, 100, ctypes.byref(ws)) == _lib.OK
+    small = ws.value
+    assert lib.spm_coo_to_csc_workspace(10, 10, 10_000, ctypes.byref(ws)) == _lib.OK
+    assert ws.value > small and ws.value % 256 == 0
+    assert lib.spm_coo_to_csc_workspace(-1, 10, 100, ctypes.byref(ws)) == _lib.EINVAL
+    assert lib.spm_coo_to_csc_workspace(10, 2 ** 31, 100, ctypes.byref(ws)) == _lib.EOVERFLOW
+    assert lib.spm_coo_to_csc_workspace(10, 10, 2 ** 31, ctypes.byref(ws)) == _lib.EOVERFLOW
+    assert lib.spm_coo_to_csc_workspace(10, 10, 10, None) == _lib.EINVAL
+    pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.spm_csc_plan_size(100, 50, 1000, ctypes.byref(pb), ctypes.byref(wb)) == _lib.OK
+    assert pb.value >= 4 * (101 + 2000) and wb.value >= 16 * 1000
+
+
+def test_host_validation_rejects_before_launch():
+    lib = _lib_or_build()
+    fake = 0x1000  # never dereferenced: every call below fails validation first
+    ws = ctypes.c_void_p(0x100000)
+    args = dict(n_rows=4, n_cols=4, nnz=8)
+
+    def c2c(n_rows=4, n_cols=4, nnz=8, row=fake, col=fake, val=fake, vt=_lib.F64, cp=fake,
+            ri=fake, vo=fake, ot=_lib.F64, info=fake, w=ws, wsb=1 << 30):
+        return lib.spm_coo_to_csc(n_rows, n_cols, nnz, row, col, val, vt, cp, ri, vo, ot, info,
+                                  w, wsb, None)
+
+    assert c2c(n_rows=-1) == _lib.EINVAL
+    assert c2c(nnz=2 ** 31) == _lib.EOVERFLOW
+    assert c2c(vt=7) == _lib.EDTYPE
+    assert c2c(ot=_lib.BF16) == _lib.EDTYPE
+    assert c2c(row=None) == _lib.EINVAL
+    assert c2c(info=None) == _lib.EINVAL
+    assert c2c(w=ctypes.c_void_p(0x100010)) == _lib.EINVAL  # not 256-byte aligned
+    assert c2c(wsb=16) == _lib.EWORKSPACE
+    # spmm / backward argument checks
+    assert lib.spm_csc_spmm(4, 4, 8, 0, fake, fake, _lib.F32, fake, 4, _lib.F32, fake, 4,
+                            _lib.F32, None) == _lib.EINVAL
+    assert lib.spm_csc_spmm(4, 4, 8, 8, fake, fake, _lib.F32, fake, 4, _lib.F32, fake, 8,
+                            _lib.F32, None) == _lib.EINVAL  # ldx < k
+    assert lib.spm_csc_spmm(4, 4, 8, 4, fake, fake, _lib.BF16, fake, 4, _lib.F32, fake, 4,
+                            _lib.F32, None) == _lib.EDTYPE
+    assert lib.spm_csc_spmm_backward(4, 4, 8, 4, None, fake, fake, _lib.F32, fake, 4, fake, 4,
+                                     _lib.F32, fake, 4, _lib.F32, fake, _lib.F32,
+                                     None) == _lib.EINVAL
+    assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, 16, fake, ws, 1 << 30,
+                                  None) == _lib.EWORKSPACE
+
+
+def test_tuning_roundtrip():
+    lib = _lib_or_build()
+    t = _lib.Tuning()
+    assert lib.spm_tuning_get(ctypes.byref(t)) == _lib.OK
+    saved = _lib.Tuning.from_buffer_copy(t)
+    bad = _lib.Tuning.from_buffer_copy(t)
+    bad.spmm_block = 100
+    assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
+    good = _lib.Tuning.from_buffer_copy(t)
+    good.spmm_block = 128
+    assert lib.spm_tuning_set(ctypes.byref(good)) == _lib.OK
+    chk = _lib.Tuning()
+    lib.spm_tuning_get(ctypes.byref(chk))
+    assert chk.spmm_block == 128
+    assert lib.spm_tuning_set(ctypes.byref(saved)) == _lib.OK

@@ -1,0 +1,136 @@
+"""GPU parity of COO -> CSC assembly (spm_coo_to_csc) against the oracle: structure and
+values bit-exact (binary64 fold in input order, rounded once)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1805_03380_amd import ops, synth
+from gpu_util import assemble_gpu, assert_csc_equal, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _ref(p):
+    st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    assert st == oracle.OK
+    return A
+
+
+def test_tiny_spmv_f64():
+    p = synth.tiny_spmv()
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), np.float64)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("shape", [(1, 1), (7, 3), (64, 64), (300, 5000), (5000, 300)])
+def test_random_small(seed, shape):
+    n_rows, n_cols = shape
+    nnz = int(np.random.Generator(np.random.PCG64(seed)).integers(0, 6000))
+    nnz = min(nnz, 3 * n_rows * n_cols)
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    row = rng.integers(0, n_rows, nnz).astype(np.int32)
+    col = rng.integers(0, n_cols, nnz).astype(np.int32)
+    val = rng.choice([-1.0, -0.5, 0.0, -0.0, 0.5, 1.0, 2.0], nnz) + \
+        rng.standard_normal(nnz) * (rng.random(nnz) < 0.5)
+    p = synth.COOProblem("r", n_rows, n_cols, row, col, val)
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), np.float64)
+    A32 = assemble_gpu(p, out_dtype=torch.float32)
+    assert_csc_equal(A32, _ref(p), np.float32)
+
+
+def test_float32_and_bf16_inputs():
+    p = synth.random_coo(11, 2000, 3000, 50_000, dup_frac=0.3, zero_frac=0.01,
+                         dtype=np.float32, dist="normal")
+    A = assemble_gpu(p)
+    assert A.values.dtype == torch.float32
+    assert_csc_equal(A, _ref(p), np.float32)
+    vb = torch.from_numpy(p.val).to(torch.bfloat16)
+    Ab = ops.coo_to_csc(dev(p.row), dev(p.col), vb.to("cuda:0"), (p.n_rows, p.n_cols))
+    st, R = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, oracle.widen(vb))
+    assert_csc_equal(Ab, R, np.float32)
+
+
+def test_specials_nan_inf_signed_zero():
+    row = np.array([0, 1, 2, 2, 3, 3, 3, 4, 4, 5], np.int32)
+    col = np.zeros(10, np.int32)
+    val = np.array([np.nan, np.inf, np.inf, -np.inf, 0.7, -0.7, 0.125, -0.0, -0.0, 1e-310])
+    p = synth.COOProblem("s", 6, 1, row, col, val)
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), np.float64)
+    assert A.row_idx.cpu().tolist() == [0, 1, 2, 3, 5]
+
+
+def test_empty_and_degenerate_shapes():
+    e = np.zeros(0, np.int32)
+    A = assemble_gpu(synth.COOProblem("e", 5, 7, e, e, np.zeros(0)))
+    assert A.nnz == 0 and A.col_ptr.cpu().tolist() == [0] * 8
+    A = assemble_gpu(synth.COOProblem("e0", 5, 0, e, e, np.zeros(0)))
+    assert A.col_ptr.cpu().tolist() == [0]
+    A = assemble_gpu(synth.COOProblem("r0", 0, 3, e, e, np.zeros(0)))
+    assert A.col_ptr.cpu().tolist() == [0, 0, 0, 0]
+    # all inputs cancel
+    p = synth.COOProblem("c", 3, 3, np.array([1, 1], np.int32), np.array([2, 2], np.int32),
+                         np.array([0.25, -0.25]))
+    A = assemble_gpu(p)
+    assert A.nnz == 0 and A.col_ptr.cpu().tolist() == [0, 0, 0, 0]
+
+
+def test_one_location_long_fold():
+    """200,000 triplets on one location: one left fold in input order (bit-exact)."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 200_000
+    p = synth.COOProblem("one", 10, 10, np.full(n, 3, np.int32), np.full(n, 7, np.int32),
+                         rng.standard_normal(n))
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), np.float64)
+
+
+def test_giant_and_large_columns():
+    """Columns longer than one LDS sort chunk take the merge-sort path; tiles holding several
+    large columns take the multi-chunk path."""
+    rng = np.random.Generator(np.random.PCG64(6))
+    parts = []
+    # one giant column (60k triplets, rows drawn from 20k -> many duplicates)
+    parts.append((rng.integers(0, 20_000, 60_000), np.full(60_000, 3)))
+    # ten columns of ~3000 each
+    parts.append((rng.integers(0, 20_000, 30_000), rng.integers(10, 20, 30_000)))
+    # sprinkle of small columns
+    parts.append((rng.integers(0, 20_000, 20_000), rng.integers(0, 5000, 20_000)))
+    row = np.concatenate([a for a, _ in parts]).astype(np.int32)
+    col = np.concatenate([b for _, b in parts]).astype(np.int32)
+    perm = rng.permutation(row.size)
+    row, col = row[perm], col[perm]
+    val = rng.standard_normal(row.size)
+    p = synth.COOProblem("giant", 20_000, 5000, row, col, val)
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), np.float64)
+
+
+def test_out_of_range_raises():
+    p = synth.COOProblem("oob", 4, 4, np.array([0, 4, 1], np.int32),
+                         np.array([0, 0, 1], np.int32), np.ones(3))
+    with pytest.raises(IndexError):
+        assemble_gpu(p)
+    p = synth.COOProblem("neg", 4, 4, np.array([0, 1], np.int32), np.array([-1, 1], np.int32),
+                         np.ones(2))
+    with pytest.raises(IndexError):
+        assemble_gpu(p)
+
+
+@pytest.mark.parametrize("value_dtype", [np.float32, np.float64])
+def test_uniform_1e5_full(value_dtype):
+    p = synth.uniform_1e5(value_dtype=value_dtype, k=1)
+    A = assemble_gpu(p)
+    assert_csc_equal(A, _ref(p), value_dtype)
+
+
+def test_deterministic_rerun():
+    p = synth.random_coo(21, 50_000, 50_000, 400_000, dup_frac=0.2, dist="normal")
+    A = assemble_gpu(p)
+    B = assemble_gpu(p)
+    assert torch.equal(A.col_ptr, B.col_ptr)
+    assert torch.equal(A.row_idx, B.row_idx)
+    assert torch.equal(A.values.view(torch.int64), B.values.view(torch.int64))
