@@ -1,0 +1,173 @@
+#!/usr/bin/env python
+"""Benchmark of the sparse hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input already resident in
+HBM: COO -> CSC assembly (spm_coo_to_csc), plan (spm_csc_plan_build), forward Y = A.X
+(spm_csc_spmm) and adjoint dX, dvalues (spm_csc_spmm_backward).  Workload: the 100,000 x
+100,000 matrix from 1,000,000 triplets (5 % duplicates, float32 values U[-1,1]) with dense
+X 100,000 x 64 float32 N(0,1) and G of the same shape (seed 1002).
+
+Prints ONE JSON line.  `value` is input triplets per second through the whole step;
+`roofline` covers the kernel that takes the largest share of the step; `cpu_baseline` is the
+oracle timed on the host cores on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip batched vs per-matrix")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--value-dtype", default="float32", choices=["float32", "float64"])
+    return ap.parse_args()
+
+
+def model_bytes(n_rows, n_cols, nnz_in, nnz, k, s_vin, s_v, s_x, s_y, s_dx):
+    """Algorithmic (compulsory) HBM bytes of each call: every input read once, every output
+    written once (the dense operands once per row, not once per nonzero)."""
+    asm = nnz_in * (4 + 4 + s_vin) + nnz * (4 + s_v) + 4 * (n_cols + 1)
+    plan = 4 * (n_cols + 1) + 4 * nnz + 4 * (n_rows + 1) + 8 * nnz
+    fwd = 4 * (n_rows + 1) + nnz * (4 + 4 + s_v) + n_cols * k * s_x + n_rows * k * s_y
+    bwd = (4 * (n_cols + 1) + nnz * (4 + s_v) + n_rows * k * s_x + n_cols * k * s_x
+           + n_cols * k * s_dx + nnz * s_v)
+    return dict(assemble=asm, plan=plan, forward=fwd, backward=bwd)
+
+
+def gather_bytes(nnz, k, s_x):
+    """Dense-operand bytes when every nonzero re-reads its dense row (no reuse)."""
+    return nnz * k * s_x
+
+
+def cpu_baseline(p, seconds):
+    """The oracle as it stands (single thread, binary64) on the same workload: repeat full
+    assemble + forward + adjoint passes until about `seconds` of CPU time are spent."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+        Y, _, _ = oracle.spmm(A, p.X)
+        dX, dval, _, _ = oracle.spmm_backward(A, p.G, p.X)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 50:
+            break
+    return dict(value=p.nnz_in * reps / el, unit="nnz/s", cores=1, kind="oracle",
+                sample="%d full passes (assemble + forward + adjoint) of the 1e5 x 1e5, 1e6-triplet"
+                       " workload, k=64, binary64 oracle, single thread, %.1f s" % (reps, el))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1805_03380_amd import synth
+    from paper_1805_03380_amd.pipeline import Pipeline, PHASES
+
+    vdt = np.float32 if args.value_dtype == "float32" else np.float64
+    p = synth.uniform_1e5(value_dtype=vdt, k=64)
+    dev = torch.device("cuda:0")
+    row = torch.from_numpy(p.row).to(dev)
+    col = torch.from_numpy(p.col).to(dev)
+    val = torch.from_numpy(p.val).to(dev)
+    X = torch.from_numpy(p.X).to(dev)
+    G = torch.from_numpy(p.G.astype(np.float32)).to(dev)
+    pipe = Pipeline(p.n_rows, p.n_cols, p.nnz_in, p.k, val_dtype=val.dtype, x_dtype=X.dtype)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        pipe.step(row, col, val, X, G, stream)
+    torch.cuda.synchronize()
+    nnz, st_a, st_p = pipe.status()
+    if st_a or st_p:
+        raise RuntimeError("library reported status %d / %d" % (st_a, st_p))
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(args.steps):
+        pipe.step(row, col, val, X, G, stream, events=evs[i])
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    ms_step = total_ms / args.steps
+    phase_ms = {ph: float(np.mean([evs[i][j].elapsed_time(evs[i][j + 1])
+                                   for i in range(args.steps)]))
+                for j, ph in enumerate(PHASES)}
+
+    s_vin = p.val.dtype.itemsize
+    s_v = pipe.values.element_size()
+    s_y = pipe.Y.element_size()
+    bytes_ = model_bytes(p.n_rows, p.n_cols, p.nnz_in, nnz, p.k, s_vin, s_v, 4, s_y,
+                         pipe.dX.element_size())
+    dominant = max(PHASES, key=lambda ph: phase_ms[ph])
+    kernel_name = dict(assemble="spm_coo_to_csc (6 kernels)", plan="spm_csc_plan_build",
+                       forward="k_spmm_fwd", backward="k_spmm_bwd")[dominant]
+    ach = bytes_[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
+    spmm_ms = phase_ms["forward"] + phase_ms["backward"]
+    spmm_gbps = (bytes_["forward"] + bytes_["backward"]) / (spmm_ms * 1e-3) / 1e9
+    traffic = None
+    tr_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                           "traffic_uniform_1e5_f32_k64.json")
+    if os.path.exists(tr_path):
+        with open(tr_path) as f:
+            tr = json.load(f)
+        traffic = tr.get(dominant)
+
+    out = {
+        "metric": "COO->CSC nnz/s; SpMM fwd+bwd HBM GB/s and % of roofline, batched vs single",
+        "value": p.nnz_in / (ms_step * 1e-3),
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform_1e5x1e5_nnz1e6_%s_k64" % args.value_dtype,
+                   "n_rows": p.n_rows, "n_cols": p.n_cols, "nnz_in": p.nnz_in, "nnz": nnz,
+                   "k": p.k, "seed": 1002, "value_dtype": args.value_dtype,
+                   "dense_dtype": "float32", "accumulate": "binary64",
+                   "step": "assemble+plan+forward+adjoint", "parallelism": "single GPU"},
+        "phase_ms": phase_ms,
+        "assembly_nnz_per_s": p.nnz_in / (phase_ms["assemble"] * 1e-3),
+        "spmm_fwd_bwd_GBps": spmm_gbps,
+        "spmm_fwd_bwd_frac": spmm_gbps / HBM_PEAK_GBPS,
+        "spmm_gather_GBps": (bytes_["forward"] + bytes_["backward"]
+                             + 2 * gather_bytes(nnz, p.k, 4)) / (spmm_ms * 1e-3) / 1e9,
+        "algorithmic_bytes": bytes_,
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": ach,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+                     "traffic": traffic},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

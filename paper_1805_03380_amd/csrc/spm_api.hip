@@ -10,6 +10,9 @@
 #include "spm.h"
 #include "spm_assemble.h"
 #include "spm_spmm.h"
+#include "spm_batch.h"
+#include <algorithm>
+#include <vector>
 
 
 namespace {
@@ -468,17 +471,127 @@ spm_status spm_tuning_set(const spm_tuning* in) {
 
 }  // extern "C"
 
-// Batched entry points: not built yet in this revision.
+// ============================================================================================
+// Batched path
+// ============================================================================================
+namespace {
+
+size_t batch_stride(int64_t max_dim, int64_t max_nnz) {
+  return align256(sizeof(uint64_t) * 2 * (size_t)max_nnz + sizeof(uint32_t) * (size_t)(max_dim + 1));
+}
+
+int batch_workers(int32_t workers, int32_t batch) {
+  const spm_tuning tu = tuning();
+  int w = workers > 0 ? workers : cu_count() * tu.batch_wg_per_cu;
+  if (batch > 0 && w > batch) w = batch;
+  return w < 1 ? 1 : w;
+}
+
+template <int NT, typename VIN, typename XT, typename ACC>
+void launch_batch(const BatchArgs& a, int workers, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch<NT, VIN, XT, ACC>), dim3(workers), dim3(NT), 0, s, a);
+}
+
+template <int NT>
+void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers,
+                     hipStream_t s) {
+  if (vt == SPM_F32) {
+    if (xt == SPM_F32) launch_batch<NT, float, float, double>(a, workers, s);
+    else launch_batch<NT, float, bf16_t, float>(a, workers, s);
+  } else {
+    if (xt == SPM_F32) launch_batch<NT, bf16_t, float, double>(a, workers, s);
+    else launch_batch<NT, bf16_t, bf16_t, float>(a, workers, s);
+  }
+}
+
+}  // namespace
+
 extern "C" {
-spm_status spm_batch_workspace(int64_t, int64_t, int32_t, size_t*) { return SPM_EINVAL; }
-spm_status spm_batch_schedule(const spm_batch_item*, int32_t, int64_t, int32_t*) {
-  return SPM_EINVAL;
+
+spm_status spm_batch_workspace(int64_t max_dim, int64_t max_nnz_in, int32_t workers,
+                               size_t* ws_bytes) {
+  if (!ws_bytes || max_dim < 0 || max_nnz_in < 0 || workers < 0) return SPM_EINVAL;
+  if (!fits_i32(max_dim) || !fits_i32(max_nnz_in) || max_dim == INT32_MAX) return SPM_EOVERFLOW;
+  const int w = batch_workers(workers, 0);
+  *ws_bytes = 256 + (size_t)w * batch_stride(max_dim, max_nnz_in);
+  return SPM_OK;
 }
-spm_status spm_batch_run(int32_t, int64_t, const spm_batch_item*, const int32_t*, const int32_t*,
-                         const int32_t*, const void*, spm_dtype, const void*, const void*,
-                         spm_dtype, int32_t*, int32_t*, float*, int32_t*, int32_t*, int32_t*,
-                         float*, float*, float*, int32_t*, int64_t, int64_t, int32_t, void*,
-                         size_t, void*) {
-  return SPM_EINVAL;
+
+spm_status spm_batch_schedule(const spm_batch_item* items, int32_t batch, int64_t k,
+                              int32_t* order) {
+  if (batch < 0 || (batch > 0 && (!items || !order)) || k < 1) return SPM_EINVAL;
+  std::vector<int32_t> idx(batch);
+  std::vector<double> cost(batch);
+  for (int32_t b = 0; b < batch; ++b) {
+    idx[b] = b;
+    // assembly + plan work grows with the triplets, the products with nnz * k and (n_r+n_c)*k
+    const double nnz = items[b].nnz_in > 0 ? items[b].nnz_in : 0;
+    const double dim = (double)(items[b].n_rows > 0 ? items[b].n_rows : 0) +
+                       (double)(items[b].n_cols > 0 ? items[b].n_cols : 0);
+    cost[b] = nnz * (8.0 + 0.5 * (double)k) + dim * (double)k;
+  }
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  std::memcpy(order, idx.data(), sizeof(int32_t) * (size_t)batch);
+  return SPM_OK;
 }
+
+spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
+                         const int32_t* order, const int32_t* row, const int32_t* col,
+                         const void* val, spm_dtype val_type, const void* X, const void* Gm,
+                         spm_dtype x_type, int32_t* col_ptr, int32_t* row_idx, float* val_out,
+                         int32_t* row_ptr, int32_t* col_t, int32_t* perm, float* Y, float* dX,
+                         float* dval, int32_t* info, int64_t max_dim, int64_t max_nnz_in,
+                         int32_t workers, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 0 || k < 1 || max_dim < 0 || max_nnz_in < 0 || workers < 0) return SPM_EINVAL;
+  if (!fits_i32(k) || !fits_i32(max_dim) || !fits_i32(max_nnz_in) || max_dim == INT32_MAX)
+    return SPM_EOVERFLOW;
+  if (val_type != SPM_F32 && val_type != SPM_BF16) return SPM_EDTYPE;
+  if (x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
+  if (batch == 0) return SPM_OK;
+  if (!items || !order || !row || !col || !val || !X || !Gm || !col_ptr || !row_idx ||
+      !val_out || !row_ptr || !col_t || !perm || !Y || !dX || !dval || !info || !ws)
+    return SPM_EINVAL;
+  if (!aligned(ws, 256)) return SPM_EINVAL;
+  const int w = batch_workers(workers, batch);
+  const size_t stride = batch_stride(max_dim, max_nnz_in);
+  if (ws_bytes < 256 + (size_t)w * stride) return SPM_EWORKSPACE;
+  const spm_tuning tu = tuning();
+  BatchArgs a;
+  a.items = items;
+  a.order = order;
+  a.batch = batch;
+  a.k = k;
+  a.G = group_width(k);
+  a.row = row;
+  a.col = col;
+  a.val = val;
+  a.X = X;
+  a.Gm = Gm;
+  a.col_ptr = col_ptr;
+  a.row_idx = row_idx;
+  a.val_out = val_out;
+  a.row_ptr = row_ptr;
+  a.col_t = col_t;
+  a.perm = perm;
+  a.Y = Y;
+  a.dX = dX;
+  a.dval = dval;
+  a.info = info;
+  a.max_dim = max_dim;
+  a.max_nnz = max_nnz_in;
+  a.ws = static_cast<char*>(ws) + 256;
+  a.ws_stride = stride;
+  a.queue = static_cast<uint32_t*>(ws);
+  a.xal = (k % 4 == 0 && aligned(X, 4 * dsize(x_type)) && aligned(Gm, 4 * dsize(x_type))) ? 1 : 0;
+  a.yal = (k % 4 == 0 && aligned(Y, 16) && aligned(dX, 16)) ? 1 : 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, (uint32_t*)nullptr,
+                     (int64_t)0);
+  if (tu.batch_block == 512) launch_batch_nt<512>(a, val_type, x_type, w, s);
+  else launch_batch_nt<256>(a, val_type, x_type, w, s);
+  return launch_status();
 }
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+// Batched path: one persistent launch assembles, plans, multiplies forward and backward many
+// independent matrices.  Each workgroup takes whole matrices from a device queue (in the
+// order the caller gives, largest first) and runs every phase of one matrix itself, with its
+// per-column / per-row counters in LDS and its keys in a per-workgroup slice of the workspace
+// (so one matrix's working set stays in the L2 of the XCD that runs it).  The phases call the
+// same device functions as the per-matrix kernels (segment sort, fold, spmm_row,
+// spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
+#pragma once
+
+#include "spm_assemble.h"
+#include "spm_spmm.h"
+#include "spm.h"
+
+namespace spm {
+
+constexpr int kBatchMaxLdsDim = 8192;  // counters of up to this many columns / rows live in LDS
+constexpr int kBatchCap = 2048;        // LDS sort chunk (keys)
+
+// In-place inclusive scan of a[0..n) by the whole workgroup (blocked chunks with a carry).
+template <int NT>
+__device__ void wg_inclusive_scan_inplace(uint32_t* a, int64_t n, uint32_t* s_w) {
+  constexpr int IPT = 8;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
+      v[s] = (i < n) ? a[i] : 0u;
+      sum += v[s];
+    }
+    uint32_t total;
+    const uint32_t excl = wg_excl_scan<NT>(sum, s_w, &total);
+    uint32_t run = carry + excl;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
+      run += v[s];
+      if (i < n) a[i] = run;
+    }
+    carry += total;
+    __syncthreads();
+  }
+}
+
+struct BatchArgs {
+  const spm_batch_item* items;
+  const int32_t* order;
+  int32_t batch;
+  int64_t k;
+  int G;
+  const int32_t* row;
+  const int32_t* col;
+  const void* val;
+  const void* X;
+  const void* Gm;
+  int32_t* col_ptr;
+  int32_t* row_idx;
+  float* val_out;
+  int32_t* row_ptr;
+  int32_t* col_t;
+  int32_t* perm;
+  float* Y;
+  float* dX;
+  float* dval;
+  int32_t* info;
+  int64_t max_dim;
+  int64_t max_nnz;
+  char* ws;           // per-worker slices
+  size_t ws_stride;   // bytes per worker
+  uint32_t* queue;    // zeroed before the launch
+  int xal;            // X / G rows start on 4-element boundaries (vector loads allowed)
+  int yal;            // Y / dX rows likewise (vector stores allowed)
+};
+
+template <int NT, typename VIN, typename XT, typename ACC>
+__global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
+  constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
+  constexpr int T = NT * kBatchFoldIPT;
+  __shared__ uint32_t s_cnt[kBatchMaxLdsDim + 1];
+  __shared__ uint64_t s_key[kBatchCap];
+  __shared__ uint8_t s_flag[kBatchCap];
+  __shared__ uint32_t s_pre[T + 1];
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_b[4];
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_bad;
+
+  char* wsw = a.ws + (size_t)blockIdx.x * a.ws_stride;
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(wsw);
+  uint64_t* scratch = bucket + a.max_nnz;
+  uint32_t* gcnt = reinterpret_cast<uint32_t*>(scratch + a.max_nnz);
+  const VIN* vin = static_cast<const VIN*>(a.val);
+  const XT* Xa = static_cast<const XT*>(a.X);
+  const XT* Ga = static_cast<const XT*>(a.Gm);
+
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t q = atomicAdd(a.queue, 1u);
+      int32_t m = -1;  // -1: queue drained
+      if (q < (uint32_t)a.batch) {
+        m = a.order[q];
+        if (m < 0 || m >= a.batch) m = -2;  // not a matrix index: skipped
+      }
+      s_item = m;
+      s_bad = 0;
+    }
+    __syncthreads();
+    const int32_t b = s_item;
+    if (b == -1) break;  // every workgroup leaves through here once the queue is drained
+    if (b == -2) {
+      __syncthreads();
+      continue;
+    }
+    const spm_batch_item it = a.items[b];
+    const int64_t n_r = it.n_rows, n_c = it.n_cols, nnz_in = it.nnz_in;
+    if (n_r < 0 || n_c < 0 || nnz_in < 0 || n_r > a.max_dim || n_c > a.max_dim ||
+        nnz_in > a.max_nnz) {
+      if (threadIdx.x == 0) {
+        a.info[2 * (int64_t)b] = 0;
+        a.info[2 * (int64_t)b + 1] = kStEinval;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int64_t to = it.trip_off;
+    const int32_t* trow = a.row + to;
+    const int32_t* tcol = a.col + to;
+    const VIN* tval = vin + to;
+    int32_t* cp = a.col_ptr + it.colptr_off;
+    int32_t* ri = a.row_idx + to;
+    float* vo = a.val_out + to;
+    int32_t* rp = a.row_ptr + it.rowptr_off;
+    uint32_t* cnt = (n_r <= kBatchMaxLdsDim && n_c <= kBatchMaxLdsDim) ? s_cnt : gcnt;
+
+    // ---- 1. column histogram (bounds-checked) -------------------------------------------
+    for (int64_t i = threadIdx.x; i <= n_c; i += NT) cnt[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int64_t t = threadIdx.x; t < nnz_in; t += NT) {
+      const int32_t r = trow[t], c = tcol[t];
+      if (r >= 0 && r < n_r && c >= 0 && c < n_c) atomicAdd(&cnt[c], 1u);
+      else bad = true;
+    }
+    if (bad) s_bad = 1;
+    // ---- 2. inclusive scan: cnt[c] = end of column c -------------------------------------
+    __syncthreads();
+    wg_inclusive_scan_inplace<NT>(cnt, n_c, s_w);
+    if (threadIdx.x == 0) cnt[n_c] = n_c > 0 ? cnt[n_c - 1] : 0u;
+    __syncthreads();
+    // ---- 3. scatter keys (row << 32 | position); counters end as column starts ------------
+    for (int64_t t = threadIdx.x; t < nnz_in; t += NT) {
+      const int32_t r = trow[t], c = tcol[t];
+      if (r >= 0 && r < n_r && c >= 0 && c < n_c) {
+        const uint32_t pos = atomicSub(&cnt[c], 1u) - 1u;
+        bucket[pos] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)t;
+      }
+    }
+    __syncthreads();
+    const int64_t N = cnt[n_c];
+    // ---- 4. sort each column's keys --------------------------------------------------------
+    sort_segments<NT, kBatchCap, false>(bucket, cnt, 0, n_c, scratch, (int32_t*)nullptr,
+                                        (int32_t*)nullptr, s_key, s_flag, &s_b[0]);
+    __syncthreads();
+    // ---- 5. fold, drop zeros, compact, column offsets --------------------------------------
+    uint32_t running = 0;
+    for (int64_t base = 0; base < N || base == 0; base += T) {
+      const int cntb = (int)((N - base) < T ? (N - base) : T);
+      for (int li = threadIdx.x; li < cntb; li += NT) s_key[li] = bucket[base + li];
+      __syncthreads();
+      uint32_t rows[kBatchFoldIPT];
+      double sums[kBatchFoldIPT];
+      const uint32_t mask = fold_tile<NT, kBatchFoldIPT, VIN>(bucket, s_key, base, cntb, N, tval,
+                                                               rows, sums);
+      uint32_t blk_kept;
+      const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk_kept);
+      {
+        uint32_t run = excl;
+#pragma unroll
+        for (int s = 0; s < kBatchFoldIPT; ++s) {
+          const int li = threadIdx.x * kBatchFoldIPT + s;
+          if (li < cntb) s_pre[li] = run;
+          run += (mask >> s) & 1u;
+        }
+        if (threadIdx.x == 0) {
+          s_pre[cntb] = blk_kept;
+          const bool last = base + T >= N;
+          s_b[1] = lower_bound(cnt, n_c + 1, base);
+          s_b[2] = last ? n_c + 1 : lower_bound(cnt, n_c + 1, base + T);
+        }
+      }
+      __syncthreads();
+      {
+        int64_t o = (int64_t)running + excl;
+#pragma unroll
+        for (int s = 0; s < kBatchFoldIPT; ++s) {
+          if ((mask >> s) & 1u) {
+            ri[o] = (int32_t)rows[s];
+            vo[o] = (float)sums[s];
+            ++o;
+          }
+        }
+      }
+      for (int64_t c = s_b[1] + threadIdx.x; c < s_b[2]; c += NT) {
+        int64_t p = (int64_t)cnt[c] - base;
+        if (p > cntb) p = cntb;
+        cp[c] = (int32_t)(running + s_pre[p]);
+      }
+      running += blk_kept;
+      __syncthreads();
+      if (base + T >= N) break;
+    }
+    const int64_t nnz = running;
+    if (threadIdx.x == 0) {
+      a.info[2 * (int64_t)b] = (int32_t)nnz;
+      a.info[2 * (int64_t)b + 1] = s_bad ? kStBounds : 0;
+    }
+    __syncthreads();
+    // ---- 6. plan: row counts, row starts, (col << 32 | slot) keys sorted per row -----------
+    for (int64_t i = threadIdx.x; i <= n_r; i += NT) cnt[i] = 0;
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < nnz; p += NT) atomicAdd(&cnt[ri[p]], 1u);
+    __syncthreads();
+    wg_inclusive_scan_inplace<NT>(cnt, n_r, s_w);
+    if (threadIdx.x == 0) cnt[n_r] = n_r > 0 ? cnt[n_r - 1] : 0u;
+    __syncthreads();
+    for (int64_t p0 = (int64_t)threadIdx.x * 4; p0 < nnz; p0 += (int64_t)NT * 4) {
+      int64_t c = upper_bound(cp, n_c + 1, p0) - 1;
+      const int64_t p1 = (p0 + 4 < nnz) ? p0 + 4 : nnz;
+      for (int64_t p = p0; p < p1; ++p) {
+        while (c + 1 < n_c && (int64_t)cp[c + 1] <= p) ++c;
+        const int32_t r = ri[p];
+        const uint32_t pos = atomicSub(&cnt[r], 1u) - 1u;
+        bucket[pos] = ((uint64_t)c << 32) | (uint32_t)p;
+      }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i <= n_r; i += NT) rp[i] = (int32_t)cnt[i];
+    sort_segments<NT, kBatchCap, true>(bucket, cnt, 0, n_r, scratch, a.col_t + to, a.perm + to,
+                                       s_key, s_flag, &s_b[0]);
+    __syncthreads();
+    // ---- 7. forward Y = A.X and 8. adjoint dX, dval ---------------------------------------
+    {
+      const int G = a.G;
+      const int lg = threadIdx.x & (G - 1);
+      const int64_t groups = NT / G;
+      const int64_t gid = threadIdx.x / G;
+      const XT* Xb = Xa + it.x_off;
+      const XT* Gb = Ga + it.g_off;
+      for (int64_t r = gid; r < n_r; r += groups)
+        spmm_row<float, XT, ACC, 4>(r, lg, G, a.k, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
+                                    Xb, a.k, a.xal != 0, a.Y + it.g_off, a.k, false, a.yal != 0);
+      for (int64_t c = gid; c < n_c; c += groups) {
+        const int64_t p0 = cp[c], p1 = cp[c + 1];
+        spmm_col_bwd<float, XT, ACC, 4>(c, p0, p1, lg, G, a.k, n_r, ri, vo, Gb, a.k,
+                                        a.xal != 0, Xb, a.k, a.xal != 0, a.dX + it.x_off, a.k,
+                                        false, a.yal != 0, a.dval + to, false);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace spm

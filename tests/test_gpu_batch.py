@@ -1,0 +1,123 @@
+"""GPU tests of the batched persistent path (spm_batch_run): bitwise equal to the per-matrix
+entry points, and per matrix equal to the oracle (assembly bit-exact, products within the
+a-priori bound)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1805_03380_amd import synth
+from paper_1805_03380_amd.batch import PackedBatch
+from gpu_util import assert_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(seed, count, lo, hi, per_col=16, k=32):
+    return synth.batch_problems(seed=seed, count=count, lo=lo, hi=hi, per_col=per_col, k=k)
+
+
+def _bitwise_equal(pb, o1, o2):
+    info1 = o1["info"].cpu().numpy()
+    info2 = o2["info"].cpu().numpy()
+    assert np.array_equal(info1, info2)
+    for key in ("col_ptr", "row_ptr", "Y", "dX"):
+        assert torch.equal(o1[key].view(torch.int32), o2[key].view(torch.int32)), key
+    for b in range(pb.B):
+        to, n = int(pb.trip_off[b]), int(info1[2 * b])
+        for key in ("row_idx", "val_out", "dval", "col_t", "perm"):
+            a = o1[key][to:to + n].view(torch.int32)
+            c = o2[key][to:to + n].view(torch.int32)
+            assert torch.equal(a, c), (key, b)
+
+
+def _oracle_check(pb, out, problems, b, acc_f32=False):
+    p = problems[b]
+    m = pb.matrix(out, b)
+    assert m["info"][1] == 0
+    vals = p.val
+    if pb.val_dtype == torch.bfloat16:
+        vals = oracle.widen(torch.from_numpy(p.val.astype(np.float32)).to(torch.bfloat16))
+    st, R = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, vals)
+    assert np.array_equal(m["col_ptr"], R.col_ptr)
+    assert np.array_equal(m["row_idx"], R.row_idx)
+    assert np.array_equal(m["values"], R.values.astype(np.float32))
+    X = p.X.astype(np.float32)
+    G = p.G.astype(np.float32)
+    if pb.x_dtype == torch.bfloat16:
+        X = oracle.widen(torch.from_numpy(X).to(torch.bfloat16))
+        G = oracle.widen(torch.from_numpy(G).to(torch.bfloat16))
+    rv = m["values"].astype(np.float64)
+    Yr, S, M = oracle.spmm(R, X, values=rv)
+    dXr, dvr, SdX, Sdv = oracle.spmm_backward(R, G, X, values=rv)
+    assert_close(m["Y"], Yr, S, M, torch.float32, acc_f32, "Y[%d]" % b)
+    assert_close(m["dX"], dXr, SdX, np.diff(R.col_ptr), torch.float32, acc_f32, "dX[%d]" % b)
+    assert_close(m["dval"], dvr, Sdv, pb.k, torch.float32, acc_f32, "dval[%d]" % b)
+
+
+@pytest.mark.parametrize("x_dtype", [torch.float32, torch.bfloat16])
+def test_small_batch_equals_single_and_oracle(x_dtype):
+    bt = _small_batch(2005, 96, 24, 600)
+    pb = PackedBatch(bt.problems, val_dtype=x_dtype, x_dtype=x_dtype)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_b, o_s)
+    for b in range(0, pb.B, 7):
+        _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
+
+
+def test_large_dims_global_counters_and_giant_column():
+    """One matrix larger than the LDS counter capacity, one with a column longer than an LDS
+    sort chunk, one with an out-of-range triplet (its own status only)."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    probs = []
+    n = 12_000
+    probs.append(synth.random_coo(32, n, n, 50_000, dup_frac=0.1, dtype=np.float32,
+                                  dist="normal", k=32))
+    m = 3000
+    row = rng.integers(0, m, 9000).astype(np.int32)
+    col = np.where(rng.random(9000) < 0.8, 17, rng.integers(0, m, 9000)).astype(np.int32)
+    g = synth.COOProblem("giant", m, m, row, col, rng.standard_normal(9000).astype(np.float32),
+                         rng.standard_normal((m, 32)).astype(np.float32),
+                         rng.standard_normal((m, 32)).astype(np.float32))
+    probs.append(g)
+    bad = synth.random_coo(33, 100, 100, 500, dtype=np.float32, dist="normal", k=32)
+    bad.row = bad.row.copy()
+    bad.row[10] = 100  # out of range
+    probs.append(bad)
+    probs.append(synth.random_coo(34, 50, 70, 0, dtype=np.float32, k=32))  # empty
+    pb = PackedBatch(probs)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    info = o_b["info"].cpu().numpy().reshape(-1, 2)
+    assert info[2, 1] == 2 and info[0, 1] == 0 and info[1, 1] == 0 and info[3, 1] == 0
+    assert info[3, 0] == 0
+    _bitwise_equal(pb, o_b, o_s)
+    _oracle_check(pb, o_b, probs, 0)
+    _oracle_check(pb, o_b, probs, 1)
+
+
+def test_full_batch_workload_bitwise_and_sampled_oracle():
+    """The 4096-matrix workload (n log-uniform in [64, 8192], 16 triplets per column, 10 %
+    duplicates, k = 32): one persistent launch is bitwise equal to 4096 per-matrix calls, and
+    sampled matrices match the oracle."""
+    bt = synth.batch_problems()
+    pb = PackedBatch(bt.problems)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_b, o_s)
+    order = pb.order_host
+    for b in [int(order[0]), int(order[-1]), 0, 1234, 4095]:
+        _oracle_check(pb, o_b, bt.problems, b)
+
+
+def test_deterministic_rerun():
+    bt = _small_batch(2006, 40, 64, 2000)
+    pb = PackedBatch(bt.problems)
+    o1 = pb.run_batched(out=pb.new_outputs())
+    o2 = pb.run_batched(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o1, o2)
