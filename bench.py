@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip batched vs per-matrix")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--value-dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -72,8 +74,71 @@ def cpu_baseline(p, seconds):
                        " workload, k=64, binary64 oracle, single thread, %.1f s" % (reps, el))
 
 
+def batched_vs_single(reps_batched=5, reps_single=3):
+    """The 4096-matrix workload: one persistent launch vs 4096 x 4 per-matrix calls of the
+    same kernels; outputs compared bitwise."""
+    import numpy as np
+    import torch
+    from paper_1805_03380_amd import synth
+    from paper_1805_03380_amd.batch import PackedBatch
+    t0 = time.perf_counter()
+    bt = synth.batch_problems()
+    pb = PackedBatch(bt.problems)
+    gen_s = time.perf_counter() - t0
+    o_single = pb.new_outputs()
+    pb.run_batched()
+    pb.run_single(out=o_single, keep_plan=False)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_b = timed(lambda: pb.run_batched(), reps_batched)
+    ms_s = timed(lambda: pb.run_single(out=o_single, keep_plan=False), reps_single)
+    ob = pb.out
+    same = bool(torch.equal(ob["info"], o_single["info"]))
+    for key in ("col_ptr", "Y", "dX"):
+        same = same and bool(torch.equal(ob[key].view(torch.int32), o_single[key].view(torch.int32)))
+    info = ob["info"].cpu().numpy().reshape(-1, 2)
+    mask = torch.zeros(ob["row_idx"].numel(), dtype=torch.bool, device=ob["row_idx"].device)
+    offs = pb.trip_off
+    for b in range(pb.B):
+        mask[int(offs[b]): int(offs[b]) + int(info[b, 0])] = True
+    for key in ("row_idx", "val_out", "dval"):
+        same = same and bool(torch.equal(ob[key].view(torch.int32)[mask],
+                                         o_single[key].view(torch.int32)[mask]))
+    nnz_in = int(pb.trip_off[-1])
+    return {"workload": "4096 matrices, n log-uniform [64, 8192], 16 triplets/column, 10 % dup, "
+                        "float32, k=32 (seed 1005)",
+            "nnz_in": nnz_in, "batched_ms": ms_b, "per_matrix_ms": ms_s,
+            "speedup": ms_s / ms_b, "batched_nnz_per_s": nnz_in / (ms_b * 1e-3),
+            "bitwise_equal": same, "setup_s": gen_s}
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n, "dispatches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calib_mib:
+        copy_calibration(args.copy_calib_mib)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -164,6 +229,8 @@ def main():
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
                      "traffic": traffic},
     }
+    if not args.no_batch:
+        out["batched_vs_single"] = batched_vs_single()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

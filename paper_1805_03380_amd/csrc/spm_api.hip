@@ -24,10 +24,10 @@ constexpr int kScanIPT = 8;       // scan tile = 2048 counts
 constexpr int kFoldIPT = 8;       // fold tile = 2048 keys
 constexpr int kSortT = 2048;      // segment-sort tile (segments starting in a tile)
 constexpr int kSortCap = 4096;    // LDS capacity of one sort chunk (keys)
-constexpr int kUnroll = 4;
 
 constexpr int64_t kScanTile = (int64_t)kNT * kScanIPT;
 constexpr int64_t kFoldTile = (int64_t)kNT * kFoldIPT;
+static_assert(kFoldTile == kSortT, "sort and fold tiles share one tile -> first-segment table");
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -81,47 +81,116 @@ spm_status launch_status() {
 }
 
 // ------------------------------------------------------------------------------------------
-// Assembly workspace layout.  The first region (counts, look-back states, tickets) is zeroed
-// by one kernel at the start of every call.
+// Two-level partition parameters (spm_partition.h).  b = log2(segments per coarse bucket):
+// at least what keeps the number of buckets <= kPartMaxBuckets, and about 2048 elements per
+// bucket when the sizes allow it.  Returns ok = false when no b <= 12 fits (more than
+// kPartMaxBuckets * kPartMaxWidth segments); then the atomic-histogram path is used.
+// ------------------------------------------------------------------------------------------
+constexpr int kPartNT = 256;
+constexpr int kPartCap = 4096;
+
+struct PartParams {
+  bool ok;
+  int b;
+  int32_t CB;
+  int64_t ntiles;
+  int64_t T1;  // level-1 tile: elements per workgroup
+};
+
+int ceil_log2(int64_t x) {
+  int b = 0;
+  while (((int64_t)1 << b) < x) ++b;
+  return b;
+}
+int floor_log2(int64_t x) {
+  int b = 0;
+  while (((int64_t)2 << b) <= x) ++b;
+  return b;
+}
+
+PartParams part_params(int64_t nseg, int64_t n) {
+  PartParams P{false, 0, 0, 1, 1024};
+  if (nseg <= 0) return P;
+  const int bmin = ceil_log2(ceil_div(nseg, kPartMaxBuckets));
+  const int btarget = n > 0 ? floor_log2(std::max<int64_t>(1, nseg * 2048 / n)) : 12;
+  int b = std::max(bmin, btarget);
+  if (b > 12) b = 12;
+  if (b < bmin) return P;
+  P.ok = true;
+  P.b = b;
+  P.CB = (int32_t)ceil_div(nseg, (int64_t)1 << b);
+  // level-1 tiles: at least 1024 elements, at most about 2048 tiles (the bucket x tile table
+  // stays below kPartMaxBuckets * 2048 entries)
+  int64_t T1 = 1024;
+  while (ceil_div(n, T1) > 2048) T1 <<= 1;
+  P.T1 = T1;
+  P.ntiles = std::max<int64_t>(1, ceil_div(n, T1));
+  return P;
+}
+
+// ------------------------------------------------------------------------------------------
+// Assembly workspace layout.  The first region (counters, look-back states, tickets) is
+// zeroed by one kernel at the start of every call.
 // ------------------------------------------------------------------------------------------
 struct AsmLayout {
+  PartParams pp;
   size_t colcnt, scan_state, fold_state, tickets, zero_bytes;
-  size_t colstart, bucket, scratch, total;
-  int64_t scan_tiles, fold_tiles;
+  size_t colstart, first, bucket, scratch, table, offs, bkey, bseg, total;
+  int64_t scan_n, fold_tiles;
 };
 
 AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   AsmLayout L;
   Carve c;
-  L.scan_tiles = n_cols > 0 ? ceil_div(n_cols, kScanTile) : 1;
+  L.pp = part_params(n_cols, nnz_in);
+  const int64_t tab = L.pp.ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
+  L.scan_n = L.pp.ok ? tab : n_cols;
+  const int64_t scan_tiles = L.scan_n > 0 ? ceil_div(L.scan_n, kScanTile) : 1;
   L.fold_tiles = nnz_in > 0 ? ceil_div(nnz_in, kFoldTile) : 1;
-  L.colcnt = c.take(sizeof(uint32_t) * (size_t)n_cols);
-  L.scan_state = c.take(sizeof(uint64_t) * (size_t)L.scan_tiles);
+  L.colcnt = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? 0 : n_cols));
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)scan_tiles);
   L.fold_state = c.take(sizeof(uint64_t) * (size_t)L.fold_tiles);
   L.tickets = c.take(sizeof(uint32_t) * 4);
   L.zero_bytes = c.off;
   L.colstart = c.take(sizeof(int32_t) * (size_t)(n_cols + 1));
+  L.first = c.take(sizeof(int32_t) * (size_t)(L.fold_tiles + 1));
   L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_in);
   L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_in);
+  L.table = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.offs = c.take(sizeof(int32_t) * (size_t)(tab + 1));
+  L.bkey = c.take(sizeof(uint64_t) * (size_t)(L.pp.ok ? nnz_in : 0));
+  L.bseg = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? nnz_in : 0));
   L.total = c.off;
   return L;
 }
 
 struct PlanLayout {
-  size_t rowcnt, scan_state, tickets, zero_bytes, bucket, scratch, total;
-  int64_t scan_tiles;
+  PartParams pp;
+  size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch, colarr, table, offs,
+      bkey, bseg, total;
+  int64_t scan_n, sort_tiles;
 };
 
 PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
   PlanLayout L;
   Carve c;
-  L.scan_tiles = n_rows > 0 ? ceil_div(n_rows, kScanTile) : 1;
-  L.rowcnt = c.take(sizeof(uint32_t) * (size_t)n_rows);
-  L.scan_state = c.take(sizeof(uint64_t) * (size_t)L.scan_tiles);
+  L.pp = part_params(n_rows, nnz_cap);
+  const int64_t tab = L.pp.ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
+  L.scan_n = L.pp.ok ? tab : n_rows;
+  const int64_t scan_tiles = L.scan_n > 0 ? ceil_div(L.scan_n, kScanTile) : 1;
+  L.rowcnt = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? 0 : n_rows));
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)scan_tiles);
   L.tickets = c.take(sizeof(uint32_t) * 4);
   L.zero_bytes = c.off;
+  L.sort_tiles = nnz_cap > 0 ? ceil_div(nnz_cap, kSortT) : 1;
+  L.first = c.take(sizeof(int32_t) * (size_t)(L.pp.ok ? 0 : L.sort_tiles + 1));
   L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
   L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
+  L.colarr = c.take(sizeof(int32_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
+  L.table = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.offs = c.take(sizeof(int32_t) * (size_t)(tab + 1));
+  L.bkey = c.take(sizeof(uint64_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
+  L.bseg = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
   L.total = c.off;
   return L;
 }
@@ -159,35 +228,68 @@ void launch_scan(const uint32_t* in, int64_t n, int32_t* out, uint64_t* state, u
 template <typename VT>
 void launch_fold(const uint64_t* keys, const int32_t* colstart, int64_t n_cols, const VT* val,
                  int32_t* col_ptr, int32_t* row_idx, void* val_out, int out_f64, int32_t* info,
-                 uint64_t* state, uint32_t* ticket, int64_t tiles, hipStream_t s) {
+                 const int32_t* first, uint64_t* state, uint32_t* ticket, int64_t tiles,
+                 hipStream_t s) {
   hipLaunchKernelGGL((k_fold<kNT, kFoldIPT, VT>), dim3((unsigned)tiles), dim3(kNT), 0, s, keys,
-                     colstart, n_cols, val, col_ptr, row_idx, val_out, out_f64, info, state,
-                     ticket);
+                     colstart, n_cols, val, col_ptr, row_idx, val_out, out_f64, info, first,
+                     state, ticket);
 }
 
 // ------------------------------------------------------------------------------------------
 // SpMM dispatch over element types.
 // ------------------------------------------------------------------------------------------
+// The lane-group width is a compile-time parameter of the product kernels; it depends on k
+// alone (group_width), never on tuning, so results do not depend on the launch shape.
+#define SPM_GW_SWITCH(G, CALL) \
+  switch (G) {                 \
+    case 1: CALL(1); break;    \
+    case 2: CALL(2); break;    \
+    case 4: CALL(4); break;    \
+    case 8: CALL(8); break;    \
+    case 16: CALL(16); break;  \
+    case 32: CALL(32); break;  \
+    default: CALL(64); break;  \
+  }
+
+// FULL kernels (k == 4 * group width, aligned rows: no tail handling) are built for the
+// widths of the common dense widths k = 32, 64, 128; every other case runs the general kernel,
+// which computes the same values in the same order.
 template <typename VT, typename XT, typename ACC>
-void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G,
+void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G, bool full,
                   const int32_t* row_ptr, const int32_t* col_t,
                   const int32_t* perm, const void* val, const void* X, int64_t ldx, int xal,
                   void* Y, int64_t ldy, int y_f64, int yal, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((k_spmm_fwd<VT, XT, ACC, kUnroll>), dim3(grid), dim3(block), 0, s, n_rows,
-                     n_cols, nnz_cap, k, G, row_ptr, col_t, perm, static_cast<const VT*>(val),
-                     static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal);
+#define SPM_CALL_F(GW, F)                                                                      \
+  hipLaunchKernelGGL((k_spmm_fwd<VT, XT, ACC, GW, F>), dim3(grid), dim3(block), 0, s, n_rows,  \
+                     n_cols, nnz_cap, k, row_ptr, col_t, perm, static_cast<const VT*>(val),    \
+                     static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal)
+#define SPM_CALL(GW) SPM_CALL_F(GW, false)
+  if (full && G == 8) SPM_CALL_F(8, true);
+  else if (full && G == 16) SPM_CALL_F(16, true);
+  else if (full && G == 32) SPM_CALL_F(32, true);
+  else SPM_GW_SWITCH(G, SPM_CALL)
+#undef SPM_CALL
+#undef SPM_CALL_F
 }
 
 template <typename VT, typename XT, typename ACC>
-void launch_bwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G,
+void launch_bwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G, bool full,
                   const int32_t* col_ptr, const int32_t* row_idx, const void* val, const void* Gm,
                   int64_t ldg, int gal, const void* X, int64_t ldx, int xal, void* dX,
                   int64_t lddx, int dx_f64, int dxal, void* dval, int dv_f64, int grid,
                   int block, hipStream_t s) {
-  hipLaunchKernelGGL((k_spmm_bwd<VT, XT, ACC, kUnroll>), dim3(grid), dim3(block), 0, s, n_rows,
-                     n_cols, nnz_cap, k, G, col_ptr, row_idx, static_cast<const VT*>(val),
-                     static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal,
-                     dX, lddx, dx_f64, dxal, dval, dv_f64);
+#define SPM_CALL_F(GW, F)                                                                      \
+  hipLaunchKernelGGL((k_spmm_bwd<VT, XT, ACC, GW, F>), dim3(grid), dim3(block), 0, s, n_rows,  \
+                     n_cols, nnz_cap, k, col_ptr, row_idx, static_cast<const VT*>(val),        \
+                     static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal, \
+                     dX, lddx, dx_f64, dxal, dval, dv_f64)
+#define SPM_CALL(GW) SPM_CALL_F(GW, false)
+  if (full && G == 8) SPM_CALL_F(8, true);
+  else if (full && G == 16) SPM_CALL_F(16, true);
+  else if (full && G == 32) SPM_CALL_F(32, true);
+  else SPM_GW_SWITCH(G, SPM_CALL)
+#undef SPM_CALL
+#undef SPM_CALL_F
 }
 
 size_t dsize(spm_dtype t) { return t == SPM_F64 ? 8 : (t == SPM_F32 ? 4 : 2); }
@@ -257,6 +359,7 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
   uint64_t* fold_state = reinterpret_cast<uint64_t*>(w + L.fold_state);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
   int32_t* colstart = reinterpret_cast<int32_t*>(w + L.colstart);
+  int32_t* first = reinterpret_cast<int32_t*>(w + L.first);
   uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
   uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
 
@@ -265,34 +368,60 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
   hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
                      dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
                      (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
-  if (nnz_in > 0)
-    hipLaunchKernelGGL((k_col_hist<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0, s,
-                       row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
-  launch_scan<kNT, kScanIPT>(colcnt, n_cols, colstart, scan_state, tickets + 0, s);
-  if (nnz_in > 0) {
-    hipLaunchKernelGGL((k_col_scatter<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0,
-                       s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colstart, colcnt,
-                       bucket);
-    hipLaunchKernelGGL((k_segsort<kNT, kSortCap, false>),
-                       dim3((unsigned)ceil_div(nnz_in, kSortT)), dim3(kNT), 0, s, bucket,
-                       colstart, n_cols, (int64_t)kSortT, scratch, (int32_t*)nullptr,
-                       (int32_t*)nullptr);
+  if (L.pp.ok) {
+    // two-level partition by column: no device-wide atomics
+    const PartParams& P = L.pp;
+    uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
+    int32_t* offs = reinterpret_cast<int32_t*>(w + L.offs);
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
+    uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
+    PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
+    hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
+                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, info);
+    launch_scan<kNT, kScanIPT>(table, L.scan_n, offs, scan_state, tickets + 0, s);
+    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo>),
+                       dim3((unsigned)P.ntiles), dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles,
+                       P.T1, (const int32_t*)offs, bkey, bseg);
+    hipLaunchKernelGGL((k_part_sort<kNT, kPartCap, false>), dim3((unsigned)P.CB), dim3(kNT), 0,
+                       s, P.b, P.CB, P.ntiles, n_cols, (const int32_t*)offs,
+                       (const uint64_t*)bkey, (const uint32_t*)bseg, bucket, scratch, colstart,
+                       (int32_t*)nullptr, (int32_t*)nullptr);
+    hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_cols + 1, kNT, cap)), dim3(kNT), 0, s,
+                       (const int32_t*)colstart, n_cols, (int64_t)kFoldTile, L.fold_tiles, first);
+  } else {
+    // one counter per column in global memory (shapes with more columns than the partition
+    // covers, and n_cols = 0)
+    if (nnz_in > 0)
+      hipLaunchKernelGGL((k_col_hist<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0,
+                         s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
+    launch_scan<kNT, kScanIPT>(colcnt, n_cols, colstart, scan_state, tickets + 0, s);
+    hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_cols + 1, kNT, cap)), dim3(kNT), 0, s,
+                       (const int32_t*)colstart, n_cols, (int64_t)kFoldTile, L.fold_tiles, first);
+    if (nnz_in > 0) {
+      hipLaunchKernelGGL((k_col_scatter<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT),
+                         0, s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colstart,
+                         colcnt, bucket);
+      hipLaunchKernelGGL((k_segsort<kNT, kSortCap, false>),
+                         dim3((unsigned)ceil_div(nnz_in, kSortT)), dim3(kNT), 0, s, bucket,
+                         colstart, n_cols, (int64_t)kSortT, (const int32_t*)first, scratch,
+                         (int32_t*)nullptr, (int32_t*)nullptr);
+    }
   }
   const int out_f64 = out_type == SPM_F64 ? 1 : 0;
   switch (val_type) {
     case SPM_F64:
       launch_fold<double>(bucket, colstart, n_cols, static_cast<const double*>(val), col_ptr,
-                          row_idx, val_out, out_f64, info, fold_state, tickets + 1, L.fold_tiles,
-                          s);
+                          row_idx, val_out, out_f64, info, first, fold_state, tickets + 1,
+                          L.fold_tiles, s);
       break;
     case SPM_F32:
       launch_fold<float>(bucket, colstart, n_cols, static_cast<const float*>(val), col_ptr,
-                         row_idx, val_out, out_f64, info, fold_state, tickets + 1, L.fold_tiles,
-                         s);
+                         row_idx, val_out, out_f64, info, first, fold_state, tickets + 1,
+                         L.fold_tiles, s);
       break;
     default:
       launch_fold<bf16_t>(bucket, colstart, n_cols, static_cast<const bf16_t*>(val), col_ptr,
-                          row_idx, val_out, out_f64, info, fold_state, tickets + 1,
+                          row_idx, val_out, out_f64, info, first, fold_state, tickets + 1,
                           L.fold_tiles, s);
       break;
   }
@@ -325,7 +454,6 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   char* pl = static_cast<char*>(plan);
-  uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
   uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
   uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
@@ -339,16 +467,42 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
   hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
                      dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
                      (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
-  hipLaunchKernelGGL((k_plan_hist<kNT>),
-                     dim3(grid_for(nnz_cap > n_cols ? nnz_cap : n_cols, kNT, cap)), dim3(kNT), 0,
-                     s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, rowcnt, info);
-  launch_scan<kNT, kScanIPT>(rowcnt, n_rows, row_ptr, scan_state, tickets, s);
-  if (nnz_cap > 0 && n_cols > 0) {
-    hipLaunchKernelGGL((k_row_scatter<kNT>), dim3(grid_for(nnz_cap, kNT * 4, cap)), dim3(kNT), 0,
-                       s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, row_ptr, rowcnt, bucket);
-    hipLaunchKernelGGL((k_segsort<kNT, kSortCap, true>),
-                       dim3((unsigned)ceil_div(nnz_cap, kSortT)), dim3(kNT), 0, s, bucket,
-                       row_ptr, n_rows, (int64_t)kSortT, scratch, col_t, perm);
+  if (L.pp.ok) {
+    // two-level partition by row: no device-wide atomics
+    const PartParams& Q = L.pp;
+    int32_t* colarr = reinterpret_cast<int32_t*>(w + L.colarr);
+    uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
+    int32_t* offs = reinterpret_cast<int32_t*>(w + L.offs);
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
+    uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
+    hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(grid_for(n_cols > 0 ? n_cols : 1, kNT, cap)),
+                       dim3(kNT), 0, s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info);
+    PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
+    hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
+                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1, table, (int32_t*)nullptr);
+    launch_scan<kNT, kScanIPT>(table, L.scan_n, offs, scan_state, tickets, s);
+    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc>),
+                       dim3((unsigned)Q.ntiles), dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles,
+                       Q.T1, (const int32_t*)offs, bkey, bseg);
+    hipLaunchKernelGGL((k_part_sort<kNT, kPartCap, true>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
+                       Q.b, Q.CB, Q.ntiles, n_rows, (const int32_t*)offs, (const uint64_t*)bkey,
+                       (const uint32_t*)bseg, bucket, scratch, row_ptr, col_t, perm);
+  } else {
+    uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
+    int32_t* first = reinterpret_cast<int32_t*>(w + L.first);
+    hipLaunchKernelGGL((k_plan_hist<kNT>),
+                       dim3(grid_for(nnz_cap > n_cols ? nnz_cap : n_cols, kNT, cap)), dim3(kNT), 0,
+                       s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, rowcnt, info);
+    launch_scan<kNT, kScanIPT>(rowcnt, n_rows, row_ptr, scan_state, tickets, s);
+    if (nnz_cap > 0 && n_cols > 0) {
+      hipLaunchKernelGGL((k_row_scatter<kNT>), dim3(grid_for(n_cols, kNT, cap)), dim3(kNT), 0, s,
+                         col_ptr, row_idx, n_rows, n_cols, nnz_cap, row_ptr, rowcnt, bucket);
+      hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_rows + 1, kNT, cap)), dim3(kNT), 0, s,
+                         (const int32_t*)row_ptr, n_rows, (int64_t)kSortT, L.sort_tiles, first);
+      hipLaunchKernelGGL((k_segsort<kNT, kSortCap, true>),
+                         dim3((unsigned)L.sort_tiles), dim3(kNT), 0, s, bucket, row_ptr, n_rows,
+                         (int64_t)kSortT, (const int32_t*)first, scratch, col_t, perm);
+    }
   }
   return launch_status();
 }
@@ -384,8 +538,9 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const bool f32acc = acc_is_f32(val_type, x_type);
+  const bool full = k == 4 * (int64_t)G && xal && yal;
 #define SPM_FWD(VT, XT, ACC)                                                                   \
-  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, \
+  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, \
                             yal, grid, block, s)
   if (val_type == SPM_F64) {
     if (x_type == SPM_F64) SPM_FWD(double, double, double);
@@ -432,8 +587,9 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const bool f32acc = acc_is_f32(val_type, x_type);
+  const bool full = k == 4 * (int64_t)G && gal && xal && (!dX || dxal);
 #define SPM_BWD(VT, XT, ACC)                                                                   \
-  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, col_ptr, row_idx, val, Gm, ldg, gal, X, \
+  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm, ldg, gal, X, \
                             ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, block, s)
   if (val_type == SPM_F64) {
     if (x_type == SPM_F64) SPM_BWD(double, double, double);
@@ -462,7 +618,7 @@ spm_status spm_tuning_set(const spm_tuning* in) {
       in->spmm_unroll != 8)
     return SPM_EINVAL;
   if (in->spmm_waves_per_cu < 1 || in->spmm_waves_per_cu > 64) return SPM_EINVAL;
-  if (in->batch_block != 256 && in->batch_block != 512) return SPM_EINVAL;
+  if (in->batch_block != 256) return SPM_EINVAL;
   if (in->batch_wg_per_cu < 1 || in->batch_wg_per_cu > 8) return SPM_EINVAL;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning = *in;
@@ -489,7 +645,10 @@ int batch_workers(int32_t workers, int32_t batch) {
 
 template <int NT, typename VIN, typename XT, typename ACC>
 void launch_batch(const BatchArgs& a, int workers, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch<NT, VIN, XT, ACC>), dim3(workers), dim3(NT), 0, s, a);
+#define SPM_CALL(GW) \
+  hipLaunchKernelGGL((k_batch<NT, VIN, XT, ACC, GW>), dim3(workers), dim3(NT), 0, s, a)
+  SPM_GW_SWITCH(a.G, SPM_CALL)
+#undef SPM_CALL
 }
 
 template <int NT>
@@ -589,8 +748,7 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, (uint32_t*)nullptr,
                      (int64_t)0);
-  if (tu.batch_block == 512) launch_batch_nt<512>(a, val_type, x_type, w, s);
-  else launch_batch_nt<256>(a, val_type, x_type, w, s);
+  launch_batch_nt<256>(a, val_type, x_type, w, s);
   return launch_status();
 }
 

@@ -140,6 +140,25 @@ __global__ __launch_bounds__(NT) void k_scan_excl(const uint32_t* __restrict__ i
 }
 
 // ------------------------------------------------------------------------------------------
+// first[t] = the first index c in [0, n] with starts[c] >= t*T, for every tile t with
+// t*T <= starts[n].  One thread per c writes the tiles whose boundary falls in
+// (starts[c-1], starts[c]]; this replaces per-tile binary searches (chains of dependent
+// global loads) in the sort and fold kernels.
+// ------------------------------------------------------------------------------------------
+__global__ void k_tile_first(const int32_t* __restrict__ starts, int64_t n, int64_t T,
+                             int64_t max_tiles, int32_t* __restrict__ first) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n; c += stride) {
+    const int64_t lo = (c == 0) ? -1 : (int64_t)starts[c - 1];
+    const int64_t hi = starts[c];
+    int64_t t = (lo < 0) ? 0 : lo / T + 1;
+    int64_t t_end = hi / T;
+    if (t_end > max_tiles) t_end = max_tiles;
+    for (; t <= t_end; ++t) first[t] = (int32_t)c;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // K2: scatter each in-range triplet's key into its column's bucket.  The per-column counter
 // counts down, so it is zero again afterwards; slot order inside a bucket is arbitrary and
 // is fixed by the sort that follows.
@@ -191,9 +210,22 @@ __device__ void chunk_sort(uint64_t* __restrict__ keys, const ST* starts, int64_
                            uint64_t* s_key, uint8_t* s_flag) {
   const int64_t e0 = starts[a];
   const int cnt = (int)((int64_t)starts[b] - e0);
-  for (int i = threadIdx.x; i < cnt; i += NT) {
-    s_key[i] = keys[e0 + i];
-    s_flag[i] = 0;
+  constexpr int U = 4;
+  for (int i0 = threadIdx.x; i0 < cnt; i0 += NT * U) {
+    uint64_t kv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      kv[u] = (i < cnt) ? keys[e0 + i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      if (i < cnt) {
+        s_key[i] = kv[u];
+        s_flag[i] = 0;
+      }
+    }
   }
   __syncthreads();
   for (int64_t s = a + threadIdx.x; s < b; s += NT) {
@@ -318,6 +350,7 @@ template <int NT, int CAP, bool PLAN>
 __global__ __launch_bounds__(NT) void k_segsort(uint64_t* __restrict__ keys,
                                                 const int32_t* __restrict__ starts,
                                                 int64_t nseg, int64_t T,
+                                                const int32_t* __restrict__ first,
                                                 uint64_t* __restrict__ scratch,
                                                 int32_t* __restrict__ out_hi,
                                                 int32_t* __restrict__ out_lo) {
@@ -328,13 +361,10 @@ __global__ __launch_bounds__(NT) void k_segsort(uint64_t* __restrict__ keys,
   const int64_t ntiles = N > 0 ? (N + T - 1) / T : 1;
   const int64_t t = blockIdx.x;
   if (t >= ntiles) return;
-  if (threadIdx.x == 0) {
-    s_b[0] = lower_bound(starts, nseg, t * T);
-    s_b[1] = (t == ntiles - 1) ? nseg : lower_bound(starts, nseg, (t + 1) * T);
-  }
-  __syncthreads();
-  const int64_t a = s_b[0], b_end = s_b[1];
-  __syncthreads();
+  int64_t a = first[t];
+  int64_t b_end = (t == ntiles - 1) ? nseg : (int64_t)first[t + 1];
+  if (a > nseg) a = nseg;
+  if (b_end > nseg) b_end = nseg;
   sort_segments<NT, CAP, PLAN>(keys, starts, a, b_end, scratch, out_hi, out_lo, s_key, s_flag,
                                &s_b[2]);
 }
@@ -350,31 +380,41 @@ __device__ __forceinline__ uint32_t fold_tile(const uint64_t* __restrict__ keys,
                                               const uint64_t* s_k, int64_t base, int cnt,
                                               int64_t N, const VT* __restrict__ val,
                                               uint32_t (&rows)[IPT], double (&sums)[IPT]) {
-  uint32_t mask = 0;
+  // head flags and the first value of every run are gathered for all IPT elements at once
+  // (independent loads in flight), then each head folds the rest of its run in order.
+  bool head[IPT];
 #pragma unroll
   for (int s = 0; s < IPT; ++s) {
     const int li = threadIdx.x * IPT + s;
+    head[s] = false;
     rows[s] = 0;
     sums[s] = 0.0;
     if (li < cnt) {
       const uint64_t key = s_k[li];
       const uint32_t row = key_row(key);
-      bool head = (key & kSegHead) != 0;
-      if (!head) {
+      bool h = (key & kSegHead) != 0;
+      if (!h) {
         const uint64_t pk = (li > 0) ? s_k[li - 1] : keys[base - 1];
-        head = key_row(pk) != row;
+        h = key_row(pk) != row;
       }
-      if (head) {
-        double acc = to_acc<double>(val[(uint32_t)key]);
-        for (int64_t j = base + li + 1; j < N; ++j) {
-          const uint64_t k2 = (j < base + cnt) ? s_k[j - base] : keys[j];
-          if ((k2 & kSegHead) || key_row(k2) != row) break;
-          acc = acc + to_acc<double>(val[(uint32_t)k2]);
-        }
-        rows[s] = row;
-        sums[s] = acc;
-        if (acc != 0.0) mask |= 1u << s;
+      head[s] = h;
+      rows[s] = row;
+      if (h) sums[s] = to_acc<double>(val[(uint32_t)key]);
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int s = 0; s < IPT; ++s) {
+    if (head[s]) {
+      const int li = threadIdx.x * IPT + s;
+      double acc = sums[s];
+      for (int64_t j = base + li + 1; j < N; ++j) {
+        const uint64_t k2 = (j < base + cnt) ? s_k[j - base] : keys[j];
+        if ((k2 & kSegHead) || key_row(k2) != rows[s]) break;
+        acc = acc + to_acc<double>(val[(uint32_t)k2]);
       }
+      sums[s] = acc;
+      if (acc != 0.0) mask |= 1u << s;
     }
   }
   return mask;
@@ -389,6 +429,7 @@ __global__ __launch_bounds__(NT) void k_fold(const uint64_t* __restrict__ keys,
                                              int32_t* __restrict__ row_idx,
                                              void* __restrict__ val_out, int out_f64,
                                              int32_t* __restrict__ info,
+                                             const int32_t* __restrict__ first,
                                              uint64_t* __restrict__ state,
                                              uint32_t* __restrict__ ticket) {
   constexpr int T = NT * IPT;
@@ -440,8 +481,8 @@ __global__ __launch_bounds__(NT) void k_fold(const uint64_t* __restrict__ keys,
     }
     if (threadIdx.x == 0) {
       s_off = prefix;
-      s_c[0] = lower_bound(colstart, n_cols + 1, base);
-      s_c[1] = (t == ntiles - 1) ? n_cols + 1 : lower_bound(colstart, n_cols + 1, base + T);
+      s_c[0] = first[t];
+      s_c[1] = (t == ntiles - 1) ? n_cols + 1 : (int64_t)first[t + 1];
     }
   }
   __syncthreads();
@@ -495,8 +536,8 @@ __global__ __launch_bounds__(NT) void k_plan_hist(const int32_t* __restrict__ co
   if (bad_row) set_status(info, kStBounds);
 }
 
-// Scatter (col << 32 | slot) of every stored element into its row's bucket.  Each thread
-// takes 4 consecutive slots and finds their column by one binary search plus a forward walk.
+// Scatter (col << 32 | slot) of every stored element into its row's bucket: one thread per
+// column walks that column's slots.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_row_scatter(const int32_t* __restrict__ col_ptr,
                                                     const int32_t* __restrict__ row_idx,
@@ -505,17 +546,14 @@ __global__ __launch_bounds__(NT) void k_row_scatter(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ row_ptr,
                                                     uint32_t* __restrict__ cursor,
                                                     uint64_t* __restrict__ bucket) {
-  constexpr int PER = 4;
   const int64_t raw = col_ptr[n_cols];
   const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
-  const int64_t stride = (int64_t)gridDim.x * NT * PER;
-  for (int64_t p0 = ((int64_t)blockIdx.x * NT + threadIdx.x) * PER; p0 < nnz; p0 += stride) {
-    int64_t c = upper_bound(col_ptr, n_cols + 1, p0) - 1;
-    if (c < 0) c = 0;
-    if (c > n_cols - 1) c = n_cols - 1;
-    const int64_t p1 = (p0 + PER < nnz) ? p0 + PER : nnz;
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < n_cols; c += stride) {
+    int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
+    p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
+    p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
     for (int64_t p = p0; p < p1; ++p) {
-      while (c + 1 < n_cols && (int64_t)col_ptr[c + 1] <= p) ++c;
       const int32_t r = row_idx[p];
       if (r >= 0 && (int64_t)r < n_rows) {
         const uint32_t slot = atomicSub(&cursor[r], 1u) - 1u;

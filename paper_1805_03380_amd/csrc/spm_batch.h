@@ -7,7 +7,7 @@
 // spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
 #pragma once
 
-#include "spm_assemble.h"
+#include "spm_partition.h"
 #include "spm_spmm.h"
 #include "spm.h"
 
@@ -15,34 +15,6 @@ namespace spm {
 
 constexpr int kBatchMaxLdsDim = 8192;  // counters of up to this many columns / rows live in LDS
 constexpr int kBatchCap = 2048;        // LDS sort chunk (keys)
-
-// In-place inclusive scan of a[0..n) by the whole workgroup (blocked chunks with a carry).
-template <int NT>
-__device__ void wg_inclusive_scan_inplace(uint32_t* a, int64_t n, uint32_t* s_w) {
-  constexpr int IPT = 8;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
-    uint32_t v[IPT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int s = 0; s < IPT; ++s) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
-      v[s] = (i < n) ? a[i] : 0u;
-      sum += v[s];
-    }
-    uint32_t total;
-    const uint32_t excl = wg_excl_scan<NT>(sum, s_w, &total);
-    uint32_t run = carry + excl;
-#pragma unroll
-    for (int s = 0; s < IPT; ++s) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
-      run += v[s];
-      if (i < n) a[i] = run;
-    }
-    carry += total;
-    __syncthreads();
-  }
-}
 
 struct BatchArgs {
   const spm_batch_item* items;
@@ -74,7 +46,7 @@ struct BatchArgs {
   int yal;            // Y / dX rows likewise (vector stores allowed)
 };
 
-template <int NT, typename VIN, typename XT, typename ACC>
+template <int NT, typename VIN, typename XT, typename ACC, int GW>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
   constexpr int T = NT * kBatchFoldIPT;
@@ -242,20 +214,32 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     __syncthreads();
     // ---- 7. forward Y = A.X and 8. adjoint dX, dval ---------------------------------------
     {
-      const int G = a.G;
-      const int lg = threadIdx.x & (G - 1);
-      const int64_t groups = NT / G;
-      const int64_t gid = threadIdx.x / G;
+      const int lg = threadIdx.x & (GW - 1);
+      const int64_t groups = NT / GW;
+      const int64_t gid = threadIdx.x / GW;
       const XT* Xb = Xa + it.x_off;
       const XT* Gb = Ga + it.g_off;
-      for (int64_t r = gid; r < n_r; r += groups)
-        spmm_row<float, XT, ACC, 4>(r, lg, G, a.k, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
-                                    Xb, a.k, a.xal != 0, a.Y + it.g_off, a.k, false, a.yal != 0);
+      const bool full = a.k == 4 * GW && a.xal && a.yal;
+      for (int64_t r = gid; r < n_r; r += groups) {
+        if (full)
+          spmm_row<float, XT, ACC, GW, true>(r, lg, a.k, n_c, nnz, rp, a.col_t + to, a.perm + to,
+                                             vo, Xb, a.k, true, a.Y + it.g_off, a.k, false, true);
+        else
+          spmm_row<float, XT, ACC, GW, false>(r, lg, a.k, n_c, nnz, rp, a.col_t + to,
+                                              a.perm + to, vo, Xb, a.k, a.xal != 0,
+                                              a.Y + it.g_off, a.k, false, a.yal != 0);
+      }
       for (int64_t c = gid; c < n_c; c += groups) {
         const int64_t p0 = cp[c], p1 = cp[c + 1];
-        spmm_col_bwd<float, XT, ACC, 4>(c, p0, p1, lg, G, a.k, n_r, ri, vo, Gb, a.k,
-                                        a.xal != 0, Xb, a.k, a.xal != 0, a.dX + it.x_off, a.k,
-                                        false, a.yal != 0, a.dval + to, false);
+        if (full)
+          spmm_col_bwd<float, XT, ACC, GW, true>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k, true,
+                                                 Xb, a.k, true, a.dX + it.x_off, a.k, false, true,
+                                                 a.dval + to, false);
+        else
+          spmm_col_bwd<float, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
+                                                  a.xal != 0, Xb, a.k, a.xal != 0,
+                                                  a.dX + it.x_off, a.k, false, a.yal != 0,
+                                                  a.dval + to, false);
       }
     }
     __syncthreads();

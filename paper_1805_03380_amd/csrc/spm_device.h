@@ -147,6 +147,34 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t x, uint32_t* lds, uint
   return excl;
 }
 
+// In-place inclusive scan of a[0..n) by the whole workgroup (blocked chunks with a carry).
+template <int NT>
+__device__ void wg_inclusive_scan_inplace(uint32_t* a, int64_t n, uint32_t* s_w) {
+  constexpr int IPT = 8;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
+      v[s] = (i < n) ? a[i] : 0u;
+      sum += v[s];
+    }
+    uint32_t total;
+    const uint32_t excl = wg_excl_scan<NT>(sum, s_w, &total);
+    uint32_t run = carry + excl;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + s;
+      run += v[s];
+      if (i < n) a[i] = run;
+    }
+    carry += total;
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Decoupled look-back (single-pass chained scan; Merrill & Garland, "Single-pass Parallel
 // Prefix Scan with Decoupled Look-back", 2016).  Each tile publishes one 64-bit word:
@@ -157,11 +185,14 @@ constexpr uint64_t kLbAgg = 1ull << 62;
 constexpr uint64_t kLbPre = 2ull << 62;
 constexpr uint64_t kLbVal = (1ull << 62) - 1;
 
+// The state and the value share one 64-bit word, so a reader never needs any other memory
+// made visible by the writer: relaxed device-scope atomics suffice.  (Acquire / release at
+// device scope would also write back / invalidate the XCD-local L2 on every access.)
 __device__ __forceinline__ void lb_publish(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t lb_read(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Called by all 64 lanes of ONE wave of tile `tile` (> 0) after it published its aggregate.

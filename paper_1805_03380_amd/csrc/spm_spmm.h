@@ -8,8 +8,8 @@
 //     owning 4 consecutive dense columns; G depends on k alone (group_width);
 //   * every Y / dX element is ONE accumulator updated with fma in ascending column (forward)
 //     or ascending row (adjoint) order, starting from 0;
-//   * dval[p]: each lane folds its 4-element pieces with fma in ascending j, then the G lane
-//     partials are combined by a fixed xor butterfly.
+//   * dval[p]: each lane folds its 4-element pieces with fma in ascending j, then the group's
+//     lane partials are combined by a fixed tree (group_sum).
 // The batched kernel calls the same device functions, so its results are bitwise equal.
 #pragma once
 
@@ -36,11 +36,56 @@ __device__ __forceinline__ float fma_acc<float>(float a, float b, float c) {
   return __fmaf_rn(a, b, c);
 }
 
-// Forward: Y[r, :] for one row r, by the G lanes of a group (lane lg in [0, G)).
-// A plan entry whose column or slot is out of range (only possible for a plan that was not
-// built from a valid CSC) contributes nothing and is never dereferenced.
-template <typename VT, typename XT, typename ACC, int U>
-__device__ __forceinline__ void spmm_row(int64_t r, int lg, int G, int64_t k, int64_t n_cols,
+// ------------------------------------------------------------------------------------------
+// Sum of one value over the GW lanes of an aligned lane group (GW a power of two <= 64),
+// returned in every lane of the group.  Within a 16-lane DPP row the steps are: swap
+// neighbours, swap pairs, mirror each half-row, mirror the row (each step adds the lane's
+// partner, so after step s all lanes of a 2^s block hold that block's sum); across rows an
+// xor exchange.  The tree is fixed by GW alone.
+// ------------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, typename T> __device__ __forceinline__ T dpp_mov(T x);
+template <> __device__ __forceinline__ float dpp_mov<0xB1, float>(float x) { return dpp_f32<0xB1>(x); }
+template <> __device__ __forceinline__ float dpp_mov<0x4E, float>(float x) { return dpp_f32<0x4E>(x); }
+template <> __device__ __forceinline__ float dpp_mov<0x141, float>(float x) { return dpp_f32<0x141>(x); }
+template <> __device__ __forceinline__ float dpp_mov<0x140, float>(float x) { return dpp_f32<0x140>(x); }
+template <> __device__ __forceinline__ double dpp_mov<0xB1, double>(double x) { return dpp_f64<0xB1>(x); }
+template <> __device__ __forceinline__ double dpp_mov<0x4E, double>(double x) { return dpp_f64<0x4E>(x); }
+template <> __device__ __forceinline__ double dpp_mov<0x141, double>(double x) { return dpp_f64<0x141>(x); }
+template <> __device__ __forceinline__ double dpp_mov<0x140, double>(double x) { return dpp_f64<0x140>(x); }
+
+template <int GW, typename ACC>
+__device__ __forceinline__ ACC group_sum(ACC d) {
+  if (GW >= 2) d += dpp_mov<0xB1, ACC>(d);   // quad_perm [1,0,3,2]
+  if (GW >= 4) d += dpp_mov<0x4E, ACC>(d);   // quad_perm [2,3,0,1]
+  if (GW >= 8) d += dpp_mov<0x141, ACC>(d);  // row_half_mirror
+  if (GW >= 16) d += dpp_mov<0x140, ACC>(d); // row_mirror
+  if (GW >= 32) d += __shfl_xor(d, 16, kWave);
+  if (GW >= 64) d += __shfl_xor(d, 32, kWave);
+  return d;
+}
+
+// ------------------------------------------------------------------------------------------
+// Forward: Y[r, :] for one row r by the GW lanes of a group (lane lg).  Each lane owns the
+// 4-element pieces j0 = (m*GW + lg)*4; for every piece it walks the row's stored elements in
+// ascending column order, U at a time (their indices, values and dense pieces all in flight
+// before the fma chain consumes them).  FULL: k == 4*GW with aligned rows (one vector piece
+// per lane, no tail handling).  A plan entry whose column or slot is out of range (only
+// possible for a plan not built from a valid CSC) contributes nothing and is not followed.
+// ------------------------------------------------------------------------------------------
+constexpr int kU = 4;
+
+template <typename VT, typename XT, typename ACC, int GW, bool FULL>
+__device__ __forceinline__ void spmm_row(int64_t r, int lg, int64_t k, int64_t n_cols,
                                          int64_t nnz_cap,
                                          const int32_t* __restrict__ row_ptr,
                                          const int32_t* __restrict__ col_t,
@@ -51,28 +96,32 @@ __device__ __forceinline__ void spmm_row(int64_t r, int lg, int G, int64_t k, in
   int64_t q0 = row_ptr[r], q1 = row_ptr[r + 1];
   q0 = q0 < 0 ? 0 : (q0 > nnz_cap ? nnz_cap : q0);
   q1 = q1 < q0 ? q0 : (q1 > nnz_cap ? nnz_cap : q1);
-  for (int64_t j0 = (int64_t)lg * 4; j0 < k; j0 += (int64_t)G * 4) {
-    const int avail = (int)((k - j0) < 4 ? (k - j0) : 4);
+  const int nch = FULL ? 1 : (int)((k + 4 * GW - 1) / (4 * GW));
+  for (int m = 0; m < nch; ++m) {
+    const int64_t j0 = ((int64_t)m * GW + lg) * 4;
+    const int avail = FULL ? 4 : (int)((k - j0) < 0 ? 0 : ((k - j0) < 4 ? (k - j0) : 4));
+    if (!FULL && avail <= 0) break;
+    const bool al = FULL ? true : xal;
     ACC acc[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
     int64_t q = q0;
-    for (; q + U <= q1; q += U) {
-      int32_t c[U], pp[U];
-      bool ok[U];
-      ACC v[U];
-      ACC x[U][4];
+    for (; q + kU <= q1; q += kU) {
+      int32_t c[kU], pp[kU];
+      bool ok[kU];
+      ACC v[kU];
+      ACC x[kU][4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < kU; ++u) {
         c[u] = col_t[q + u];
         pp[u] = perm[q + u];
         ok[u] = (uint32_t)c[u] < (uint64_t)n_cols && (uint32_t)pp[u] < (uint64_t)nnz_cap;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = ok[u] ? to_acc<ACC>(val[pp[u]]) : (ACC)0;
+      for (int u = 0; u < kU; ++u) v[u] = ok[u] ? to_acc<ACC>(val[pp[u]]) : (ACC)0;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        load4<ACC>(X + (int64_t)(ok[u] ? c[u] : 0) * ldx + j0, ok[u] ? avail : 0, xal, x[u]);
+      for (int u = 0; u < kU; ++u)
+        load4<ACC>(X + (int64_t)(ok[u] ? c[u] : 0) * ldx + j0, ok[u] ? avail : 0, al, x[u]);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < kU; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = fma_acc<ACC>(v[u], x[u][e], acc[e]);
     }
@@ -81,17 +130,24 @@ __device__ __forceinline__ void spmm_row(int64_t r, int lg, int G, int64_t k, in
       const bool ok = (uint32_t)c < (uint64_t)n_cols && (uint32_t)pq < (uint64_t)nnz_cap;
       const ACC v = ok ? to_acc<ACC>(val[pq]) : (ACC)0;
       ACC x[4];
-      load4<ACC>(X + (int64_t)(ok ? c : 0) * ldx + j0, ok ? avail : 0, xal, x);
+      load4<ACC>(X + (int64_t)(ok ? c : 0) * ldx + j0, ok ? avail : 0, al, x);
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[e] = fma_acc<ACC>(v, x[e], acc[e]);
     }
-    store_n<ACC>(Y, r * ldy + j0, avail, y_f64, yal, acc);
+    store_n<ACC>(Y, r * ldy + j0, avail, y_f64, FULL ? true : yal, acc);
   }
 }
 
-// Adjoint for one column c, by the G lanes of a group.  p range already clamped.
-template <typename VT, typename XT, typename ACC, int U>
-__device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, int lg, int G,
+// ------------------------------------------------------------------------------------------
+// Adjoint for one column c by the GW lanes of a group (p range already clamped): X[c, piece]
+// is loaded once per piece; for every stored element p (ascending row) the lane's G-row piece
+// updates dX with one fma chain per output and contributes a 4-term partial (fma, ascending j)
+// to dval[p]; the group sums the partials with group_sum and its first lane stores dval[p].
+// When k > 4*GW a lane owns several pieces; its dval partial then runs over its pieces in
+// order before the group sum.
+// ------------------------------------------------------------------------------------------
+template <typename VT, typename XT, typename ACC, int GW, bool FULL>
+__device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, int lg,
                                              int64_t k, int64_t n_rows,
                                              const int32_t* __restrict__ row_idx,
                                              const VT* __restrict__ val,
@@ -99,39 +155,39 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
                                              const XT* __restrict__ X, int64_t ldx, bool xal,
                                              void* __restrict__ dX, int64_t lddx, bool dx_f64,
                                              bool dxal, void* __restrict__ dval, bool dv_f64) {
-  const int64_t span = (int64_t)G * 4;
-  const int nch = (int)((k + span - 1) / span);
-  if (nch <= 1) {
+  const int nch = FULL ? 1 : (int)((k + 4 * GW - 1) / (4 * GW));
+  if (nch == 1) {
     const int64_t j0 = (int64_t)lg * 4;
-    const int avail = (int)((k - j0) < 0 ? 0 : ((k - j0) < 4 ? (k - j0) : 4));
+    const int avail = FULL ? 4 : (int)((k - j0) < 0 ? 0 : ((k - j0) < 4 ? (k - j0) : 4));
+    const bool gl = FULL ? true : gal;
     ACC x[4];
-    load4<ACC>(X + c * ldx + j0, avail, xal, x);
+    load4<ACC>(X + c * ldx + j0, avail, FULL ? true : xal, x);
     ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
     int64_t p = p0;
-    for (; p + U <= p1; p += U) {
-      int32_t r[U];
-      ACC v[U];
-      ACC g[U][4];
+    for (; p + kU <= p1; p += kU) {
+      int32_t r[kU];
+      ACC v[kU];
+      ACC g[kU][4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < kU; ++u) {
         r[u] = row_idx[p + u];
         if (r[u] < 0 || (int64_t)r[u] >= n_rows) r[u] = -1;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = to_acc<ACC>(val[p + u]);
+      for (int u = 0; u < kU; ++u) v[u] = to_acc<ACC>(val[p + u]);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        load4<ACC>(Gm + (int64_t)(r[u] < 0 ? 0 : r[u]) * ldg + j0, r[u] < 0 ? 0 : avail, gal,
+      for (int u = 0; u < kU; ++u)
+        load4<ACC>(Gm + (int64_t)(r[u] < 0 ? 0 : r[u]) * ldg + j0, r[u] < 0 ? 0 : avail, gl,
                    g[u]);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < kU; ++u) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) dx[e] = fma_acc<ACC>(v[u], g[u][e], dx[e]);
         if (dval) {
           ACC d = (ACC)0;
 #pragma unroll
           for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[u][e], x[e], d);
-          for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+          d = group_sum<GW, ACC>(d);
           if (lg == 0) {
             if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d;
             else static_cast<float*>(dval)[p + u] = (float)d;
@@ -144,27 +200,28 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
       if (r < 0 || (int64_t)r >= n_rows) r = -1;
       const ACC v = to_acc<ACC>(val[p]);
       ACC g[4];
-      load4<ACC>(Gm + (int64_t)(r < 0 ? 0 : r) * ldg + j0, r < 0 ? 0 : avail, gal, g);
+      load4<ACC>(Gm + (int64_t)(r < 0 ? 0 : r) * ldg + j0, r < 0 ? 0 : avail, gl, g);
 #pragma unroll
       for (int e = 0; e < 4; ++e) dx[e] = fma_acc<ACC>(v, g[e], dx[e]);
       if (dval) {
         ACC d = (ACC)0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
-        for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+        d = group_sum<GW, ACC>(d);
         if (lg == 0) {
           if (dv_f64) static_cast<double*>(dval)[p] = (double)d;
           else static_cast<float*>(dval)[p] = (float)d;
         }
       }
     }
-    if (dX && avail > 0) store_n<ACC>(dX, c * lddx + j0, avail, dx_f64, dxal, dx);
+    if (dX && avail > 0)
+      store_n<ACC>(dX, c * lddx + j0, avail, dx_f64, FULL ? true : dxal, dx);
     return;
   }
-  // k wider than one wavefront's 4-element pieces: several pieces per lane.
+  // several 4-element pieces per lane
   if (dX) {
     for (int m = 0; m < nch; ++m) {
-      const int64_t j0 = ((int64_t)m * G + lg) * 4;
+      const int64_t j0 = ((int64_t)m * GW + lg) * 4;
       if (j0 >= k) break;
       const int avail = (int)((k - j0) < 4 ? (k - j0) : 4);
       ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
@@ -186,7 +243,7 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
       if (r < 0 || (int64_t)r >= n_rows) r = -1;
       ACC d = (ACC)0;
       for (int m = 0; m < nch; ++m) {
-        const int64_t j0 = ((int64_t)m * G + lg) * 4;
+        const int64_t j0 = ((int64_t)m * GW + lg) * 4;
         const int avail = (r < 0 || j0 >= k) ? 0 : (int)((k - j0) < 4 ? (k - j0) : 4);
         ACC g[4], x[4];
         load4<ACC>(Gm + (int64_t)(r < 0 ? 0 : r) * ldg + (avail ? j0 : 0), avail, gal, g);
@@ -194,7 +251,7 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
       }
-      for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
+      d = group_sum<GW, ACC>(d);
       if (lg == 0) {
         if (dv_f64) static_cast<double*>(dval)[p] = (double)d;
         else static_cast<float*>(dval)[p] = (float)d;
@@ -203,48 +260,46 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
   }
 }
 
-template <typename VT, typename XT, typename ACC, int U>
+template <typename VT, typename XT, typename ACC, int GW, bool FULL>
 __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
-                                                  int64_t k, int G,
-                                                  const int32_t* __restrict__ row_ptr,
+                                                  int64_t k, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_t,
                                                   const int32_t* __restrict__ perm,
                                                   const VT* __restrict__ val,
                                                   const XT* __restrict__ X, int64_t ldx,
                                                   int xal, void* __restrict__ Y, int64_t ldy,
                                                   int y_f64, int yal) {
-  const int lg = threadIdx.x & (G - 1);
-  const int64_t groups_per_block = blockDim.x / G;
+  const int lg = threadIdx.x & (GW - 1);
+  const int64_t groups_per_block = blockDim.x / GW;
   const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
-  for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; r < n_rows;
+  for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / GW; r < n_rows;
        r += ngroups)
-    spmm_row<VT, XT, ACC, U>(r, lg, G, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X, ldx,
-                             xal != 0, Y, ldy, y_f64 != 0, yal != 0);
+    spmm_row<VT, XT, ACC, GW, FULL>(r, lg, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X,
+                                    ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);
 }
 
-template <typename VT, typename XT, typename ACC, int U>
+template <typename VT, typename XT, typename ACC, int GW, bool FULL>
 __global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
-                                                  int64_t k, int G,
-                                                  const int32_t* __restrict__ col_ptr,
+                                                  int64_t k, const int32_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ row_idx,
                                                   const VT* __restrict__ val,
                                                   const XT* __restrict__ Gm, int64_t ldg, int gal,
                                                   const XT* __restrict__ X, int64_t ldx, int xal,
                                                   void* __restrict__ dX, int64_t lddx, int dx_f64,
                                                   int dxal, void* __restrict__ dval, int dv_f64) {
-  const int lg = threadIdx.x & (G - 1);
-  const int64_t groups_per_block = blockDim.x / G;
+  const int lg = threadIdx.x & (GW - 1);
+  const int64_t groups_per_block = blockDim.x / GW;
   const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
   const int64_t raw = col_ptr[n_cols];
   const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
-  for (int64_t c = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; c < n_cols;
+  for (int64_t c = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / GW; c < n_cols;
        c += ngroups) {
     int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
     p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
     p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
-    spmm_col_bwd<VT, XT, ACC, U>(c, p0, p1, lg, G, k, n_rows, row_idx, val, Gm, ldg, gal != 0,
-                                 X, ldx, xal != 0, dX, lddx, dx_f64 != 0, dxal != 0, dval,
-                                 dv_f64 != 0);
+    spmm_col_bwd<VT, XT, ACC, GW, FULL>(c, p0, p1, lg, k, n_rows, row_idx, val, Gm, ldg,
+                                        gal != 0, X, ldx, xal != 0, dX, lddx, dx_f64 != 0,
+                                        dxal != 0, dval, dv_f64 != 0);
   }
 }
 
