@@ -87,7 +87,7 @@ spm_status launch_status() {
 // kPartMaxBuckets * kPartMaxWidth segments); then the atomic-histogram path is used.
 // ------------------------------------------------------------------------------------------
 constexpr int kPartNT = 256;
-constexpr int kPartCap = 4096;
+constexpr int kPartCap = 2048;  // bucket size kept entirely in LDS by the fused level 2
 
 struct PartParams {
   bool ok;
@@ -119,10 +119,10 @@ PartParams part_params(int64_t nseg, int64_t n) {
   P.ok = true;
   P.b = b;
   P.CB = (int32_t)ceil_div(nseg, (int64_t)1 << b);
-  // level-1 tiles: at least 1024 elements, at most about 2048 tiles (the bucket x tile table
-  // stays below kPartMaxBuckets * 2048 entries)
+  // level-1 tiles: at least 1024 elements, at most about 512 tiles (the bucket x tile table
+  // stays below kPartMaxBuckets * 512 entries)
   int64_t T1 = 1024;
-  while (ceil_div(n, T1) > 2048) T1 <<= 1;
+  while (ceil_div(n, T1) > 512) T1 <<= 1;
   P.T1 = T1;
   P.ntiles = std::max<int64_t>(1, ceil_div(n, T1));
   return P;
@@ -134,63 +134,83 @@ PartParams part_params(int64_t nseg, int64_t n) {
 // ------------------------------------------------------------------------------------------
 struct AsmLayout {
   PartParams pp;
+  // zeroed at the start of every call (only the fallback path needs these)
   size_t colcnt, scan_state, fold_state, tickets, zero_bytes;
-  size_t colstart, first, bucket, scratch, table, offs, bkey, bseg, total;
-  int64_t scan_n, fold_tiles;
+  // fallback path
+  size_t colstart, first;
+  // shared
+  size_t bucket, scratch;
+  // partition path
+  size_t table, rowoff, btot, bstart, bkey, bseg, trow, tval, bkept, boff;
+  size_t total;
+  int64_t fold_tiles;
 };
 
 AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   AsmLayout L;
   Carve c;
   L.pp = part_params(n_cols, nnz_in);
-  const int64_t tab = L.pp.ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
-  L.scan_n = L.pp.ok ? tab : n_cols;
-  const int64_t scan_tiles = L.scan_n > 0 ? ceil_div(L.scan_n, kScanTile) : 1;
+  const bool ok = L.pp.ok;
+  const int64_t tab = ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
+  const int64_t cb = ok ? L.pp.CB : 0;
+  const int64_t nP = ok ? nnz_in : 0;  // per-element partition arrays
+  const int64_t nF = ok ? 0 : n_cols;  // fallback-only arrays
+  const int64_t scan_tiles = (!ok && n_cols > 0) ? ceil_div(n_cols, kScanTile) : 1;
   L.fold_tiles = nnz_in > 0 ? ceil_div(nnz_in, kFoldTile) : 1;
-  L.colcnt = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? 0 : n_cols));
-  L.scan_state = c.take(sizeof(uint64_t) * (size_t)scan_tiles);
-  L.fold_state = c.take(sizeof(uint64_t) * (size_t)L.fold_tiles);
+  L.colcnt = c.take(sizeof(uint32_t) * (size_t)nF);
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)(ok ? 0 : scan_tiles));
+  L.fold_state = c.take(sizeof(uint64_t) * (size_t)(ok ? 0 : L.fold_tiles));
   L.tickets = c.take(sizeof(uint32_t) * 4);
   L.zero_bytes = c.off;
-  L.colstart = c.take(sizeof(int32_t) * (size_t)(n_cols + 1));
-  L.first = c.take(sizeof(int32_t) * (size_t)(L.fold_tiles + 1));
+  L.colstart = c.take(sizeof(int32_t) * (size_t)(ok ? 0 : n_cols + 1));
+  L.first = c.take(sizeof(int32_t) * (size_t)(ok ? 0 : L.fold_tiles + 1));
   L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_in);
   L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_in);
   L.table = c.take(sizeof(uint32_t) * (size_t)tab);
-  L.offs = c.take(sizeof(int32_t) * (size_t)(tab + 1));
-  L.bkey = c.take(sizeof(uint64_t) * (size_t)(L.pp.ok ? nnz_in : 0));
-  L.bseg = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? nnz_in : 0));
+  L.rowoff = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
+  L.bkey = c.take(sizeof(uint64_t) * (size_t)nP);
+  L.bseg = c.take(sizeof(uint32_t) * (size_t)nP);
+  L.trow = c.take(sizeof(uint32_t) * (size_t)nP);
+  L.tval = c.take(sizeof(double) * (size_t)nP);
+  L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.boff = c.take(sizeof(int32_t) * (size_t)(cb + 1));
   L.total = c.off;
   return L;
 }
 
 struct PlanLayout {
   PartParams pp;
-  size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch, colarr, table, offs,
-      bkey, bseg, total;
-  int64_t scan_n, sort_tiles;
+  size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
+  size_t colarr, table, rowoff, btot, bstart, bkey, bseg, total;
+  int64_t sort_tiles;
 };
 
 PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
   PlanLayout L;
   Carve c;
   L.pp = part_params(n_rows, nnz_cap);
-  const int64_t tab = L.pp.ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
-  L.scan_n = L.pp.ok ? tab : n_rows;
-  const int64_t scan_tiles = L.scan_n > 0 ? ceil_div(L.scan_n, kScanTile) : 1;
-  L.rowcnt = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? 0 : n_rows));
-  L.scan_state = c.take(sizeof(uint64_t) * (size_t)scan_tiles);
+  const bool ok = L.pp.ok;
+  const int64_t tab = ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
+  const int64_t cb = ok ? L.pp.CB : 0;
+  const int64_t nP = ok ? nnz_cap : 0;
+  const int64_t scan_tiles = (!ok && n_rows > 0) ? ceil_div(n_rows, kScanTile) : 1;
+  L.sort_tiles = nnz_cap > 0 ? ceil_div(nnz_cap, kSortT) : 1;
+  L.rowcnt = c.take(sizeof(uint32_t) * (size_t)(ok ? 0 : n_rows));
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)(ok ? 0 : scan_tiles));
   L.tickets = c.take(sizeof(uint32_t) * 4);
   L.zero_bytes = c.off;
-  L.sort_tiles = nnz_cap > 0 ? ceil_div(nnz_cap, kSortT) : 1;
-  L.first = c.take(sizeof(int32_t) * (size_t)(L.pp.ok ? 0 : L.sort_tiles + 1));
+  L.first = c.take(sizeof(int32_t) * (size_t)(ok ? 0 : L.sort_tiles + 1));
   L.bucket = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
   L.scratch = c.take(sizeof(uint64_t) * (size_t)nnz_cap);
-  L.colarr = c.take(sizeof(int32_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
+  L.colarr = c.take(sizeof(int32_t) * (size_t)nP);
   L.table = c.take(sizeof(uint32_t) * (size_t)tab);
-  L.offs = c.take(sizeof(int32_t) * (size_t)(tab + 1));
-  L.bkey = c.take(sizeof(uint64_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
-  L.bseg = c.take(sizeof(uint32_t) * (size_t)(L.pp.ok ? nnz_cap : 0));
+  L.rowoff = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
+  L.bkey = c.take(sizeof(uint64_t) * (size_t)nP);
+  L.bseg = c.take(sizeof(uint32_t) * (size_t)nP);
   L.total = c.off;
   return L;
 }
@@ -369,25 +389,46 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
                      dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
                      (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
   if (L.pp.ok) {
-    // two-level partition by column: no device-wide atomics
+    // two-level partition by column: no device-wide atomics, no inter-workgroup waiting
     const PartParams& P = L.pp;
     uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
-    int32_t* offs = reinterpret_cast<int32_t*>(w + L.offs);
+    uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
+    uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
+    int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
     uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
     uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
+    uint32_t* trow = reinterpret_cast<uint32_t*>(w + L.trow);
+    double* tval = reinterpret_cast<double*>(w + L.tval);
+    uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
+    int32_t* boff = reinterpret_cast<int32_t*>(w + L.boff);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
     hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
                        dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, info);
-    launch_scan<kNT, kScanIPT>(table, L.scan_n, offs, scan_state, tickets + 0, s);
-    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo>),
-                       dim3((unsigned)P.ntiles), dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles,
-                       P.T1, (const int32_t*)offs, bkey, bseg);
-    hipLaunchKernelGGL((k_part_sort<kNT, kPartCap, false>), dim3((unsigned)P.CB), dim3(kNT), 0,
-                       s, P.b, P.CB, P.ntiles, n_cols, (const int32_t*)offs,
-                       (const uint64_t*)bkey, (const uint32_t*)bseg, bucket, scratch, colstart,
-                       (int32_t*)nullptr, (int32_t*)nullptr);
-    hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_cols + 1, kNT, cap)), dim3(kNT), 0, s,
-                       (const int32_t*)colstart, n_cols, (int64_t)kFoldTile, L.fold_tiles, first);
+    hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s,
+                       (const uint32_t*)table, P.ntiles, rowoff, btot);
+    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)btot,
+                       (int64_t)P.CB, bstart);
+    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
+                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1,
+                       (const uint32_t*)rowoff, (const int32_t*)bstart, bkey, bseg);
+    const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
+#define SPM_L2(VT)                                                                             \
+  hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, false, VT>), dim3((unsigned)P.CB), dim3(kNT), \
+                     lds, s, P.b, n_cols, (const int32_t*)bstart, (const uint64_t*)bkey,       \
+                     (const uint32_t*)bseg, bucket, scratch, (int32_t*)nullptr,               \
+                     (int32_t*)nullptr, (int32_t*)nullptr, static_cast<const VT*>(val),        \
+                     col_ptr, trow, tval, bkept)
+    if (val_type == SPM_F64) SPM_L2(double);
+    else if (val_type == SPM_F32) SPM_L2(float);
+    else SPM_L2(bf16_t);
+#undef SPM_L2
+    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)bkept,
+                       (int64_t)P.CB, boff);
+    hipLaunchKernelGGL((k_part_emit<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s, P.b, P.CB,
+                       n_cols, (const int32_t*)bstart, (const int32_t*)boff,
+                       (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out,
+                       out_type == SPM_F64 ? 1 : 0, info);
+    return launch_status();
   } else {
     // one counter per column in global memory (shapes with more columns than the partition
     // covers, and n_cols = 0)
@@ -468,25 +509,34 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                      dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
                      (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
   if (L.pp.ok) {
-    // two-level partition by row: no device-wide atomics
+    // two-level partition by row: no device-wide atomics, no inter-workgroup waiting
     const PartParams& Q = L.pp;
     int32_t* colarr = reinterpret_cast<int32_t*>(w + L.colarr);
     uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
-    int32_t* offs = reinterpret_cast<int32_t*>(w + L.offs);
+    uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
+    uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
+    int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
     uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
     uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
     hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(grid_for(n_cols > 0 ? n_cols : 1, kNT, cap)),
                        dim3(kNT), 0, s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
     hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
-                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1, table, (int32_t*)nullptr);
-    launch_scan<kNT, kScanIPT>(table, L.scan_n, offs, scan_state, tickets, s);
-    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc>),
-                       dim3((unsigned)Q.ntiles), dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles,
-                       Q.T1, (const int32_t*)offs, bkey, bseg);
-    hipLaunchKernelGGL((k_part_sort<kNT, kPartCap, true>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
-                       Q.b, Q.CB, Q.ntiles, n_rows, (const int32_t*)offs, (const uint64_t*)bkey,
-                       (const uint32_t*)bseg, bucket, scratch, row_ptr, col_t, perm);
+                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1, table,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
+                       (const uint32_t*)table, Q.ntiles, rowoff, btot);
+    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)btot,
+                       (int64_t)Q.CB, bstart);
+    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
+                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1,
+                       (const uint32_t*)rowoff, (const int32_t*)bstart, bkey, bseg);
+    hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, true, float>), dim3((unsigned)Q.CB),
+                       dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s, Q.b, n_rows,
+                       (const int32_t*)bstart, (const uint64_t*)bkey, (const uint32_t*)bseg,
+                       bucket, scratch, row_ptr, col_t, perm, (const float*)nullptr,
+                       (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
+                       (uint32_t*)nullptr);
   } else {
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
     int32_t* first = reinterpret_cast<int32_t*>(w + L.first);

@@ -196,27 +196,50 @@ __device__ __forceinline__ uint64_t lb_read(const uint64_t* p) {
 }
 
 // Called by all 64 lanes of ONE wave of tile `tile` (> 0) after it published its aggregate.
-// Returns the sum of every earlier tile.
+// Returns the sum of every earlier tile.  Each pass reads a window of 4 states per lane
+// (256 predecessors): device-coherent reads cross the XCD fabric, so fewer, wider passes
+// shorten the chain.  Lane l holds the states of tiles base - 4l - q, q = 0..3 (q = 0 is the
+// closest); the window is summed up to and including the closest inclusive prefix.
 __device__ inline uint64_t lookback_exclusive(const uint64_t* state, int64_t tile) {
+  constexpr int Q = 4;
   const int lane = lane_id();
   uint64_t excl = 0;
   int64_t base = tile - 1;
   while (base >= 0) {
-    const int64_t i = base - lane;
-    const uint64_t v = (i >= 0) ? lb_read(state + i) : kLbPre;
-    const uint32_t st = (uint32_t)(v >> 62);
-    const uint64_t pm = __ballot(st == 2);
-    const uint64_t zm = __ballot(st == 0);
-    const int first_p = pm ? (__ffsll((unsigned long long)pm) - 1) : kWave;
-    const uint64_t need = (first_p >= kWave - 1) ? ~0ull : ((2ull << first_p) - 1ull);
-    if (zm & need) {  // a tile we depend on has not published yet: wait and re-read
+    uint64_t v[Q];
+    int firstp_q = Q;     // closest (smallest q) inclusive prefix in this lane, Q if none
+    bool zero_before = false;  // a not-yet-published state closer than that prefix
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = base - (int64_t)lane * Q - q;
+      v[q] = (i >= 0) ? lb_read(state + i) : kLbPre;
+    }
+#pragma unroll
+    for (int q = Q - 1; q >= 0; --q) {
+      if ((v[q] >> 62) == 2) firstp_q = q;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (q < firstp_q && (v[q] >> 62) == 0) zero_before = true;
+    const uint64_t pm = __ballot(firstp_q < Q);
+    const int first_lane = pm ? (__ffsll((unsigned long long)pm) - 1) : kWave;
+    // lanes up to first_lane matter; in first_lane only states up to its prefix matter
+    const bool relevant = lane <= first_lane;
+    const uint64_t zm = __ballot(relevant && zero_before);
+    if (zm) {  // a tile we depend on has not published yet: wait and re-read
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    const uint64_t mine = (lane <= first_p) ? (v & kLbVal) : 0ull;
+    uint64_t mine = 0;
+    if (relevant) {
+      const int qmax = (lane == first_lane) ? firstp_q : Q - 1;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (q <= qmax) mine += v[q] & kLbVal;
+    }
     excl += wave_sum_u64(mine);
     if (pm) break;
-    base -= kWave;
+    base -= (int64_t)kWave * Q;
   }
   return excl;
 }

@@ -1,17 +1,19 @@
 // Grouping elements by segment (the column of a triplet for assembly, the row of a stored
 // element for the plan) without device-wide atomics.  Device-scope atomics on gfx950 are
-// performed beyond the XCD-local L2 and cost far more than LDS atomics, so the grouping is a
-// two-level partition whose counters all live in LDS:
+// performed beyond the XCD-local L2 (and contended ones serialize there), so the grouping is
+// a two-level partition whose counters all live in LDS, and no workgroup ever waits for
+// another:
 //   level 1  the segments are cut into CB coarse buckets of W = 2^b consecutive segments.
 //            k_part_hist: each tile of T1 elements counts its elements per coarse bucket in
-//            LDS and writes one column of a (bucket x tile) table;  an exclusive scan of the
-//            table (bucket-major) gives every (bucket, tile) pair its output range;
+//            LDS and writes one column of a (bucket x tile) table;  k_rows_scan scans every
+//            bucket's row of the table and k_small_scan the bucket totals, which gives every
+//            (bucket, tile) pair its output range;
 //            k_part_scatter: each tile ranks its elements per bucket with LDS atomics and
 //            writes (key, segment-within-bucket) into the bucket's range.
-//   level 2  k_part_sort: one workgroup per coarse bucket counts its elements per segment in
-//            LDS, writes the segments' start offsets, scatters the keys into segment order and
-//            sorts every segment by key (sort_segments: LDS rank sort, merge sort for segments
-//            longer than an LDS chunk).
+//   level 2  k_part_level2: one workgroup per coarse bucket counts its elements per segment
+//            in LDS, scatters them into segment order and sorts every segment by key; the plan
+//            writes its row index from there, the assembly folds the runs and compacts them
+//            per bucket, and k_small_scan + k_part_emit place the buckets' survivors.
 // Keys carry a unique element index, so the grouping order inside a bucket never matters.
 #pragma once
 
@@ -129,16 +131,20 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
   if (bad && info) set_status(info, kStBounds);
 }
 
-// Level 1b: scatter (key, segment-within-bucket) into the buckets.
+// Level 1b: scatter (key, segment-within-bucket) into the buckets.  The range of (bucket cb,
+// tile t) starts at bstart[cb] + rowoff[cb * ntiles + t].
 template <int NT, typename SRC>
 __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB, int64_t ntiles,
-                                                     int64_t T1, const int32_t* __restrict__ offs,
+                                                     int64_t T1,
+                                                     const uint32_t* __restrict__ rowoff,
+                                                     const int32_t* __restrict__ bstart,
                                                      uint64_t* __restrict__ bkey,
                                                      uint32_t* __restrict__ bseg) {
   __shared__ uint32_t cur[kPartMaxBuckets];
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
-  for (int i = threadIdx.x; i < CB; i += NT) cur[i] = (uint32_t)offs[(int64_t)i * ntiles + t];
+  for (int i = threadIdx.x; i < CB; i += NT)
+    cur[i] = (uint32_t)bstart[i] + rowoff[(int64_t)i * ntiles + t];
   __syncthreads();
   const uint32_t wmask = (1u << b) - 1u;
   const int64_t base = t * T1;
@@ -164,52 +170,275 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
   }
 }
 
-// Level 2: one workgroup per coarse bucket.  Writes segstart for the bucket's segments
-// (and segstart[nseg] = total from the last bucket) and the segments' sorted keys into `out`
-// (in place with kSegHead tags, or split into out_hi / out_lo when PLAN).
-template <int NT, int CAP, bool PLAN>
-__global__ __launch_bounds__(NT) void k_part_sort(int b, int32_t CB, int64_t ntiles,
-                                                  int64_t nseg,
-                                                  const int32_t* __restrict__ offs,
-                                                  const uint64_t* __restrict__ bkey,
-                                                  const uint32_t* __restrict__ bseg,
-                                                  uint64_t* __restrict__ out,
-                                                  uint64_t* __restrict__ scratch,
-                                                  int32_t* __restrict__ segstart,
-                                                  int32_t* __restrict__ out_hi,
-                                                  int32_t* __restrict__ out_lo) {
-  __shared__ uint32_t cnt[kPartMaxWidth + 1];
-  __shared__ uint64_t s_key[CAP];
-  __shared__ uint8_t s_flag[CAP];
+// Per-bucket exclusive scan of one row of the (bucket x tile) table: rowoff[cb][t] = number of
+// bucket-cb elements in tiles before t; btot[cb] = the bucket's total.  One workgroup per row.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ table,
+                                                  int64_t ntiles, uint32_t* __restrict__ rowoff,
+                                                  uint32_t* __restrict__ btot) {
   __shared__ uint32_t s_w[NT / kWave + 1];
-  __shared__ int64_t s_b[1];
+  constexpr int IPT = 4;
   const int64_t cb = blockIdx.x;
-  const int64_t bstart = offs[cb * ntiles];
-  const int64_t bend = offs[(cb + 1) * ntiles];  // offs has CB * ntiles + 1 entries
+  const uint32_t* in = table + cb * ntiles;
+  uint32_t* out = rowoff + cb * ntiles;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < ntiles; base += (int64_t)NT * IPT) {
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      v[q] = i < ntiles ? in[i] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = carry + wg_excl_scan<NT>(sum, s_w, &tot);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      if (i < ntiles) out[i] = run;
+      run += v[q];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) btot[cb] = carry;
+}
+
+// Exclusive scan of n (a few thousand) counts by ONE workgroup: out[i] = sum in[0..i),
+// out[n] = total.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ in, int64_t n,
+                                                   int32_t* __restrict__ out) {
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  constexpr int IPT = 8;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      v[q] = i < n ? in[i] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = carry + wg_excl_scan<NT>(sum, s_w, &tot);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      if (i < n) out[i] = (int32_t)run;
+      run += v[q];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = (int32_t)carry;
+}
+
+// ------------------------------------------------------------------------------------------
+// Level 2, fused with what follows it.  One workgroup per coarse bucket (bucket elements
+// bstarts[cb] .. bstarts[cb+1]).
+//   PLAN = true : writes row_ptr for the bucket's rows and col_t / perm of their elements.
+//   PLAN = false: (assembly) folds every run of equal (column, row) left to right in input
+//                 order in binary64, drops zero sums, and writes the survivors compacted
+//                 within the bucket to temporaries (trow, tval at the bucket's own offset),
+//                 the bucket-relative column offsets to col_rel and the survivor count to
+//                 bkept[cb]; k_small_scan and k_part_emit then place them.
+// A bucket of at most CAP elements stays in LDS from load to output (fast path); a larger
+// one goes through global staging: segment scatter, sort_segments, then fold_tile over
+// blocks of CAP keys.
+// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_pre[CAP+1] u32 |
+//              s_seg[CAP] u16 | s_flag[CAP] u8   (part_level2_lds_bytes)
+// ------------------------------------------------------------------------------------------
+__host__ __device__ inline size_t part_level2_lds_bytes(int b, int cap) {
+  const size_t w = ((size_t)1 << b) + 1;
+  size_t off = (w * 4 + 15) & ~(size_t)15;
+  off += (size_t)cap * 8 * 2;
+  off += (((size_t)cap + 1) * 4 + 15) & ~(size_t)15;
+  off += (((size_t)cap * 2) + 15) & ~(size_t)15;
+  off += (size_t)cap;
+  return off;
+}
+
+template <int NT, int CAP, bool PLAN, typename VT>
+__global__ __launch_bounds__(NT) void k_part_level2(
+    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint64_t* __restrict__ bkey,
+    const uint32_t* __restrict__ bseg, uint64_t* __restrict__ gkeys,
+    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
+    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel,
+    uint32_t* __restrict__ trow, double* __restrict__ tval, uint32_t* __restrict__ bkept) {
+  constexpr int IPT = CAP / NT;
+  static_assert(IPT * NT == CAP, "CAP must be a multiple of the workgroup size");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const size_t wcnt = ((size_t)1 << b) + 1;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
+  size_t off = (wcnt * 4 + 15) & ~(size_t)15;
+  uint64_t* s_in = reinterpret_cast<uint64_t*>(smem + off);
+  off += (size_t)CAP * 8;
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(smem + off);
+  off += (size_t)CAP * 8;
+  uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + off);
+  off += (((size_t)CAP + 1) * 4 + 15) & ~(size_t)15;
+  uint16_t* s_seg = reinterpret_cast<uint16_t*>(smem + off);
+  off += (((size_t)CAP * 2) + 15) & ~(size_t)15;
+  uint8_t* s_flag = smem + off;
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_b[3];
+
+  const int64_t cb = blockIdx.x;
+  const int64_t bstart = bstarts[cb];
+  const int64_t bend = bstarts[cb + 1];
+  const int64_t m = bend - bstart;
   const int64_t seg0 = cb << b;
   const int64_t rem = nseg - seg0;
   const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
-  for (int64_t i = threadIdx.x; i <= nW; i += NT) cnt[i] = 0;
-  __syncthreads();
+  const bool last_bucket = seg0 + nW >= nseg;
   constexpr int U = 8;
-  for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
-    uint32_t sg[U];
+
+  for (int64_t j = threadIdx.x; j <= nW; j += NT) cnt[j] = 0;
+  const bool fast = m <= CAP;
+  if (fast) {
+    for (int64_t i0 = threadIdx.x; i0 < m; i0 += (int64_t)NT * U) {
+      uint64_t ky[U];
+      uint32_t sg[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + (int64_t)u * NT;
-      sg[u] = (e < bend) ? bseg[e] : 0xffffffffu;
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        ky[u] = i < m ? bkey[bstart + i] : 0ull;
+        sg[u] = i < m ? bseg[bstart + i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i < m) {
+          s_in[i] = ky[u];
+          s_seg[i] = (uint16_t)sg[u];
+        }
+      }
     }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < m; i += NT) atomicAdd(&cnt[s_seg[i]], 1u);
+  } else {
+    __syncthreads();
+    for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
+      uint32_t sg[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (sg[u] != 0xffffffffu) atomicAdd(&cnt[sg[u]], 1u);
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + (int64_t)u * NT;
+        sg[u] = (e < bend) ? bseg[e] : 0xffffffffu;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (sg[u] != 0xffffffffu) atomicAdd(&cnt[sg[u]], 1u);
+    }
   }
   __syncthreads();
   wg_inclusive_scan_inplace<NT>(cnt, nW, s_w);  // cnt[j] = end of segment j (relative)
-  for (int64_t j = threadIdx.x; j < nW; j += NT)
-    segstart[seg0 + j] = (int32_t)(bstart + (j == 0 ? 0 : (int64_t)cnt[j - 1]));
-  if (cb == CB - 1 && threadIdx.x == 0) segstart[nseg] = (int32_t)bend;
+  if (PLAN) {
+    for (int64_t j = threadIdx.x; j < nW; j += NT)
+      row_ptr[seg0 + j] = (int32_t)(bstart + (j == 0 ? 0 : (int64_t)cnt[j - 1]));
+    if (last_bucket && threadIdx.x == 0) row_ptr[nseg] = (int32_t)bend;
+  }
   __syncthreads();
-  uint64_t* obase = out + bstart;
+
+  if (fast) {
+    // ---- everything in LDS ----------------------------------------------------------------
+    for (int64_t i = threadIdx.x; i < m; i += NT) {
+      const uint32_t pos = atomicSub(&cnt[s_seg[i]], 1u) - 1u;
+      s_key[pos] = s_in[i];
+      s_flag[i] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;  // cnt[j] = start of segment j
+    for (int64_t j = threadIdx.x; j < nW; j += NT) {
+      const uint32_t lo = cnt[j];
+      if (lo < (uint32_t)m) s_flag[lo] = 1;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < m; i += NT) {
+      const uint64_t key = s_key[i];
+      int64_t lo = i;
+      while (!s_flag[lo]) --lo;
+      int r = 0;
+      int64_t j = lo;
+      do {
+        r += (s_key[j] < key) ? 1 : 0;
+        ++j;
+      } while (j < m && !s_flag[j]);
+      s_in[lo + r] = key;  // s_in now holds the bucket sorted by (segment, key)
+    }
+    __syncthreads();
+    if (PLAN) {
+      for (int64_t i = threadIdx.x; i < m; i += NT) {
+        const uint64_t key = s_in[i];
+        col_t[bstart + i] = (int32_t)(key >> 32);
+        perm[bstart + i] = (int32_t)(uint32_t)key;
+      }
+      return;
+    }
+    // fold: thread owns IPT consecutive positions; the first value of every run is gathered
+    // for all of them at once, then each run is folded in order
+    uint32_t rows[IPT];
+    double sums[IPT];
+    bool head[IPT];
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int64_t li = (int64_t)threadIdx.x * IPT + s;
+      head[s] = false;
+      rows[s] = 0;
+      sums[s] = 0.0;
+      if (li < m) {
+        const uint64_t key = s_in[li];
+        rows[s] = key_row(key);
+        head[s] = s_flag[li] || key_row(s_in[li - 1]) != rows[s];
+        if (head[s]) sums[s] = to_acc<double>(val[(uint32_t)key]);
+      }
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      if (head[s]) {
+        const int64_t li = (int64_t)threadIdx.x * IPT + s;
+        double acc = sums[s];
+        for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
+          const uint64_t k2 = s_in[j];
+          if (key_row(k2) != rows[s]) break;
+          acc = acc + to_acc<double>(val[(uint32_t)k2]);
+        }
+        sums[s] = acc;
+        if (acc != 0.0) mask |= 1u << s;
+      }
+    }
+    uint32_t kept;
+    const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &kept);
+    {
+      uint32_t run = excl;
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        const int64_t li = (int64_t)threadIdx.x * IPT + s;
+        if (li < m) s_pre[li] = run;
+        run += (mask >> s) & 1u;
+      }
+      if (threadIdx.x == 0) s_pre[m] = kept;
+    }
+    __syncthreads();
+    {
+      int64_t o = bstart + excl;
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        if ((mask >> s) & 1u) {
+          trow[o] = rows[s];
+          tval[o] = sums[s];
+          ++o;
+        }
+      }
+    }
+    for (int64_t j = threadIdx.x; j < nW; j += NT) col_rel[seg0 + j] = (int32_t)s_pre[cnt[j]];
+    if (threadIdx.x == 0) bkept[cb] = kept;
+    return;
+  }
+
+  // ---- large bucket: global staging ---------------------------------------------------------
+  uint64_t* gk = gkeys + bstart;
   for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
     uint32_t sg[U];
     uint64_t ky[U];
@@ -223,16 +452,97 @@ __global__ __launch_bounds__(NT) void k_part_sort(int b, int32_t CB, int64_t nti
     for (int u = 0; u < U; ++u) {
       if (sg[u] != 0xffffffffu) {
         const uint32_t pos = atomicSub(&cnt[sg[u]], 1u) - 1u;
-        obase[pos] = ky[u];
+        gk[pos] = ky[u];
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) cnt[nW] = (uint32_t)(bend - bstart);  // cnt[j] = start of segment j
+  if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;
   __syncthreads();
-  sort_segments<NT, CAP, PLAN>(obase, cnt, 0, nW, scratch + bstart,
-                               PLAN ? out_hi + bstart : out_hi, PLAN ? out_lo + bstart : out_lo,
-                               s_key, s_flag, s_b);
+  sort_segments<NT, CAP, PLAN>(gk, cnt, 0, nW, scratch + bstart, PLAN ? col_t + bstart : col_t,
+                               PLAN ? perm + bstart : perm, s_key, s_flag, &s_b[0]);
+  if (PLAN) return;
+  __syncthreads();
+  // one pass over blocks of CAP sorted (tagged) keys: fold, compact into the temporaries
+  uint32_t running = 0;
+  for (int64_t base = 0; base < m; base += CAP) {
+    const int nb = (int)((m - base) < CAP ? (m - base) : CAP);
+    for (int i = threadIdx.x; i < nb; i += NT) s_in[i] = gk[base + i];
+    __syncthreads();
+    uint32_t rows[IPT];
+    double sums[IPT];
+    const uint32_t mask = fold_tile<NT, IPT, VT>(gk, s_in, base, nb, m, val, rows, sums);
+    uint32_t blk;
+    const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk);
+    {
+      uint32_t run = excl;
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        const int li = threadIdx.x * IPT + s;
+        if (li < nb) s_pre[li] = run;
+        run += (mask >> s) & 1u;
+      }
+      if (threadIdx.x == 0) {
+        s_pre[nb] = blk;
+        const bool last = base + CAP >= m;
+        s_b[1] = lower_bound(cnt, nW + 1, base);
+        s_b[2] = last ? nW + 1 : lower_bound(cnt, nW + 1, base + CAP);
+      }
+    }
+    __syncthreads();
+    {
+      int64_t o = bstart + running + excl;
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        if ((mask >> s) & 1u) {
+          trow[o] = rows[s];
+          tval[o] = sums[s];
+          ++o;
+        }
+      }
+    }
+    for (int64_t j = s_b[1] + threadIdx.x; j < s_b[2]; j += NT) {
+      if (j >= nW) continue;  // cnt[nW] = m marks the bucket end, not a column
+      int64_t p = (int64_t)cnt[j] - base;
+      if (p > nb) p = nb;
+      col_rel[seg0 + j] = (int32_t)(running + s_pre[p]);
+    }
+    running += blk;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bkept[cb] = running;
+}
+
+// After the scan of the per-bucket survivor counts (boff[cb], boff[CB] = nnz_out): move each
+// bucket's survivors from the temporaries to their final place (rounded once to the output
+// type), turn the bucket-relative column offsets into col_ptr, and finish col_ptr / info.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nseg,
+                                                  const int32_t* __restrict__ bstarts,
+                                                  const int32_t* __restrict__ boff,
+                                                  const uint32_t* __restrict__ trow,
+                                                  const double* __restrict__ tval,
+                                                  int32_t* __restrict__ col_ptr,
+                                                  int32_t* __restrict__ row_idx,
+                                                  void* __restrict__ val_out, int out_f64,
+                                                  int32_t* __restrict__ info) {
+  const int64_t cb = blockIdx.x;
+  const int64_t src0 = bstarts[cb];
+  const int64_t dst0 = boff[cb];
+  const int64_t kept = (int64_t)boff[cb + 1] - dst0;
+  for (int64_t i = threadIdx.x; i < kept; i += NT) {
+    row_idx[dst0 + i] = (int32_t)trow[src0 + i];
+    if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
+    else static_cast<float*>(val_out)[dst0 + i] = (float)tval[src0 + i];
+  }
+  const int64_t seg0 = cb << b;
+  const int64_t rem = nseg - seg0;
+  const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
+  for (int64_t j = threadIdx.x; j < nW; j += NT) col_ptr[seg0 + j] += (int32_t)dst0;
+  if (cb == CB - 1 && threadIdx.x == 0) {
+    col_ptr[nseg] = boff[CB];
+    info[0] = boff[CB];
+  }
 }
 
 }  // namespace spm
