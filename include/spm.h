@@ -192,15 +192,23 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item *items,
                          int32_t workers, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------------------
- * Tuning.  Launch-shape parameters that never change results (see Numerics above).  The
- * values are process-wide; spm_tuning_set validates and copies them (host only).
+ * Tuning.  Launch-shape parameters that never change results (see Numerics above): they
+ * decide how work is cut into workgroups, never the order in which any output is summed.
+ * The values are process-wide; spm_tuning_set validates and copies them (host only).  The
+ * grouping parameters change the workspace sizes that spm_coo_to_csc_workspace and
+ * spm_csc_plan_size report: ask for sizes after setting the tuning (a call made with a smaller
+ * workspace fails with SPM_EWORKSPACE, it never overruns).
  * ------------------------------------------------------------------------------------------ */
 typedef struct spm_tuning {
-  int32_t spmm_block;       /* threads per workgroup of the forward / backward kernels */
-  int32_t spmm_unroll;      /* stored elements loaded ahead per group (1, 2, 4 or 8) */
-  int32_t spmm_waves_per_cu;/* forward / backward grid = CUs * this * (64 / block) groups */
-  int32_t batch_block;      /* threads per workgroup of the batched kernel (256 or 512) */
-  int32_t batch_wg_per_cu;  /* persistent batched workgroups per compute unit */
+  int32_t spmm_block;          /* threads per workgroup of the forward / backward kernels:
+                                  64, 128 or 256 */
+  int32_t spmm_blocks_per_cu;  /* forward / backward grid cap, in workgroups per compute unit
+                                  (1..64); rows or columns beyond it are strided */
+  int32_t batch_wg_per_cu;     /* persistent batched workgroups per compute unit (1..8) */
+  int32_t part_bucket_target;  /* assembly / plan grouping: target elements per coarse bucket
+                                  (256..2048, power of two) */
+  int32_t part_max_tiles;      /* assembly / plan grouping: at most this many first-level
+                                  tiles (64..4096, power of two) */
   int32_t reserved[3];
 } spm_tuning;
 

@@ -35,9 +35,33 @@ class BatchItem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """spm_tuning."""
-    _fields_ = [("spmm_block", ctypes.c_int32), ("spmm_unroll", ctypes.c_int32),
-                ("spmm_waves_per_cu", ctypes.c_int32), ("batch_block", ctypes.c_int32),
-                ("batch_wg_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("spmm_block", ctypes.c_int32), ("spmm_blocks_per_cu", ctypes.c_int32),
+                ("batch_wg_per_cu", ctypes.c_int32), ("part_bucket_target", ctypes.c_int32),
+                ("part_max_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    FIELDS = ("spmm_block", "spmm_blocks_per_cu", "batch_wg_per_cu", "part_bucket_target",
+              "part_max_tiles")
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in self.FIELDS}
+
+
+def get_tuning() -> Tuning:
+    t = Tuning()
+    check(load().spm_tuning_get(ctypes.byref(t)), "spm_tuning_get")
+    return t
+
+
+def set_tuning(**kw) -> Tuning:
+    """Update some tuning fields (spm_tuning_set); returns the previous values."""
+    old = get_tuning()
+    t = Tuning.from_buffer_copy(old)
+    for k, v in kw.items():
+        if k not in Tuning.FIELDS:
+            raise KeyError(k)
+        setattr(t, k, int(v))
+    check(load().spm_tuning_set(ctypes.byref(t)), "spm_tuning_set")
+    return old
 
 
 # name -> (restype, argtypes)

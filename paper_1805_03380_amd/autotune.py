@@ -1,0 +1,186 @@
+"""Autotuner for the launch-shape parameters of libspm (spm_tuning).
+
+Every parameter only decides how work is cut into workgroups -- never the order in which an
+output is summed -- so any choice gives bitwise the same results; the tuner only measures
+time.  It sweeps each group of parameters on a given problem with HIP-event timing, keeps the
+fastest, and persists the choice in a JSON table keyed by device name, library version and a
+problem signature (shape class, triplets, k, element types).
+
+    python -m paper_1805_03380_amd.autotune            # tune the benchmark workloads
+    table = autotune.load_table(); autotune.apply(table, signature)
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+
+from . import _lib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.json")
+
+SPMM_SPACE = {"spmm_block": [64, 128, 256], "spmm_blocks_per_cu": [8, 16, 32, 64]}
+PART_SPACE = {"part_bucket_target": [512, 1024, 2048], "part_max_tiles": [256, 512, 1024, 2048]}
+BATCH_SPACE = {"batch_wg_per_cu": [1, 2, 3, 4]}
+
+
+def table_path() -> str:
+    return os.environ.get("SPM_TUNE_CACHE", DEFAULT_TABLE)
+
+
+def signature(kind: str, n_rows: int, n_cols: int, nnz_in: int, k: int, val_dtype: str,
+              x_dtype: str) -> str:
+    """Problem class: sizes rounded to powers of two (tuned values carry over to neighbours)."""
+    def p2(x):
+        return 0 if x <= 0 else int(round(math.log2(x)))
+    return "%s:r%d:c%d:n%d:k%d:%s:%s" % (kind, p2(n_rows), p2(n_cols), p2(nnz_in), k,
+                                         val_dtype, x_dtype)
+
+
+def device_key() -> str:
+    import torch
+    lib = _lib.load()
+    return "%s|%s" % (torch.cuda.get_device_name(0), lib.spm_version().decode())
+
+
+def load_table(path: str | None = None) -> dict:
+    path = path or table_path()
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_table(table: dict, path: str | None = None) -> str:
+    path = path or table_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return path
+
+
+def lookup(table: dict, sig: str, dev: str | None = None) -> dict | None:
+    entry = table.get(dev or device_key(), {})
+    return entry.get(sig, {}).get("tuning")
+
+
+def apply(table: dict, sig: str, dev: str | None = None) -> dict | None:
+    """Set the tuned values for `sig` if the table has them; returns what was applied."""
+    tu = lookup(table, sig, dev)
+    if tu:
+        _lib.set_tuning(**tu)
+    return tu
+
+
+def _time(fn, reps: int, warm: int = 2) -> float:
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _sweep(space: dict, run, reps: int) -> tuple[dict, float, list]:
+    keys = list(space)
+    best, best_ms, log = None, float("inf"), []
+    saved = _lib.get_tuning().as_dict()
+    try:
+        for vals in itertools.product(*(space[k] for k in keys)):
+            cand = dict(zip(keys, vals))
+            _lib.set_tuning(**cand)
+            ms = _time(run, reps)
+            log.append((cand, ms))
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    finally:
+        _lib.set_tuning(**saved)
+    return best, best_ms, log
+
+
+def tune_pipeline(p, reps: int = 10):
+    """Tune the single-matrix path on problem p (a synth.COOProblem with X and G)."""
+    import torch
+    from .pipeline import Pipeline
+    dev = torch.device("cuda:0")
+    row = torch.from_numpy(p.row).to(dev)
+    col = torch.from_numpy(p.col).to(dev)
+    val = torch.from_numpy(p.val).to(dev)
+    X = torch.from_numpy(p.X).to(dev)
+    G = torch.from_numpy(p.G).to(dev).to(X.dtype)
+    result = {}
+
+    def make():  # the workspace sizes follow the grouping parameters
+        return Pipeline(p.n_rows, p.n_cols, p.nnz_in, p.k, val_dtype=val.dtype, x_dtype=X.dtype)
+
+    pipe = make()
+    pipe.step(row, col, val, X, G)
+    torch.cuda.synchronize()
+
+    def spmm_only():
+        pipe.step_spmm(X, G)
+    best_s, ms_s, log_s = _sweep(SPMM_SPACE, spmm_only, reps)
+    result.update(best_s)
+
+    # grouping: rebuild the pipeline per candidate (workspace sizes change), time assembly+plan
+    keys = list(PART_SPACE)
+    best_p, best_pms, log_p = None, float("inf"), []
+    saved = _lib.get_tuning().as_dict()
+    try:
+        for vals in itertools.product(*(PART_SPACE[k] for k in keys)):
+            cand = dict(zip(keys, vals))
+            _lib.set_tuning(**cand)
+            q = make()
+            ms = _time(lambda: q.step_assemble_plan(row, col, val), reps)
+            log_p.append((cand, ms))
+            if ms < best_pms:
+                best_p, best_pms = cand, ms
+            del q
+    finally:
+        _lib.set_tuning(**saved)
+    result.update(best_p)
+    return result, {"spmm_ms": ms_s, "assemble_plan_ms": best_pms,
+                    "spmm_log": log_s, "part_log": log_p}
+
+
+def tune_batch(problems, reps: int = 3):
+    from .batch import PackedBatch
+    pb = PackedBatch(problems)
+    best, ms, log = _sweep(BATCH_SPACE, lambda: pb.run_batched(), reps)
+    return best, {"batch_ms": ms, "batch_log": log}
+
+
+def main():
+    import numpy as np
+    from . import synth
+    table = load_table()
+    dev = device_key()
+    entries = table.setdefault(dev, {})
+    t0 = time.time()
+    p = synth.uniform_1e5(value_dtype=np.float32, k=64)
+    tu, info = tune_pipeline(p)
+    sig = signature("pipeline", p.n_rows, p.n_cols, p.nnz_in, p.k, "float32", "float32")
+    entries[sig] = {"tuning": tu, "ms": {"spmm": info["spmm_ms"],
+                                          "assemble_plan": info["assemble_plan_ms"]}}
+    print(sig, tu, info["spmm_ms"], info["assemble_plan_ms"], flush=True)
+    bt = synth.batch_problems()
+    tb, infob = tune_batch(bt.problems)
+    sigb = signature("batch", 8192, 8192, 131072, 32, "float32", "float32")
+    entries[sigb] = {"tuning": tb, "ms": {"batch": infob["batch_ms"]}}
+    print(sigb, tb, infob["batch_ms"], flush=True)
+    print("saved", save_table(table), "in %.1f s" % (time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main()

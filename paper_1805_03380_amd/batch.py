@@ -105,8 +105,17 @@ class PackedBatch:
     def new_outputs(self):
         return self._outputs()
 
+    def _ensure_workspace(self):
+        """The workspace grows with the number of persistent workgroups (a tuning value)."""
+        ws = ctypes.c_size_t(0)
+        _lib.check(self.lib.spm_batch_workspace(self.max_dim, self.max_nnz, self.workers,
+                                                ctypes.byref(ws)), "spm_batch_workspace")
+        if ws.value > self.ws.numel():
+            self.ws = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
+
     def run_batched(self, out=None, stream=None):
         """All matrices in one persistent launch."""
+        self._ensure_workspace()
         o = self.out if out is None else out
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         st = self.lib.spm_batch_run(

@@ -43,7 +43,7 @@ struct Carve {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-spm_tuning g_tuning = {256, 4, 8, 256, 2, {0, 0, 0}};
+spm_tuning g_tuning = {256, 64, 2, 2048, 512, {0, 0, 0}};
 std::mutex g_tuning_mu;
 
 spm_tuning tuning() {
@@ -111,18 +111,20 @@ int floor_log2(int64_t x) {
 PartParams part_params(int64_t nseg, int64_t n) {
   PartParams P{false, 0, 0, 1, 1024};
   if (nseg <= 0) return P;
+  const spm_tuning tu = tuning();
   const int bmin = ceil_log2(ceil_div(nseg, kPartMaxBuckets));
-  const int btarget = n > 0 ? floor_log2(std::max<int64_t>(1, nseg * 2048 / n)) : 12;
+  const int btarget =
+      n > 0 ? floor_log2(std::max<int64_t>(1, nseg * (int64_t)tu.part_bucket_target / n)) : 12;
   int b = std::max(bmin, btarget);
   if (b > 12) b = 12;
   if (b < bmin) return P;
   P.ok = true;
   P.b = b;
   P.CB = (int32_t)ceil_div(nseg, (int64_t)1 << b);
-  // level-1 tiles: at least 1024 elements, at most about 512 tiles (the bucket x tile table
-  // stays below kPartMaxBuckets * 512 entries)
+  // level-1 tiles: at least 1024 elements, at most part_max_tiles tiles (the bucket x tile
+  // table stays below kPartMaxBuckets * part_max_tiles entries)
   int64_t T1 = 1024;
-  while (ceil_div(n, T1) > 512) T1 <<= 1;
+  while (ceil_div(n, T1) > tu.part_max_tiles) T1 <<= 1;
   P.T1 = T1;
   P.ntiles = std::max<int64_t>(1, ceil_div(n, T1));
   return P;
@@ -321,7 +323,7 @@ int spmm_grid(int64_t groups, int G, int block) {
   const spm_tuning tu = tuning();
   const int64_t per_block = block / G;
   int64_t want = ceil_div(groups, per_block);
-  int64_t cap = (int64_t)cu_count() * tu.spmm_waves_per_cu * 16;
+  int64_t cap = (int64_t)cu_count() * tu.spmm_blocks_per_cu;
   if (want > cap) want = cap;
   if (want < 1) want = 1;
   return (int)want;
@@ -663,13 +665,15 @@ spm_status spm_tuning_get(spm_tuning* out) {
 
 spm_status spm_tuning_set(const spm_tuning* in) {
   if (!in) return SPM_EINVAL;
+  auto pow2 = [](int32_t x) { return x > 0 && (x & (x - 1)) == 0; };
   if (in->spmm_block != 64 && in->spmm_block != 128 && in->spmm_block != 256) return SPM_EINVAL;
-  if (in->spmm_unroll != 1 && in->spmm_unroll != 2 && in->spmm_unroll != 4 &&
-      in->spmm_unroll != 8)
-    return SPM_EINVAL;
-  if (in->spmm_waves_per_cu < 1 || in->spmm_waves_per_cu > 64) return SPM_EINVAL;
-  if (in->batch_block != 256) return SPM_EINVAL;
+  if (in->spmm_blocks_per_cu < 1 || in->spmm_blocks_per_cu > 64) return SPM_EINVAL;
   if (in->batch_wg_per_cu < 1 || in->batch_wg_per_cu > 8) return SPM_EINVAL;
+  if (!pow2(in->part_bucket_target) || in->part_bucket_target < 256 ||
+      in->part_bucket_target > 2048)
+    return SPM_EINVAL;
+  if (!pow2(in->part_max_tiles) || in->part_max_tiles < 64 || in->part_max_tiles > 4096)
+    return SPM_EINVAL;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning = *in;
   return SPM_OK;

@@ -88,6 +88,42 @@ class Pipeline:
         if events is not None:
             events[4].record(s)
 
+    def step_assemble_plan(self, row, col, val, stream=None):
+        """Only the first two calls (assembly and plan)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = s.cuda_stream
+        lib = self.lib
+        n_rows, n_cols, nnz = self.n_rows, self.n_cols, self.nnz_in
+        _lib.check(lib.spm_coo_to_csc(n_rows, n_cols, nnz, row.data_ptr(), col.data_ptr(),
+                                      val.data_ptr(), _DT[val.dtype], self.col_ptr.data_ptr(),
+                                      self.row_idx.data_ptr(), self.values.data_ptr(),
+                                      _DT[self.csc_dtype], self.info.data_ptr(),
+                                      self.asm_ws.data_ptr(), self.asm_ws.numel(), h),
+                   "spm_coo_to_csc")
+        _lib.check(lib.spm_csc_plan_build(n_rows, n_cols, nnz, self.col_ptr.data_ptr(),
+                                          self.row_idx.data_ptr(), self.plan.data_ptr(),
+                                          self.plan.numel(), self.plan_info.data_ptr(),
+                                          self.plan_ws.data_ptr(), self.plan_ws.numel(), h),
+                   "spm_csc_plan_build")
+
+    def step_spmm(self, X, G, stream=None):
+        """Only the products (forward and adjoint) on the current CSC and plan."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = s.cuda_stream
+        lib = self.lib
+        n_rows, n_cols, nnz, k = self.n_rows, self.n_cols, self.nnz_in, self.k
+        _lib.check(lib.spm_csc_spmm(n_rows, n_cols, nnz, k, self.plan.data_ptr(),
+                                    self.values.data_ptr(), _DT[self.csc_dtype], X.data_ptr(),
+                                    X.stride(0), _DT[X.dtype], self.Y.data_ptr(),
+                                    self.Y.stride(0), _DT[self.y_dtype], h), "spm_csc_spmm")
+        _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
+                                             self.row_idx.data_ptr(), self.values.data_ptr(),
+                                             _DT[self.csc_dtype], G.data_ptr(), G.stride(0),
+                                             X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                             self.dX.data_ptr(), self.dX.stride(0),
+                                             _DT[self.dx_dtype], self.dval.data_ptr(),
+                                             _DT[self.csc_dtype], h), "spm_csc_spmm_backward")
+
     def status(self):
         """(nnz_out, assembly status, plan status) -- synchronises."""
         a = self.info.cpu()

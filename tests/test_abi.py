@@ -43,6 +43,8 @@ def test_status_strings_and_version():
 
 def test_workspace_sizes():
     lib = _lib_or_build()
+    # the partition layout follows the tuning: sizes must be asked for with the same tuning
+    # that runs the call
     ws = ctypes.c_size_t(0)
     assert lib.spm_coo_to_csc_workspace(10, 10, 100, ctypes.byref(ws)) == _lib.OK
     small = ws.value
@@ -98,10 +100,17 @@ def test_tuning_roundtrip():
     bad = _lib.Tuning.from_buffer_copy(t)
     bad.spmm_block = 100
     assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
+    bad = _lib.Tuning.from_buffer_copy(t)
+    bad.part_bucket_target = 1000  # not a power of two
+    assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
+    bad = _lib.Tuning.from_buffer_copy(t)
+    bad.part_max_tiles = 8192
+    assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
     good = _lib.Tuning.from_buffer_copy(t)
     good.spmm_block = 128
+    good.part_bucket_target = 1024
     assert lib.spm_tuning_set(ctypes.byref(good)) == _lib.OK
     chk = _lib.Tuning()
     lib.spm_tuning_get(ctypes.byref(chk))
-    assert chk.spmm_block == 128
+    assert chk.spmm_block == 128 and chk.part_bucket_target == 1024
     assert lib.spm_tuning_set(ctypes.byref(saved)) == _lib.OK
