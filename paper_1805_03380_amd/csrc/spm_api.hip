@@ -590,7 +590,9 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const bool f32acc = acc_is_f32(val_type, x_type);
-  const bool full = k == 4 * (int64_t)G && xal && yal;
+  // The full path loads a clamped (valid) dense row for out-of-range plan entries, so it
+  // needs at least one dense row.
+  const bool full = k == 4 * (int64_t)G && xal && yal && n_cols > 0;
 #define SPM_FWD(VT, XT, ACC)                                                                   \
   launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, \
                             yal, grid, block, s)
@@ -639,7 +641,7 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const bool f32acc = acc_is_f32(val_type, x_type);
-  const bool full = k == 4 * (int64_t)G && gal && xal && (!dX || dxal);
+  const bool full = k == 4 * (int64_t)G && gal && xal && (!dX || dxal) && n_rows > 0;
 #define SPM_BWD(VT, XT, ACC)                                                                   \
   launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm, ldg, gal, X, \
                             ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, block, s)

@@ -222,8 +222,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
       const bool full = a.k == 4 * GW && a.xal && a.yal;
       for (int64_t r = gid; r < n_r; r += groups) {
         if (full)
-          spmm_row<float, XT, ACC, GW, true>(r, lg, a.k, n_c, nnz, rp, a.col_t + to, a.perm + to,
-                                             vo, Xb, a.k, true, a.Y + it.g_off, a.k, false, true);
+          spmm_row_full<float, XT, ACC, GW>(r, lg, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
+                                            Xb, a.k, a.Y + it.g_off, a.k, false);
         else
           spmm_row<float, XT, ACC, GW, false>(r, lg, a.k, n_c, nnz, rp, a.col_t + to,
                                               a.perm + to, vo, Xb, a.k, a.xal != 0,
@@ -232,9 +232,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
       for (int64_t c = gid; c < n_c; c += groups) {
         const int64_t p0 = cp[c], p1 = cp[c + 1];
         if (full)
-          spmm_col_bwd<float, XT, ACC, GW, true>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k, true,
-                                                 Xb, a.k, true, a.dX + it.x_off, a.k, false, true,
-                                                 a.dval + to, false);
+          spmm_col_bwd_full<float, XT, ACC, GW>(c, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
+                                                a.dX + it.x_off, a.k, false, a.dval + to, false);
         else
           spmm_col_bwd<float, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
                                                   a.xal != 0, Xb, a.k, a.xal != 0,

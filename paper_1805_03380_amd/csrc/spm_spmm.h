@@ -84,6 +84,162 @@ __device__ __forceinline__ ACC group_sum(ACC d) {
 // ------------------------------------------------------------------------------------------
 constexpr int kU = 4;
 
+// One aligned 4-element vector of row `r` (always a valid row), widened; the caller zeroes
+// the contribution of invalid entries with selects, so the loop has no divergent branches.
+template <typename ACC>
+__device__ __forceinline__ void vload4(const float* __restrict__ p, ACC (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = (ACC)v.x; o[1] = (ACC)v.y; o[2] = (ACC)v.z; o[3] = (ACC)v.w;
+}
+template <typename ACC>
+__device__ __forceinline__ void vload4(const double* __restrict__ p, ACC (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = (ACC)a.x; o[1] = (ACC)a.y; o[2] = (ACC)b.x; o[3] = (ACC)b.y;
+}
+template <typename ACC>
+__device__ __forceinline__ void vload4(const bf16_t* __restrict__ p, ACC (&o)[4]) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  o[0] = (ACC)__uint_as_float(v.x << 16);
+  o[1] = (ACC)__uint_as_float(v.x & 0xffff0000u);
+  o[2] = (ACC)__uint_as_float(v.y << 16);
+  o[3] = (ACC)__uint_as_float(v.y & 0xffff0000u);
+}
+
+// Forward, full aligned pieces (k == 4*GW): lane lg owns columns [4 lg, 4 lg + 4).
+template <typename VT, typename XT, typename ACC, int GW>
+__device__ __forceinline__ void spmm_row_full(int64_t r, int lg, int64_t n_cols, int64_t nnz_cap,
+                                              const int32_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col_t,
+                                              const int32_t* __restrict__ perm,
+                                              const VT* __restrict__ val,
+                                              const XT* __restrict__ X, int64_t ldx,
+                                              void* __restrict__ Y, int64_t ldy, bool y_f64) {
+  int64_t q0 = row_ptr[r], q1 = row_ptr[r + 1];
+  q0 = q0 < 0 ? 0 : (q0 > nnz_cap ? nnz_cap : q0);
+  q1 = q1 < q0 ? q0 : (q1 > nnz_cap ? nnz_cap : q1);
+  const XT* Xl = X + (int64_t)lg * 4;
+  ACC acc[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
+  int64_t q = q0;
+  for (; q + kU <= q1; q += kU) {
+    int32_t c[kU], pp[kU];
+    bool ok[kU];
+    ACC v[kU];
+    ACC x[kU][4];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      c[u] = col_t[q + u];
+      pp[u] = perm[q + u];
+      ok[u] = (uint32_t)c[u] < (uint64_t)n_cols && (uint32_t)pp[u] < (uint64_t)nnz_cap;
+      c[u] = ok[u] ? c[u] : 0;
+      pp[u] = ok[u] ? pp[u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = to_acc<ACC>(val[pp[u]]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) vload4<ACC>(Xl + (int64_t)c[u] * ldx, x[u]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const ACC t = fma_acc<ACC>(v[u], x[u][e], acc[e]);
+        acc[e] = ok[u] ? t : acc[e];
+      }
+    }
+  }
+  for (; q < q1; ++q) {
+    int32_t c = col_t[q], pq = perm[q];
+    const bool ok = (uint32_t)c < (uint64_t)n_cols && (uint32_t)pq < (uint64_t)nnz_cap;
+    c = ok ? c : 0;
+    pq = ok ? pq : 0;
+    const ACC v = to_acc<ACC>(val[pq]);
+    ACC x[4];
+    vload4<ACC>(Xl + (int64_t)c * ldx, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const ACC t = fma_acc<ACC>(v, x[e], acc[e]);
+      acc[e] = ok ? t : acc[e];
+    }
+  }
+  store_n<ACC>(Y, r * ldy + (int64_t)lg * 4, 4, y_f64, true, acc);
+}
+
+// Adjoint, full aligned pieces (k == 4*GW).
+template <typename VT, typename XT, typename ACC, int GW>
+__device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t p1, int lg,
+                                                  int64_t n_rows,
+                                                  const int32_t* __restrict__ row_idx,
+                                                  const VT* __restrict__ val,
+                                                  const XT* __restrict__ Gm, int64_t ldg,
+                                                  const XT* __restrict__ X, int64_t ldx,
+                                                  void* __restrict__ dX, int64_t lddx,
+                                                  bool dx_f64, void* __restrict__ dval,
+                                                  bool dv_f64) {
+  const XT* Gl = Gm + (int64_t)lg * 4;
+  ACC x[4];
+  vload4<ACC>(X + c * ldx + (int64_t)lg * 4, x);
+  ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
+  int64_t p = p0;
+  for (; p + kU <= p1; p += kU) {
+    int32_t r[kU];
+    bool ok[kU];
+    ACC v[kU];
+    ACC g[kU][4];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      r[u] = row_idx[p + u];
+      ok[u] = r[u] >= 0 && (int64_t)r[u] < n_rows;
+      r[u] = ok[u] ? r[u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = to_acc<ACC>(val[p + u]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) vload4<ACC>(Gl + (int64_t)r[u] * ldg, g[u]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        g[u][e] = ok[u] ? g[u][e] : (ACC)0;
+        dx[e] = fma_acc<ACC>(v[u], g[u][e], dx[e]);
+      }
+      if (dval) {
+        ACC d = (ACC)0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[u][e], x[e], d);
+        d = group_sum<GW, ACC>(d);
+        if (lg == 0) {
+          if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d;
+          else static_cast<float*>(dval)[p + u] = (float)d;
+        }
+      }
+    }
+  }
+  for (; p < p1; ++p) {
+    int32_t r = row_idx[p];
+    const bool ok = r >= 0 && (int64_t)r < n_rows;
+    r = ok ? r : 0;
+    const ACC v = to_acc<ACC>(val[p]);
+    ACC g[4];
+    vload4<ACC>(Gl + (int64_t)r * ldg, g);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      g[e] = ok ? g[e] : (ACC)0;
+      dx[e] = fma_acc<ACC>(v, g[e], dx[e]);
+    }
+    if (dval) {
+      ACC d = (ACC)0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
+      d = group_sum<GW, ACC>(d);
+      if (lg == 0) {
+        if (dv_f64) static_cast<double*>(dval)[p] = (double)d;
+        else static_cast<float*>(dval)[p] = (float)d;
+      }
+    }
+  }
+  if (dX) store_n<ACC>(dX, c * lddx + (int64_t)lg * 4, 4, dx_f64, true, dx);
+}
+
 template <typename VT, typename XT, typename ACC, int GW, bool FULL>
 __device__ __forceinline__ void spmm_row(int64_t r, int lg, int64_t k, int64_t n_cols,
                                          int64_t nnz_cap,
@@ -274,8 +430,12 @@ __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols
   const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
   for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / GW; r < n_rows;
        r += ngroups)
-    spmm_row<VT, XT, ACC, GW, FULL>(r, lg, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X,
-                                    ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);
+    if (FULL)
+      spmm_row_full<VT, XT, ACC, GW>(r, lg, n_cols, nnz_cap, row_ptr, col_t, perm, val, X, ldx,
+                                     Y, ldy, y_f64 != 0);
+    else
+      spmm_row<VT, XT, ACC, GW, false>(r, lg, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X,
+                                       ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);
 }
 
 template <typename VT, typename XT, typename ACC, int GW, bool FULL>
@@ -297,9 +457,13 @@ __global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols
     int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
     p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
     p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
-    spmm_col_bwd<VT, XT, ACC, GW, FULL>(c, p0, p1, lg, k, n_rows, row_idx, val, Gm, ldg,
-                                        gal != 0, X, ldx, xal != 0, dX, lddx, dx_f64 != 0,
-                                        dxal != 0, dval, dv_f64 != 0);
+    if (FULL)
+      spmm_col_bwd_full<VT, XT, ACC, GW>(c, p0, p1, lg, n_rows, row_idx, val, Gm, ldg, X, ldx,
+                                         dX, lddx, dx_f64 != 0, dval, dv_f64 != 0);
+    else
+      spmm_col_bwd<VT, XT, ACC, GW, false>(c, p0, p1, lg, k, n_rows, row_idx, val, Gm, ldg,
+                                           gal != 0, X, ldx, xal != 0, dX, lddx, dx_f64 != 0,
+                                           dxal != 0, dval, dv_f64 != 0);
   }
 }
 
