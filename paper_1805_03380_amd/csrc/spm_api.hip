@@ -143,7 +143,7 @@ struct AsmLayout {
   // shared
   size_t bucket, scratch;
   // partition path
-  size_t table, rowoff, btot, bstart, bkey, bseg, trow, tval, bkept, boff;
+  size_t table, rowoff, btot, bstart, bkey, bseg, trow, tval, bkept;
   size_t total;
   int64_t fold_tiles;
 };
@@ -177,7 +177,6 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.trow = c.take(sizeof(uint32_t) * (size_t)nP);
   L.tval = c.take(sizeof(double) * (size_t)nP);
   L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
-  L.boff = c.take(sizeof(int32_t) * (size_t)(cb + 1));
   L.total = c.off;
   return L;
 }
@@ -402,17 +401,14 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     uint32_t* trow = reinterpret_cast<uint32_t*>(w + L.trow);
     double* tval = reinterpret_cast<double*>(w + L.tval);
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
-    int32_t* boff = reinterpret_cast<int32_t*>(w + L.boff);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
     hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
                        dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, info);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s,
                        (const uint32_t*)table, P.ntiles, rowoff, btot);
-    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)btot,
-                       (int64_t)P.CB, bstart);
     hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
                        dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1,
-                       (const uint32_t*)rowoff, (const int32_t*)bstart, bkey, bseg);
+                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, bkey, bseg);
     const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
 #define SPM_L2(VT)                                                                             \
   hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, false, VT>), dim3((unsigned)P.CB), dim3(kNT), \
@@ -424,10 +420,8 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     else if (val_type == SPM_F32) SPM_L2(float);
     else SPM_L2(bf16_t);
 #undef SPM_L2
-    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)bkept,
-                       (int64_t)P.CB, boff);
     hipLaunchKernelGGL((k_part_emit<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s, P.b, P.CB,
-                       n_cols, (const int32_t*)bstart, (const int32_t*)boff,
+                       n_cols, (const int32_t*)bstart, (const uint32_t*)bkept,
                        (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out,
                        out_type == SPM_F64 ? 1 : 0, info);
     return launch_status();
@@ -528,11 +522,9 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                        (int32_t*)nullptr);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
                        (const uint32_t*)table, Q.ntiles, rowoff, btot);
-    hipLaunchKernelGGL((k_small_scan<kNT>), dim3(1), dim3(kNT), 0, s, (const uint32_t*)btot,
-                       (int64_t)Q.CB, bstart);
     hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
                        dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1,
-                       (const uint32_t*)rowoff, (const int32_t*)bstart, bkey, bseg);
+                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, bkey, bseg);
     hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, true, float>), dim3((unsigned)Q.CB),
                        dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s, Q.b, n_rows,
                        (const int32_t*)bstart, (const uint64_t*)bkey, (const uint32_t*)bseg,

@@ -6,14 +6,14 @@
 //   level 1  the segments are cut into CB coarse buckets of W = 2^b consecutive segments.
 //            k_part_hist: each tile of T1 elements counts its elements per coarse bucket in
 //            LDS and writes one column of a (bucket x tile) table;  k_rows_scan scans every
-//            bucket's row of the table and k_small_scan the bucket totals, which gives every
-//            (bucket, tile) pair its output range;
+//            bucket's row of the table, and each scatter workgroup scans the bucket totals,
+//            which gives every (bucket, tile) pair its output range;
 //            k_part_scatter: each tile ranks its elements per bucket with LDS atomics and
 //            writes (key, segment-within-bucket) into the bucket's range.
 //   level 2  k_part_level2: one workgroup per coarse bucket counts its elements per segment
 //            in LDS, scatters them into segment order and sorts every segment by key; the plan
 //            writes its row index from there, the assembly folds the runs and compacts them
-//            per bucket, and k_small_scan + k_part_emit place the buckets' survivors.
+//            per bucket, and k_part_emit places the buckets' survivors.
 // Keys carry a unique element index, so the grouping order inside a bucket never matters.
 #pragma once
 
@@ -132,19 +132,44 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
 }
 
 // Level 1b: scatter (key, segment-within-bucket) into the buckets.  The range of (bucket cb,
-// tile t) starts at bstart[cb] + rowoff[cb * ntiles + t].
+// tile t) starts at bstart[cb] + rowoff[cb * ntiles + t], where bstart is the exclusive scan
+// of the bucket totals: every workgroup scans btot (a few KB) itself, and workgroup 0 also
+// stores the scan (bstart[0..CB], bstart[CB] = total) for the kernels that follow.
 template <int NT, typename SRC>
 __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB, int64_t ntiles,
                                                      int64_t T1,
                                                      const uint32_t* __restrict__ rowoff,
-                                                     const int32_t* __restrict__ bstart,
+                                                     const uint32_t* __restrict__ btot,
+                                                     int32_t* __restrict__ bstart,
                                                      uint64_t* __restrict__ bkey,
                                                      uint32_t* __restrict__ bseg) {
   __shared__ uint32_t cur[kPartMaxBuckets];
+  __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
-  for (int i = threadIdx.x; i < CB; i += NT)
-    cur[i] = (uint32_t)bstart[i] + rowoff[(int64_t)i * ntiles + t];
+  {
+    constexpr int IPT = kPartMaxBuckets / NT;
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int i = threadIdx.x * IPT + q;
+      v[q] = i < CB ? btot[i] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = wg_excl_scan<NT>(sum, s_w, &tot);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int i = threadIdx.x * IPT + q;
+      if (i < CB) {
+        cur[i] = run + rowoff[(int64_t)i * ntiles + t];
+        if (t == 0) bstart[i] = (int32_t)run;
+      }
+      run += v[q];
+    }
+    if (t == 0 && threadIdx.x == 0) bstart[CB] = (int32_t)tot;
+  }
   __syncthreads();
   const uint32_t wmask = (1u << b) - 1u;
   const int64_t base = t * T1;
@@ -204,36 +229,6 @@ __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ t
   if (threadIdx.x == 0) btot[cb] = carry;
 }
 
-// Exclusive scan of n (a few thousand) counts by ONE workgroup: out[i] = sum in[0..i),
-// out[n] = total.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ in, int64_t n,
-                                                   int32_t* __restrict__ out) {
-  __shared__ uint32_t s_w[NT / kWave + 1];
-  constexpr int IPT = 8;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
-    uint32_t v[IPT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
-      v[q] = i < n ? in[i] : 0u;
-      sum += v[q];
-    }
-    uint32_t tot;
-    uint32_t run = carry + wg_excl_scan<NT>(sum, s_w, &tot);
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
-      if (i < n) out[i] = (int32_t)run;
-      run += v[q];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) out[n] = (int32_t)carry;
-}
-
 // ------------------------------------------------------------------------------------------
 // Level 2, fused with what follows it.  One workgroup per coarse bucket (bucket elements
 // bstarts[cb] .. bstarts[cb+1]).
@@ -242,25 +237,26 @@ __global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ 
 //                 order in binary64, drops zero sums, and writes the survivors compacted
 //                 within the bucket to temporaries (trow, tval at the bucket's own offset),
 //                 the bucket-relative column offsets to col_rel and the survivor count to
-//                 bkept[cb]; k_small_scan and k_part_emit then place them.
+//                 bkept[cb]; k_part_emit then places them.
 // A bucket of at most CAP elements stays in LDS from load to output (fast path); a larger
 // one goes through global staging: segment scatter, sort_segments, then fold_tile over
 // blocks of CAP keys.
-// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_pre[CAP+1] u32 |
-//              s_seg[CAP] u16 | s_flag[CAP] u8   (part_level2_lds_bytes)
+// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_seg[CAP] u16 |
+//              s_flag[CAP] u8   (part_level2_lds_bytes).  The fold's survivor prefix
+//              s_pre[CAP+1] u32 reuses s_key, which is dead once the bucket is sorted; at
+//              b = 7 this keeps a workgroup under 40 KB, four per CU.
 // ------------------------------------------------------------------------------------------
 __host__ __device__ inline size_t part_level2_lds_bytes(int b, int cap) {
   const size_t w = ((size_t)1 << b) + 1;
   size_t off = (w * 4 + 15) & ~(size_t)15;
   off += (size_t)cap * 8 * 2;
-  off += (((size_t)cap + 1) * 4 + 15) & ~(size_t)15;
   off += (((size_t)cap * 2) + 15) & ~(size_t)15;
   off += (size_t)cap;
   return off;
 }
 
 template <int NT, int CAP, bool PLAN, typename VT>
-__global__ __launch_bounds__(NT) void k_part_level2(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_part_level2(
     int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint64_t* __restrict__ bkey,
     const uint32_t* __restrict__ bseg, uint64_t* __restrict__ gkeys,
     uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
@@ -275,9 +271,9 @@ __global__ __launch_bounds__(NT) void k_part_level2(
   uint64_t* s_in = reinterpret_cast<uint64_t*>(smem + off);
   off += (size_t)CAP * 8;
   uint64_t* s_key = reinterpret_cast<uint64_t*>(smem + off);
+  uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + off);  // aliases s_key (see above)
+  static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
   off += (size_t)CAP * 8;
-  uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + off);
-  off += (((size_t)CAP + 1) * 4 + 15) & ~(size_t)15;
   uint16_t* s_seg = reinterpret_cast<uint16_t*>(smem + off);
   off += (((size_t)CAP * 2) + 15) & ~(size_t)15;
   uint8_t* s_flag = smem + off;
@@ -342,29 +338,47 @@ __global__ __launch_bounds__(NT) void k_part_level2(
 
   if (fast) {
     // ---- everything in LDS ----------------------------------------------------------------
-    for (int64_t i = threadIdx.x; i < m; i += NT) {
-      const uint32_t pos = atomicSub(&cnt[s_seg[i]], 1u) - 1u;
-      s_key[pos] = s_in[i];
-      s_flag[i] = 0;
+    // Group by segment: each element (load order) takes the next free slot of its segment;
+    // the thread keeps the (key, segment) of its elements for the ranking.
+    uint64_t ky[IPT];
+    uint32_t sg[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int64_t i = threadIdx.x + (int64_t)u * NT;
+      sg[u] = 0xffffffffu;
+      ky[u] = 0;
+      if (i < m) {
+        sg[u] = s_seg[i];
+        ky[u] = s_in[i];
+        const uint32_t pos = atomicSub(&cnt[sg[u]], 1u) - 1u;
+        s_key[pos] = ky[u];
+      }
     }
+    for (int64_t i = threadIdx.x; i < m; i += NT) s_flag[i] = 0;
     __syncthreads();
     if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;  // cnt[j] = start of segment j
+    __syncthreads();
     for (int64_t j = threadIdx.x; j < nW; j += NT) {
       const uint32_t lo = cnt[j];
       if (lo < (uint32_t)m) s_flag[lo] = 1;
     }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < m; i += NT) {
-      const uint64_t key = s_key[i];
-      int64_t lo = i;
-      while (!s_flag[lo]) --lo;
-      int r = 0;
-      int64_t j = lo;
-      do {
-        r += (s_key[j] < key) ? 1 : 0;
-        ++j;
-      } while (j < m && !s_flag[j]);
-      s_in[lo + r] = key;  // s_in now holds the bucket sorted by (segment, key)
+    // Rank each element among the keys of its segment (keys are unique, so the ranks are a
+    // permutation): the segment's bounds come from cnt, so the loads are independent and
+    // issued four at a time.
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      if (sg[u] != 0xffffffffu) {
+        const uint32_t lo = cnt[sg[u]], hi = cnt[sg[u] + 1];
+        const uint64_t key = ky[u];
+        uint32_t r = 0, q = lo;
+        for (; q + 4 <= hi; q += 4) {
+          const uint64_t k0 = s_key[q], k1 = s_key[q + 1], k2 = s_key[q + 2], k3 = s_key[q + 3];
+          r += (uint32_t)(k0 < key) + (uint32_t)(k1 < key) + (uint32_t)(k2 < key) +
+               (uint32_t)(k3 < key);
+        }
+        for (; q < hi; ++q) r += (uint32_t)(s_key[q] < key);
+        s_in[lo + r] = key;  // s_in now holds the bucket sorted by (segment, key)
+      }
     }
     __syncthreads();
     if (PLAN) {
@@ -375,37 +389,47 @@ __global__ __launch_bounds__(NT) void k_part_level2(
       }
       return;
     }
-    // fold: thread owns IPT consecutive positions; the first value of every run is gathered
-    // for all of them at once, then each run is folded in order
+    // Fold.  Every element's value is gathered once, all of a thread's loads in flight, into
+    // LDS (s_val reuses s_key, dead after the ranking); then each thread takes IPT
+    // consecutive positions and folds every run that starts there, from LDS, in key order
+    // (= input order within a run).
+    double* s_val = reinterpret_cast<double*>(s_key);
+    static_assert(sizeof(double) <= sizeof(uint64_t), "s_val must fit in s_key");
+    {
+      VT v[IPT];
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const int64_t i = threadIdx.x + (int64_t)u * NT;
+        if (i < m) v[u] = val[(uint32_t)s_in[i]];
+      }
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const int64_t i = threadIdx.x + (int64_t)u * NT;
+        if (i < m) s_val[i] = to_acc<double>(v[u]);
+      }
+    }
+    __syncthreads();
     uint32_t rows[IPT];
     double sums[IPT];
-    bool head[IPT];
+    uint32_t mask = 0;
 #pragma unroll
     for (int s = 0; s < IPT; ++s) {
       const int64_t li = (int64_t)threadIdx.x * IPT + s;
-      head[s] = false;
       rows[s] = 0;
       sums[s] = 0.0;
       if (li < m) {
         const uint64_t key = s_in[li];
         rows[s] = key_row(key);
-        head[s] = s_flag[li] || key_row(s_in[li - 1]) != rows[s];
-        if (head[s]) sums[s] = to_acc<double>(val[(uint32_t)key]);
-      }
-    }
-    uint32_t mask = 0;
-#pragma unroll
-    for (int s = 0; s < IPT; ++s) {
-      if (head[s]) {
-        const int64_t li = (int64_t)threadIdx.x * IPT + s;
-        double acc = sums[s];
-        for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
-          const uint64_t k2 = s_in[j];
-          if (key_row(k2) != rows[s]) break;
-          acc = acc + to_acc<double>(val[(uint32_t)k2]);
+        const bool head = s_flag[li] || key_row(s_in[li - 1]) != rows[s];
+        if (head) {
+          double acc = s_val[li];
+          for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
+            if (key_row(s_in[j]) != rows[s]) break;
+            acc = acc + s_val[j];
+          }
+          sums[s] = acc;
+          if (acc != 0.0) mask |= 1u << s;
         }
-        sums[s] = acc;
-        if (acc != 0.0) mask |= 1u << s;
       }
     }
     uint32_t kept;
@@ -513,23 +537,32 @@ __global__ __launch_bounds__(NT) void k_part_level2(
   if (threadIdx.x == 0) bkept[cb] = running;
 }
 
-// After the scan of the per-bucket survivor counts (boff[cb], boff[CB] = nnz_out): move each
-// bucket's survivors from the temporaries to their final place (rounded once to the output
-// type), turn the bucket-relative column offsets into col_ptr, and finish col_ptr / info.
+// Place each bucket's survivors: the bucket's output offset is the sum of the survivor
+// counts of the buckets before it (each workgroup reduces bkept[0..cb) itself; the last one
+// also takes its own, giving nnz_out).  Moves the survivors from the temporaries to their
+// final place (rounded once to the output type), turns the bucket-relative column offsets
+// into col_ptr, and finishes col_ptr / info.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nseg,
                                                   const int32_t* __restrict__ bstarts,
-                                                  const int32_t* __restrict__ boff,
+                                                  const uint32_t* __restrict__ bkept,
                                                   const uint32_t* __restrict__ trow,
                                                   const double* __restrict__ tval,
                                                   int32_t* __restrict__ col_ptr,
                                                   int32_t* __restrict__ row_idx,
                                                   void* __restrict__ val_out, int out_f64,
                                                   int32_t* __restrict__ info) {
+  __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t cb = blockIdx.x;
+  const bool last = cb == (int64_t)CB - 1;
+  const int64_t lim = last ? CB : cb;
+  uint32_t part = 0;
+  for (int64_t i = threadIdx.x; i < lim; i += NT) part += bkept[i];
+  uint32_t tot;
+  (void)wg_excl_scan<NT>(part, s_w, &tot);
   const int64_t src0 = bstarts[cb];
-  const int64_t dst0 = boff[cb];
-  const int64_t kept = (int64_t)boff[cb + 1] - dst0;
+  const int64_t kept = bkept[cb];
+  const int64_t dst0 = last ? (int64_t)tot - kept : (int64_t)tot;
   for (int64_t i = threadIdx.x; i < kept; i += NT) {
     row_idx[dst0 + i] = (int32_t)trow[src0 + i];
     if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
@@ -539,9 +572,9 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   const int64_t rem = nseg - seg0;
   const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
   for (int64_t j = threadIdx.x; j < nW; j += NT) col_ptr[seg0 + j] += (int32_t)dst0;
-  if (cb == CB - 1 && threadIdx.x == 0) {
-    col_ptr[nseg] = boff[CB];
-    info[0] = boff[CB];
+  if (last && threadIdx.x == 0) {
+    col_ptr[nseg] = (int32_t)tot;
+    info[0] = (int32_t)tot;
   }
 }
 
