@@ -86,7 +86,7 @@ spm_status launch_status() {
 // bucket when the sizes allow it.  Returns ok = false when no b <= 12 fits (more than
 // kPartMaxBuckets * kPartMaxWidth segments); then the atomic-histogram path is used.
 // ------------------------------------------------------------------------------------------
-constexpr int kPartNT = 256;
+constexpr int kPartNT = 1024;  // level-1 workgroup (hist, scatter): long per-bucket runs
 constexpr int kPartCap = 2048;  // bucket size kept entirely in LDS by the fused level 2
 
 struct PartParams {
@@ -143,7 +143,7 @@ struct AsmLayout {
   // shared
   size_t bucket, scratch;
   // partition path
-  size_t table, rowoff, btot, bstart, bkey, bseg, trow, tval, bkept;
+  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept;
   size_t total;
   int64_t fold_tiles;
 };
@@ -172,8 +172,8 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.rowoff = c.take(sizeof(uint32_t) * (size_t)tab);
   L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
   L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
-  L.bkey = c.take(sizeof(uint64_t) * (size_t)nP);
-  L.bseg = c.take(sizeof(uint32_t) * (size_t)nP);
+  L.brec = c.take(16 * (size_t)nP);               // bucket records (key, segment, value word)
+  L.bvhi = c.take(sizeof(uint32_t) * (size_t)nP);  // high words of float64 values
   L.trow = c.take(sizeof(uint32_t) * (size_t)nP);
   L.tval = c.take(sizeof(double) * (size_t)nP);
   L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
@@ -184,7 +184,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
 struct PlanLayout {
   PartParams pp;
   size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
-  size_t colarr, table, rowoff, btot, bstart, bkey, bseg, total;
+  size_t colarr, table, rowoff, btot, bstart, brec, total;
   int64_t sort_tiles;
 };
 
@@ -210,8 +210,7 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
   L.rowoff = c.take(sizeof(uint32_t) * (size_t)tab);
   L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
   L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
-  L.bkey = c.take(sizeof(uint64_t) * (size_t)nP);
-  L.bseg = c.take(sizeof(uint32_t) * (size_t)nP);
+  L.brec = c.take(16 * (size_t)nP);
   L.total = c.off;
   return L;
 }
@@ -396,8 +395,8 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
     uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
     int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
-    uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
-    uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
+    uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
+    uint32_t* bvhi = reinterpret_cast<uint32_t*>(w + L.bvhi);
     uint32_t* trow = reinterpret_cast<uint32_t*>(w + L.trow);
     double* tval = reinterpret_cast<double*>(w + L.tval);
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
@@ -406,16 +405,19 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
                        dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, info);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s,
                        (const uint32_t*)table, P.ntiles, rowoff, btot);
-    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
-                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1,
-                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, bkey, bseg);
     const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
 #define SPM_L2(VT)                                                                             \
+  do {                                                                                         \
+  hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo, VT>), dim3((unsigned)P.ntiles),       \
+                     dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1,                       \
+                     (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, brec,              \
+                     static_cast<const VT*>(val), bvhi);                                        \
   hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, false, VT>), dim3((unsigned)P.CB), dim3(kNT), \
-                     lds, s, P.b, n_cols, (const int32_t*)bstart, (const uint64_t*)bkey,       \
-                     (const uint32_t*)bseg, bucket, scratch, (int32_t*)nullptr,               \
+                     lds, s, P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec,          \
+                     (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,               \
                      (int32_t*)nullptr, (int32_t*)nullptr, static_cast<const VT*>(val),        \
-                     col_ptr, trow, tval, bkept)
+                     col_ptr, trow, tval, bkept);                                              \
+  } while (0)
     if (val_type == SPM_F64) SPM_L2(double);
     else if (val_type == SPM_F32) SPM_L2(float);
     else SPM_L2(bf16_t);
@@ -512,8 +514,7 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
     uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
     int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
-    uint64_t* bkey = reinterpret_cast<uint64_t*>(w + L.bkey);
-    uint32_t* bseg = reinterpret_cast<uint32_t*>(w + L.bseg);
+    uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
     hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(grid_for(n_cols > 0 ? n_cols : 1, kNT, cap)),
                        dim3(kNT), 0, s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
@@ -522,12 +523,13 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                        (int32_t*)nullptr);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
                        (const uint32_t*)table, Q.ntiles, rowoff, btot);
-    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
+    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc, float>), dim3((unsigned)Q.ntiles),
                        dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1,
-                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, bkey, bseg);
+                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, brec,
+                       (const float*)nullptr, (uint32_t*)nullptr);
     hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, true, float>), dim3((unsigned)Q.CB),
                        dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s, Q.b, n_rows,
-                       (const int32_t*)bstart, (const uint64_t*)bkey, (const uint32_t*)bseg,
+                       (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)nullptr,
                        bucket, scratch, row_ptr, col_t, perm, (const float*)nullptr,
                        (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
                        (uint32_t*)nullptr);

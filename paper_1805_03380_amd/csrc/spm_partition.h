@@ -131,39 +131,75 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
   if (bad && info) set_status(info, kStBounds);
 }
 
-// Level 1b: scatter (key, segment-within-bucket) into the buckets.  The range of (bucket cb,
+// One element in a coarse bucket is one 16-byte record, so the scatter issues a single
+// store per element (the scatter is bound by the number of scattered stores, not bytes):
+// x, y = low and high word of the key, z = segment within the bucket, w = the value's low
+// word (all of a float32 or bfloat16 value; a float64 value's high word goes to bvhi).
+template <typename VT> struct ValWords;
+template <> struct ValWords<float> {
+  static constexpr bool kHi = false;
+  __device__ __forceinline__ static uint32_t lo(float v) { return __float_as_uint(v); }
+  __device__ __forceinline__ static uint32_t hi(float) { return 0u; }
+  __device__ __forceinline__ static float make(uint32_t l, uint32_t) { return __uint_as_float(l); }
+};
+template <> struct ValWords<double> {
+  static constexpr bool kHi = true;
+  __device__ __forceinline__ static uint32_t lo(double v) { return (uint32_t)__double2loint(v); }
+  __device__ __forceinline__ static uint32_t hi(double v) { return (uint32_t)__double2hiint(v); }
+  __device__ __forceinline__ static double make(uint32_t l, uint32_t h) {
+    return __hiloint2double((int)h, (int)l);
+  }
+};
+template <> struct ValWords<bf16_t> {
+  static constexpr bool kHi = false;
+  __device__ __forceinline__ static uint32_t lo(bf16_t v) { return (uint32_t)v; }
+  __device__ __forceinline__ static uint32_t hi(bf16_t) { return 0u; }
+  __device__ __forceinline__ static bf16_t make(uint32_t l, uint32_t) { return (bf16_t)l; }
+};
+__device__ __forceinline__ uint64_t rec_key(const uint4& r) {
+  return ((uint64_t)r.y << 32) | r.x;
+}
+
+// Level 1b: scatter the elements' records into the buckets.  The range of (bucket cb,
 // tile t) starts at bstart[cb] + rowoff[cb * ntiles + t], where bstart is the exclusive scan
 // of the bucket totals: every workgroup scans btot (a few KB) itself, and workgroup 0 also
 // stores the scan (bstart[0..CB], bstart[CB] = total) for the kernels that follow.
-template <int NT, typename SRC>
+// With vin != nullptr each element's value travels in its record: read here in input order,
+// coalesced, instead of gathered one cache line per element later.
+template <int NT, typename SRC, typename VT>
 __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB, int64_t ntiles,
                                                      int64_t T1,
                                                      const uint32_t* __restrict__ rowoff,
                                                      const uint32_t* __restrict__ btot,
                                                      int32_t* __restrict__ bstart,
-                                                     uint64_t* __restrict__ bkey,
-                                                     uint32_t* __restrict__ bseg) {
+                                                     uint4* __restrict__ brec,
+                                                     const VT* __restrict__ vin,
+                                                     uint32_t* __restrict__ bvhi) {
   __shared__ uint32_t cur[kPartMaxBuckets];
   __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
   {
+    // blocked: thread tid takes buckets [tid*ipt, tid*ipt + ipt); both loads in flight at once
     constexpr int IPT = kPartMaxBuckets / NT;
-    uint32_t v[IPT];
+    const int ipt = (CB + NT - 1) / NT;
+    uint32_t v[IPT], ro[IPT];
     uint32_t sum = 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      const int i = threadIdx.x * IPT + q;
-      v[q] = i < CB ? btot[i] : 0u;
+      const int i = threadIdx.x * ipt + q;
+      const bool in = q < ipt && i < CB;
+      v[q] = in ? btot[i] : 0u;
+      ro[q] = in ? rowoff[(int64_t)i * ntiles + t] : 0u;
       sum += v[q];
     }
     uint32_t tot;
     uint32_t run = wg_excl_scan<NT>(sum, s_w, &tot);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      const int i = threadIdx.x * IPT + q;
-      if (i < CB) {
-        cur[i] = run + rowoff[(int64_t)i * ntiles + t];
+      const int i = threadIdx.x * ipt + q;
+      if (q < ipt && i < CB) {
+        cur[i] = run + ro[q];
         if (t == 0) bstart[i] = (int32_t)run;
       }
       run += v[q];
@@ -175,21 +211,25 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
   const int64_t base = t * T1;
   const int64_t end = (base + T1 < n) ? base + T1 : n;
   constexpr int U = 4;
+  const bool carry = vin != nullptr;
   for (int64_t e0 = base + threadIdx.x; e0 < end; e0 += (int64_t)NT * U) {
     uint32_t seg[U];
     uint64_t key[U];
+    VT v[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + (int64_t)u * NT;
       ok[u] = (e < end) ? src.elem(e, seg[u], key[u]) : false;
+      if (carry && e < end) v[u] = vin[e];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (ok[u]) {
         const uint32_t pos = atomicAdd(&cur[seg[u] >> b], 1u);
-        bkey[pos] = key[u];
-        bseg[pos] = seg[u] & wmask;
+        const uint32_t vlo = carry ? ValWords<VT>::lo(v[u]) : 0u;
+        brec[pos] = make_uint4((uint32_t)key[u], (uint32_t)(key[u] >> 32), seg[u] & wmask, vlo);
+        if (ValWords<VT>::kHi && carry) bvhi[pos] = ValWords<VT>::hi(v[u]);
       }
     }
   }
@@ -241,242 +281,258 @@ __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ t
 // A bucket of at most CAP elements stays in LDS from load to output (fast path); a larger
 // one goes through global staging: segment scatter, sort_segments, then fold_tile over
 // blocks of CAP keys.
-// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_seg[CAP] u16 |
-//              s_flag[CAP] u8   (part_level2_lds_bytes).  The fold's survivor prefix
-//              s_pre[CAP+1] u32 reuses s_key, which is dead once the bucket is sorted; at
-//              b = 7 this keeps a workgroup under 40 KB, four per CU.
+// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_flag[CAP] u8
+//              (part_level2_lds_bytes).  The fold's values s_val[CAP] f64 and survivor
+//              prefix s_pre[CAP+1] u32 reuse s_key, which is dead once the bucket is sorted;
+//              at b = 7 a workgroup takes about 35 KB, four per CU.
+// In the fast path every thread keeps the key, segment (and, folding, the value) of its
+// elements i = tid + u*NT in registers from the first load to the ranking; the value gather
+// is issued before the counting so that its latency overlaps the LDS work.
 // ------------------------------------------------------------------------------------------
 __host__ __device__ inline size_t part_level2_lds_bytes(int b, int cap) {
   const size_t w = ((size_t)1 << b) + 1;
   size_t off = (w * 4 + 15) & ~(size_t)15;
   off += (size_t)cap * 8 * 2;
-  off += (((size_t)cap * 2) + 15) & ~(size_t)15;
   off += (size_t)cap;
   return off;
 }
 
-template <int NT, int CAP, bool PLAN, typename VT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_part_level2(
-    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint64_t* __restrict__ bkey,
-    const uint32_t* __restrict__ bseg, uint64_t* __restrict__ gkeys,
-    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
-    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel,
-    uint32_t* __restrict__ trow, double* __restrict__ tval, uint32_t* __restrict__ bkept) {
-  constexpr int IPT = CAP / NT;
-  static_assert(IPT * NT == CAP, "CAP must be a multiple of the workgroup size");
-  extern __shared__ __align__(16) unsigned char smem[];
-  const size_t wcnt = ((size_t)1 << b) + 1;
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
-  size_t off = (wcnt * 4 + 15) & ~(size_t)15;
-  uint64_t* s_in = reinterpret_cast<uint64_t*>(smem + off);
-  off += (size_t)CAP * 8;
-  uint64_t* s_key = reinterpret_cast<uint64_t*>(smem + off);
-  uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + off);  // aliases s_key (see above)
-  static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
-  off += (size_t)CAP * 8;
-  uint16_t* s_seg = reinterpret_cast<uint16_t*>(smem + off);
-  off += (((size_t)CAP * 2) + 15) & ~(size_t)15;
-  uint8_t* s_flag = smem + off;
-  __shared__ uint32_t s_w[NT / kWave + 1];
-  __shared__ int64_t s_b[3];
+// What one level-2 workgroup sees of its bucket.
+struct L2Bucket {
+  int64_t cb, bstart, bend, m, seg0, nW, nseg;
+  bool last_bucket;
+};
 
-  const int64_t cb = blockIdx.x;
-  const int64_t bstart = bstarts[cb];
-  const int64_t bend = bstarts[cb + 1];
-  const int64_t m = bend - bstart;
-  const int64_t seg0 = cb << b;
-  const int64_t rem = nseg - seg0;
-  const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
-  const bool last_bucket = seg0 + nW >= nseg;
-  constexpr int U = 8;
+// LDS views of the dynamic shared memory (layout as in part_level2_lds_bytes).
+template <int CAP>
+struct L2Lds {
+  uint32_t* cnt;
+  uint64_t* s_in;
+  uint64_t* s_key;
+  uint8_t* s_flag;
+  __device__ __forceinline__ L2Lds(unsigned char* smem, int b) {
+    const size_t wcnt = ((size_t)1 << b) + 1;
+    size_t off = (wcnt * 4 + 15) & ~(size_t)15;
+    cnt = reinterpret_cast<uint32_t*>(smem);
+    s_in = reinterpret_cast<uint64_t*>(smem + off);
+    off += (size_t)CAP * 8;
+    s_key = reinterpret_cast<uint64_t*>(smem + off);
+    off += (size_t)CAP * 8;
+    s_flag = smem + off;
+  }
+};
+
+// PLAN: row_ptr of the bucket's rows from the inclusive counts (cnt[j] = end of row j).
+template <int NT>
+__device__ __forceinline__ void l2_row_ptr(const L2Bucket& B, const uint32_t* cnt,
+                                           int32_t* __restrict__ row_ptr) {
+  for (int64_t j = threadIdx.x; j < B.nW; j += NT)
+    row_ptr[B.seg0 + j] = (int32_t)(B.bstart + (j == 0 ? 0 : (int64_t)cnt[j - 1]));
+  if (B.last_bucket && threadIdx.x == 0) row_ptr[B.nseg] = (int32_t)B.bend;
+}
+
+// Fast path (m <= CAP): the whole bucket stays in LDS from load to output.
+template <int NT, int CAP, bool PLAN, typename VT>
+__device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, uint32_t* s_w,
+                                        const uint4* __restrict__ brec,
+                                        const uint32_t* __restrict__ bvhi,
+                                        int32_t* __restrict__ row_ptr,
+                                        int32_t* __restrict__ col_t, int32_t* __restrict__ perm,
+                                        int32_t* __restrict__ col_rel,
+                                        uint32_t* __restrict__ trow, double* __restrict__ tval,
+                                        uint32_t* __restrict__ bkept) {
+  constexpr int IPT = CAP / NT;
+  const int64_t m = B.m, nW = B.nW;
+  uint32_t* cnt = L.cnt;
+  uint64_t* s_in = L.s_in;
+  uint64_t* s_key = L.s_key;
+  uint8_t* s_flag = L.s_flag;
 
   for (int64_t j = threadIdx.x; j <= nW; j += NT) cnt[j] = 0;
-  const bool fast = m <= CAP;
-  if (fast) {
-    for (int64_t i0 = threadIdx.x; i0 < m; i0 += (int64_t)NT * U) {
-      uint64_t ky[U];
-      uint32_t sg[U];
+  uint64_t ky[IPT];
+  uint32_t sg[IPT];
+  VT vv[IPT];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + (int64_t)u * NT;
-        ky[u] = i < m ? bkey[bstart + i] : 0ull;
-        sg[u] = i < m ? bseg[bstart + i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + (int64_t)u * NT;
-        if (i < m) {
-          s_in[i] = ky[u];
-          s_seg[i] = (uint16_t)sg[u];
-        }
-      }
-    }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < m; i += NT) atomicAdd(&cnt[s_seg[i]], 1u);
-  } else {
-    __syncthreads();
-    for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
-      uint32_t sg[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = e0 + (int64_t)u * NT;
-        sg[u] = (e < bend) ? bseg[e] : 0xffffffffu;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (sg[u] != 0xffffffffu) atomicAdd(&cnt[sg[u]], 1u);
+  for (int u = 0; u < IPT; ++u) {
+    const int64_t i = threadIdx.x + (int64_t)u * NT;
+    ky[u] = 0ull;
+    sg[u] = 0xffffffffu;
+    if (i < m) {
+      const uint4 r = brec[B.bstart + i];
+      ky[u] = rec_key(r);
+      sg[u] = r.z;
+      if (!PLAN) vv[u] = ValWords<VT>::make(r.w, ValWords<VT>::kHi ? bvhi[B.bstart + i] : 0u);
     }
   }
+  __syncthreads();  // cnt cleared
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+    if (sg[u] != 0xffffffffu) atomicAdd(&cnt[sg[u]], 1u);
   __syncthreads();
   wg_inclusive_scan_inplace<NT>(cnt, nW, s_w);  // cnt[j] = end of segment j (relative)
-  if (PLAN) {
-    for (int64_t j = threadIdx.x; j < nW; j += NT)
-      row_ptr[seg0 + j] = (int32_t)(bstart + (j == 0 ? 0 : (int64_t)cnt[j - 1]));
-    if (last_bucket && threadIdx.x == 0) row_ptr[nseg] = (int32_t)bend;
-  }
+  if (PLAN) l2_row_ptr<NT>(B, cnt, row_ptr);
   __syncthreads();
 
-  if (fast) {
-    // ---- everything in LDS ----------------------------------------------------------------
-    // Group by segment: each element (load order) takes the next free slot of its segment;
-    // the thread keeps the (key, segment) of its elements for the ranking.
-    uint64_t ky[IPT];
-    uint32_t sg[IPT];
+  // Group by segment: each element takes the next free slot of its segment.
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int64_t i = threadIdx.x + (int64_t)u * NT;
-      sg[u] = 0xffffffffu;
-      ky[u] = 0;
-      if (i < m) {
-        sg[u] = s_seg[i];
-        ky[u] = s_in[i];
-        const uint32_t pos = atomicSub(&cnt[sg[u]], 1u) - 1u;
-        s_key[pos] = ky[u];
+  for (int u = 0; u < IPT; ++u) {
+    if (sg[u] != 0xffffffffu) {
+      const uint32_t pos = atomicSub(&cnt[sg[u]], 1u) - 1u;
+      s_key[pos] = ky[u];
+    }
+  }
+  for (int64_t i = threadIdx.x; i < m; i += NT) s_flag[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;  // cnt[j] = start of segment j
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < nW; j += NT) {
+    const uint32_t lo = cnt[j];
+    if (lo < (uint32_t)m) s_flag[lo] = 1;
+  }
+  // Rank each element among the keys of its segment (keys are unique, so the ranks are a
+  // permutation): the segment's bounds come from cnt, so the loads are independent and
+  // issued four at a time.
+  uint32_t dst[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    dst[u] = 0;
+    if (sg[u] != 0xffffffffu) {
+      const uint32_t lo = cnt[sg[u]], hi = cnt[sg[u] + 1];
+      const uint64_t key = ky[u];
+      uint32_t r = 0, q = lo;
+      for (; q + 4 <= hi; q += 4) {
+        const uint64_t k0 = s_key[q], k1 = s_key[q + 1], k2 = s_key[q + 2], k3 = s_key[q + 3];
+        r += (uint32_t)(k0 < key) + (uint32_t)(k1 < key) + (uint32_t)(k2 < key) +
+             (uint32_t)(k3 < key);
       }
+      for (; q < hi; ++q) r += (uint32_t)(s_key[q] < key);
+      dst[u] = lo + r;
+      s_in[lo + r] = key;  // s_in now holds the bucket sorted by (segment, key)
     }
-    for (int64_t i = threadIdx.x; i < m; i += NT) s_flag[i] = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;  // cnt[j] = start of segment j
-    __syncthreads();
-    for (int64_t j = threadIdx.x; j < nW; j += NT) {
-      const uint32_t lo = cnt[j];
-      if (lo < (uint32_t)m) s_flag[lo] = 1;
+  }
+  __syncthreads();
+  if (PLAN) {
+    for (int64_t i = threadIdx.x; i < m; i += NT) {
+      const uint64_t key = s_in[i];
+      col_t[B.bstart + i] = (int32_t)(key >> 32);
+      perm[B.bstart + i] = (int32_t)(uint32_t)key;
     }
-    // Rank each element among the keys of its segment (keys are unique, so the ranks are a
-    // permutation): the segment's bounds come from cnt, so the loads are independent and
-    // issued four at a time.
+    return;
+  }
+  // Fold.  Each element's value (loaded with its key) goes to its sorted position in s_val
+  // (reusing s_key, dead after the ranking).  Each thread then takes IPT consecutive
+  // positions and folds every run that starts there, from LDS, in key order (= input order
+  // within a run); the sum replaces the value at the run's head, which no other thread reads.
+  double* s_val = reinterpret_cast<double*>(s_key);
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      if (sg[u] != 0xffffffffu) {
-        const uint32_t lo = cnt[sg[u]], hi = cnt[sg[u] + 1];
-        const uint64_t key = ky[u];
-        uint32_t r = 0, q = lo;
-        for (; q + 4 <= hi; q += 4) {
-          const uint64_t k0 = s_key[q], k1 = s_key[q + 1], k2 = s_key[q + 2], k3 = s_key[q + 3];
-          r += (uint32_t)(k0 < key) + (uint32_t)(k1 < key) + (uint32_t)(k2 < key) +
-               (uint32_t)(k3 < key);
+  for (int u = 0; u < IPT; ++u)
+    if (sg[u] != 0xffffffffu) s_val[dst[u]] = to_acc<double>(vv[u]);
+  __syncthreads();
+  uint32_t mask = 0;
+#pragma unroll
+  for (int s = 0; s < IPT; ++s) {
+    const int64_t li = (int64_t)threadIdx.x * IPT + s;
+    if (li < m) {
+      const uint32_t row = key_row(s_in[li]);
+      const bool head = s_flag[li] || key_row(s_in[li - 1]) != row;
+      if (head) {
+        double acc = s_val[li];
+        for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
+          if (key_row(s_in[j]) != row) break;
+          acc = acc + s_val[j];
         }
-        for (; q < hi; ++q) r += (uint32_t)(s_key[q] < key);
-        s_in[lo + r] = key;  // s_in now holds the bucket sorted by (segment, key)
+        s_val[li] = acc;
+        if (acc != 0.0) mask |= 1u << s;
       }
     }
-    __syncthreads();
-    if (PLAN) {
-      for (int64_t i = threadIdx.x; i < m; i += NT) {
-        const uint64_t key = s_in[i];
-        col_t[bstart + i] = (int32_t)(key >> 32);
-        perm[bstart + i] = (int32_t)(uint32_t)key;
-      }
-      return;
-    }
-    // Fold.  Every element's value is gathered once, all of a thread's loads in flight, into
-    // LDS (s_val reuses s_key, dead after the ranking); then each thread takes IPT
-    // consecutive positions and folds every run that starts there, from LDS, in key order
-    // (= input order within a run).
-    double* s_val = reinterpret_cast<double*>(s_key);
-    static_assert(sizeof(double) <= sizeof(uint64_t), "s_val must fit in s_key");
-    {
-      VT v[IPT];
+  }
+  uint32_t kept;
+  const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &kept);
+  {
+    int64_t o = B.bstart + excl;
 #pragma unroll
-      for (int u = 0; u < IPT; ++u) {
-        const int64_t i = threadIdx.x + (int64_t)u * NT;
-        if (i < m) v[u] = val[(uint32_t)s_in[i]];
-      }
-#pragma unroll
-      for (int u = 0; u < IPT; ++u) {
-        const int64_t i = threadIdx.x + (int64_t)u * NT;
-        if (i < m) s_val[i] = to_acc<double>(v[u]);
+    for (int s = 0; s < IPT; ++s) {
+      if ((mask >> s) & 1u) {
+        const int64_t li = (int64_t)threadIdx.x * IPT + s;
+        trow[o] = key_row(s_in[li]);
+        tval[o] = s_val[li];
+        ++o;
       }
     }
-    __syncthreads();
-    uint32_t rows[IPT];
-    double sums[IPT];
-    uint32_t mask = 0;
+  }
+  __syncthreads();  // s_val is read; the survivor prefix s_pre takes its place
+  uint32_t* s_pre = reinterpret_cast<uint32_t*>(s_key);
+  {
+    uint32_t run = excl;
 #pragma unroll
     for (int s = 0; s < IPT; ++s) {
       const int64_t li = (int64_t)threadIdx.x * IPT + s;
-      rows[s] = 0;
-      sums[s] = 0.0;
-      if (li < m) {
-        const uint64_t key = s_in[li];
-        rows[s] = key_row(key);
-        const bool head = s_flag[li] || key_row(s_in[li - 1]) != rows[s];
-        if (head) {
-          double acc = s_val[li];
-          for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
-            if (key_row(s_in[j]) != rows[s]) break;
-            acc = acc + s_val[j];
-          }
-          sums[s] = acc;
-          if (acc != 0.0) mask |= 1u << s;
-        }
-      }
+      if (li < m) s_pre[li] = run;
+      run += (mask >> s) & 1u;
     }
-    uint32_t kept;
-    const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &kept);
-    {
-      uint32_t run = excl;
-#pragma unroll
-      for (int s = 0; s < IPT; ++s) {
-        const int64_t li = (int64_t)threadIdx.x * IPT + s;
-        if (li < m) s_pre[li] = run;
-        run += (mask >> s) & 1u;
-      }
-      if (threadIdx.x == 0) s_pre[m] = kept;
-    }
-    __syncthreads();
-    {
-      int64_t o = bstart + excl;
-#pragma unroll
-      for (int s = 0; s < IPT; ++s) {
-        if ((mask >> s) & 1u) {
-          trow[o] = rows[s];
-          tval[o] = sums[s];
-          ++o;
-        }
-      }
-    }
-    for (int64_t j = threadIdx.x; j < nW; j += NT) col_rel[seg0 + j] = (int32_t)s_pre[cnt[j]];
-    if (threadIdx.x == 0) bkept[cb] = kept;
-    return;
+    if (threadIdx.x == 0) s_pre[m] = kept;
   }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < nW; j += NT) col_rel[B.seg0 + j] = (int32_t)s_pre[cnt[j]];
+  if (threadIdx.x == 0) bkept[B.cb] = kept;
+}
 
-  // ---- large bucket: global staging ---------------------------------------------------------
-  uint64_t* gk = gkeys + bstart;
+// Slow path (m > CAP): segment scatter through global staging, sort_segments, then
+// fold_tile over blocks of CAP keys.
+template <int NT, int CAP, bool PLAN, typename VT>
+__device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, uint32_t* s_w,
+                                        int64_t* s_b, const uint4* __restrict__ brec,
+                                        uint64_t* __restrict__ gkeys,
+                                        uint64_t* __restrict__ scratch,
+                                        int32_t* __restrict__ row_ptr,
+                                        int32_t* __restrict__ col_t, int32_t* __restrict__ perm,
+                                        const VT* __restrict__ val,
+                                        int32_t* __restrict__ col_rel,
+                                        uint32_t* __restrict__ trow, double* __restrict__ tval,
+                                        uint32_t* __restrict__ bkept) {
+  constexpr int IPT = CAP / NT;
+  constexpr int U = 8;
+  const int64_t m = B.m, nW = B.nW, bstart = B.bstart, bend = B.bend;
+  uint32_t* cnt = L.cnt;
+  uint64_t* s_in = L.s_in;
+  uint32_t* s_pre = reinterpret_cast<uint32_t*>(L.s_key);
+  for (int64_t j = threadIdx.x; j <= nW; j += NT) cnt[j] = 0;
+  __syncthreads();
   for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
-    uint32_t sg[U];
-    uint64_t ky[U];
+    uint32_t gs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + (int64_t)u * NT;
-      sg[u] = (e < bend) ? bseg[e] : 0xffffffffu;
-      ky[u] = (e < bend) ? bkey[e] : 0ull;
+      gs[u] = (e < bend) ? brec[e].z : 0xffffffffu;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (gs[u] != 0xffffffffu) atomicAdd(&cnt[gs[u]], 1u);
+  }
+  __syncthreads();
+  wg_inclusive_scan_inplace<NT>(cnt, nW, s_w);  // cnt[j] = end of segment j (relative)
+  if (PLAN) l2_row_ptr<NT>(B, cnt, row_ptr);
+  __syncthreads();
+  uint64_t* gk = gkeys + bstart;
+  for (int64_t e0 = bstart + threadIdx.x; e0 < bend; e0 += (int64_t)NT * U) {
+    uint32_t gs[U];
+    uint64_t gy[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * NT;
+      gs[u] = 0xffffffffu;
+      gy[u] = 0ull;
+      if (e < bend) {
+        const uint4 r = brec[e];
+        gs[u] = r.z;
+        gy[u] = rec_key(r);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (sg[u] != 0xffffffffu) {
-        const uint32_t pos = atomicSub(&cnt[sg[u]], 1u) - 1u;
-        gk[pos] = ky[u];
+      if (gs[u] != 0xffffffffu) {
+        const uint32_t pos = atomicSub(&cnt[gs[u]], 1u) - 1u;
+        gk[pos] = gy[u];
       }
     }
   }
@@ -484,7 +540,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;
   __syncthreads();
   sort_segments<NT, CAP, PLAN>(gk, cnt, 0, nW, scratch + bstart, PLAN ? col_t + bstart : col_t,
-                               PLAN ? perm + bstart : perm, s_key, s_flag, &s_b[0]);
+                               PLAN ? perm + bstart : perm, L.s_key, L.s_flag, s_b);
   if (PLAN) return;
   __syncthreads();
   // one pass over blocks of CAP sorted (tagged) keys: fold, compact into the temporaries
@@ -529,12 +585,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (j >= nW) continue;  // cnt[nW] = m marks the bucket end, not a column
       int64_t p = (int64_t)cnt[j] - base;
       if (p > nb) p = nb;
-      col_rel[seg0 + j] = (int32_t)(running + s_pre[p]);
+      col_rel[B.seg0 + j] = (int32_t)(running + s_pre[p]);
     }
     running += blk;
     __syncthreads();
   }
-  if (threadIdx.x == 0) bkept[cb] = running;
+  if (threadIdx.x == 0) bkept[B.cb] = running;
+}
+
+template <int NT, int CAP, bool PLAN, typename VT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_part_level2(
+    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
+    const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
+    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
+    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
+    uint32_t* __restrict__ bkept) {
+  static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
+  static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_b[3];
+  const L2Lds<CAP> L(smem, b);
+  L2Bucket B;
+  B.cb = blockIdx.x;
+  B.bstart = bstarts[B.cb];
+  B.bend = bstarts[B.cb + 1];
+  B.m = B.bend - B.bstart;
+  B.seg0 = B.cb << b;
+  B.nseg = nseg;
+  const int64_t rem = nseg - B.seg0;
+  B.nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
+  B.last_bucket = B.seg0 + B.nW >= nseg;
+  if (B.m <= CAP)
+    l2_fast<NT, CAP, PLAN, VT>(B, L, s_w, brec, bvhi, row_ptr, col_t, perm, col_rel, trow, tval,
+                               bkept);
+  else
+    l2_slow<NT, CAP, PLAN, VT>(B, L, s_w, s_b, brec, gkeys, scratch, row_ptr, col_t, perm,
+                               val, col_rel, trow, tval, bkept);
 }
 
 // Place each bucket's survivors: the bucket's output offset is the sum of the survivor
