@@ -143,7 +143,7 @@ struct AsmLayout {
   // shared
   size_t bucket, scratch;
   // partition path
-  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept;
+  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, flags;
   size_t total;
   int64_t fold_tiles;
 };
@@ -177,6 +177,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.trow = c.take(sizeof(uint32_t) * (size_t)nP);
   L.tval = c.take(sizeof(double) * (size_t)nP);
   L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? L.pp.ntiles : 0));
   L.total = c.off;
   return L;
 }
@@ -184,11 +185,16 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
 struct PlanLayout {
   PartParams pp;
   size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
-  size_t colarr, table, rowoff, btot, bstart, brec, total;
+  size_t colarr, table, rowoff, btot, bstart, brec, flags, total;
   int64_t sort_tiles;
 };
 
-PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
+// Workgroups of k_expand_columns (one thread per column, grid-stride beyond the cap); a
+// fixed cap keeps the workspace size independent of the device.
+constexpr int kExpandMaxGroups = 4096;
+int expand_grid(int64_t n_cols) { return grid_for(n_cols > 0 ? n_cols : 1, kNT, kExpandMaxGroups); }
+
+PlanLayout plan_ws_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_cap) {
   PlanLayout L;
   Carve c;
   L.pp = part_params(n_rows, nnz_cap);
@@ -211,6 +217,7 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t nnz_cap) {
   L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
   L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
   L.brec = c.take(16 * (size_t)nP);
+  L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) : 0));
   L.total = c.off;
   return L;
 }
@@ -385,9 +392,6 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
 
   (void)hipGetLastError();
   const int cap = cu_count() * 16;
-  hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
-                     dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
-                     (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
   if (L.pp.ok) {
     // two-level partition by column: no device-wide atomics, no inter-workgroup waiting
     const PartParams& P = L.pp;
@@ -401,10 +405,12 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     double* tval = reinterpret_cast<double*>(w + L.tval);
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
+    uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
     hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
-                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, info);
+                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, flags);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s,
-                       (const uint32_t*)table, P.ntiles, rowoff, btot);
+                       (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
+                       P.ntiles, info);
     const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
 #define SPM_L2(VT)                                                                             \
   do {                                                                                         \
@@ -429,7 +435,10 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     return launch_status();
   } else {
     // one counter per column in global memory (shapes with more columns than the partition
-    // covers, and n_cols = 0)
+    // covers, and n_cols = 0); counters, look-back states and info start at zero
+    hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
+                       dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
+                       (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
     if (nnz_in > 0)
       hipLaunchKernelGGL((k_col_hist<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0,
                          s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
@@ -473,7 +482,7 @@ spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, si
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   *plan_bytes = plan_parts(n_rows, nnz_cap).total;
-  *ws_bytes = plan_ws_layout(n_rows, nnz_cap).total;
+  *ws_bytes = plan_ws_layout(n_rows, n_cols, nnz_cap).total;
   return SPM_OK;
 }
 
@@ -487,7 +496,7 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
   if (nnz_cap > 0 && !row_idx) return SPM_EINVAL;
   if (!aligned(ws, 256) || !aligned(plan, 256)) return SPM_EINVAL;
   const PlanParts P = plan_parts(n_rows, nnz_cap);
-  const PlanLayout L = plan_ws_layout(n_rows, nnz_cap);
+  const PlanLayout L = plan_ws_layout(n_rows, n_cols, nnz_cap);
   if (plan_bytes < P.total || ws_bytes < L.total) return SPM_EWORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -503,9 +512,6 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
 
   (void)hipGetLastError();
   const int cap = cu_count() * 16;
-  hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
-                     dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
-                     (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
   if (L.pp.ok) {
     // two-level partition by row: no device-wide atomics, no inter-workgroup waiting
     const PartParams& Q = L.pp;
@@ -515,14 +521,16 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
     int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
     uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
-    hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(grid_for(n_cols > 0 ? n_cols : 1, kNT, cap)),
-                       dim3(kNT), 0, s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info);
+    uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
+    hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(expand_grid(n_cols)), dim3(kNT), 0, s,
+                       col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info, flags);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
     hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
                        dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1, table,
-                       (int32_t*)nullptr);
+                       (uint32_t*)nullptr);
     hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
-                       (const uint32_t*)table, Q.ntiles, rowoff, btot);
+                       (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
+                       (int64_t)expand_grid(n_cols), info);
     hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc, float>), dim3((unsigned)Q.ntiles),
                        dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1,
                        (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, brec,
@@ -534,6 +542,9 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                        (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
                        (uint32_t*)nullptr);
   } else {
+    hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
+                       dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
+                       (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
     int32_t* first = reinterpret_cast<int32_t*>(w + L.first);
     hipLaunchKernelGGL((k_plan_hist<kNT>),

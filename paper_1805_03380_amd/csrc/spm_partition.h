@@ -62,15 +62,26 @@ struct PartSrcCsc {  // plan: segment = row, key = column << 32 | CSC slot
   }
 };
 
+// Status without a cleared word: every workgroup of a checking kernel writes its own flag
+// word (kFlagShape | kFlagIndex bits, 0 if clean) and k_rows_scan folds them into info[1],
+// an invalid shape taking precedence over an out-of-range index.
+constexpr uint32_t kFlagShape = 1u;
+constexpr uint32_t kFlagIndex = 2u;
+
 // Column of every stored slot of a CSC, plus the checks the plan needs (monotone offsets,
-// col_ptr[0] = 0, nnz <= capacity, rows in range).  One thread per column.
+// col_ptr[0] = 0, nnz <= capacity, rows in range).  One thread per column; flags[blockIdx.x]
+// receives the workgroup's findings.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_expand_columns(const int32_t* __restrict__ col_ptr,
                                                        const int32_t* __restrict__ row_idx,
                                                        int64_t n_rows, int64_t n_cols,
                                                        int64_t nnz_cap,
                                                        int32_t* __restrict__ colarr,
-                                                       int32_t* __restrict__ info) {
+                                                       int32_t* __restrict__ info,
+                                                       uint32_t* __restrict__ flags) {
+  __shared__ uint32_t s_flag;
+  if (threadIdx.x == 0) s_flag = 0;
+  __syncthreads();
   const int64_t raw = col_ptr[n_cols];
   const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
   const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -91,19 +102,23 @@ __global__ __launch_bounds__(NT) void k_expand_columns(const int32_t* __restrict
       if (r < 0 || (int64_t)r >= n_rows) bad_row = true;
     }
   }
-  if (bad_shape) set_status(info, kStEinval);
-  if (bad_row) set_status(info, kStBounds);
+  const uint32_t f = (bad_shape ? kFlagShape : 0u) | (bad_row ? kFlagIndex : 0u);
+  if (f) atomicOr(&s_flag, f);
+  __syncthreads();
+  if (threadIdx.x == 0) flags[blockIdx.x] = s_flag;
 }
 
 // Level 1a: per-tile coarse-bucket counts -> table[cb * ntiles + t].
 template <int NT, typename SRC>
 __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, int64_t ntiles,
                                                   int64_t T1, uint32_t* __restrict__ table,
-                                                  int32_t* __restrict__ info) {
+                                                  uint32_t* __restrict__ flags) {
+  __shared__ uint32_t s_flag;
   __shared__ uint32_t h[kPartMaxBuckets];
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
   for (int i = threadIdx.x; i < CB; i += NT) h[i] = 0;
+  if (threadIdx.x == 0) s_flag = 0;
   __syncthreads();
   bool bad = false;
   const int64_t base = t * T1;
@@ -126,9 +141,10 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
     for (int u = 0; u < U; ++u)
       if (ok[u]) atomicAdd(&h[seg[u] >> b], 1u);
   }
+  if (bad) s_flag = kFlagIndex;
   __syncthreads();
   for (int i = threadIdx.x; i < CB; i += NT) table[(int64_t)i * ntiles + t] = h[i];
-  if (bad && info) set_status(info, kStBounds);
+  if (flags && threadIdx.x == 0) flags[t] = s_flag;
 }
 
 // One element in a coarse bucket is one 16-byte record, so the scatter issues a single
@@ -237,11 +253,25 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
 
 // Per-bucket exclusive scan of one row of the (bucket x tile) table: rowoff[cb][t] = number of
 // bucket-cb elements in tiles before t; btot[cb] = the bucket's total.  One workgroup per row.
+// Workgroup 0 also folds the nflags status flags of the checking kernel into info[1].
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ table,
                                                   int64_t ntiles, uint32_t* __restrict__ rowoff,
-                                                  uint32_t* __restrict__ btot) {
+                                                  uint32_t* __restrict__ btot,
+                                                  const uint32_t* __restrict__ flags,
+                                                  int64_t nflags, int32_t* __restrict__ info) {
   __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ uint32_t s_flag;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    uint32_t f = 0;
+    for (int64_t i = threadIdx.x; i < nflags; i += NT) f |= flags[i];
+    if (f) atomicOr(&s_flag, f);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      info[1] = (s_flag & kFlagShape) ? kStEinval : ((s_flag & kFlagIndex) ? kStBounds : 0);
+  }
   constexpr int IPT = 4;
   const int64_t cb = blockIdx.x;
   const uint32_t* in = table + cb * ntiles;
@@ -420,58 +450,71 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
     return;
   }
   // Fold.  Each element's value (loaded with its key) goes to its sorted position in s_val
-  // (reusing s_key, dead after the ranking).  Each thread then takes IPT consecutive
-  // positions and folds every run that starts there, from LDS, in key order (= input order
-  // within a run); the sum replaces the value at the run's head, which no other thread reads.
+  // (reusing s_key, dead after the ranking).  The thread owning a run's head folds the run
+  // from LDS in key order (= input order within a run); the sum replaces the value at the
+  // head, which no other thread reads.
   double* s_val = reinterpret_cast<double*>(s_key);
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
     if (sg[u] != 0xffffffffu) s_val[dst[u]] = to_acc<double>(vv[u]);
   __syncthreads();
-  uint32_t mask = 0;
+  // Position i = u*NT + tid (u = 0..IPT-1): rounds of consecutive positions, so a wave's
+  // ballot of survivors gives each lane its rank within the wave, and one scan of the
+  // (round, wave) counts in position order gives the rest.  Survivors go out coalesced.
+  constexpr int NWV = NT / kWave;
+  __shared__ uint32_t s_cw[IPT * NWV + 1];
+  uint64_t bal[IPT];
 #pragma unroll
-  for (int s = 0; s < IPT; ++s) {
-    const int64_t li = (int64_t)threadIdx.x * IPT + s;
-    if (li < m) {
-      const uint32_t row = key_row(s_in[li]);
-      const bool head = s_flag[li] || key_row(s_in[li - 1]) != row;
+  for (int u = 0; u < IPT; ++u) {
+    const int64_t i = (int64_t)u * NT + threadIdx.x;
+    bool keep = false;
+    if (i < m) {
+      const uint32_t row = key_row(s_in[i]);
+      const bool head = s_flag[i] || key_row(s_in[i - 1]) != row;
       if (head) {
-        double acc = s_val[li];
-        for (int64_t j = li + 1; j < m && !s_flag[j]; ++j) {
+        double acc = s_val[i];
+        for (int64_t j = i + 1; j < m && !s_flag[j]; ++j) {
           if (key_row(s_in[j]) != row) break;
           acc = acc + s_val[j];
         }
-        s_val[li] = acc;
-        if (acc != 0.0) mask |= 1u << s;
+        s_val[i] = acc;
+        keep = acc != 0.0;
       }
     }
+    bal[u] = __ballot(keep);
+    if (lane_id() == 0) s_cw[u * NWV + wave_id()] = (uint32_t)__popcll(bal[u]);
   }
-  uint32_t kept;
-  const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &kept);
-  {
-    int64_t o = B.bstart + excl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < IPT * NWV; ++k) {
+      const uint32_t c = s_cw[k];
+      s_cw[k] = run;
+      run += c;
+    }
+    s_cw[IPT * NWV] = run;
+  }
+  __syncthreads();
+  const uint32_t kept = s_cw[IPT * NWV];
+  const uint64_t lt = (1ull << lane_id()) - 1ull;
+  uint32_t rank[IPT];
 #pragma unroll
-    for (int s = 0; s < IPT; ++s) {
-      if ((mask >> s) & 1u) {
-        const int64_t li = (int64_t)threadIdx.x * IPT + s;
-        trow[o] = key_row(s_in[li]);
-        tval[o] = s_val[li];
-        ++o;
-      }
+  for (int u = 0; u < IPT; ++u) {
+    const int64_t i = (int64_t)u * NT + threadIdx.x;
+    rank[u] = s_cw[u * NWV + wave_id()] + (uint32_t)__popcll(bal[u] & lt);
+    if ((bal[u] >> lane_id()) & 1ull) {
+      trow[B.bstart + rank[u]] = key_row(s_in[i]);
+      tval[B.bstart + rank[u]] = s_val[i];
     }
   }
   __syncthreads();  // s_val is read; the survivor prefix s_pre takes its place
   uint32_t* s_pre = reinterpret_cast<uint32_t*>(s_key);
-  {
-    uint32_t run = excl;
 #pragma unroll
-    for (int s = 0; s < IPT; ++s) {
-      const int64_t li = (int64_t)threadIdx.x * IPT + s;
-      if (li < m) s_pre[li] = run;
-      run += (mask >> s) & 1u;
-    }
-    if (threadIdx.x == 0) s_pre[m] = kept;
+  for (int u = 0; u < IPT; ++u) {
+    const int64_t i = (int64_t)u * NT + threadIdx.x;
+    if (i < m) s_pre[i] = rank[u];
   }
+  if (threadIdx.x == 0) s_pre[m] = kept;
   __syncthreads();
   for (int64_t j = threadIdx.x; j < nW; j += NT) col_rel[B.seg0 + j] = (int32_t)s_pre[cnt[j]];
   if (threadIdx.x == 0) bkept[B.cb] = kept;
