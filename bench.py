@@ -126,6 +126,26 @@ def batched_vs_single(reps_batched=5, reps_single=3):
             "bitwise_equal": same, "setup_s": gen_s}
 
 
+def stored_traffic(phase, tuning):
+    """HBM bytes per launch of the SpMM kernel of `phase`, from the committed counter runs
+    (profiles/traffic_uniform_1e5_f32_k64.json) -- None unless the kernel sources and the
+    launch tuning are still the ones the counters were taken with."""
+    from paper_1805_03380_amd import profiling
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "traffic_uniform_1e5_f32_k64.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("spmm_source_sha256") != profiling.spmm_source_hash():
+        return None
+    for k, v in (tr.get("tuning") or {}).items():
+        if tuning.get(k) != v:
+            return None
+    entry = tr.get(phase)
+    return None if entry is None else float(entry["bytes_per_launch"])
+
+
 def copy_calibration(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -201,13 +221,7 @@ def main():
     ach = bytes_[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
     spmm_ms = phase_ms["forward"] + phase_ms["backward"]
     spmm_gbps = (bytes_["forward"] + bytes_["backward"]) / (spmm_ms * 1e-3) / 1e9
-    traffic = None
-    tr_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                           "traffic_uniform_1e5_f32_k64.json")
-    if os.path.exists(tr_path):
-        with open(tr_path) as f:
-            tr = json.load(f)
-        traffic = tr.get(dominant)
+    traffic = stored_traffic(dominant, tuning_used) if args.value_dtype == "float32" else None
 
     out = {
         "metric": "COO->CSC nnz/s; SpMM fwd+bwd HBM GB/s and % of roofline, batched vs single",
@@ -236,7 +250,10 @@ def main():
         "algorithmic_bytes": bytes_,
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": ach,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
-                     "traffic": traffic, "kernel_ms": phase_ms[dominant],
+                     "traffic": traffic,
+                     "traffic_GBps": None if traffic is None
+                     else traffic / (phase_ms[dominant] * 1e-3) / 1e9,
+                     "kernel_ms": phase_ms[dominant],
                      "algorithmic_bytes": bytes_[dominant],
                      "gather_model_GBps": (bytes_[dominant] + gather_bytes(nnz, p.k, 4))
                      / (phase_ms[dominant] * 1e-3) / 1e9},

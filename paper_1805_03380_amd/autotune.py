@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.json")
 
 SPMM_SPACE = {"spmm_block": [64, 128, 256], "spmm_blocks_per_cu": [8, 16, 32, 64]}
-PART_SPACE = {"part_bucket_target": [512, 1024, 2048], "part_max_tiles": [256, 512, 1024, 2048]}
+PART_SPACE = {"part_bucket_target": [512, 1024, 2048], "part_max_tiles": [64, 128, 256, 512]}
 BATCH_SPACE = {"batch_wg_per_cu": [1, 2, 3, 4]}
 
 
