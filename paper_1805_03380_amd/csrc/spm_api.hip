@@ -65,6 +65,21 @@ int cu_count() {
   return cached[dev];
 }
 
+// Largest dynamic LDS a workgroup may request on the current device (cached per device).
+int max_lds_per_block() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        n <= 0)
+      n = 65536;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 int grid_for(int64_t work_items, int64_t per_block, int cap) {
   int64_t g = ceil_div(work_items, per_block);
   if (g < 1) g = 1;
@@ -82,12 +97,25 @@ spm_status launch_status() {
 
 // ------------------------------------------------------------------------------------------
 // Two-level partition parameters (spm_partition.h).  b = log2(segments per coarse bucket):
-// at least what keeps the number of buckets <= kPartMaxBuckets, and about 2048 elements per
-// bucket when the sizes allow it.  Returns ok = false when no b <= 12 fits (more than
-// kPartMaxBuckets * kPartMaxWidth segments); then the atomic-histogram path is used.
+// at least what keeps the number of buckets within the level-1 LDS counters, and an expected
+// bucket size of at most min(part_bucket_target, 3/4 of kPartCap) when the sizes allow it.
+// Returns ok = false when no b <= 12 fits (more than about kPartMaxBuckets * kPartMaxWidth
+// segments); then the atomic-histogram path is used.
 // ------------------------------------------------------------------------------------------
 constexpr int kPartNT = 1024;  // level-1 workgroup (hist, scatter): long per-bucket runs
 constexpr int kPartCap = 2048;  // bucket size kept entirely in LDS by the fused level 2
+// Up to this many buckets k_part_emit reduces the survivor counts of the buckets before it
+// per workgroup; beyond it one k_small_scan launch computes them.
+constexpr int kEmitReduceMax = 1024;
+
+// Level 2 splits each segment into R = 2^l2_sub_log2(b) sub-ranges of the key's high word
+// (values in [0, key_range)): the shift that maps that range onto [0, R).
+int sub_shift(int64_t key_range, int b) {
+  int bits = 0;
+  while (((int64_t)1 << bits) < key_range) ++bits;
+  const int lr = l2_sub_log2(b);
+  return bits > lr ? bits - lr : 0;
+}
 
 struct PartParams {
   bool ok;
@@ -112,9 +140,14 @@ PartParams part_params(int64_t nseg, int64_t n) {
   PartParams P{false, 0, 0, 1, 1024};
   if (nseg <= 0) return P;
   const spm_tuning tu = tuning();
-  const int bmin = ceil_log2(ceil_div(nseg, kPartMaxBuckets));
-  const int btarget =
-      n > 0 ? floor_log2(std::max<int64_t>(1, nseg * (int64_t)tu.part_bucket_target / n)) : 12;
+  // level-1 kernels keep one LDS counter per bucket (plus under 1 KB of static LDS)
+  const int64_t max_buckets =
+      std::min<int64_t>(kPartMaxBuckets, ((int64_t)max_lds_per_block() - 1024) / 4);
+  const int bmin = ceil_log2(ceil_div(nseg, max_buckets));
+  // floor_log2 puts the expected bucket size in (target/2, target]; keep it at most 3/4 of
+  // the in-LDS capacity so that ordinary fluctuations stay on the in-LDS path
+  const int64_t target = std::min<int64_t>(tu.part_bucket_target, kPartCap * 3 / 4);
+  const int btarget = n > 0 ? floor_log2(std::max<int64_t>(1, nseg * target / n)) : 12;
   int b = std::max(bmin, btarget);
   if (b > 12) b = 12;
   if (b < bmin) return P;
@@ -143,7 +176,7 @@ struct AsmLayout {
   // shared
   size_t bucket, scratch;
   // partition path
-  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, flags;
+  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, boff, flags;
   size_t total;
   int64_t fold_tiles;
 };
@@ -177,6 +210,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.trow = c.take(sizeof(uint32_t) * (size_t)nP);
   L.tval = c.take(sizeof(double) * (size_t)nP);
   L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.boff = c.take(sizeof(int32_t) * (size_t)(cb > kEmitReduceMax ? cb + 1 : 0));
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? L.pp.ntiles : 0));
   L.total = c.off;
   return L;
@@ -217,7 +251,8 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_cap) {
   L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
   L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
   L.brec = c.take(16 * (size_t)nP);
-  L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) : 0));
+  // status flags: one per k_expand_columns workgroup, then one per k_part_hist tile
+  L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) + L.pp.ntiles : 0));
   L.total = c.off;
   return L;
 }
@@ -248,8 +283,8 @@ template <int NT, int IPT>
 void launch_scan(const uint32_t* in, int64_t n, int32_t* out, uint64_t* state, uint32_t* ticket,
                  hipStream_t s) {
   const int64_t tiles = n > 0 ? ceil_div(n, (int64_t)NT * IPT) : 1;
-  hipLaunchKernelGGL((k_scan_excl<NT, IPT>), dim3((unsigned)tiles), dim3(NT), 0, s, in, n, out,
-                     state, ticket);
+  k_scan_excl<NT, IPT><<<dim3((unsigned)tiles), dim3(NT), 0, s>>>(
+      in, n, out, state, ticket);
 }
 
 template <typename VT>
@@ -257,9 +292,9 @@ void launch_fold(const uint64_t* keys, const int32_t* colstart, int64_t n_cols, 
                  int32_t* col_ptr, int32_t* row_idx, void* val_out, int out_f64, int32_t* info,
                  const int32_t* first, uint64_t* state, uint32_t* ticket, int64_t tiles,
                  hipStream_t s) {
-  hipLaunchKernelGGL((k_fold<kNT, kFoldIPT, VT>), dim3((unsigned)tiles), dim3(kNT), 0, s, keys,
-                     colstart, n_cols, val, col_ptr, row_idx, val_out, out_f64, info, first,
-                     state, ticket);
+  k_fold<kNT, kFoldIPT, VT><<<dim3((unsigned)tiles), dim3(kNT), 0, s>>>(
+      keys, colstart, n_cols, val, col_ptr, row_idx, val_out, out_f64, info, first, state,
+      ticket);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -287,9 +322,9 @@ void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, in
                   const int32_t* perm, const void* val, const void* X, int64_t ldx, int xal,
                   void* Y, int64_t ldy, int y_f64, int yal, int grid, int block, hipStream_t s) {
 #define SPM_CALL_F(GW, F)                                                                      \
-  hipLaunchKernelGGL((k_spmm_fwd<VT, XT, ACC, GW, F>), dim3(grid), dim3(block), 0, s, n_rows,  \
-                     n_cols, nnz_cap, k, row_ptr, col_t, perm, static_cast<const VT*>(val),    \
-                     static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal)
+  k_spmm_fwd<VT, XT, ACC, GW, F><<<dim3(grid), dim3(block), 0, s>>>(                           \
+      n_rows, n_cols, nnz_cap, k, row_ptr, col_t, perm, static_cast<const VT*>(val),           \
+      static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal)
 #define SPM_CALL(GW) SPM_CALL_F(GW, false)
   if (full && G == 8) SPM_CALL_F(8, true);
   else if (full && G == 16) SPM_CALL_F(16, true);
@@ -306,10 +341,10 @@ void launch_bwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, in
                   int64_t lddx, int dx_f64, int dxal, void* dval, int dv_f64, int grid,
                   int block, hipStream_t s) {
 #define SPM_CALL_F(GW, F)                                                                      \
-  hipLaunchKernelGGL((k_spmm_bwd<VT, XT, ACC, GW, F>), dim3(grid), dim3(block), 0, s, n_rows,  \
-                     n_cols, nnz_cap, k, col_ptr, row_idx, static_cast<const VT*>(val),        \
-                     static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal, \
-                     dX, lddx, dx_f64, dxal, dval, dv_f64)
+  k_spmm_bwd<VT, XT, ACC, GW, F><<<dim3(grid), dim3(block), 0, s>>>(                           \
+      n_rows, n_cols, nnz_cap, k, col_ptr, row_idx, static_cast<const VT*>(val),               \
+      static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal, dX, lddx,     \
+      dx_f64, dxal, dval, dv_f64)
 #define SPM_CALL(GW) SPM_CALL_F(GW, false)
   if (full && G == 8) SPM_CALL_F(8, true);
   else if (full && G == 16) SPM_CALL_F(16, true);
@@ -406,53 +441,57 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
-    hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCoo>), dim3((unsigned)P.ntiles),
-                       dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1, table, flags);
-    hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s,
-                       (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
-                       P.ntiles, info);
+    k_part_hist<kPartNT, PartSrcCoo>
+        <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
+            src, P.b, P.CB, P.ntiles, P.T1, table, flags);
+    k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
+        (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info);
     const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
 #define SPM_L2(VT)                                                                             \
   do {                                                                                         \
-  hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCoo, VT>), dim3((unsigned)P.ntiles),       \
-                     dim3(kPartNT), 0, s, src, P.b, P.CB, P.ntiles, P.T1,                       \
-                     (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, brec,              \
-                     static_cast<const VT*>(val), bvhi);                                        \
-  hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, false, VT>), dim3((unsigned)P.CB), dim3(kNT), \
-                     lds, s, P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec,          \
-                     (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,               \
-                     (int32_t*)nullptr, (int32_t*)nullptr, static_cast<const VT*>(val),        \
-                     col_ptr, trow, tval, bkept);                                              \
+  k_part_scatter<kPartNT, PartSrcCoo, VT>                                                      \
+      <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(                      \
+          src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,      \
+          bstart, brec, static_cast<const VT*>(val), bvhi);                                    \
+  k_part_level2<kNT, kPartCap, false, VT><<<dim3((unsigned)P.CB), dim3(kNT), lds, s>>>(        \
+      P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi, bucket,  \
+      scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,                        \
+      static_cast<const VT*>(val), col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b));        \
   } while (0)
     if (val_type == SPM_F64) SPM_L2(double);
     else if (val_type == SPM_F32) SPM_L2(float);
     else SPM_L2(bf16_t);
 #undef SPM_L2
-    hipLaunchKernelGGL((k_part_emit<kNT>), dim3((unsigned)P.CB), dim3(kNT), 0, s, P.b, P.CB,
-                       n_cols, (const int32_t*)bstart, (const uint32_t*)bkept,
-                       (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out,
-                       out_type == SPM_F64 ? 1 : 0, info);
+    int32_t* boff = nullptr;
+    if (P.CB > kEmitReduceMax) {
+      boff = reinterpret_cast<int32_t*>(w + L.boff);
+      k_small_scan<kNT><<<dim3(1), dim3(kNT), 0, s>>>(
+          (const uint32_t*)bkept, (int64_t)P.CB, boff);
+    }
+    k_part_emit<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
+        P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint32_t*)bkept, (const int32_t*)boff,
+        (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out,
+        out_type == SPM_F64 ? 1 : 0, info);
     return launch_status();
   } else {
     // one counter per column in global memory (shapes with more columns than the partition
     // covers, and n_cols = 0); counters, look-back states and info start at zero
-    hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
-                       dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
-                       (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
+    k_zero2<<<dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)), dim3(kNT), 0, s>>>(
+        reinterpret_cast<uint32_t*>(w), (int64_t)(L.zero_bytes / 4),
+        reinterpret_cast<uint32_t*>(info), (int64_t)2);
     if (nnz_in > 0)
-      hipLaunchKernelGGL((k_col_hist<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0,
-                         s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
+      k_col_hist<kNT><<<dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0, s>>>(
+          row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colcnt, info);
     launch_scan<kNT, kScanIPT>(colcnt, n_cols, colstart, scan_state, tickets + 0, s);
-    hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_cols + 1, kNT, cap)), dim3(kNT), 0, s,
-                       (const int32_t*)colstart, n_cols, (int64_t)kFoldTile, L.fold_tiles, first);
+    k_tile_first<<<dim3(grid_for(n_cols + 1, kNT, cap)), dim3(kNT), 0, s>>>(
+        (const int32_t*)colstart, n_cols, (int64_t)kFoldTile, L.fold_tiles, first);
     if (nnz_in > 0) {
-      hipLaunchKernelGGL((k_col_scatter<kNT>), dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT),
-                         0, s, row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colstart,
-                         colcnt, bucket);
-      hipLaunchKernelGGL((k_segsort<kNT, kSortCap, false>),
-                         dim3((unsigned)ceil_div(nnz_in, kSortT)), dim3(kNT), 0, s, bucket,
-                         colstart, n_cols, (int64_t)kSortT, (const int32_t*)first, scratch,
-                         (int32_t*)nullptr, (int32_t*)nullptr);
+      k_col_scatter<kNT><<<dim3(grid_for(nnz_in, kNT * 4, cap)), dim3(kNT), 0, s>>>(
+          row, col, nnz_in, (int32_t)n_rows, (int32_t)n_cols, colstart, colcnt, bucket);
+      k_segsort<kNT, kSortCap, false>
+          <<<dim3((unsigned)ceil_div(nnz_in, kSortT)), dim3(kNT), 0, s>>>(
+              bucket, colstart, n_cols, (int64_t)kSortT, (const int32_t*)first, scratch,
+              (int32_t*)nullptr, (int32_t*)nullptr);
     }
   }
   const int out_f64 = out_type == SPM_F64 ? 1 : 0;
@@ -522,43 +561,41 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
     uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
-    hipLaunchKernelGGL((k_expand_columns<kNT>), dim3(expand_grid(n_cols)), dim3(kNT), 0, s,
-                       col_ptr, row_idx, n_rows, n_cols, nnz_cap, colarr, info, flags);
+    k_expand_columns<kNT><<<dim3(expand_grid(n_cols)), dim3(kNT), 0, s>>>(
+        col_ptr, n_cols, nnz_cap, colarr, info, flags);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
-    hipLaunchKernelGGL((k_part_hist<kPartNT, PartSrcCsc>), dim3((unsigned)Q.ntiles),
-                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1, table,
-                       (uint32_t*)nullptr);
-    hipLaunchKernelGGL((k_rows_scan<kNT>), dim3((unsigned)Q.CB), dim3(kNT), 0, s,
-                       (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
-                       (int64_t)expand_grid(n_cols), info);
-    hipLaunchKernelGGL((k_part_scatter<kPartNT, PartSrcCsc, float>), dim3((unsigned)Q.ntiles),
-                       dim3(kPartNT), 0, s, src, Q.b, Q.CB, Q.ntiles, Q.T1,
-                       (const uint32_t*)rowoff, (const uint32_t*)btot, bstart, brec,
-                       (const float*)nullptr, (uint32_t*)nullptr);
-    hipLaunchKernelGGL((k_part_level2<kNT, kPartCap, true, float>), dim3((unsigned)Q.CB),
-                       dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s, Q.b, n_rows,
-                       (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)nullptr,
-                       bucket, scratch, row_ptr, col_t, perm, (const float*)nullptr,
-                       (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
-                       (uint32_t*)nullptr);
+    k_part_hist<kPartNT, PartSrcCsc>
+        <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
+            src, Q.b, Q.CB, Q.ntiles, Q.T1, table, flags + expand_grid(n_cols));
+    k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
+        (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
+        (int64_t)expand_grid(n_cols) + Q.ntiles, info);
+    k_part_scatter<kPartNT, PartSrcCsc, float>
+        <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
+            src, Q.b, Q.CB, Q.ntiles, Q.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
+            bstart, brec, (const float*)nullptr, (uint32_t*)nullptr);
+    k_part_level2<kNT, kPartCap, true, float>
+        <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(
+            Q.b, n_rows, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)nullptr,
+            bucket, scratch, row_ptr, col_t, perm, (const float*)nullptr, (int32_t*)nullptr,
+            (uint32_t*)nullptr, (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b));
   } else {
-    hipLaunchKernelGGL(k_zero2, dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)),
-                       dim3(kNT), 0, s, reinterpret_cast<uint32_t*>(w),
-                       (int64_t)(L.zero_bytes / 4), reinterpret_cast<uint32_t*>(info), (int64_t)2);
+    k_zero2<<<dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)), dim3(kNT), 0, s>>>(
+        reinterpret_cast<uint32_t*>(w), (int64_t)(L.zero_bytes / 4),
+        reinterpret_cast<uint32_t*>(info), (int64_t)2);
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(w + L.rowcnt);
     int32_t* first = reinterpret_cast<int32_t*>(w + L.first);
-    hipLaunchKernelGGL((k_plan_hist<kNT>),
-                       dim3(grid_for(nnz_cap > n_cols ? nnz_cap : n_cols, kNT, cap)), dim3(kNT), 0,
-                       s, col_ptr, row_idx, n_rows, n_cols, nnz_cap, rowcnt, info);
+    k_plan_hist<kNT>
+        <<<dim3(grid_for(nnz_cap > n_cols ? nnz_cap : n_cols, kNT, cap)), dim3(kNT), 0, s>>>(
+            col_ptr, row_idx, n_rows, n_cols, nnz_cap, rowcnt, info);
     launch_scan<kNT, kScanIPT>(rowcnt, n_rows, row_ptr, scan_state, tickets, s);
     if (nnz_cap > 0 && n_cols > 0) {
-      hipLaunchKernelGGL((k_row_scatter<kNT>), dim3(grid_for(n_cols, kNT, cap)), dim3(kNT), 0, s,
-                         col_ptr, row_idx, n_rows, n_cols, nnz_cap, row_ptr, rowcnt, bucket);
-      hipLaunchKernelGGL(k_tile_first, dim3(grid_for(n_rows + 1, kNT, cap)), dim3(kNT), 0, s,
-                         (const int32_t*)row_ptr, n_rows, (int64_t)kSortT, L.sort_tiles, first);
-      hipLaunchKernelGGL((k_segsort<kNT, kSortCap, true>),
-                         dim3((unsigned)L.sort_tiles), dim3(kNT), 0, s, bucket, row_ptr, n_rows,
-                         (int64_t)kSortT, (const int32_t*)first, scratch, col_t, perm);
+      k_row_scatter<kNT><<<dim3(grid_for(n_cols, kNT, cap)), dim3(kNT), 0, s>>>(
+          col_ptr, row_idx, n_rows, n_cols, nnz_cap, row_ptr, rowcnt, bucket);
+      k_tile_first<<<dim3(grid_for(n_rows + 1, kNT, cap)), dim3(kNT), 0, s>>>(
+          (const int32_t*)row_ptr, n_rows, (int64_t)kSortT, L.sort_tiles, first);
+      k_segsort<kNT, kSortCap, true><<<dim3((unsigned)L.sort_tiles), dim3(kNT), 0, s>>>(
+          bucket, row_ptr, n_rows, (int64_t)kSortT, (const int32_t*)first, scratch, col_t, perm);
     }
   }
   return launch_status();
@@ -598,9 +635,9 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
   // The full path loads a clamped (valid) dense row for out-of-range plan entries, so it
   // needs at least one dense row.
   const bool full = k == 4 * (int64_t)G && xal && yal && n_cols > 0;
-#define SPM_FWD(VT, XT, ACC)                                                                   \
-  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, \
-                            yal, grid, block, s)
+#define SPM_FWD(VT, XT, ACC)                                                                  \
+  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, row_ptr, col_t, perm, val, X, \
+                            ldx, xal, Y, ldy, y_f64, yal, grid, block, s)
   if (val_type == SPM_F64) {
     if (x_type == SPM_F64) SPM_FWD(double, double, double);
     else if (x_type == SPM_F32) SPM_FWD(double, float, double);
@@ -647,9 +684,10 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
   (void)hipGetLastError();
   const bool f32acc = acc_is_f32(val_type, x_type);
   const bool full = k == 4 * (int64_t)G && gal && xal && (!dX || dxal) && n_rows > 0;
-#define SPM_BWD(VT, XT, ACC)                                                                   \
-  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm, ldg, gal, X, \
-                            ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, block, s)
+#define SPM_BWD(VT, XT, ACC)                                                                  \
+  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm,    \
+                            ldg, gal, X, ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, \
+                            block, s)
   if (val_type == SPM_F64) {
     if (x_type == SPM_F64) SPM_BWD(double, double, double);
     else if (x_type == SPM_F32) SPM_BWD(double, float, double);
@@ -694,7 +732,8 @@ spm_status spm_tuning_set(const spm_tuning* in) {
 namespace {
 
 size_t batch_stride(int64_t max_dim, int64_t max_nnz) {
-  return align256(sizeof(uint64_t) * 2 * (size_t)max_nnz + sizeof(uint32_t) * (size_t)(max_dim + 1));
+  return align256(sizeof(uint64_t) * 2 * (size_t)max_nnz +
+                  sizeof(uint32_t) * (size_t)(max_dim + 1));
 }
 
 int batch_workers(int32_t workers, int32_t batch) {
@@ -706,8 +745,7 @@ int batch_workers(int32_t workers, int32_t batch) {
 
 template <int NT, typename VIN, typename XT, typename ACC>
 void launch_batch(const BatchArgs& a, int workers, hipStream_t s) {
-#define SPM_CALL(GW) \
-  hipLaunchKernelGGL((k_batch<NT, VIN, XT, ACC, GW>), dim3(workers), dim3(NT), 0, s, a)
+#define SPM_CALL(GW) k_batch<NT, VIN, XT, ACC, GW><<<dim3(workers), dim3(NT), 0, s>>>(a)
   SPM_GW_SWITCH(a.G, SPM_CALL)
 #undef SPM_CALL
 }
@@ -807,8 +845,8 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
   a.yal = (k % 4 == 0 && aligned(Y, 16) && aligned(dX, 16)) ? 1 : 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, (uint32_t*)nullptr,
-                     (int64_t)0);
+  k_zero2<<<dim3(1), dim3(64), 0, s>>>(
+      a.queue, (int64_t)1, (uint32_t*)nullptr, (int64_t)0);
   launch_batch_nt<256>(a, val_type, x_type, w, s);
   return launch_status();
 }

@@ -21,7 +21,7 @@
 
 namespace spm {
 
-constexpr int kPartMaxBuckets = 4096;   // coarse buckets per level (LDS counters)
+constexpr int kPartMaxBuckets = 16384;  // coarse buckets per level (LDS counters, <= 64 KB)
 constexpr int kPartMaxWidth = 4096;     // segments per coarse bucket (LDS counters)
 
 // Element sources.  part_elem returns false for an element that is skipped (out of range).
@@ -68,42 +68,60 @@ struct PartSrcCsc {  // plan: segment = row, key = column << 32 | CSC slot
 constexpr uint32_t kFlagShape = 1u;
 constexpr uint32_t kFlagIndex = 2u;
 
-// Column of every stored slot of a CSC, plus the checks the plan needs (monotone offsets,
-// col_ptr[0] = 0, nnz <= capacity, rows in range).  One thread per column; flags[blockIdx.x]
-// receives the workgroup's findings.
+// Column of every stored slot of a CSC, plus the offset checks the plan needs (monotone,
+// col_ptr[0] = 0, nnz <= capacity; row indices are checked by k_part_hist, which reads them
+// anyway); flags[blockIdx.x] receives the workgroup's findings.  A workgroup takes chunks of
+// NT columns (grid-stride) and stages their offsets in LDS.  A column of at most kShort slots
+// is written by its own thread; longer ones are queued and each is then written by the whole
+// workgroup, so long columns do not serialise one thread.  Offsets are clamped to [0, nnz]:
+// a malformed col_ptr can only produce wrong columns (and a status), never an access out of
+// range.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_expand_columns(const int32_t* __restrict__ col_ptr,
-                                                       const int32_t* __restrict__ row_idx,
-                                                       int64_t n_rows, int64_t n_cols,
-                                                       int64_t nnz_cap,
+                                                       int64_t n_cols, int64_t nnz_cap,
                                                        int32_t* __restrict__ colarr,
                                                        int32_t* __restrict__ info,
                                                        uint32_t* __restrict__ flags) {
+  constexpr int64_t kShort = 32;
   __shared__ uint32_t s_flag;
+  __shared__ int64_t s_cp[NT + 1];
+  __shared__ int32_t s_long[NT];
+  __shared__ int32_t s_nlong;
   if (threadIdx.x == 0) s_flag = 0;
-  __syncthreads();
   const int64_t raw = col_ptr[n_cols];
   const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
-  const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * NT;
-  bool bad_shape = false, bad_row = false;
-  if (gid == 0) {
+  bool bad_shape = false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (col_ptr[0] != 0 || raw < 0 || raw > nnz_cap) bad_shape = true;
     info[0] = (int32_t)nnz;
   }
-  for (int64_t c = gid; c < n_cols; c += stride) {
-    int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
-    if (p0 > p1) bad_shape = true;
-    p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
-    p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
-    for (int64_t p = p0; p < p1; ++p) {
-      colarr[p] = (int32_t)c;
-      const int32_t r = row_idx[p];
-      if (r < 0 || (int64_t)r >= n_rows) bad_row = true;
+  for (int64_t c0 = (int64_t)blockIdx.x * NT; c0 < n_cols; c0 += (int64_t)gridDim.x * NT) {
+    const int nc = (int)((n_cols - c0) < NT ? (n_cols - c0) : NT);
+    __syncthreads();  // the previous chunk is done with s_cp and s_long
+    if (threadIdx.x == 0) s_nlong = 0;
+    for (int j = threadIdx.x; j <= nc; j += NT) {
+      const int64_t v = col_ptr[c0 + j];
+      s_cp[j] = v < 0 ? 0 : (v > nnz ? nnz : v);
+      if (j < nc && v > (int64_t)col_ptr[c0 + j + 1]) bad_shape = true;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      const int j = threadIdx.x;
+      const int64_t p0 = s_cp[j], p1 = s_cp[j + 1];
+      if (p1 - p0 <= kShort) {
+        for (int64_t p = p0; p < p1; ++p) colarr[p] = (int32_t)(c0 + j);
+      } else {
+        s_long[atomicAdd(&s_nlong, 1)] = j;
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < s_nlong; ++q) {
+      const int j = s_long[q];
+      const int64_t p1 = s_cp[j + 1];
+      for (int64_t p = s_cp[j] + threadIdx.x; p < p1; p += NT) colarr[p] = (int32_t)(c0 + j);
     }
   }
-  const uint32_t f = (bad_shape ? kFlagShape : 0u) | (bad_row ? kFlagIndex : 0u);
-  if (f) atomicOr(&s_flag, f);
+  if (bad_shape) atomicOr(&s_flag, kFlagShape);
   __syncthreads();
   if (threadIdx.x == 0) flags[blockIdx.x] = s_flag;
 }
@@ -114,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
                                                   int64_t T1, uint32_t* __restrict__ table,
                                                   uint32_t* __restrict__ flags) {
   __shared__ uint32_t s_flag;
-  __shared__ uint32_t h[kPartMaxBuckets];
+  extern __shared__ uint32_t h[];  // CB counters (dynamic LDS, 4*CB bytes)
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
   for (int i = threadIdx.x; i < CB; i += NT) h[i] = 0;
@@ -191,37 +209,23 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
                                                      uint4* __restrict__ brec,
                                                      const VT* __restrict__ vin,
                                                      uint32_t* __restrict__ bvhi) {
-  __shared__ uint32_t cur[kPartMaxBuckets];
+  extern __shared__ uint32_t cur[];  // CB cursors (dynamic LDS, 4*CB bytes)
   __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t t = blockIdx.x;
   const int64_t n = src.count();
-  {
-    // blocked: thread tid takes buckets [tid*ipt, tid*ipt + ipt); both loads in flight at once
-    constexpr int IPT = kPartMaxBuckets / NT;
-    const int ipt = (CB + NT - 1) / NT;
-    uint32_t v[IPT], ro[IPT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      const int i = threadIdx.x * ipt + q;
-      const bool in = q < ipt && i < CB;
-      v[q] = in ? btot[i] : 0u;
-      ro[q] = in ? rowoff[(int64_t)i * ntiles + t] : 0u;
-      sum += v[q];
-    }
-    uint32_t tot;
-    uint32_t run = wg_excl_scan<NT>(sum, s_w, &tot);
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      const int i = threadIdx.x * ipt + q;
-      if (q < ipt && i < CB) {
-        cur[i] = run + ro[q];
-        if (t == 0) bstart[i] = (int32_t)run;
-      }
-      run += v[q];
-    }
-    if (t == 0 && threadIdx.x == 0) bstart[CB] = (int32_t)tot;
+  // cur[i] = bstart[i] + rowoff[i][t]: the bucket totals are scanned in LDS
+  for (int64_t i = threadIdx.x; i < CB; i += NT) cur[i] = btot[i];
+  __syncthreads();
+  wg_inclusive_scan_inplace<NT>(cur, CB, s_w);
+  __syncthreads();
+  const uint32_t total = CB > 0 ? cur[CB - 1] : 0u;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < CB; i += NT) {
+    const uint32_t ex = cur[i] - btot[i];
+    if (t == 0) bstart[i] = (int32_t)ex;
+    cur[i] = ex + rowoff[i * ntiles + t];
   }
+  if (t == 0 && threadIdx.x == 0) bstart[CB] = (int32_t)total;
   __syncthreads();
   const uint32_t wmask = (1u << b) - 1u;
   const int64_t base = t * T1;
@@ -311,16 +315,23 @@ __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ t
 // A bucket of at most CAP elements stays in LDS from load to output (fast path); a larger
 // one goes through global staging: segment scatter, sort_segments, then fold_tile over
 // blocks of CAP keys.
-// Dynamic LDS: cnt[W+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_flag[CAP] u8
+// Dynamic LDS: cnt[W*R+1] u32 | s_in[CAP] u64 | s_key[CAP] u64 | s_flag[CAP] u8
 //              (part_level2_lds_bytes).  The fold's values s_val[CAP] f64 and survivor
 //              prefix s_pre[CAP+1] u32 reuse s_key, which is dead once the bucket is sorted;
-//              at b = 7 a workgroup takes about 35 KB, four per CU.
+//              at b = 7 a workgroup takes about 39 KB, four per CU.
+// In the fast path each segment is split into R = 2^lr sub-segments by the top bits of the
+// key's high word (the row for assembly, the column for the plan: key_hi >> rshift < R), so
+// the ranking runs over short sub-segments even when a segment is long; the sub-segments of
+// a segment are in ascending key order, so the sorted result is the same.
 // In the fast path every thread keeps the key, segment (and, folding, the value) of its
 // elements i = tid + u*NT in registers from the first load to the ranking; the value gather
 // is issued before the counting so that its latency overlaps the LDS work.
 // ------------------------------------------------------------------------------------------
+// Sub-segments per segment in the in-LDS path: R = 2^l2_sub_log2(b), so that W*R >= 1024.
+__host__ __device__ inline int l2_sub_log2(int b) { return b >= 10 ? 0 : 10 - b; }
+
 __host__ __device__ inline size_t part_level2_lds_bytes(int b, int cap) {
-  const size_t w = ((size_t)1 << b) + 1;
+  const size_t w = ((size_t)1 << (b + l2_sub_log2(b))) + 1;
   size_t off = (w * 4 + 15) & ~(size_t)15;
   off += (size_t)cap * 8 * 2;
   off += (size_t)cap;
@@ -341,7 +352,7 @@ struct L2Lds {
   uint64_t* s_key;
   uint8_t* s_flag;
   __device__ __forceinline__ L2Lds(unsigned char* smem, int b) {
-    const size_t wcnt = ((size_t)1 << b) + 1;
+    const size_t wcnt = ((size_t)1 << (b + l2_sub_log2(b))) + 1;
     size_t off = (wcnt * 4 + 15) & ~(size_t)15;
     cnt = reinterpret_cast<uint32_t*>(smem);
     s_in = reinterpret_cast<uint64_t*>(smem + off);
@@ -364,7 +375,7 @@ __device__ __forceinline__ void l2_row_ptr(const L2Bucket& B, const uint32_t* cn
 // Fast path (m <= CAP): the whole bucket stays in LDS from load to output.
 template <int NT, int CAP, bool PLAN, typename VT>
 __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, uint32_t* s_w,
-                                        const uint4* __restrict__ brec,
+                                        int lr, int rshift, const uint4* __restrict__ brec,
                                         const uint32_t* __restrict__ bvhi,
                                         int32_t* __restrict__ row_ptr,
                                         int32_t* __restrict__ col_t, int32_t* __restrict__ perm,
@@ -373,12 +384,14 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
                                         uint32_t* __restrict__ bkept) {
   constexpr int IPT = CAP / NT;
   const int64_t m = B.m, nW = B.nW;
+  const int64_t nS = nW << lr;  // sub-segments
+  const uint32_t rmax = (1u << lr) - 1u;
   uint32_t* cnt = L.cnt;
   uint64_t* s_in = L.s_in;
   uint64_t* s_key = L.s_key;
   uint8_t* s_flag = L.s_flag;
 
-  for (int64_t j = threadIdx.x; j <= nW; j += NT) cnt[j] = 0;
+  for (int64_t j = threadIdx.x; j <= nS; j += NT) cnt[j] = 0;
   uint64_t ky[IPT];
   uint32_t sg[IPT];
   VT vv[IPT];
@@ -390,7 +403,9 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
     if (i < m) {
       const uint4 r = brec[B.bstart + i];
       ky[u] = rec_key(r);
-      sg[u] = r.z;
+      // clamped: a malformed CSC handed to the plan may carry any column word
+      const uint32_t sub = min((uint32_t)(ky[u] >> 32) >> rshift, rmax);
+      sg[u] = (r.z << lr) | sub;
       if (!PLAN) vv[u] = ValWords<VT>::make(r.w, ValWords<VT>::kHi ? bvhi[B.bstart + i] : 0u);
     }
   }
@@ -399,11 +414,15 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
   for (int u = 0; u < IPT; ++u)
     if (sg[u] != 0xffffffffu) atomicAdd(&cnt[sg[u]], 1u);
   __syncthreads();
-  wg_inclusive_scan_inplace<NT>(cnt, nW, s_w);  // cnt[j] = end of segment j (relative)
-  if (PLAN) l2_row_ptr<NT>(B, cnt, row_ptr);
+  wg_inclusive_scan_inplace<NT>(cnt, nS, s_w);  // cnt[s] = end of sub-segment s (relative)
+  if (PLAN) {
+    for (int64_t j = threadIdx.x; j < nW; j += NT)
+      row_ptr[B.seg0 + j] = (int32_t)(B.bstart + (j == 0 ? 0 : (int64_t)cnt[(j << lr) - 1]));
+    if (B.last_bucket && threadIdx.x == 0) row_ptr[B.nseg] = (int32_t)B.bend;
+  }
   __syncthreads();
 
-  // Group by segment: each element takes the next free slot of its segment.
+  // Group by sub-segment: each element takes the next free slot of its sub-segment.
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     if (sg[u] != 0xffffffffu) {
@@ -413,15 +432,15 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
   }
   for (int64_t i = threadIdx.x; i < m; i += NT) s_flag[i] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;  // cnt[j] = start of segment j
+  if (threadIdx.x == 0) cnt[nS] = (uint32_t)m;  // cnt[s] = start of sub-segment s
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < nW; j += NT) {
-    const uint32_t lo = cnt[j];
+  for (int64_t j = threadIdx.x; j < nW; j += NT) {  // flags mark segment starts
+    const uint32_t lo = cnt[j << lr];
     if (lo < (uint32_t)m) s_flag[lo] = 1;
   }
-  // Rank each element among the keys of its segment (keys are unique, so the ranks are a
-  // permutation): the segment's bounds come from cnt, so the loads are independent and
-  // issued four at a time.
+  // Rank each element among the keys of its sub-segment (keys are unique, so the ranks are a
+  // permutation): the bounds come from cnt, so the loads are independent and issued four at
+  // a time.
   uint32_t dst[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
@@ -516,7 +535,8 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
   }
   if (threadIdx.x == 0) s_pre[m] = kept;
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < nW; j += NT) col_rel[B.seg0 + j] = (int32_t)s_pre[cnt[j]];
+  for (int64_t j = threadIdx.x; j < nW; j += NT)
+    col_rel[B.seg0 + j] = (int32_t)s_pre[cnt[j << lr]];
   if (threadIdx.x == 0) bkept[B.cb] = kept;
 }
 
@@ -641,8 +661,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
     const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
     uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
-    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
-    uint32_t* __restrict__ bkept) {
+    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel,
+    uint32_t* __restrict__ trow, double* __restrict__ tval, uint32_t* __restrict__ bkept,
+    int rshift) {
   static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
   static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -660,22 +681,55 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   B.nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
   B.last_bucket = B.seg0 + B.nW >= nseg;
   if (B.m <= CAP)
-    l2_fast<NT, CAP, PLAN, VT>(B, L, s_w, brec, bvhi, row_ptr, col_t, perm, col_rel, trow, tval,
-                               bkept);
+    l2_fast<NT, CAP, PLAN, VT>(B, L, s_w, l2_sub_log2(b), rshift, brec, bvhi, row_ptr, col_t,
+                               perm, col_rel, trow, tval, bkept);
   else
     l2_slow<NT, CAP, PLAN, VT>(B, L, s_w, s_b, brec, gkeys, scratch, row_ptr, col_t, perm,
                                val, col_rel, trow, tval, bkept);
 }
 
-// Place each bucket's survivors: the bucket's output offset is the sum of the survivor
-// counts of the buckets before it (each workgroup reduces bkept[0..cb) itself; the last one
-// also takes its own, giving nnz_out).  Moves the survivors from the temporaries to their
-// final place (rounded once to the output type), turns the bucket-relative column offsets
-// into col_ptr, and finishes col_ptr / info.
+// Exclusive scan of n counts by ONE workgroup: out[i] = sum in[0..i), out[n] = total.  Used
+// for the survivor offsets when there are too many buckets for k_part_emit to reduce them
+// per workgroup.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ in, int64_t n,
+                                                   int32_t* __restrict__ out) {
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  constexpr int IPT = 8;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      v[q] = i < n ? in[i] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = carry + wg_excl_scan<NT>(sum, s_w, &tot);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      if (i < n) out[i] = (int32_t)run;
+      run += v[q];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = (int32_t)carry;
+}
+
+// Place each bucket's survivors.  The bucket's output offset is the sum of the survivor
+// counts of the buckets before it: boff[cb] when the caller scanned them (boff != nullptr,
+// many buckets), else each workgroup reduces bkept[0..cb) itself (the last one also takes
+// its own, giving nnz_out).  Moves the survivors from the temporaries to their final place
+// (rounded once to the output type), turns the bucket-relative column offsets into col_ptr,
+// and finishes col_ptr / info.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nseg,
                                                   const int32_t* __restrict__ bstarts,
                                                   const uint32_t* __restrict__ bkept,
+                                                  const int32_t* __restrict__ boff,
                                                   const uint32_t* __restrict__ trow,
                                                   const double* __restrict__ tval,
                                                   int32_t* __restrict__ col_ptr,
@@ -685,14 +739,21 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t cb = blockIdx.x;
   const bool last = cb == (int64_t)CB - 1;
-  const int64_t lim = last ? CB : cb;
-  uint32_t part = 0;
-  for (int64_t i = threadIdx.x; i < lim; i += NT) part += bkept[i];
-  uint32_t tot;
-  (void)wg_excl_scan<NT>(part, s_w, &tot);
-  const int64_t src0 = bstarts[cb];
   const int64_t kept = bkept[cb];
-  const int64_t dst0 = last ? (int64_t)tot - kept : (int64_t)tot;
+  int64_t dst0, total;
+  if (boff) {
+    dst0 = boff[cb];
+    total = boff[CB];
+  } else {
+    const int64_t lim = last ? CB : cb;
+    uint32_t part = 0;
+    for (int64_t i = threadIdx.x; i < lim; i += NT) part += bkept[i];
+    uint32_t tot;
+    (void)wg_excl_scan<NT>(part, s_w, &tot);
+    dst0 = last ? (int64_t)tot - kept : (int64_t)tot;
+    total = tot;
+  }
+  const int64_t src0 = bstarts[cb];
   for (int64_t i = threadIdx.x; i < kept; i += NT) {
     row_idx[dst0 + i] = (int32_t)trow[src0 + i];
     if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
@@ -703,8 +764,8 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
   for (int64_t j = threadIdx.x; j < nW; j += NT) col_ptr[seg0 + j] += (int32_t)dst0;
   if (last && threadIdx.x == 0) {
-    col_ptr[nseg] = (int32_t)tot;
-    info[0] = (int32_t)tot;
+    col_ptr[nseg] = (int32_t)total;
+    info[0] = (int32_t)total;
   }
 }
 

@@ -175,6 +175,7 @@ __device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t
                                                   void* __restrict__ dX, int64_t lddx,
                                                   bool dx_f64, void* __restrict__ dval,
                                                   bool dv_f64) {
+  static_assert(kU == 4, "the dvalues store selects among four sums");
   const XT* Gl = Gm + (int64_t)lg * 4;
   ACC x[4];
   vload4<ACC>(X + c * ldx + (int64_t)lg * 4, x);
@@ -195,6 +196,7 @@ __device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t
     for (int u = 0; u < kU; ++u) v[u] = to_acc<ACC>(val[p + u]);
 #pragma unroll
     for (int u = 0; u < kU; ++u) vload4<ACC>(Gl + (int64_t)r[u] * ldg, g[u]);
+    ACC d[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
 #pragma unroll
@@ -203,13 +205,26 @@ __device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t
         dx[e] = fma_acc<ACC>(v[u], g[u][e], dx[e]);
       }
       if (dval) {
-        ACC d = (ACC)0;
+        d[u] = (ACC)0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[u][e], x[e], d);
-        d = group_sum<GW, ACC>(d);
-        if (lg == 0) {
-          if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d;
-          else static_cast<float*>(dval)[p + u] = (float)d;
+        for (int e = 0; e < 4; ++e) d[u] = fma_acc<ACC>(g[u][e], x[e], d[u]);
+        d[u] = group_sum<GW, ACC>(d[u]);
+      }
+    }
+    if (dval) {
+      // every lane ends with all kU sums; with GW >= kU lanes 0..kU-1 store the kU
+      // consecutive dvalues with one store instruction instead of kU single-lane stores
+      if constexpr (GW >= kU) {
+        if (lg < kU) {
+          const ACC dv = lg == 0 ? d[0] : (lg == 1 ? d[1] : (lg == 2 ? d[2] : d[3]));
+          if (dv_f64) static_cast<double*>(dval)[p + lg] = (double)dv;
+          else static_cast<float*>(dval)[p + lg] = (float)dv;
+        }
+      } else if (lg == 0) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d[u];
+          else static_cast<float*>(dval)[p + u] = (float)d[u];
         }
       }
     }
@@ -430,7 +445,7 @@ __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols
   const int64_t ngroups = (int64_t)gridDim.x * groups_per_block;
   for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / GW; r < n_rows;
        r += ngroups)
-    if (FULL)
+    if constexpr (FULL)
       spmm_row_full<VT, XT, ACC, GW>(r, lg, n_cols, nnz_cap, row_ptr, col_t, perm, val, X, ldx,
                                      Y, ldy, y_f64 != 0);
     else
@@ -457,7 +472,7 @@ __global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols
     int64_t p0 = col_ptr[c], p1 = col_ptr[c + 1];
     p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
     p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
-    if (FULL)
+    if constexpr (FULL)
       spmm_col_bwd_full<VT, XT, ACC, GW>(c, p0, p1, lg, n_rows, row_idx, val, Gm, ldg, X, ldx,
                                          dX, lddx, dx_f64 != 0, dval, dv_f64 != 0);
     else

@@ -120,6 +120,21 @@ def test_out_of_range_raises():
         assemble_gpu(p)
 
 
+def test_many_buckets():
+    """2^21 columns from 3e6 triplets: more than 1024 coarse buckets, so the survivor offsets
+    come from the scan launch instead of per-workgroup reductions; the plan over 2^21 rows
+    likewise."""
+    p = synth.random_coo(2121, 1 << 21, 1 << 21, 3_000_000, dup_frac=0.2, zero_frac=0.01)
+    A = assemble_gpu(p)
+    R = _ref(p)
+    assert_csc_equal(A, R, np.float64)
+    rp, ct, pm = ops.plan_arrays(ops.build_plan(A), p.n_rows, A.nnz_cap)
+    order = np.lexsort((np.repeat(np.arange(p.n_cols), np.diff(R.col_ptr)), R.row_idx))
+    assert np.array_equal(rp.cpu().numpy(), np.searchsorted(R.row_idx[order],
+                                                             np.arange(p.n_rows + 1)))
+    assert np.array_equal(pm[:R.nnz].cpu().numpy(), order)
+
+
 @pytest.mark.parametrize("value_dtype", [np.float32, np.float64])
 def test_uniform_1e5_full(value_dtype):
     p = synth.uniform_1e5(value_dtype=value_dtype, k=1)
