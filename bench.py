@@ -40,10 +40,12 @@ def parse():
 
 def model_bytes(n_rows, n_cols, nnz_in, nnz, k, s_vin, s_v, s_x, s_y, s_dx):
     """Algorithmic (compulsory) HBM bytes of each call: every input read once, every output
-    written once (the dense operands once per row, not once per nonzero)."""
+    written once (the dense operands once per row, not once per nonzero).  The plan build
+    also carries the values to plan order (read in CSC order, written in plan order), and
+    the forward product reads row_ptr, col_t and those values."""
     asm = nnz_in * (4 + 4 + s_vin) + nnz * (4 + s_v) + 4 * (n_cols + 1)
-    plan = 4 * (n_cols + 1) + 4 * nnz + 4 * (n_rows + 1) + 8 * nnz
-    fwd = 4 * (n_rows + 1) + nnz * (4 + 4 + s_v) + n_cols * k * s_x + n_rows * k * s_y
+    plan = 4 * (n_cols + 1) + nnz * (4 + s_v) + 4 * (n_rows + 1) + nnz * (8 + s_v)
+    fwd = 4 * (n_rows + 1) + nnz * (4 + s_v) + n_cols * k * s_x + n_rows * k * s_y
     bwd = (4 * (n_cols + 1) + nnz * (4 + s_v) + n_rows * k * s_x + n_cols * k * s_x
            + n_cols * k * s_dx + nnz * s_v)
     return dict(assemble=asm, plan=plan, forward=fwd, backward=bwd)

@@ -64,6 +64,14 @@ typedef enum spm_dtype {
   SPM_BF16 = 2  /* bfloat16, stored as uint16 */
 } spm_dtype;
 
+/* Order of the stored values handed to the forward product:
+ *   SPM_ORDER_CSC   val[p] for CSC slot p (as assembled); the product reads val[perm[q]].
+ *   SPM_ORDER_PLAN  val[q] for plan slot q, i.e. val_csc[perm[q]] (as written by
+ *                   spm_csc_plan_build with values); the product reads val[q] contiguously.
+ * Plan-order values are a copy: after the CSC values change they must be rebuilt (or the
+ * CSC order used). */
+typedef enum spm_val_order { SPM_ORDER_CSC = 0, SPM_ORDER_PLAN = 1 } spm_val_order;
+
 /* Human-readable name of a status code (static string, never NULL). */
 const char *spm_status_string(int status);
 
@@ -112,25 +120,33 @@ spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
 
 /* Build the plan of the CSC pattern (col_ptr[n_cols+1], row_idx[nnz]) where nnz =
  * col_ptr[n_cols] is read on the device and must not exceed nnz_cap.
+ *   val, val_plan  optional (both NULL, or both given): the CSC values (val_type F64 or F32,
+ *         nnz_cap capacity) and a buffer of nnz_cap elements of the same type that receives
+ *         them in plan order, val_plan[q] = val[perm[q]] (see SPM_ORDER_PLAN).  The values
+ *         travel with the pattern through the grouping, so this costs a contiguous write
+ *         rather than a gather.
  *   info  int32[2]: info[0] = nnz seen, info[1] = 0, SPM_EINVAL (col_ptr not monotone,
  *         col_ptr[0] != 0 or nnz > nnz_cap) or SPM_EBOUNDS (a row index out of range). */
 spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
-                              const int32_t *col_ptr, const int32_t *row_idx, void *plan,
-                              size_t plan_bytes, int32_t *info, void *ws, size_t ws_bytes,
+                              const int32_t *col_ptr, const int32_t *row_idx, const void *val,
+                              spm_dtype val_type, void *plan, size_t plan_bytes,
+                              void *val_plan, int32_t *info, void *ws, size_t ws_bytes,
                               void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Forward product Y = A . X  (Section 3 use case (iv), through the plan of A's pattern).
- *   val      CSC values of A, val_type F64 or F32 (indexed through plan.perm).
+ *   val      values of A, val_type F64 or F32, in val_order: CSC order (indexed through
+ *            plan.perm) or plan order (read contiguously; from spm_csc_plan_build).
  *   X        n_cols x k, x_type F64, F32 or BF16, leading dimension ldx >= k.
  *   Y        n_rows x k, y_type F64 or F32, leading dimension ldy >= k; fully written
  *            (rows with no stored element are 0).
- * Y[r, j] = sum over q in row r, ascending column, of val[perm[q]] * X[col_t[q], j].
+ * Y[r, j] = sum over q in row r, ascending column, of val[perm[q]] * X[col_t[q], j]; the
+ * order of the values changes where they are read from, never the result.
  * ------------------------------------------------------------------------------------------ */
 spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
-                        const void *plan, const void *val, spm_dtype val_type, const void *X,
-                        int64_t ldx, spm_dtype x_type, void *Y, int64_t ldy, spm_dtype y_type,
-                        void *stream);
+                        const void *plan, const void *val, spm_dtype val_type,
+                        spm_val_order val_order, const void *X, int64_t ldx, spm_dtype x_type,
+                        void *Y, int64_t ldy, spm_dtype y_type, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Adjoint of Y = A . X for a loss with dL/dY = G (n_rows x k):

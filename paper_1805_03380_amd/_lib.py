@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "lib", "libspm.so")
 OK, EINVAL, EBOUNDS, EOVERFLOW, EWORKSPACE, EDTYPE, EHIP = range(7)
 # spm_dtype
 F64, F32, BF16 = 0, 1, 2
+# spm_val_order
+ORDER_CSC, ORDER_PLAN = 0, 1
 
 _lib = None
 
@@ -72,10 +74,12 @@ SIGNATURES = {
     "spm_coo_to_csc": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                       c_p, ctypes.c_int, c_p, c_p, ctypes.c_size_t, c_p]),
     "spm_csc_plan_size": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p, c_size_p]),
-    "spm_csc_plan_build": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_size_t,
-                                          c_p, c_p, ctypes.c_size_t, c_p]),
-    "spm_csc_spmm": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int, c_p,
-                                    c_i64, ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p]),
+    "spm_csc_plan_build": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p,
+                                          ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
+                                          c_p]),
+    "spm_csc_spmm": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int,
+                                    ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p, c_i64,
+                                    ctypes.c_int, c_p]),
     "spm_csc_spmm_backward": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, c_p,
                                              ctypes.c_int, c_p, c_i64, c_p, c_i64, ctypes.c_int,
                                              c_p, c_i64, ctypes.c_int, c_p, ctypes.c_int, c_p]),

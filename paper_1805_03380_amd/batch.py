@@ -154,8 +154,8 @@ class PackedBatch:
                                     o["info"].data_ptr() + 8 * b, self.asm_ws.data_ptr(),
                                     self.asm_ws.numel(), h)
             _lib.check(st, "spm_coo_to_csc[%d]" % b)
-            st = lib.spm_csc_plan_build(nr, nc, nz, cp, ri, self.plan.data_ptr(),
-                                        self.plan.numel(), self.plan_info.data_ptr(),
+            st = lib.spm_csc_plan_build(nr, nc, nz, cp, ri, None, _lib.F32, self.plan.data_ptr(),
+                                        self.plan.numel(), None, self.plan_info.data_ptr(),
                                         self.plan_ws.data_ptr(), self.plan_ws.numel(), h)
             _lib.check(st, "spm_csc_plan_build[%d]" % b)
             if keep_plan:
@@ -166,7 +166,8 @@ class PackedBatch:
                 o["perm"][to: to + nz].copy_(pm)
             xp = self.X.data_ptr() + esz_x * int(self.x_off[b])
             gp = self.G.data_ptr() + esz_x * int(self.g_off[b])
-            st = lib.spm_csc_spmm(nr, nc, nz, k, self.plan.data_ptr(), vo, _lib.F32, xp, k, xt,
+            st = lib.spm_csc_spmm(nr, nc, nz, k, self.plan.data_ptr(), vo, _lib.F32,
+                                  _lib.ORDER_CSC, xp, k, xt,
                                   o["Y"].data_ptr() + 4 * int(self.g_off[b]), k, _lib.F32, h)
             _lib.check(st, "spm_csc_spmm[%d]" % b)
             st = lib.spm_csc_spmm_backward(nr, nc, nz, k, cp, ri, vo, _lib.F32, gp, k, xp, k, xt,

@@ -219,7 +219,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
 struct PlanLayout {
   PartParams pp;
   size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
-  size_t colarr, table, rowoff, btot, bstart, brec, flags, total;
+  size_t colarr, table, rowoff, btot, bstart, brec, bvhi, flags, total;
   int64_t sort_tiles;
 };
 
@@ -251,6 +251,7 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_cap) {
   L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
   L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
   L.brec = c.take(16 * (size_t)nP);
+  L.bvhi = c.take(sizeof(uint32_t) * (size_t)nP);  // high words of float64 values
   // status flags: one per k_expand_columns workgroup, then one per k_part_hist tile
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) + L.pp.ntiles : 0));
   L.total = c.off;
@@ -318,19 +319,28 @@ void launch_fold(const uint64_t* keys, const int32_t* colstart, int64_t n_cols, 
 // which computes the same values in the same order.
 template <typename VT, typename XT, typename ACC>
 void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G, bool full,
-                  const int32_t* row_ptr, const int32_t* col_t,
+                  bool pv, const int32_t* row_ptr, const int32_t* col_t,
                   const int32_t* perm, const void* val, const void* X, int64_t ldx, int xal,
                   void* Y, int64_t ldy, int y_f64, int yal, int grid, int block, hipStream_t s) {
-#define SPM_CALL_F(GW, F)                                                                      \
-  k_spmm_fwd<VT, XT, ACC, GW, F><<<dim3(grid), dim3(block), 0, s>>>(                           \
-      n_rows, n_cols, nnz_cap, k, row_ptr, col_t, perm, static_cast<const VT*>(val),           \
+  // plan-order values: the full kernels take them as a template flag, the general kernel
+  // as perm == nullptr
+  const int32_t* gperm = pv ? nullptr : perm;
+#define SPM_CALL_F(GW, F, PV, PERM)                                                            \
+  k_spmm_fwd<VT, XT, ACC, GW, F, PV><<<dim3(grid), dim3(block), 0, s>>>(                       \
+      n_rows, n_cols, nnz_cap, k, row_ptr, col_t, PERM, static_cast<const VT*>(val),           \
       static_cast<const XT*>(X), ldx, xal, Y, ldy, y_f64, yal)
-#define SPM_CALL(GW) SPM_CALL_F(GW, false)
-  if (full && G == 8) SPM_CALL_F(8, true);
-  else if (full && G == 16) SPM_CALL_F(16, true);
-  else if (full && G == 32) SPM_CALL_F(32, true);
+#define SPM_CALL_FULL(GW)                                                                      \
+  do {                                                                                         \
+    if (pv) SPM_CALL_F(GW, true, true, perm);                                                  \
+    else SPM_CALL_F(GW, true, false, perm);                                                    \
+  } while (0)
+#define SPM_CALL(GW) SPM_CALL_F(GW, false, false, gperm)
+  if (full && G == 8) SPM_CALL_FULL(8);
+  else if (full && G == 16) SPM_CALL_FULL(16);
+  else if (full && G == 32) SPM_CALL_FULL(32);
   else SPM_GW_SWITCH(G, SPM_CALL)
 #undef SPM_CALL
+#undef SPM_CALL_FULL
 #undef SPM_CALL_F
 }
 
@@ -456,7 +466,8 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
   k_part_level2<kNT, kPartCap, false, VT><<<dim3((unsigned)P.CB), dim3(kNT), lds, s>>>(        \
       P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi, bucket,  \
       scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,                        \
-      static_cast<const VT*>(val), col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b));        \
+      static_cast<const VT*>(val), (VT*)nullptr, col_ptr, trow, tval, bkept,                   \
+      sub_shift(n_rows, P.b));                                                                 \
   } while (0)
     if (val_type == SPM_F64) SPM_L2(double);
     else if (val_type == SPM_F32) SPM_L2(float);
@@ -525,22 +536,15 @@ spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, si
   return SPM_OK;
 }
 
-spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
-                              const int32_t* col_ptr, const int32_t* row_idx, void* plan,
-                              size_t plan_bytes, int32_t* info, void* ws, size_t ws_bytes,
-                              void* stream) {
-  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
-  if (st != SPM_OK) return st;
-  if (!col_ptr || !plan || !info || !ws) return SPM_EINVAL;
-  if (nnz_cap > 0 && !row_idx) return SPM_EINVAL;
-  if (!aligned(ws, 256) || !aligned(plan, 256)) return SPM_EINVAL;
-  const PlanParts P = plan_parts(n_rows, nnz_cap);
-  const PlanLayout L = plan_ws_layout(n_rows, n_cols, nnz_cap);
-  if (plan_bytes < P.total || ws_bytes < L.total) return SPM_EWORKSPACE;
+}  // extern "C"
 
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
-  char* pl = static_cast<char*>(plan);
+namespace {
+
+// Plan build for one value type VT (the type of the optional values carried to plan order).
+template <typename VT>
+void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t* col_ptr,
+                  const int32_t* row_idx, const VT* val, VT* val_plan, char* pl, int32_t* info,
+                  char* w, const PlanParts& P, const PlanLayout& L, hipStream_t s) {
   uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
   uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
@@ -548,11 +552,10 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
   int32_t* row_ptr = reinterpret_cast<int32_t*>(pl + P.row_ptr);
   int32_t* col_t = reinterpret_cast<int32_t*>(pl + P.col_t);
   int32_t* perm = reinterpret_cast<int32_t*>(pl + P.perm);
-
-  (void)hipGetLastError();
   const int cap = cu_count() * 16;
   if (L.pp.ok) {
-    // two-level partition by row: no device-wide atomics, no inter-workgroup waiting
+    // two-level partition by row: no device-wide atomics, no inter-workgroup waiting; the
+    // values (if any) travel in the partition records
     const PartParams& Q = L.pp;
     int32_t* colarr = reinterpret_cast<int32_t*>(w + L.colarr);
     uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
@@ -560,6 +563,7 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
     int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
     uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
+    uint32_t* bvhi = reinterpret_cast<uint32_t*>(w + L.bvhi);
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
     k_expand_columns<kNT><<<dim3(expand_grid(n_cols)), dim3(kNT), 0, s>>>(
         col_ptr, n_cols, nnz_cap, colarr, info, flags);
@@ -570,14 +574,14 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
         (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
         (int64_t)expand_grid(n_cols) + Q.ntiles, info);
-    k_part_scatter<kPartNT, PartSrcCsc, float>
+    k_part_scatter<kPartNT, PartSrcCsc, VT>
         <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
             src, Q.b, Q.CB, Q.ntiles, Q.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
-            bstart, brec, (const float*)nullptr, (uint32_t*)nullptr);
-    k_part_level2<kNT, kPartCap, true, float>
+            bstart, brec, val_plan ? val : (const VT*)nullptr, bvhi);
+    k_part_level2<kNT, kPartCap, true, VT>
         <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(
-            Q.b, n_rows, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)nullptr,
-            bucket, scratch, row_ptr, col_t, perm, (const float*)nullptr, (int32_t*)nullptr,
+            Q.b, n_rows, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi,
+            bucket, scratch, row_ptr, col_t, perm, val, val_plan, (int32_t*)nullptr,
             (uint32_t*)nullptr, (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b));
   } else {
     k_zero2<<<dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)), dim3(kNT), 0, s>>>(
@@ -596,15 +600,49 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
           (const int32_t*)row_ptr, n_rows, (int64_t)kSortT, L.sort_tiles, first);
       k_segsort<kNT, kSortCap, true><<<dim3((unsigned)L.sort_tiles), dim3(kNT), 0, s>>>(
           bucket, row_ptr, n_rows, (int64_t)kSortT, (const int32_t*)first, scratch, col_t, perm);
+      if (val_plan)
+        k_plan_values<kNT, VT><<<dim3(grid_for(nnz_cap, kNT * 4, cap)), dim3(kNT), 0, s>>>(
+            col_ptr, n_cols, nnz_cap, perm, val, val_plan);
     }
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                              const int32_t* col_ptr, const int32_t* row_idx, const void* val,
+                              spm_dtype val_type, void* plan, size_t plan_bytes,
+                              void* val_plan, int32_t* info, void* ws, size_t ws_bytes,
+                              void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  if (!col_ptr || !plan || !info || !ws) return SPM_EINVAL;
+  if (nnz_cap > 0 && !row_idx) return SPM_EINVAL;
+  if ((val == nullptr) != (val_plan == nullptr)) return SPM_EINVAL;
+  if (val && val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (!aligned(ws, 256) || !aligned(plan, 256)) return SPM_EINVAL;
+  const PlanParts P = plan_parts(n_rows, nnz_cap);
+  const PlanLayout L = plan_ws_layout(n_rows, n_cols, nnz_cap);
+  if (plan_bytes < P.total || ws_bytes < L.total) return SPM_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (val && val_type == SPM_F64)
+    plan_build_t<double>(n_rows, n_cols, nnz_cap, col_ptr, row_idx,
+                         static_cast<const double*>(val), static_cast<double*>(val_plan),
+                         static_cast<char*>(plan), info, static_cast<char*>(ws), P, L, s);
+  else
+    plan_build_t<float>(n_rows, n_cols, nnz_cap, col_ptr, row_idx,
+                        static_cast<const float*>(val), static_cast<float*>(val_plan),
+                        static_cast<char*>(plan), info, static_cast<char*>(ws), P, L, s);
   return launch_status();
 }
 
 spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
-                        const void* plan, const void* val, spm_dtype val_type, const void* X,
-                        int64_t ldx, spm_dtype x_type, void* Y, int64_t ldy, spm_dtype y_type,
-                        void* stream) {
+                        const void* plan, const void* val, spm_dtype val_type,
+                        spm_val_order val_order, const void* X, int64_t ldx, spm_dtype x_type,
+                        void* Y, int64_t ldy, spm_dtype y_type, void* stream) {
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (k < 1 || ldx < k || ldy < k) return SPM_EINVAL;
@@ -612,6 +650,7 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
       (n_rows > 0 && ldy > INT64_MAX / n_rows))
     return SPM_EOVERFLOW;
   if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (val_order != SPM_ORDER_CSC && val_order != SPM_ORDER_PLAN) return SPM_EINVAL;
   if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
   if (y_type != SPM_F64 && y_type != SPM_F32) return SPM_EDTYPE;
   if (!plan || !Y || (nnz_cap > 0 && !val) || (n_cols > 0 && !X)) return SPM_EINVAL;
@@ -636,8 +675,9 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
   // needs at least one dense row.
   const bool full = k == 4 * (int64_t)G && xal && yal && n_cols > 0;
 #define SPM_FWD(VT, XT, ACC)                                                                  \
-  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, row_ptr, col_t, perm, val, X, \
-                            ldx, xal, Y, ldy, y_f64, yal, grid, block, s)
+  launch_fwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, val_order == SPM_ORDER_PLAN,  \
+                            row_ptr, col_t, perm, val, X, ldx, xal, Y, ldy, y_f64, yal, grid, \
+                            block, s)
   if (val_type == SPM_F64) {
     if (x_type == SPM_F64) SPM_FWD(double, double, double);
     else if (x_type == SPM_F32) SPM_FWD(double, float, double);

@@ -379,6 +379,7 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
                                         const uint32_t* __restrict__ bvhi,
                                         int32_t* __restrict__ row_ptr,
                                         int32_t* __restrict__ col_t, int32_t* __restrict__ perm,
+                                        VT* __restrict__ val_plan,
                                         int32_t* __restrict__ col_rel,
                                         uint32_t* __restrict__ trow, double* __restrict__ tval,
                                         uint32_t* __restrict__ bkept) {
@@ -406,7 +407,8 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
       // clamped: a malformed CSC handed to the plan may carry any column word
       const uint32_t sub = min((uint32_t)(ky[u] >> 32) >> rshift, rmax);
       sg[u] = (r.z << lr) | sub;
-      if (!PLAN) vv[u] = ValWords<VT>::make(r.w, ValWords<VT>::kHi ? bvhi[B.bstart + i] : 0u);
+      if (!PLAN || val_plan)
+        vv[u] = ValWords<VT>::make(r.w, ValWords<VT>::kHi ? bvhi[B.bstart + i] : 0u);
     }
   }
   __syncthreads();  // cnt cleared
@@ -465,6 +467,14 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
       const uint64_t key = s_in[i];
       col_t[B.bstart + i] = (int32_t)(key >> 32);
       perm[B.bstart + i] = (int32_t)(uint32_t)key;
+    }
+    if (val_plan) {  // the values follow their keys to the sorted slots (s_key is dead)
+      double* s_pv = reinterpret_cast<double*>(s_key);
+#pragma unroll
+      for (int u = 0; u < IPT; ++u)
+        if (sg[u] != 0xffffffffu) s_pv[dst[u]] = to_acc<double>(vv[u]);
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < m; i += NT) val_plan[B.bstart + i] = (VT)s_pv[i];
     }
     return;
   }
@@ -549,7 +559,7 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
                                         uint64_t* __restrict__ scratch,
                                         int32_t* __restrict__ row_ptr,
                                         int32_t* __restrict__ col_t, int32_t* __restrict__ perm,
-                                        const VT* __restrict__ val,
+                                        const VT* __restrict__ val, VT* __restrict__ val_plan,
                                         int32_t* __restrict__ col_rel,
                                         uint32_t* __restrict__ trow, double* __restrict__ tval,
                                         uint32_t* __restrict__ bkept) {
@@ -604,7 +614,13 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
   __syncthreads();
   sort_segments<NT, CAP, PLAN>(gk, cnt, 0, nW, scratch + bstart, PLAN ? col_t + bstart : col_t,
                                PLAN ? perm + bstart : perm, L.s_key, L.s_flag, s_b);
-  if (PLAN) return;
+  if (PLAN) {
+    if (val_plan) {  // staged buckets gather their values (val in CSC order, slots < cap)
+      __syncthreads();
+      for (int64_t q = bstart + threadIdx.x; q < bend; q += NT) val_plan[q] = val[perm[q]];
+    }
+    return;
+  }
   __syncthreads();
   // one pass over blocks of CAP sorted (tagged) keys: fold, compact into the temporaries
   uint32_t running = 0;
@@ -661,9 +677,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
     const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
     uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
-    int32_t* __restrict__ perm, const VT* __restrict__ val, int32_t* __restrict__ col_rel,
-    uint32_t* __restrict__ trow, double* __restrict__ tval, uint32_t* __restrict__ bkept,
-    int rshift) {
+    int32_t* __restrict__ perm, const VT* __restrict__ val, VT* __restrict__ val_plan,
+    int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
+    uint32_t* __restrict__ bkept, int rshift) {
   static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
   static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -682,10 +698,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   B.last_bucket = B.seg0 + B.nW >= nseg;
   if (B.m <= CAP)
     l2_fast<NT, CAP, PLAN, VT>(B, L, s_w, l2_sub_log2(b), rshift, brec, bvhi, row_ptr, col_t,
-                               perm, col_rel, trow, tval, bkept);
+                               perm, val_plan, col_rel, trow, tval, bkept);
   else
     l2_slow<NT, CAP, PLAN, VT>(B, L, s_w, s_b, brec, gkeys, scratch, row_ptr, col_t, perm,
-                               val, col_rel, trow, tval, bkept);
+                               val, val_plan, col_rel, trow, tval, bkept);
+}
+
+// Values in plan order for the plans built without the partition: val_plan[q] =
+// val[perm[q]] for q < nnz (nnz = col_ptr[n_cols] clamped to the capacity; a slot outside
+// the capacity, possible only for a malformed CSC, is skipped).
+template <int NT, typename VT>
+__global__ __launch_bounds__(NT) void k_plan_values(const int32_t* __restrict__ col_ptr,
+                                                    int64_t n_cols, int64_t nnz_cap,
+                                                    const int32_t* __restrict__ perm,
+                                                    const VT* __restrict__ val,
+                                                    VT* __restrict__ val_plan) {
+  const int64_t raw = col_ptr[n_cols];
+  const int64_t nnz = raw < 0 ? 0 : (raw > nnz_cap ? nnz_cap : raw);
+  for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < nnz;
+       q += (int64_t)gridDim.x * NT) {
+    const int32_t p = perm[q];
+    if (p >= 0 && (int64_t)p < nnz_cap) val_plan[q] = val[p];
+  }
 }
 
 // Exclusive scan of n counts by ONE workgroup: out[i] = sum in[0..i), out[n] = total.  Used

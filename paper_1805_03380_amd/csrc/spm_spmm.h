@@ -106,8 +106,9 @@ __device__ __forceinline__ void vload4(const bf16_t* __restrict__ p, ACC (&o)[4]
   o[3] = (ACC)__uint_as_float(v.y & 0xffff0000u);
 }
 
-// Forward, full aligned pieces (k == 4*GW): lane lg owns columns [4 lg, 4 lg + 4).
-template <typename VT, typename XT, typename ACC, int GW>
+// Forward, full aligned pieces (k == 4*GW): lane lg owns columns [4 lg, 4 lg + 4).  PV: the
+// values are in plan order (val[q], read contiguously) instead of CSC order (val[perm[q]]).
+template <typename VT, typename XT, typename ACC, int GW, bool PV = false>
 __device__ __forceinline__ void spmm_row_full(int64_t r, int lg, int64_t n_cols, int64_t nnz_cap,
                                               const int32_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col_t,
@@ -129,7 +130,7 @@ __device__ __forceinline__ void spmm_row_full(int64_t r, int lg, int64_t n_cols,
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       c[u] = col_t[q + u];
-      pp[u] = perm[q + u];
+      pp[u] = PV ? (int32_t)(q + u) : perm[q + u];
       ok[u] = (uint32_t)c[u] < (uint64_t)n_cols && (uint32_t)pp[u] < (uint64_t)nnz_cap;
       c[u] = ok[u] ? c[u] : 0;
       pp[u] = ok[u] ? pp[u] : 0;
@@ -148,7 +149,7 @@ __device__ __forceinline__ void spmm_row_full(int64_t r, int lg, int64_t n_cols,
     }
   }
   for (; q < q1; ++q) {
-    int32_t c = col_t[q], pq = perm[q];
+    int32_t c = col_t[q], pq = PV ? (int32_t)q : perm[q];
     const bool ok = (uint32_t)c < (uint64_t)n_cols && (uint32_t)pq < (uint64_t)nnz_cap;
     c = ok ? c : 0;
     pq = ok ? pq : 0;
@@ -283,7 +284,7 @@ __device__ __forceinline__ void spmm_row(int64_t r, int lg, int64_t k, int64_t n
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         c[u] = col_t[q + u];
-        pp[u] = perm[q + u];
+        pp[u] = perm ? perm[q + u] : (int32_t)(q + u);
         ok[u] = (uint32_t)c[u] < (uint64_t)n_cols && (uint32_t)pp[u] < (uint64_t)nnz_cap;
       }
 #pragma unroll
@@ -297,7 +298,7 @@ __device__ __forceinline__ void spmm_row(int64_t r, int lg, int64_t k, int64_t n
         for (int e = 0; e < 4; ++e) acc[e] = fma_acc<ACC>(v[u], x[u][e], acc[e]);
     }
     for (; q < q1; ++q) {
-      const int32_t c = col_t[q], pq = perm[q];
+      const int32_t c = col_t[q], pq = perm ? perm[q] : (int32_t)q;
       const bool ok = (uint32_t)c < (uint64_t)n_cols && (uint32_t)pq < (uint64_t)nnz_cap;
       const ACC v = ok ? to_acc<ACC>(val[pq]) : (ACC)0;
       ACC x[4];
@@ -431,7 +432,8 @@ __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, 
   }
 }
 
-template <typename VT, typename XT, typename ACC, int GW, bool FULL>
+// perm == nullptr (general path) or PV (full path): values in plan order.
+template <typename VT, typename XT, typename ACC, int GW, bool FULL, bool PV>
 __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                                                   int64_t k, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_t,
@@ -446,8 +448,8 @@ __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols
   for (int64_t r = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / GW; r < n_rows;
        r += ngroups)
     if constexpr (FULL)
-      spmm_row_full<VT, XT, ACC, GW>(r, lg, n_cols, nnz_cap, row_ptr, col_t, perm, val, X, ldx,
-                                     Y, ldy, y_f64 != 0);
+      spmm_row_full<VT, XT, ACC, GW, PV>(r, lg, n_cols, nnz_cap, row_ptr, col_t, perm, val, X,
+                                         ldx, Y, ldy, y_f64 != 0);
     else
       spmm_row<VT, XT, ACC, GW, false>(r, lg, k, n_cols, nnz_cap, row_ptr, col_t, perm, val, X,
                                        ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);

@@ -136,18 +136,27 @@ def plan_size(n_rows: int, n_cols: int, nnz_cap: int):
     return pb.value, wb.value
 
 
-def build_plan(A: CSCMatrix, check: bool = True) -> torch.Tensor:
-    """Row index of A's pattern (spm_csc_plan_build), as a uint8 device buffer."""
+def build_plan(A: CSCMatrix, check: bool = True, values: torch.Tensor | None = None,
+               values_plan: torch.Tensor | None = None) -> torch.Tensor:
+    """Row index of A's pattern (spm_csc_plan_build), as a uint8 device buffer.  With
+    `values` (CSC order) and `values_plan` (same type and capacity), the values are also
+    written in plan order (for spmm(..., order="plan"))."""
     _require_cuda(A.col_ptr)
+    if (values is None) != (values_plan is None):
+        raise ValueError("values and values_plan go together")
+    if values is not None and values.dtype != values_plan.dtype:
+        raise ValueError("values and values_plan must share one element type")
     lib = _lib.load()
     cap = A.nnz_cap
     pb, wb = plan_size(A.n_rows, A.n_cols, cap)
     plan = torch.empty(max(pb, 256), dtype=torch.uint8, device=A.device)
     ws = _workspace(wb, A.device)
     info = torch.empty(2, dtype=torch.int32, device=A.device)
+    vt = _dtype_code(values.dtype) if values is not None else _lib.F32
     st = lib.spm_csc_plan_build(A.n_rows, A.n_cols, cap, _ptr(A.col_ptr),
-                                _ptr(A.row_idx_buf) if cap else None, _ptr(plan), plan.numel(),
-                                _ptr(info), _ptr(ws), ws.numel(), _stream(A.device))
+                                _ptr(A.row_idx_buf) if cap else None, _ptr(values), vt,
+                                _ptr(plan), plan.numel(), _ptr(values_plan), _ptr(info),
+                                _ptr(ws), ws.numel(), _stream(A.device))
     _lib.check(st, "spm_csc_plan_build")
     plan._ws = ws
     if check:
@@ -174,8 +183,14 @@ def _out_type(vt: torch.dtype, xt: torch.dtype) -> torch.dtype:
 
 def spmm(A: CSCMatrix, X: torch.Tensor, values: torch.Tensor | None = None,
          out_dtype: torch.dtype | None = None, plan: torch.Tensor | None = None,
-         out: torch.Tensor | None = None) -> torch.Tensor:
-    """Y = A.X (spm_csc_spmm).  X is n_cols x k (or a vector of length n_cols)."""
+         out: torch.Tensor | None = None, order: str = "csc") -> torch.Tensor:
+    """Y = A.X (spm_csc_spmm).  X is n_cols x k (or a vector of length n_cols).  `order`
+    says whether `values` are in CSC order ("csc") or plan order ("plan", from
+    build_plan(..., values_plan=...))."""
+    if order not in ("csc", "plan"):
+        raise ValueError("order must be 'csc' or 'plan'")
+    if order == "plan" and values is None:
+        raise ValueError("plan-order values must be passed explicitly")
     vec = X.dim() == 1
     X2 = X.reshape(-1, 1) if vec else X
     _require_cuda(X2, A.col_ptr)
@@ -192,8 +207,10 @@ def spmm(A: CSCMatrix, X: torch.Tensor, values: torch.Tensor | None = None,
     Y = out if out is not None else torch.empty(A.n_rows, k, dtype=out_dtype, device=X2.device)
     lib = _lib.load()
     st = lib.spm_csc_spmm(A.n_rows, A.n_cols, A.nnz_cap, k, _ptr(plan), _ptr(v),
-                          _dtype_code(v.dtype), _ptr(X2), X2.stride(0), _dtype_code(X2.dtype),
-                          _ptr(Y), Y.stride(0), _dtype_code(Y.dtype), _stream(X2.device))
+                          _dtype_code(v.dtype),
+                          _lib.ORDER_PLAN if order == "plan" else _lib.ORDER_CSC, _ptr(X2),
+                          X2.stride(0), _dtype_code(X2.dtype), _ptr(Y), Y.stride(0),
+                          _dtype_code(Y.dtype), _stream(X2.device))
     _lib.check(st, "spm_csc_spmm")
     return Y.reshape(-1) if vec else Y
 

@@ -4,6 +4,8 @@ All buffers (outputs, plan, workspaces) are allocated once for a given problem s
 step enqueues exactly the four library calls on one stream with no allocation and no host
 synchronisation: spm_coo_to_csc, spm_csc_plan_build, spm_csc_spmm, spm_csc_spmm_backward.
 The CSC capacity is nnz_in; kernels read the true nnz from col_ptr[n_cols] on the device.
+The plan build also writes the assembled values in plan order (they are fixed for the step),
+so the forward product reads them contiguously (SPM_ORDER_PLAN).
 """
 from __future__ import annotations
 
@@ -44,6 +46,7 @@ class Pipeline:
         self.plan = torch.empty(max(pb, 256), dtype=torch.uint8, device=d)
         self.plan_ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=d)
         self.plan_info = torch.zeros(2, dtype=torch.int32, device=d)
+        self.values_plan = torch.empty(cap, dtype=self.csc_dtype, device=d)
         self.Y = torch.empty(n_rows, k, dtype=self.y_dtype, device=d)
         self.dX = torch.empty(n_cols, k, dtype=self.dx_dtype, device=d)
         self.dval = torch.empty(cap, dtype=self.csc_dtype, device=d)
@@ -66,16 +69,19 @@ class Pipeline:
         if events is not None:
             events[1].record(s)
         _lib.check(lib.spm_csc_plan_build(n_rows, n_cols, nnz, self.col_ptr.data_ptr(),
-                                          self.row_idx.data_ptr(), self.plan.data_ptr(),
-                                          self.plan.numel(), self.plan_info.data_ptr(),
-                                          self.plan_ws.data_ptr(), self.plan_ws.numel(), h),
+                                          self.row_idx.data_ptr(), self.values.data_ptr(),
+                                          _DT[self.csc_dtype], self.plan.data_ptr(),
+                                          self.plan.numel(), self.values_plan.data_ptr(),
+                                          self.plan_info.data_ptr(), self.plan_ws.data_ptr(),
+                                          self.plan_ws.numel(), h),
                    "spm_csc_plan_build")
         if events is not None:
             events[2].record(s)
         _lib.check(lib.spm_csc_spmm(n_rows, n_cols, nnz, k, self.plan.data_ptr(),
-                                    self.values.data_ptr(), _DT[self.csc_dtype], X.data_ptr(),
-                                    X.stride(0), _DT[X.dtype], self.Y.data_ptr(),
-                                    self.Y.stride(0), _DT[self.y_dtype], h), "spm_csc_spmm")
+                                    self.values_plan.data_ptr(), _DT[self.csc_dtype],
+                                    _lib.ORDER_PLAN, X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                    self.Y.data_ptr(), self.Y.stride(0), _DT[self.y_dtype], h),
+                   "spm_csc_spmm")
         if events is not None:
             events[3].record(s)
         _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
@@ -101,9 +107,11 @@ class Pipeline:
                                       self.asm_ws.data_ptr(), self.asm_ws.numel(), h),
                    "spm_coo_to_csc")
         _lib.check(lib.spm_csc_plan_build(n_rows, n_cols, nnz, self.col_ptr.data_ptr(),
-                                          self.row_idx.data_ptr(), self.plan.data_ptr(),
-                                          self.plan.numel(), self.plan_info.data_ptr(),
-                                          self.plan_ws.data_ptr(), self.plan_ws.numel(), h),
+                                          self.row_idx.data_ptr(), self.values.data_ptr(),
+                                          _DT[self.csc_dtype], self.plan.data_ptr(),
+                                          self.plan.numel(), self.values_plan.data_ptr(),
+                                          self.plan_info.data_ptr(), self.plan_ws.data_ptr(),
+                                          self.plan_ws.numel(), h),
                    "spm_csc_plan_build")
 
     def step_spmm(self, X, G, stream=None):
@@ -113,9 +121,10 @@ class Pipeline:
         lib = self.lib
         n_rows, n_cols, nnz, k = self.n_rows, self.n_cols, self.nnz_in, self.k
         _lib.check(lib.spm_csc_spmm(n_rows, n_cols, nnz, k, self.plan.data_ptr(),
-                                    self.values.data_ptr(), _DT[self.csc_dtype], X.data_ptr(),
-                                    X.stride(0), _DT[X.dtype], self.Y.data_ptr(),
-                                    self.Y.stride(0), _DT[self.y_dtype], h), "spm_csc_spmm")
+                                    self.values_plan.data_ptr(), _DT[self.csc_dtype],
+                                    _lib.ORDER_PLAN, X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                    self.Y.data_ptr(), self.Y.stride(0), _DT[self.y_dtype], h),
+                   "spm_csc_spmm")
         _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
                                              self.row_idx.data_ptr(), self.values.data_ptr(),
                                              _DT[self.csc_dtype], G.data_ptr(), G.stride(0),

@@ -79,17 +79,24 @@ def test_host_validation_rejects_before_launch():
     assert c2c(w=ctypes.c_void_p(0x100010)) == _lib.EINVAL  # not 256-byte aligned
     assert c2c(wsb=16) == _lib.EWORKSPACE
     # spmm / backward argument checks
-    assert lib.spm_csc_spmm(4, 4, 8, 0, fake, fake, _lib.F32, fake, 4, _lib.F32, fake, 4,
+    csc = _lib.ORDER_CSC
+    assert lib.spm_csc_spmm(4, 4, 8, 0, fake, fake, _lib.F32, csc, fake, 4, _lib.F32, fake, 4,
                             _lib.F32, None) == _lib.EINVAL
-    assert lib.spm_csc_spmm(4, 4, 8, 8, fake, fake, _lib.F32, fake, 4, _lib.F32, fake, 8,
+    assert lib.spm_csc_spmm(4, 4, 8, 8, fake, fake, _lib.F32, csc, fake, 4, _lib.F32, fake, 8,
                             _lib.F32, None) == _lib.EINVAL  # ldx < k
-    assert lib.spm_csc_spmm(4, 4, 8, 4, fake, fake, _lib.BF16, fake, 4, _lib.F32, fake, 4,
+    assert lib.spm_csc_spmm(4, 4, 8, 4, fake, fake, _lib.BF16, csc, fake, 4, _lib.F32, fake, 4,
                             _lib.F32, None) == _lib.EDTYPE
+    assert lib.spm_csc_spmm(4, 4, 8, 4, fake, fake, _lib.F32, 7, fake, 4, _lib.F32, fake, 4,
+                            _lib.F32, None) == _lib.EINVAL  # unknown value order
     assert lib.spm_csc_spmm_backward(4, 4, 8, 4, None, fake, fake, _lib.F32, fake, 4, fake, 4,
                                      _lib.F32, fake, 4, _lib.F32, fake, _lib.F32,
                                      None) == _lib.EINVAL
-    assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, 16, fake, ws, 1 << 30,
-                                  None) == _lib.EWORKSPACE
+    assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, None, _lib.F32, fake, 16, None, fake, ws,
+                                  1 << 30, None) == _lib.EWORKSPACE
+    assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, _lib.F32, fake, 1 << 20, None,
+                                  fake, ws, 1 << 30, None) == _lib.EINVAL  # val without val_plan
+    assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, _lib.BF16, fake, 1 << 20, fake,
+                                  fake, ws, 1 << 30, None) == _lib.EDTYPE
 
 
 def test_tuning_roundtrip():

@@ -77,6 +77,50 @@ def test_plan_giant_row():
     _check_plan(A, _ref(p))
 
 
+def _plan_values_case(p, value_dtype, k):
+    """Values carried to plan order by the plan build: exactly values[perm], and a forward
+    product reading them (order="plan") bitwise equal to the CSC-order product."""
+    A = assemble_gpu(p)
+    vals = A.values_buf.to(value_dtype)
+    vplan = torch.empty_like(vals)
+    plan = ops.build_plan(A, values=vals, values_plan=vplan)
+    _, _, perm = ops.plan_arrays(plan, A.n_rows, A.nnz_cap)
+    n = A.nnz
+    pm = perm[:n].long()
+    assert torch.equal(vplan[:n], vals[pm])
+    rng = np.random.Generator(np.random.PCG64(77))
+    X = dev(rng.standard_normal((A.n_cols, k)), torch.float32)
+    Y_csc = ops.spmm(A, X, values=vals, plan=plan)
+    Y_plan = ops.spmm(A, X, values=vplan, plan=plan, order="plan")
+    torch.cuda.synchronize()
+    assert torch.equal(Y_csc, Y_plan)
+
+
+@pytest.mark.parametrize("value_dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k", [64, 5])
+def test_plan_order_values(value_dtype, k):
+    p = synth.random_coo(31, 3000, 2000, 60_000, dup_frac=0.1, dist="normal")
+    _plan_values_case(p, value_dtype, k)
+
+
+def test_plan_order_values_giant_row():
+    """A row longer than one in-LDS bucket: its values are gathered on the staged path."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    n = 30_000
+    row = np.concatenate([np.full(12_000, 5), rng.integers(0, 100, n)]).astype(np.int32)
+    col = np.concatenate([rng.permutation(20_000)[:12_000],
+                          rng.integers(0, 20_000, n)]).astype(np.int32)
+    p = synth.COOProblem("grv", 100, 20_000, row, col, rng.standard_normal(row.size))
+    _plan_values_case(p, torch.float64, 64)
+
+
+def test_plan_order_requires_values():
+    p = synth.random_coo(32, 50, 40, 300)
+    A = assemble_gpu(p)
+    with pytest.raises(ValueError):
+        ops.spmm(A, dev(np.ones((40, 4)), torch.float32), order="plan")
+
+
 def test_tiny_spmv_f64():
     p = synth.tiny_spmv()
     A, R = _run(p, None, torch.float64)
