@@ -74,6 +74,48 @@ __device__ __forceinline__ ACC group_sum(ACC d) {
   return d;
 }
 
+// One exchange step of the lane tree: the partner lane differs in lane bit B (and, for the
+// mirrors, in the bits below it).
+template <int B, typename ACC>
+__device__ __forceinline__ ACC exch(ACC x) {
+  if constexpr (B == 0) return dpp_mov<0xB1, ACC>(x);        // quad_perm [1,0,3,2]
+  else if constexpr (B == 1) return dpp_mov<0x4E, ACC>(x);   // quad_perm [2,3,0,1]
+  else if constexpr (B == 2) return dpp_mov<0x141, ACC>(x);  // row_half_mirror
+  else if constexpr (B == 3) return dpp_mov<0x140, ACC>(x);  // row_mirror
+  else if constexpr (B == 4) return __shfl_xor(x, 16, kWave);
+  else return __shfl_xor(x, 32, kWave);
+}
+
+template <int B, typename ACC>
+__device__ __forceinline__ ACC exch_sum_down(ACC f) {
+  if constexpr (B >= 0) {
+    f += exch<B, ACC>(f);
+    return exch_sum_down<B - 1, ACC>(f);
+  } else {
+    return f;
+  }
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+// Sums of four values d[0..3] over the GW >= 4 lanes of a group, transposed: the exchanges on
+// the two highest lane bits A and B each keep half of the values (bit A picks {0,1} or
+// {2,3}, bit B one of the pair), the remaining exchanges carry one value, so lane lg ends
+// with the group sum of value v = 2*bit_A + bit_B after log2(GW) + 1 exchanges instead of
+// 4*log2(GW).  The tree is fixed by GW alone; lanes whose bits below B are zero hold one of
+// the four sums each.
+template <int GW, typename ACC>
+__device__ __forceinline__ ACC group_sum4(const ACC (&d)[4], int lg, int& v) {
+  static_assert(GW >= 4 && GW <= 64, "four values need at least four lanes");
+  constexpr int A = ilog2(GW) - 1, B = ilog2(GW) - 2;
+  const bool ba = (lg >> A) & 1, bb = (lg >> B) & 1;
+  const ACC e0 = (ba ? d[2] : d[0]) + exch<A, ACC>(ba ? d[0] : d[2]);
+  const ACC e1 = (ba ? d[3] : d[1]) + exch<A, ACC>(ba ? d[1] : d[3]);
+  const ACC f = (bb ? e1 : e0) + exch<B, ACC>(bb ? e0 : e1);
+  v = 2 * (int)ba + (int)bb;
+  return exch_sum_down<B - 1, ACC>(f);
+}
+
 // ------------------------------------------------------------------------------------------
 // Forward: Y[r, :] for one row r by the GW lanes of a group (lane lg).  Each lane owns the
 // 4-element pieces j0 = (m*GW + lg)*4; for every piece it walks the row's stored elements in
@@ -205,27 +247,28 @@ __device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t
         g[u][e] = ok[u] ? g[u][e] : (ACC)0;
         dx[e] = fma_acc<ACC>(v[u], g[u][e], dx[e]);
       }
-      if (dval) {
-        d[u] = (ACC)0;
+      d[u] = (ACC)0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) d[u] = fma_acc<ACC>(g[u][e], x[e], d[u]);
-        d[u] = group_sum<GW, ACC>(d[u]);
-      }
+      for (int e = 0; e < 4; ++e) d[u] = fma_acc<ACC>(g[u][e], x[e], d[u]);
     }
     if (dval) {
-      // every lane ends with all kU sums; with GW >= kU lanes 0..kU-1 store the kU
-      // consecutive dvalues with one store instruction instead of kU single-lane stores
       if constexpr (GW >= kU) {
-        if (lg < kU) {
-          const ACC dv = lg == 0 ? d[0] : (lg == 1 ? d[1] : (lg == 2 ? d[2] : d[3]));
-          if (dv_f64) static_cast<double*>(dval)[p + lg] = (double)dv;
-          else static_cast<float*>(dval)[p + lg] = (float)dv;
+        // the kU group sums together (group_sum4); the lanes holding them store the kU
+        // consecutive dvalues with one store instruction
+        int vi;
+        const ACC dv = group_sum4<GW, ACC>(d, lg, vi);
+        if ((lg & ((GW / kU) - 1)) == 0) {
+          if (dv_f64) static_cast<double*>(dval)[p + vi] = (double)dv;
+          else static_cast<float*>(dval)[p + vi] = (float)dv;
         }
-      } else if (lg == 0) {
+      } else {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          if (dv_f64) static_cast<double*>(dval)[p + u] = (double)d[u];
-          else static_cast<float*>(dval)[p + u] = (float)d[u];
+          const ACC su = group_sum<GW, ACC>(d[u]);
+          if (lg == 0) {
+            if (dv_f64) static_cast<double*>(dval)[p + u] = (double)su;
+            else static_cast<float*>(dval)[p + u] = (float)su;
+          }
         }
       }
     }
