@@ -196,8 +196,9 @@ __global__ __launch_bounds__(NT) void k_col_scatter(const int32_t* __restrict__ 
 // Segment sorting.  Keys are unique within a segment (they carry an input position or a
 // CSC slot), so every correct sort gives the same result.
 //   chunk_sort : segments [a, b) whose elements fit in LDS (<= CAP); each element's rank in
-//                its segment is counted against the segment's keys in LDS (the keys of one
-//                segment are read by all its lanes at once, an LDS broadcast).
+//                its segment is counted against the segment's keys in LDS, with the segment's
+//                bounds recorded per element first (s_lohi, CAP words) so that the loads are
+//                independent.
 //   giant_sort : one segment longer than CAP, merge-sorted by the workgroup in global
 //                memory (runs of NT by rank, then merge-path merges), ping-ponging with
 //                `tmp`.
@@ -207,9 +208,14 @@ __global__ __launch_bounds__(NT) void k_col_scatter(const int32_t* __restrict__ 
 template <int NT, int CAP, bool PLAN, typename ST>
 __device__ void chunk_sort(uint64_t* __restrict__ keys, const ST* starts, int64_t a, int64_t b,
                            int32_t* __restrict__ out_hi, int32_t* __restrict__ out_lo,
-                           uint64_t* s_key, uint8_t* s_flag) {
+                           uint64_t* s_key, uint32_t* s_lohi) {
+  static_assert(CAP <= 65535, "segment bounds are packed as two 16-bit halves");
+  constexpr int kLong = 64;  // longer segments get their bounds from the whole workgroup
+  __shared__ int32_t s_long[CAP / kLong + 1];
+  __shared__ int32_t s_nlong;
   const int64_t e0 = starts[a];
   const int cnt = (int)((int64_t)starts[b] - e0);
+  if (threadIdx.x == 0) s_nlong = 0;
   constexpr int U = 4;
   for (int i0 = threadIdx.x; i0 < cnt; i0 += NT * U) {
     uint64_t kv[U];
@@ -221,28 +227,40 @@ __device__ void chunk_sort(uint64_t* __restrict__ keys, const ST* starts, int64_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * NT;
-      if (i < cnt) {
-        s_key[i] = kv[u];
-        s_flag[i] = 0;
-      }
+      if (i < cnt) s_key[i] = kv[u];
     }
   }
   __syncthreads();
+  // bounds of every element's segment, packed lo | hi << 16 (chunk-relative): one thread per
+  // short segment, the whole workgroup per long one
   for (int64_t s = a + threadIdx.x; s < b; s += NT) {
-    const int lo = (int)((int64_t)starts[s] - e0);
-    if (lo < cnt) s_flag[lo] = 1;
+    const int lo = (int)((int64_t)starts[s] - e0), hi = (int)((int64_t)starts[s + 1] - e0);
+    if (hi - lo <= kLong) {
+      for (int i = lo; i < hi; ++i) s_lohi[i] = (uint32_t)lo | ((uint32_t)hi << 16);
+    } else {
+      s_long[atomicAdd(&s_nlong, 1)] = (int32_t)(s - a);
+    }
   }
   __syncthreads();
+  for (int q = 0; q < s_nlong; ++q) {
+    const int64_t s = a + s_long[q];
+    const int lo = (int)((int64_t)starts[s] - e0), hi = (int)((int64_t)starts[s + 1] - e0);
+    for (int i = lo + threadIdx.x; i < hi; i += NT)
+      s_lohi[i] = (uint32_t)lo | ((uint32_t)hi << 16);
+  }
+  __syncthreads();
+  // rank of each key in its segment (keys are unique): the bounds are known, so the loads are
+  // independent and issued four at a time
   for (int i = threadIdx.x; i < cnt; i += NT) {
     const uint64_t key = s_key[i];
-    int lo = i;
-    while (!s_flag[lo]) --lo;
-    int r = 0;
-    int j = lo;
-    do {
-      r += (s_key[j] < key) ? 1 : 0;
-      ++j;
-    } while (j < cnt && !s_flag[j]);
+    const uint32_t lh = s_lohi[i];
+    const int lo = (int)(lh & 0xffffu), hi = (int)(lh >> 16);
+    int r = 0, j = lo;
+    for (; j + 4 <= hi; j += 4) {
+      const uint64_t k0 = s_key[j], k1 = s_key[j + 1], k2 = s_key[j + 2], k3 = s_key[j + 3];
+      r += (int)(k0 < key) + (int)(k1 < key) + (int)(k2 < key) + (int)(k3 < key);
+    }
+    for (; j < hi; ++j) r += (int)(s_key[j] < key);
     const int64_t pos = e0 + lo + r;
     if (PLAN) {
       out_hi[pos] = (int32_t)(key >> 32);
@@ -323,7 +341,7 @@ template <int NT, int CAP, bool PLAN, typename ST>
 __device__ void sort_segments(uint64_t* __restrict__ keys, const ST* starts, int64_t a,
                               int64_t b_end, uint64_t* __restrict__ scratch,
                               int32_t* __restrict__ out_hi, int32_t* __restrict__ out_lo,
-                              uint64_t* s_key, uint8_t* s_flag, int64_t* s_b) {
+                              uint64_t* s_key, uint32_t* s_lohi, int64_t* s_b) {
   while (a < b_end) {
     if (threadIdx.x == 0) {
       const int64_t e0 = starts[a];
@@ -338,7 +356,7 @@ __device__ void sort_segments(uint64_t* __restrict__ keys, const ST* starts, int
       giant_sort<NT, PLAN>(keys + e0, n, scratch + e0, e0, out_hi, out_lo, s_key);
       a += 1;
     } else {
-      chunk_sort<NT, CAP, PLAN>(keys, starts, a, b, out_hi, out_lo, s_key, s_flag);
+      chunk_sort<NT, CAP, PLAN>(keys, starts, a, b, out_hi, out_lo, s_key, s_lohi);
       a = b;
     }
   }
@@ -355,7 +373,7 @@ __global__ __launch_bounds__(NT) void k_segsort(uint64_t* __restrict__ keys,
                                                 int32_t* __restrict__ out_hi,
                                                 int32_t* __restrict__ out_lo) {
   __shared__ uint64_t s_key[CAP];
-  __shared__ uint8_t s_flag[CAP];
+  __shared__ uint32_t s_lohi[CAP];
   __shared__ int64_t s_b[3];
   const int64_t N = starts[nseg];
   const int64_t ntiles = N > 0 ? (N + T - 1) / T : 1;
@@ -365,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_segsort(uint64_t* __restrict__ keys,
   int64_t b_end = (t == ntiles - 1) ? nseg : (int64_t)first[t + 1];
   if (a > nseg) a = nseg;
   if (b_end > nseg) b_end = nseg;
-  sort_segments<NT, CAP, PLAN>(keys, starts, a, b_end, scratch, out_hi, out_lo, s_key, s_flag,
+  sort_segments<NT, CAP, PLAN>(keys, starts, a, b_end, scratch, out_hi, out_lo, s_key, s_lohi,
                                &s_b[2]);
 }
 

@@ -52,7 +52,6 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   constexpr int T = NT * kBatchFoldIPT;
   __shared__ uint32_t s_cnt[kBatchMaxLdsDim + 1];
   __shared__ uint64_t s_key[kBatchCap];
-  __shared__ uint8_t s_flag[kBatchCap];
   __shared__ uint32_t s_pre[T + 1];
   __shared__ uint32_t s_w[NT / kWave + 1];
   __shared__ int64_t s_b[4];
@@ -133,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     const int64_t N = cnt[n_c];
     // ---- 4. sort each column's keys --------------------------------------------------------
     sort_segments<NT, kBatchCap, false>(bucket, cnt, 0, n_c, scratch, (int32_t*)nullptr,
-                                        (int32_t*)nullptr, s_key, s_flag, &s_b[0]);
+                                        (int32_t*)nullptr, s_key, s_pre, &s_b[0]);
     __syncthreads();
     // ---- 5. fold, drop zeros, compact, column offsets --------------------------------------
     uint32_t running = 0;
@@ -210,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     __syncthreads();
     for (int64_t i = threadIdx.x; i <= n_r; i += NT) rp[i] = (int32_t)cnt[i];
     sort_segments<NT, kBatchCap, true>(bucket, cnt, 0, n_r, scratch, a.col_t + to, a.perm + to,
-                                       s_key, s_flag, &s_b[0]);
+                                       s_key, s_pre, &s_b[0]);
     __syncthreads();
     // ---- 7. forward Y = A.X and 8. adjoint dX, dval ---------------------------------------
     {

@@ -613,7 +613,8 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
   if (threadIdx.x == 0) cnt[nW] = (uint32_t)m;
   __syncthreads();
   sort_segments<NT, CAP, PLAN>(gk, cnt, 0, nW, scratch + bstart, PLAN ? col_t + bstart : col_t,
-                               PLAN ? perm + bstart : perm, L.s_key, L.s_flag, s_b);
+                               PLAN ? perm + bstart : perm, L.s_key,
+                               reinterpret_cast<uint32_t*>(L.s_in), s_b);
   if (PLAN) {
     if (val_plan) {  // staged buckets gather their values (val in CSC order, slots < cap)
       __syncthreads();

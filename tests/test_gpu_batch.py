@@ -99,19 +99,26 @@ def test_large_dims_global_counters_and_giant_column():
     _oracle_check(pb, o_b, probs, 1)
 
 
-def test_full_batch_workload_bitwise_and_sampled_oracle():
+@pytest.fixture(scope="module")
+def full_batch():
+    return synth.batch_problems()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_full_batch_workload_bitwise_and_sampled_oracle(full_batch, dtype):
     """The 4096-matrix workload (n log-uniform in [64, 8192], 16 triplets per column, 10 %
-    duplicates, k = 32): one persistent launch is bitwise equal to 4096 per-matrix calls, and
-    sampled matrices match the oracle."""
-    bt = synth.batch_problems()
-    pb = PackedBatch(bt.problems)
+    duplicates, k = 32), in float32 and in the bfloat16 variant (values, X and G rounded to
+    bfloat16, binary32 accumulation): one persistent launch is bitwise equal to 4096
+    per-matrix calls, and sampled matrices match the oracle."""
+    bt = full_batch
+    pb = PackedBatch(bt.problems, val_dtype=dtype, x_dtype=dtype)
     o_b = pb.run_batched()
     o_s = pb.run_single(out=pb.new_outputs())
     torch.cuda.synchronize()
     _bitwise_equal(pb, o_b, o_s)
     order = pb.order_host
     for b in [int(order[0]), int(order[-1]), 0, 1234, 4095]:
-        _oracle_check(pb, o_b, bt.problems, b)
+        _oracle_check(pb, o_b, bt.problems, b, acc_f32=(dtype == torch.bfloat16))
 
 
 def test_deterministic_rerun():
