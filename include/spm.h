@@ -134,6 +134,36 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                               void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Assembly and plan in one call (Sections 3.2 -> 3.1 and the row index of Section 3.4): the
+ * same outputs as spm_coo_to_csc followed by spm_csc_plan_build with nnz_cap = nnz_in (and,
+ * when val_plan is given, the assembled values carried to plan order), bit for bit.  The
+ * assembled elements go straight from the assembly's grouping into the plan's, so the plan
+ * does not re-read the CSC it was just given.  Shapes that the fused grouping does not cover
+ * run the two builds one after the other; the results are the same either way.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Plan bytes (as spm_csc_plan_size with nnz_cap = nnz_in) and workspace bytes of
+ * spm_coo_to_csc_plan. */
+spm_status spm_coo_to_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                    size_t *plan_bytes, size_t *ws_bytes);
+
+/* Arguments as in spm_coo_to_csc, plus
+ *   plan       plan buffer (layout above, nnz_cap = nnz_in) of at least plan_bytes, 256-byte
+ *              aligned.
+ *   val_plan   optional (NULL for none): nnz_in elements of out_type; receives the
+ *              assembled values in plan order, val_plan[q] = val_out[perm[q]].
+ *   plan_info  int32[2]: plan_info[0] = nnz_out, plan_info[1] = 0 (the CSC is valid by
+ *              construction; out-of-range triplets are reported in info[1]).
+ *   ws         at least the ws_bytes of spm_coo_to_csc_plan_size, 256-byte aligned.
+ * Errors: as spm_coo_to_csc; SPM_EINVAL also for a NULL or misaligned plan / plan_info. */
+spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                               const int32_t *row, const int32_t *col, const void *val,
+                               spm_dtype val_type, int32_t *col_ptr, int32_t *row_idx,
+                               void *val_out, spm_dtype out_type, int32_t *info, void *plan,
+                               size_t plan_bytes, void *val_plan, int32_t *plan_info, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Forward product Y = A . X  (Section 3 use case (iv), through the plan of A's pattern).
  *   val      values of A, val_type F64 or F32, in val_order: CSC order (indexed through
  *            plan.perm) or plan order (read contiguously; from spm_csc_plan_build).

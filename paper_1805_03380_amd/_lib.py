@@ -77,6 +77,11 @@ SIGNATURES = {
     "spm_csc_plan_build": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p,
                                           ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
                                           c_p]),
+    "spm_coo_to_csc_plan_size": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p, c_size_p]),
+    "spm_coo_to_csc_plan": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int,
+                                           c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
+                                           ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
+                                           c_p]),
     "spm_csc_spmm": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int,
                                     ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p, c_i64,
                                     ctypes.c_int, c_p]),

@@ -272,6 +272,61 @@ PlanParts plan_parts(int64_t n_rows, int64_t nnz_cap) {
   return P;
 }
 
+// Fused assembly + plan (spm_coo_to_csc_plan).  The assembly's survivors are counted per
+// (row bucket, column bucket) and the emit writes them a second time as records of the
+// plan's row partition, so the plan needs no column expansion, histogram or scatter of its
+// own.  Applies when the row partition exists with at most kFuseMaxRowBuckets buckets and
+// the (row bucket x column bucket) table stays small; otherwise the two builds run one after
+// the other on the same workspace.  The plan's records reuse the assembly's record buffers
+// (dead once the assembly's level 2 has run); its level 2 reuses the staging buffers.
+constexpr int64_t kFuseMaxTable = (int64_t)1 << 22;  // entries of the fused table
+static_assert(kFuseMaxRowBuckets <= 2 * kPartCap, "row-bucket counters live in level 2's s_in");
+
+struct FuseLayout {
+  AsmLayout A;
+  PartParams Q;  // plan partition by row (capacity nnz_in)
+  bool fused;
+  size_t table2, rowoff2, btot2, bstart2, total;
+};
+
+FuseLayout fuse_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_in) {
+  FuseLayout F;
+  F.A = asm_layout(n_cols, nnz_in);
+  F.Q = part_params(n_rows, nnz_in);
+  F.fused = F.A.pp.ok && F.Q.ok && nnz_in > 0 && F.Q.CB <= kFuseMaxRowBuckets &&
+            (int64_t)F.Q.CB * F.A.pp.CB <= kFuseMaxTable;
+  if (!F.fused) {
+    F.table2 = F.rowoff2 = F.btot2 = F.bstart2 = 0;
+    F.total = std::max(F.A.total, plan_ws_layout(n_rows, n_cols, nnz_in).total);
+    return F;
+  }
+  Carve c;
+  c.off = F.A.total;
+  const size_t tab = (size_t)F.Q.CB * (size_t)F.A.pp.CB;
+  F.table2 = c.take(sizeof(uint32_t) * tab);
+  F.rowoff2 = c.take(sizeof(uint32_t) * tab);
+  F.btot2 = c.take(sizeof(uint32_t) * (size_t)F.Q.CB);
+  F.bstart2 = c.take(sizeof(int32_t) * ((size_t)F.Q.CB + 1));
+  F.total = c.off;
+  return F;
+}
+
+// What the assembly's partition path needs to also build the plan.
+struct FuseCtx {
+  const FuseLayout* F;
+  int64_t n_rows;
+  const PlanParts* P;
+  char* plan;
+  void* val_plan;  // optional, of the output type
+  int32_t* plan_info;
+};
+
+spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
+                         const int32_t* col, const void* val, spm_dtype val_type,
+                         int32_t* col_ptr, int32_t* row_idx, void* val_out, spm_dtype out_type,
+                         int32_t* info, char* w, const AsmLayout& L, hipStream_t s,
+                         const FuseCtx* fz);
+
 spm_status check_dims(int64_t n_rows, int64_t n_cols, int64_t nnz) {
   if (n_rows < 0 || n_cols < 0 || nnz < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz) || n_cols == INT32_MAX ||
@@ -423,9 +478,32 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
   if (!aligned(ws, 256)) return SPM_EINVAL;
   const AsmLayout L = asm_layout(n_cols, nnz_in);
   if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  return assemble_impl(n_rows, n_cols, nnz_in, row, col, val, val_type, col_ptr, row_idx,
+                       val_out, out_type, info, static_cast<char*>(ws), L,
+                       static_cast<hipStream_t>(stream), nullptr);
+}
 
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
+spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_t* plan_bytes,
+                             size_t* ws_bytes) {
+  if (!plan_bytes || !ws_bytes) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  *plan_bytes = plan_parts(n_rows, nnz_cap).total;
+  *ws_bytes = plan_ws_layout(n_rows, n_cols, nnz_cap).total;
+  return SPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Assembly on a validated argument set.  With fz != nullptr (fused plan, partition path
+// only) the survivors also feed the plan's row partition and the plan's level 2 runs last.
+spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
+                         const int32_t* col, const void* val, spm_dtype val_type,
+                         int32_t* col_ptr, int32_t* row_idx, void* val_out, spm_dtype out_type,
+                         int32_t* info, char* w, const AsmLayout& L, hipStream_t s,
+                         const FuseCtx* fz) {
   uint32_t* colcnt = reinterpret_cast<uint32_t*>(w + L.colcnt);
   uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
   uint64_t* fold_state = reinterpret_cast<uint64_t*>(w + L.fold_state);
@@ -457,6 +535,10 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
     k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
         (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info);
     const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
+    // fused plan: level 2 also counts the survivors per (row bucket, column bucket)
+    const L2RowCount rc = fz ? L2RowCount{reinterpret_cast<uint32_t*>(w + fz->F->table2),
+                                          fz->F->Q.b, fz->F->Q.CB, P.CB}
+                             : L2RowCount{nullptr, 0, 0, 0};
 #define SPM_L2(VT)                                                                             \
   do {                                                                                         \
   k_part_scatter<kPartNT, PartSrcCoo, VT>                                                      \
@@ -467,7 +549,7 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
       P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi, bucket,  \
       scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,                        \
       static_cast<const VT*>(val), (VT*)nullptr, col_ptr, trow, tval, bkept,                   \
-      sub_shift(n_rows, P.b));                                                                 \
+      sub_shift(n_rows, P.b), rc);                                                             \
   } while (0)
     if (val_type == SPM_F64) SPM_L2(double);
     else if (val_type == SPM_F32) SPM_L2(float);
@@ -479,10 +561,45 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
       k_small_scan<kNT><<<dim3(1), dim3(kNT), 0, s>>>(
           (const uint32_t*)bkept, (int64_t)P.CB, boff);
     }
-    k_part_emit<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
+    EmitPlan ep{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t emit_lds = 0;
+    if (fz) {
+      const FuseLayout& F = *fz->F;
+      const PartParams& Q = F.Q;
+      uint32_t* table2 = reinterpret_cast<uint32_t*>(w + F.table2);
+      uint32_t* rowoff2 = reinterpret_cast<uint32_t*>(w + F.rowoff2);
+      uint32_t* btot2 = reinterpret_cast<uint32_t*>(w + F.btot2);
+      int32_t* bstart2 = reinterpret_cast<int32_t*>(w + F.bstart2);
+      // the column buckets are the tiles of the plan's level 1; no status flags to fold
+      k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
+          (const uint32_t*)table2, (int64_t)P.CB, rowoff2, btot2, (const uint32_t*)nullptr,
+          (int64_t)0, fz->plan_info);
+      ep = EmitPlan{Q.b, Q.CB, rowoff2, btot2, bstart2, brec, bvhi, fz->plan_info};
+      emit_lds = 4 * ((size_t)Q.CB + ((size_t)1 << P.b) + 1);
+    }
+    k_part_emit<kNT><<<dim3((unsigned)P.CB), dim3(kNT), emit_lds, s>>>(
         P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint32_t*)bkept, (const int32_t*)boff,
         (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out,
-        out_type == SPM_F64 ? 1 : 0, info);
+        out_type == SPM_F64 ? 1 : 0, info, ep);
+    if (fz) {
+      const PartParams& Q = fz->F->Q;
+      const PlanParts& PP = *fz->P;
+      int32_t* row_ptr = reinterpret_cast<int32_t*>(fz->plan + PP.row_ptr);
+      int32_t* col_t = reinterpret_cast<int32_t*>(fz->plan + PP.col_t);
+      int32_t* perm = reinterpret_cast<int32_t*>(fz->plan + PP.perm);
+      const int32_t* bstart2 = reinterpret_cast<const int32_t*>(w + fz->F->bstart2);
+#define SPM_PL2(VT)                                                                            \
+  k_part_level2<kNT, kPartCap, true, VT>                                                       \
+      <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(          \
+          Q.b, n_rows, bstart2, (const uint4*)brec, (const uint32_t*)bvhi, bucket, scratch,    \
+          row_ptr, col_t, perm, static_cast<const VT*>(val_out),                               \
+          static_cast<VT*>(fz->val_plan), (int32_t*)nullptr, (uint32_t*)nullptr,               \
+          (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b),                        \
+          L2RowCount{nullptr, 0, 0, 0})
+      if (out_type == SPM_F64) SPM_PL2(double);
+      else SPM_PL2(float);
+#undef SPM_PL2
+    }
     return launch_status();
   } else {
     // one counter per column in global memory (shapes with more columns than the partition
@@ -526,20 +643,6 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
   return launch_status();
 }
 
-spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_t* plan_bytes,
-                             size_t* ws_bytes) {
-  if (!plan_bytes || !ws_bytes) return SPM_EINVAL;
-  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
-  if (st != SPM_OK) return st;
-  *plan_bytes = plan_parts(n_rows, nnz_cap).total;
-  *ws_bytes = plan_ws_layout(n_rows, n_cols, nnz_cap).total;
-  return SPM_OK;
-}
-
-}  // extern "C"
-
-namespace {
-
 // Plan build for one value type VT (the type of the optional values carried to plan order).
 template <typename VT>
 void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t* col_ptr,
@@ -582,7 +685,8 @@ void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t
         <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(
             Q.b, n_rows, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi,
             bucket, scratch, row_ptr, col_t, perm, val, val_plan, (int32_t*)nullptr,
-            (uint32_t*)nullptr, (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b));
+            (uint32_t*)nullptr, (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b),
+            L2RowCount{nullptr, 0, 0, 0});
   } else {
     k_zero2<<<dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)), dim3(kNT), 0, s>>>(
         reinterpret_cast<uint32_t*>(w), (int64_t)(L.zero_bytes / 4),
@@ -636,6 +740,56 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
     plan_build_t<float>(n_rows, n_cols, nnz_cap, col_ptr, row_idx,
                         static_cast<const float*>(val), static_cast<float*>(val_plan),
                         static_cast<char*>(plan), info, static_cast<char*>(ws), P, L, s);
+  return launch_status();
+}
+
+spm_status spm_coo_to_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                    size_t* plan_bytes, size_t* ws_bytes) {
+  if (!plan_bytes || !ws_bytes) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, nnz_in);
+  if (st != SPM_OK) return st;
+  *plan_bytes = plan_parts(n_rows, nnz_in).total;
+  *ws_bytes = fuse_layout(n_rows, n_cols, nnz_in).total;
+  return SPM_OK;
+}
+
+spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                               const int32_t* row, const int32_t* col, const void* val,
+                               spm_dtype val_type, int32_t* col_ptr, int32_t* row_idx,
+                               void* val_out, spm_dtype out_type, int32_t* info, void* plan,
+                               size_t plan_bytes, void* val_plan, int32_t* plan_info, void* ws,
+                               size_t ws_bytes, void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_in);
+  if (st != SPM_OK) return st;
+  if (val_type != SPM_F64 && val_type != SPM_F32 && val_type != SPM_BF16) return SPM_EDTYPE;
+  if (out_type != SPM_F64 && out_type != SPM_F32) return SPM_EDTYPE;
+  if (!col_ptr || !info || !plan || !plan_info || !ws) return SPM_EINVAL;
+  if (nnz_in > 0 && (!row || !col || !val || !row_idx || !val_out)) return SPM_EINVAL;
+  if (!aligned(ws, 256) || !aligned(plan, 256)) return SPM_EINVAL;
+  const PlanParts P = plan_parts(n_rows, nnz_in);
+  const FuseLayout F = fuse_layout(n_rows, n_cols, nnz_in);
+  if (plan_bytes < P.total || ws_bytes < F.total) return SPM_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (F.fused) {
+    const FuseCtx fz{&F, n_rows, &P, static_cast<char*>(plan), val_plan, plan_info};
+    return assemble_impl(n_rows, n_cols, nnz_in, row, col, val, val_type, col_ptr, row_idx,
+                         val_out, out_type, info, w, F.A, s, &fz);
+  }
+  // the two builds one after the other on the same workspace
+  st = assemble_impl(n_rows, n_cols, nnz_in, row, col, val, val_type, col_ptr, row_idx,
+                     val_out, out_type, info, w, F.A, s, nullptr);
+  if (st != SPM_OK) return st;
+  const PlanLayout PL = plan_ws_layout(n_rows, n_cols, nnz_in);
+  (void)hipGetLastError();
+  if (out_type == SPM_F64)
+    plan_build_t<double>(n_rows, n_cols, nnz_in, col_ptr, row_idx,
+                         static_cast<const double*>(val_out), static_cast<double*>(val_plan),
+                         static_cast<char*>(plan), plan_info, w, P, PL, s);
+  else
+    plan_build_t<float>(n_rows, n_cols, nnz_in, col_ptr, row_idx,
+                        static_cast<const float*>(val_out), static_cast<float*>(val_plan),
+                        static_cast<char*>(plan), plan_info, w, P, PL, s);
   return launch_status();
 }
 

@@ -22,6 +22,17 @@
 namespace spm {
 
 constexpr int kPartMaxBuckets = 16384;  // coarse buckets per level (LDS counters, <= 64 KB)
+
+// Workgroups go to the chip's 8 XCDs in turn (workgroup i to XCD i mod 8), each XCD with an
+// L2 of its own.  xcd_tile hands the workgroups of one XCD consecutive logical tiles, so that
+// neighbouring columns of a (bucket x tile) table, written or read by neighbouring tiles,
+// meet in one L2 instead of eight.  A bijection of [0, n); results never depend on it.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t q = n / kXcds, r = n % kXcds;
+  const int64_t x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
 constexpr int kPartMaxWidth = 4096;     // segments per coarse bucket (LDS counters)
 
 // Element sources.  part_elem returns false for an element that is skipped (out of range).
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
                                                   uint32_t* __restrict__ flags) {
   __shared__ uint32_t s_flag;
   extern __shared__ uint32_t h[];  // CB counters (dynamic LDS, 4*CB bytes)
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = src.count();
   for (int i = threadIdx.x; i < CB; i += NT) h[i] = 0;
   if (threadIdx.x == 0) s_flag = 0;
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
                                                      uint32_t* __restrict__ bvhi) {
   extern __shared__ uint32_t cur[];  // CB cursors (dynamic LDS, 4*CB bytes)
   __shared__ uint32_t s_w[NT / kWave + 1];
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = src.count();
   // cur[i] = bstart[i] + rowoff[i][t]: the bucket totals are scanned in LDS
   for (int64_t i = threadIdx.x; i < CB; i += NT) cur[i] = btot[i];
@@ -344,6 +355,27 @@ struct L2Bucket {
   bool last_bucket;
 };
 
+// Assembly fused with the plan: the bucket's survivors counted per row bucket (2^br rows),
+// table2[rb * CB + cb] -- the (row bucket x column bucket) table the plan's partition is
+// laid out from.  table2 == nullptr: not counted.  The counters live in s_in (CBr <= CAP * 2
+// u32), which is dead once the survivors are out.
+struct L2RowCount {
+  uint32_t* table2;
+  int br;
+  int32_t CBr;
+  int32_t CB;
+};
+
+template <int NT>
+__device__ __forceinline__ void l2_clear_counts(const L2RowCount& rc, uint32_t* h) {
+  for (int64_t i = threadIdx.x; i < rc.CBr; i += NT) h[i] = 0;
+}
+template <int NT>
+__device__ __forceinline__ void l2_store_counts(const L2RowCount& rc, int64_t cb,
+                                                const uint32_t* h) {
+  for (int64_t i = threadIdx.x; i < rc.CBr; i += NT) rc.table2[i * rc.CB + cb] = h[i];
+}
+
 // LDS views of the dynamic shared memory (layout as in part_level2_lds_bytes).
 template <int CAP>
 struct L2Lds {
@@ -382,7 +414,7 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
                                         VT* __restrict__ val_plan,
                                         int32_t* __restrict__ col_rel,
                                         uint32_t* __restrict__ trow, double* __restrict__ tval,
-                                        uint32_t* __restrict__ bkept) {
+                                        uint32_t* __restrict__ bkept, const L2RowCount& rc) {
   constexpr int IPT = CAP / NT;
   const int64_t m = B.m, nW = B.nW;
   const int64_t nS = nW << lr;  // sub-segments
@@ -527,12 +559,15 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
   const uint32_t kept = s_cw[IPT * NWV];
   const uint64_t lt = (1ull << lane_id()) - 1ull;
   uint32_t rank[IPT];
+  uint32_t orow[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     const int64_t i = (int64_t)u * NT + threadIdx.x;
     rank[u] = s_cw[u * NWV + wave_id()] + (uint32_t)__popcll(bal[u] & lt);
+    orow[u] = 0;
     if ((bal[u] >> lane_id()) & 1ull) {
-      trow[B.bstart + rank[u]] = key_row(s_in[i]);
+      orow[u] = key_row(s_in[i]);
+      trow[B.bstart + rank[u]] = orow[u];
       tval[B.bstart + rank[u]] = s_val[i];
     }
   }
@@ -548,6 +583,16 @@ __device__ __forceinline__ void l2_fast(const L2Bucket& B, const L2Lds<CAP>& L, 
   for (int64_t j = threadIdx.x; j < nW; j += NT)
     col_rel[B.seg0 + j] = (int32_t)s_pre[cnt[j << lr]];
   if (threadIdx.x == 0) bkept[B.cb] = kept;
+  if (rc.table2) {
+    uint32_t* h = reinterpret_cast<uint32_t*>(s_in);  // s_in was last read before a barrier
+    l2_clear_counts<NT>(rc, h);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPT; ++u)
+      if ((bal[u] >> lane_id()) & 1ull) atomicAdd(&h[orow[u] >> rc.br], 1u);
+    __syncthreads();
+    l2_store_counts<NT>(rc, B.cb, h);
+  }
 }
 
 // Slow path (m > CAP): segment scatter through global staging, sort_segments, then
@@ -562,7 +607,7 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
                                         const VT* __restrict__ val, VT* __restrict__ val_plan,
                                         int32_t* __restrict__ col_rel,
                                         uint32_t* __restrict__ trow, double* __restrict__ tval,
-                                        uint32_t* __restrict__ bkept) {
+                                        uint32_t* __restrict__ bkept, const L2RowCount& rc) {
   constexpr int IPT = CAP / NT;
   constexpr int U = 8;
   const int64_t m = B.m, nW = B.nW, bstart = B.bstart, bend = B.bend;
@@ -671,6 +716,16 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
     __syncthreads();
   }
   if (threadIdx.x == 0) bkept[B.cb] = running;
+  if (rc.table2) {
+    // the survivors are back in trow (written by this workgroup before the last barrier)
+    uint32_t* h = reinterpret_cast<uint32_t*>(s_in);
+    l2_clear_counts<NT>(rc, h);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < (int64_t)running; i += NT)
+      atomicAdd(&h[trow[bstart + i] >> rc.br], 1u);
+    __syncthreads();
+    l2_store_counts<NT>(rc, B.cb, h);
+  }
 }
 
 template <int NT, int CAP, bool PLAN, typename VT>
@@ -680,7 +735,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
     int32_t* __restrict__ perm, const VT* __restrict__ val, VT* __restrict__ val_plan,
     int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
-    uint32_t* __restrict__ bkept, int rshift) {
+    uint32_t* __restrict__ bkept, int rshift, L2RowCount rc) {
   static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
   static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -688,7 +743,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ int64_t s_b[3];
   const L2Lds<CAP> L(smem, b);
   L2Bucket B;
-  B.cb = blockIdx.x;
+  B.cb = xcd_tile(blockIdx.x, gridDim.x);
   B.bstart = bstarts[B.cb];
   B.bend = bstarts[B.cb + 1];
   B.m = B.bend - B.bstart;
@@ -699,10 +754,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   B.last_bucket = B.seg0 + B.nW >= nseg;
   if (B.m <= CAP)
     l2_fast<NT, CAP, PLAN, VT>(B, L, s_w, l2_sub_log2(b), rshift, brec, bvhi, row_ptr, col_t,
-                               perm, val_plan, col_rel, trow, tval, bkept);
+                               perm, val_plan, col_rel, trow, tval, bkept, rc);
   else
     l2_slow<NT, CAP, PLAN, VT>(B, L, s_w, s_b, brec, gkeys, scratch, row_ptr, col_t, perm,
-                               val, val_plan, col_rel, trow, tval, bkept);
+                               val, val_plan, col_rel, trow, tval, bkept, rc);
 }
 
 // Values in plan order for the plans built without the partition: val_plan[q] =
@@ -754,12 +809,31 @@ __global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ 
   if (threadIdx.x == 0) out[n] = (int32_t)carry;
 }
 
+// Plan outputs of the fused assembly + plan: the survivors go out a second time as records
+// of the plan's row partition (key = column << 32 | CSC slot, segment = row within its row
+// bucket, value = the stored value), into row bucket rb at bstart2[rb] + rowoff2[rb][cb] +
+// rank.  rowoff2 / btot2 come from k_rows_scan over the counts level 2 took (L2RowCount).
+struct EmitPlan {
+  int br;                   // log2(rows per row bucket)
+  int32_t CBr;              // row buckets (<= kFuseMaxRowBuckets)
+  const uint32_t* rowoff2;  // [CBr][CB]: offset of column bucket cb's survivors in row bucket rb
+  const uint32_t* btot2;    // [CBr] survivors per row bucket
+  int32_t* bstart2;         // [CBr + 1] written by workgroup 0 (exclusive scan of btot2)
+  uint4* brec2;             // plan partition records
+  uint32_t* bvhi2;          // high words of float64 values
+  int32_t* plan_info;       // plan info[0] = nnz
+};
+constexpr int kFuseMaxRowBuckets = 4096;
+
 // Place each bucket's survivors.  The bucket's output offset is the sum of the survivor
 // counts of the buckets before it: boff[cb] when the caller scanned them (boff != nullptr,
 // many buckets), else each workgroup reduces bkept[0..cb) itself (the last one also takes
 // its own, giving nnz_out).  Moves the survivors from the temporaries to their final place
 // (rounded once to the output type), turns the bucket-relative column offsets into col_ptr,
-// and finishes col_ptr / info.
+// and finishes col_ptr / info.  With ep.brec2 set (fused plan) every survivor also goes out
+// as a plan partition record; its column is found by binary search over the bucket's column
+// offsets (in LDS), and its rank among the column bucket's survivors of its row bucket comes
+// from an LDS cursor per row bucket.  Dynamic LDS: 4 * (CBr + 2^b + 1) bytes when fused.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nseg,
                                                   const int32_t* __restrict__ bstarts,
@@ -770,9 +844,11 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
                                                   int32_t* __restrict__ col_ptr,
                                                   int32_t* __restrict__ row_idx,
                                                   void* __restrict__ val_out, int out_f64,
-                                                  int32_t* __restrict__ info) {
+                                                  int32_t* __restrict__ info, EmitPlan ep) {
   __shared__ uint32_t s_w[NT / kWave + 1];
-  const int64_t cb = blockIdx.x;
+  // fused plan only (dynamic LDS): cur2[CBr] cursors | crel[W + 1] column starts in the bucket
+  extern __shared__ uint32_t s_emit[];
+  const int64_t cb = xcd_tile(blockIdx.x, gridDim.x);
   const bool last = cb == (int64_t)CB - 1;
   const int64_t kept = bkept[cb];
   int64_t dst0, total;
@@ -789,18 +865,90 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
     total = tot;
   }
   const int64_t src0 = bstarts[cb];
-  for (int64_t i = threadIdx.x; i < kept; i += NT) {
-    row_idx[dst0 + i] = (int32_t)trow[src0 + i];
-    if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
-    else static_cast<float*>(val_out)[dst0 + i] = (float)tval[src0 + i];
-  }
   const int64_t seg0 = cb << b;
   const int64_t rem = nseg - seg0;
   const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
+  if (ep.brec2) {
+    // plan records: the cursor of every row bucket, and the bucket-relative column starts
+    uint32_t* cur2 = s_emit;
+    uint32_t* crel = s_emit + ep.CBr;
+    for (int64_t i = threadIdx.x; i < ep.CBr; i += NT) cur2[i] = ep.btot2[i];
+    for (int64_t j = threadIdx.x; j < nW; j += NT) crel[j] = (uint32_t)col_ptr[seg0 + j];
+    if (threadIdx.x == 0) crel[nW] = (uint32_t)kept;
+    __syncthreads();
+    wg_inclusive_scan_inplace<NT>(cur2, ep.CBr, s_w);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < ep.CBr; i += NT) {
+      const uint32_t ex = cur2[i] - ep.btot2[i];
+      if (cb == 0) ep.bstart2[i] = (int32_t)ex;
+      cur2[i] = ex + ep.rowoff2[i * CB + cb];
+    }
+    __syncthreads();
+    const uint32_t wmask2 = (1u << ep.br) - 1u;
+    const int lgw = 31 - __clz((int)nW);  // floor(log2(nW)), nW >= 1
+    constexpr int U = 4;  // elements in flight per thread
+    for (int64_t i0 = threadIdx.x; i0 < kept; i0 += (int64_t)NT * U) {
+      uint32_t r[U];
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        r[u] = 0;
+        v[u] = 0.0;
+        if (i < kept) {
+          r[u] = trow[src0 + i];
+          v[u] = tval[src0 + i];
+        }
+      }
+      // column of each element: the last j with crel[j] <= i (branch-free binary search
+      // over the bucket's nW column starts; crel[nW] = kept is never passed)
+      int c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = 0;
+      for (int step = 1 << lgw; step > 0; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t i = (uint32_t)(i0 + (int64_t)u * NT);
+          const int nx = c[u] + step;
+          if (nx < (int)nW && crel[nx] <= i) c[u] = nx;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i < kept) {
+          row_idx[dst0 + i] = (int32_t)r[u];
+          if (out_f64) static_cast<double*>(val_out)[dst0 + i] = v[u];
+          else static_cast<float*>(val_out)[dst0 + i] = (float)v[u];
+          const uint32_t pos = atomicAdd(&cur2[r[u] >> ep.br], 1u);
+          uint32_t vlo;
+          if (out_f64) {
+            vlo = (uint32_t)__double2loint(v[u]);
+            ep.bvhi2[pos] = (uint32_t)__double2hiint(v[u]);
+          } else {
+            vlo = __float_as_uint((float)v[u]);
+          }
+          ep.brec2[pos] =
+              make_uint4((uint32_t)(dst0 + i), (uint32_t)(seg0 + c[u]), r[u] & wmask2, vlo);
+        }
+      }
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < kept; i += NT) {
+      row_idx[dst0 + i] = (int32_t)trow[src0 + i];
+      if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
+      else static_cast<float*>(val_out)[dst0 + i] = (float)tval[src0 + i];
+    }
+  }
+  // (the fused branch copied the bucket-relative offsets to LDS behind a barrier)
   for (int64_t j = threadIdx.x; j < nW; j += NT) col_ptr[seg0 + j] += (int32_t)dst0;
   if (last && threadIdx.x == 0) {
     col_ptr[nseg] = (int32_t)total;
     info[0] = (int32_t)total;
+    if (ep.brec2) {
+      ep.plan_info[0] = (int32_t)total;
+      ep.bstart2[ep.CBr] = (int32_t)total;
+    }
   }
 }
 

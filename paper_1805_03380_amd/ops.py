@@ -127,6 +127,57 @@ def coo_to_csc(row: torch.Tensor, col: torch.Tensor, val: torch.Tensor, shape,
     return A
 
 
+def coo_to_csc_plan(row: torch.Tensor, col: torch.Tensor, val: torch.Tensor, shape,
+                    out_dtype: torch.dtype | None = None, values_plan: bool = True,
+                    sync: bool = True):
+    """Assembly and plan in one call (spm_coo_to_csc_plan).  Returns (A, values_plan) where
+    A carries its plan (A.plan()) and values_plan holds the assembled values in plan order
+    (None with values_plan=False); the same results as coo_to_csc + build_plan."""
+    _require_cuda(row, col, val)
+    n_rows, n_cols = int(shape[0]), int(shape[1])
+    row = row.contiguous()
+    col = col.contiguous()
+    val = val.contiguous()
+    if row.dtype != torch.int32 or col.dtype != torch.int32:
+        raise ValueError("row and col must be int32")
+    nnz_in = int(row.numel())
+    if col.numel() != nnz_in or val.numel() != nnz_in:
+        raise ValueError("row, col and val must have the same length")
+    if out_dtype is None:
+        out_dtype = torch.float64 if val.dtype == torch.float64 else torch.float32
+    lib = _lib.load()
+    dev = row.device
+    pb = _lib.ctypes.c_size_t(0)
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_coo_to_csc_plan_size(n_rows, n_cols, nnz_in, _lib.ctypes.byref(pb),
+                                            _lib.ctypes.byref(wb)), "spm_coo_to_csc_plan_size")
+    ws = _workspace(wb.value, dev)
+    plan = torch.empty(max(pb.value, 256), dtype=torch.uint8, device=dev)
+    col_ptr = torch.empty(n_cols + 1, dtype=torch.int32, device=dev)
+    row_idx = torch.empty(max(nnz_in, 1), dtype=torch.int32, device=dev)
+    vout = torch.empty(max(nnz_in, 1), dtype=out_dtype, device=dev)
+    vplan = torch.empty(max(nnz_in, 1), dtype=out_dtype, device=dev) if values_plan else None
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    plan_info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.spm_coo_to_csc_plan(n_rows, n_cols, nnz_in, _ptr(row), _ptr(col), _ptr(val),
+                                 _dtype_code(val.dtype), _ptr(col_ptr), _ptr(row_idx),
+                                 _ptr(vout), _dtype_code(out_dtype), _ptr(info), _ptr(plan),
+                                 plan.numel(), _ptr(vplan), _ptr(plan_info), _ptr(ws),
+                                 ws.numel(), _stream(dev))
+    _lib.check(st, "spm_coo_to_csc_plan")
+    A = CSCMatrix(n_rows, n_cols, col_ptr, row_idx[:nnz_in] if nnz_in else row_idx[:0],
+                  vout[:nnz_in] if nnz_in else vout[:0], info)
+    A._ws = ws
+    A._plan = plan
+    A.plan_info = plan_info
+    if sync:
+        A.sync()
+        _lib.check(int(plan_info.cpu()[1]), "spm_coo_to_csc_plan (device)")
+    if vplan is not None:
+        vplan = vplan[:nnz_in] if nnz_in else vplan[:0]
+    return A, vplan
+
+
 def plan_size(n_rows: int, n_cols: int, nnz_cap: int):
     lib = _lib.load()
     pb = _lib.ctypes.c_size_t(0)

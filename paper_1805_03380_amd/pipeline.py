@@ -1,8 +1,9 @@
 """A preallocated assemble -> plan -> forward -> adjoint pipeline over the C ABI.
 
 All buffers (outputs, plan, workspaces) are allocated once for a given problem size, so a
-step enqueues exactly the four library calls on one stream with no allocation and no host
-synchronisation: spm_coo_to_csc, spm_csc_plan_build, spm_csc_spmm, spm_csc_spmm_backward.
+step enqueues only library calls on one stream, with no allocation and no host
+synchronisation: spm_coo_to_csc_plan (assembly and plan in one call; with fused=False
+spm_coo_to_csc then spm_csc_plan_build), spm_csc_spmm, spm_csc_spmm_backward.
 The CSC capacity is nnz_in; kernels read the true nnz from col_ptr[n_cols] on the device.
 The plan build also writes the assembled values in plan order (they are fixed for the step),
 so the forward product reads them contiguously (SPM_ORDER_PLAN).
@@ -17,13 +18,16 @@ from . import _lib
 from .ops import CSCMatrix, _DT, plan_size
 
 PHASES = ("assemble", "plan", "forward", "backward")
+FUSED_PHASES = ("assemble_plan", "forward", "backward")
 
 
 class Pipeline:
     def __init__(self, n_rows: int, n_cols: int, nnz_in: int, k: int,
                  val_dtype=torch.float32, x_dtype=torch.float32, csc_dtype=None,
-                 device="cuda:0"):
+                 device="cuda:0", fused=True):
         self.lib = _lib.load()
+        self.fused = fused
+        self.phases = FUSED_PHASES if fused else PHASES
         self.n_rows, self.n_cols, self.nnz_in, self.k = n_rows, n_cols, nnz_in, k
         self.device = torch.device(device)
         self.val_dtype, self.x_dtype = val_dtype, x_dtype
@@ -33,18 +37,29 @@ class Pipeline:
             else torch.float32
         self.dx_dtype = x_dtype if x_dtype != torch.bfloat16 else torch.float32
         d = self.device
-        ws = ctypes.c_size_t(0)
-        _lib.check(self.lib.spm_coo_to_csc_workspace(n_rows, n_cols, nnz_in, ctypes.byref(ws)),
-                   "spm_coo_to_csc_workspace")
-        self.asm_ws = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=d)
+        if not fused:
+            ws = ctypes.c_size_t(0)
+            _lib.check(self.lib.spm_coo_to_csc_workspace(n_rows, n_cols, nnz_in,
+                                                         ctypes.byref(ws)),
+                       "spm_coo_to_csc_workspace")
+            self.asm_ws = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=d)
         cap = max(nnz_in, 1)
         self.col_ptr = torch.empty(n_cols + 1, dtype=torch.int32, device=d)
         self.row_idx = torch.empty(cap, dtype=torch.int32, device=d)
         self.values = torch.empty(cap, dtype=self.csc_dtype, device=d)
         self.info = torch.zeros(2, dtype=torch.int32, device=d)
-        pb, wb = plan_size(n_rows, n_cols, nnz_in)
+        if fused:
+            pb_, wb_ = ctypes.c_size_t(0), ctypes.c_size_t(0)
+            _lib.check(self.lib.spm_coo_to_csc_plan_size(n_rows, n_cols, nnz_in,
+                                                         ctypes.byref(pb_), ctypes.byref(wb_)),
+                       "spm_coo_to_csc_plan_size")
+            pb, wb = pb_.value, wb_.value
+            self.asm_ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=d)
+            self.plan_ws = self.asm_ws
+        else:
+            pb, wb = plan_size(n_rows, n_cols, nnz_in)
+            self.plan_ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=d)
         self.plan = torch.empty(max(pb, 256), dtype=torch.uint8, device=d)
-        self.plan_ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=d)
         self.plan_info = torch.zeros(2, dtype=torch.int32, device=d)
         self.values_plan = torch.empty(cap, dtype=self.csc_dtype, device=d)
         self.Y = torch.empty(n_rows, k, dtype=self.y_dtype, device=d)
@@ -52,14 +67,46 @@ class Pipeline:
         self.dval = torch.empty(cap, dtype=self.csc_dtype, device=d)
 
     def step(self, row, col, val, X, G, stream=None, events=None):
-        """Enqueue the four calls.  `events`, if given, is a list of 5 HIP events recorded
-        between the phases on the same stream."""
+        """Enqueue the calls of one step.  `events`, if given, is a list of
+        len(self.phases) + 1 HIP events recorded between the phases on the same stream."""
         lib = self.lib
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = s.cuda_stream
         n_rows, n_cols, nnz, k = self.n_rows, self.n_cols, self.nnz_in, self.k
         if events is not None:
             events[0].record(s)
+        self._assemble_plan(row, col, val, h, s, events)
+        if events is not None:
+            events[-3].record(s)
+        _lib.check(lib.spm_csc_spmm(n_rows, n_cols, nnz, k, self.plan.data_ptr(),
+                                    self.values_plan.data_ptr(), _DT[self.csc_dtype],
+                                    _lib.ORDER_PLAN, X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                    self.Y.data_ptr(), self.Y.stride(0), _DT[self.y_dtype], h),
+                   "spm_csc_spmm")
+        if events is not None:
+            events[-2].record(s)
+        _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
+                                             self.row_idx.data_ptr(), self.values.data_ptr(),
+                                             _DT[self.csc_dtype], G.data_ptr(), G.stride(0),
+                                             X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                             self.dX.data_ptr(), self.dX.stride(0),
+                                             _DT[self.dx_dtype], self.dval.data_ptr(),
+                                             _DT[self.csc_dtype], h), "spm_csc_spmm_backward")
+        if events is not None:
+            events[-1].record(s)
+
+    def _assemble_plan(self, row, col, val, h, s, events=None):
+        lib = self.lib
+        n_rows, n_cols, nnz = self.n_rows, self.n_cols, self.nnz_in
+        if self.fused:
+            _lib.check(lib.spm_coo_to_csc_plan(
+                n_rows, n_cols, nnz, row.data_ptr(), col.data_ptr(), val.data_ptr(),
+                _DT[val.dtype], self.col_ptr.data_ptr(), self.row_idx.data_ptr(),
+                self.values.data_ptr(), _DT[self.csc_dtype], self.info.data_ptr(),
+                self.plan.data_ptr(), self.plan.numel(), self.values_plan.data_ptr(),
+                self.plan_info.data_ptr(), self.asm_ws.data_ptr(), self.asm_ws.numel(), h),
+                "spm_coo_to_csc_plan")
+            return
         _lib.check(lib.spm_coo_to_csc(n_rows, n_cols, nnz, row.data_ptr(), col.data_ptr(),
                                       val.data_ptr(), _DT[val.dtype], self.col_ptr.data_ptr(),
                                       self.row_idx.data_ptr(), self.values.data_ptr(),
@@ -75,44 +122,11 @@ class Pipeline:
                                           self.plan_info.data_ptr(), self.plan_ws.data_ptr(),
                                           self.plan_ws.numel(), h),
                    "spm_csc_plan_build")
-        if events is not None:
-            events[2].record(s)
-        _lib.check(lib.spm_csc_spmm(n_rows, n_cols, nnz, k, self.plan.data_ptr(),
-                                    self.values_plan.data_ptr(), _DT[self.csc_dtype],
-                                    _lib.ORDER_PLAN, X.data_ptr(), X.stride(0), _DT[X.dtype],
-                                    self.Y.data_ptr(), self.Y.stride(0), _DT[self.y_dtype], h),
-                   "spm_csc_spmm")
-        if events is not None:
-            events[3].record(s)
-        _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
-                                             self.row_idx.data_ptr(), self.values.data_ptr(),
-                                             _DT[self.csc_dtype], G.data_ptr(), G.stride(0),
-                                             X.data_ptr(), X.stride(0), _DT[X.dtype],
-                                             self.dX.data_ptr(), self.dX.stride(0),
-                                             _DT[self.dx_dtype], self.dval.data_ptr(),
-                                             _DT[self.csc_dtype], h), "spm_csc_spmm_backward")
-        if events is not None:
-            events[4].record(s)
 
     def step_assemble_plan(self, row, col, val, stream=None):
-        """Only the first two calls (assembly and plan)."""
+        """Only assembly and plan."""
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        h = s.cuda_stream
-        lib = self.lib
-        n_rows, n_cols, nnz = self.n_rows, self.n_cols, self.nnz_in
-        _lib.check(lib.spm_coo_to_csc(n_rows, n_cols, nnz, row.data_ptr(), col.data_ptr(),
-                                      val.data_ptr(), _DT[val.dtype], self.col_ptr.data_ptr(),
-                                      self.row_idx.data_ptr(), self.values.data_ptr(),
-                                      _DT[self.csc_dtype], self.info.data_ptr(),
-                                      self.asm_ws.data_ptr(), self.asm_ws.numel(), h),
-                   "spm_coo_to_csc")
-        _lib.check(lib.spm_csc_plan_build(n_rows, n_cols, nnz, self.col_ptr.data_ptr(),
-                                          self.row_idx.data_ptr(), self.values.data_ptr(),
-                                          _DT[self.csc_dtype], self.plan.data_ptr(),
-                                          self.plan.numel(), self.values_plan.data_ptr(),
-                                          self.plan_info.data_ptr(), self.plan_ws.data_ptr(),
-                                          self.plan_ws.numel(), h),
-                   "spm_csc_plan_build")
+        self._assemble_plan(row, col, val, s.cuda_stream, s)
 
     def step_spmm(self, X, G, stream=None):
         """Only the products (forward and adjoint) on the current CSC and plan."""

@@ -55,6 +55,15 @@ def test_workspace_sizes():
     assert lib.spm_coo_to_csc_workspace(10, 10, 2 ** 31, ctypes.byref(ws)) == _lib.EOVERFLOW
     assert lib.spm_coo_to_csc_workspace(10, 10, 10, None) == _lib.EINVAL
     pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    for shape in ((10, 10, 100), (100_000, 100_000, 1_000_000), (300_000, 2000, 4_000_000)):
+        assert lib.spm_coo_to_csc_plan_size(*shape, ctypes.byref(pb), ctypes.byref(wb)) == _lib.OK
+        assert lib.spm_coo_to_csc_workspace(*shape, ctypes.byref(ws)) == _lib.OK
+        assert wb.value >= ws.value and wb.value % 256 == 0
+        plan_b, plan_w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        assert lib.spm_csc_plan_size(*shape, ctypes.byref(plan_b), ctypes.byref(plan_w)) == _lib.OK
+        assert pb.value == plan_b.value
+    assert lib.spm_coo_to_csc_plan_size(10, 10, 10, None, ctypes.byref(wb)) == _lib.EINVAL
+    pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert lib.spm_csc_plan_size(100, 50, 1000, ctypes.byref(pb), ctypes.byref(wb)) == _lib.OK
     assert pb.value >= 4 * (101 + 2000) and wb.value >= 16 * 1000
 
@@ -97,6 +106,22 @@ def test_host_validation_rejects_before_launch():
                                   fake, ws, 1 << 30, None) == _lib.EINVAL  # val without val_plan
     assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, _lib.BF16, fake, 1 << 20, fake,
                                   fake, ws, 1 << 30, None) == _lib.EDTYPE
+    # assembly + plan in one call
+
+    def c2cp(n_rows=4, n_cols=4, nnz=8, vt=_lib.F64, ot=_lib.F64, plan=fake, pb=1 << 20,
+             vplan=fake, pinfo=fake, w=ws, wsb=1 << 30):
+        return lib.spm_coo_to_csc_plan(n_rows, n_cols, nnz, fake, fake, fake, vt, fake, fake,
+                                       fake, ot, fake, plan, pb, vplan, pinfo, w, wsb, None)
+
+    assert c2cp(n_cols=-2) == _lib.EINVAL
+    assert c2cp(n_rows=2 ** 31) == _lib.EOVERFLOW
+    assert c2cp(vt=9) == _lib.EDTYPE
+    assert c2cp(ot=_lib.BF16) == _lib.EDTYPE
+    assert c2cp(plan=None) == _lib.EINVAL
+    assert c2cp(pinfo=None) == _lib.EINVAL
+    assert c2cp(plan=ctypes.c_void_p(0x1010)) == _lib.EINVAL  # not 256-byte aligned
+    assert c2cp(pb=16) == _lib.EWORKSPACE
+    assert c2cp(wsb=16) == _lib.EWORKSPACE
 
 
 def test_tuning_roundtrip():
