@@ -205,6 +205,57 @@ __device__ __forceinline__ uint64_t rec_key(const uint4& r) {
   return ((uint64_t)r.y << 32) | r.x;
 }
 
+// Cursors of one tile: cur[i] = bstart[i] + rowoff[i * ld + col] for the n buckets, where
+// bstart is the exclusive scan of the bucket totals btot (scanned in LDS by every workgroup;
+// the one with `writer` also stores bstart[0..n], bstart[n] = total).  The first RB * NT
+// totals and table entries are loaded into registers before the scan starts.
+template <int NT>
+__device__ __forceinline__ void bucket_cursors(uint32_t* cur, int64_t n,
+                                               const uint32_t* __restrict__ btot,
+                                               const uint32_t* __restrict__ rowoff, int64_t ld,
+                                               int64_t col, bool writer,
+                                               int32_t* __restrict__ bstart, uint32_t* s_w) {
+  constexpr int RB = NT >= 1024 ? 2 : 4;
+  uint32_t bt[RB], ro[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int64_t i = threadIdx.x + (int64_t)k * NT;
+    bt[k] = 0;
+    ro[k] = 0;
+    if (i < n) {
+      bt[k] = btot[i];
+      ro[k] = rowoff[i * ld + col];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int64_t i = threadIdx.x + (int64_t)k * NT;
+    if (i < n) cur[i] = bt[k];
+  }
+  for (int64_t i = threadIdx.x + (int64_t)RB * NT; i < n; i += NT) cur[i] = btot[i];
+  __syncthreads();
+  wg_inclusive_scan_inplace<NT>(cur, n, s_w);
+  __syncthreads();
+  const uint32_t total = n > 0 ? cur[n - 1] : 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int64_t i = threadIdx.x + (int64_t)k * NT;
+    if (i < n) {
+      const uint32_t ex = cur[i] - bt[k];
+      if (writer) bstart[i] = (int32_t)ex;
+      cur[i] = ex + ro[k];
+    }
+  }
+  for (int64_t i = threadIdx.x + (int64_t)RB * NT; i < n; i += NT) {
+    const uint32_t ex = cur[i] - btot[i];
+    if (writer) bstart[i] = (int32_t)ex;
+    cur[i] = ex + rowoff[i * ld + col];
+  }
+  if (writer && threadIdx.x == 0) bstart[n] = (int32_t)total;
+  __syncthreads();
+}
+
 // Level 1b: scatter the elements' records into the buckets.  The range of (bucket cb,
 // tile t) starts at bstart[cb] + rowoff[cb * ntiles + t], where bstart is the exclusive scan
 // of the bucket totals: every workgroup scans btot (a few KB) itself, and workgroup 0 also
@@ -224,6 +275,11 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
   __shared__ uint32_t s_w[NT / kWave + 1];
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = src.count();
+  const uint32_t wmask = (1u << b) - 1u;
+  const int64_t base = t * T1;
+  const int64_t end = (base + T1 < n) ? base + T1 : n;
+  constexpr int U = 4;
+  const bool carry = vin != nullptr;
   // cur[i] = bstart[i] + rowoff[i][t]: the bucket totals are scanned in LDS
   for (int64_t i = threadIdx.x; i < CB; i += NT) cur[i] = btot[i];
   __syncthreads();
@@ -238,11 +294,6 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
   }
   if (t == 0 && threadIdx.x == 0) bstart[CB] = (int32_t)total;
   __syncthreads();
-  const uint32_t wmask = (1u << b) - 1u;
-  const int64_t base = t * T1;
-  const int64_t end = (base + T1 < n) ? base + T1 : n;
-  constexpr int U = 4;
-  const bool carry = vin != nullptr;
   for (int64_t e0 = base + threadIdx.x; e0 < end; e0 += (int64_t)NT * U) {
     uint32_t seg[U];
     uint64_t key[U];
@@ -851,6 +902,35 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   const int64_t cb = xcd_tile(blockIdx.x, gridDim.x);
   const bool last = cb == (int64_t)CB - 1;
   const int64_t kept = bkept[cb];
+  const int64_t src0 = bstarts[cb];
+  const int64_t seg0 = cb << b;
+  const int64_t rem = nseg - seg0;
+  const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
+  constexpr int U = 4;  // elements in flight per thread (fused branch)
+  uint32_t r[U];
+  double v[U];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      r[u] = 0;
+      v[u] = 0.0;
+      if (i < kept) {
+        r[u] = trow[src0 + i];
+        v[u] = tval[src0 + i];
+      }
+    }
+  };
+  uint32_t* cur2 = s_emit;
+  uint32_t* crel = s_emit + ep.CBr;
+  if (ep.brec2) {
+    // the first batch, the bucket's column starts and the table column are all requested
+    // before the row-bucket totals are scanned
+    load(threadIdx.x);
+    for (int64_t j = threadIdx.x; j < nW; j += NT) crel[j] = (uint32_t)col_ptr[seg0 + j];
+    if (threadIdx.x == 0) crel[nW] = (uint32_t)kept;
+    bucket_cursors<NT>(cur2, ep.CBr, ep.btot2, ep.rowoff2, CB, cb, cb == 0, ep.bstart2, s_w);
+  }
   int64_t dst0, total;
   if (boff) {
     dst0 = boff[cb];
@@ -864,42 +944,11 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
     dst0 = last ? (int64_t)tot - kept : (int64_t)tot;
     total = tot;
   }
-  const int64_t src0 = bstarts[cb];
-  const int64_t seg0 = cb << b;
-  const int64_t rem = nseg - seg0;
-  const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
   if (ep.brec2) {
-    // plan records: the cursor of every row bucket, and the bucket-relative column starts
-    uint32_t* cur2 = s_emit;
-    uint32_t* crel = s_emit + ep.CBr;
-    for (int64_t i = threadIdx.x; i < ep.CBr; i += NT) cur2[i] = ep.btot2[i];
-    for (int64_t j = threadIdx.x; j < nW; j += NT) crel[j] = (uint32_t)col_ptr[seg0 + j];
-    if (threadIdx.x == 0) crel[nW] = (uint32_t)kept;
-    __syncthreads();
-    wg_inclusive_scan_inplace<NT>(cur2, ep.CBr, s_w);
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < ep.CBr; i += NT) {
-      const uint32_t ex = cur2[i] - ep.btot2[i];
-      if (cb == 0) ep.bstart2[i] = (int32_t)ex;
-      cur2[i] = ex + ep.rowoff2[i * CB + cb];
-    }
-    __syncthreads();
     const uint32_t wmask2 = (1u << ep.br) - 1u;
     const int lgw = 31 - __clz((int)nW);  // floor(log2(nW)), nW >= 1
-    constexpr int U = 4;  // elements in flight per thread
     for (int64_t i0 = threadIdx.x; i0 < kept; i0 += (int64_t)NT * U) {
-      uint32_t r[U];
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + (int64_t)u * NT;
-        r[u] = 0;
-        v[u] = 0.0;
-        if (i < kept) {
-          r[u] = trow[src0 + i];
-          v[u] = tval[src0 + i];
-        }
-      }
+      if (i0 != threadIdx.x) load(i0);
       // column of each element: the last j with crel[j] <= i (branch-free binary search
       // over the bucket's nW column starts; crel[nW] = kept is never passed)
       int c[U];
@@ -945,10 +994,7 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   if (last && threadIdx.x == 0) {
     col_ptr[nseg] = (int32_t)total;
     info[0] = (int32_t)total;
-    if (ep.brec2) {
-      ep.plan_info[0] = (int32_t)total;
-      ep.bstart2[ep.CBr] = (int32_t)total;
-    }
+    if (ep.brec2) ep.plan_info[0] = (int32_t)total;
   }
 }
 
