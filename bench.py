@@ -2,8 +2,9 @@
 """Benchmark of the sparse hot path on one MI355X.
 
 One step = one pass of the whole path over one batch of synthetic input already resident in
-HBM: COO -> CSC assembly (spm_coo_to_csc), plan (spm_csc_plan_build), forward Y = A.X
-(spm_csc_spmm) and adjoint dX, dvalues (spm_csc_spmm_backward).  Workload: the 100,000 x
+HBM: COO -> CSC assembly and plan in one call (spm_coo_to_csc_plan; with --separate,
+spm_coo_to_csc then spm_csc_plan_build), forward Y = A.X (spm_csc_spmm) and adjoint dX,
+dvalues (spm_csc_spmm_backward).  Workload: the 100,000 x
 100,000 matrix from 1,000,000 triplets (5 % duplicates, float32 values U[-1,1]) with dense
 X 100,000 x 64 float32 N(0,1) and G of the same shape (seed 1002).
 
@@ -11,7 +12,7 @@ Prints ONE JSON line.  `value` is input triplets per second through the whole st
 `roofline` covers the kernel that takes the largest share of the step; `cpu_baseline` is the
 oracle timed on the host cores on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch] [--separate]
 """
 from __future__ import annotations
 
@@ -125,11 +126,15 @@ def batched_vs_single(bt, dtype_name="float32", reps_batched=5, reps_single=3):
         same = same and bool(torch.equal(ob[key].view(torch.int32)[mask],
                                          o_single[key].view(torch.int32)[mask]))
     nnz_in = int(pb.trip_off[-1])
-    return {"workload": "4096 matrices, n log-uniform [64, 8192], 16 triplets/column, 10 % dup, "
-                        "%s, k=32 (seed 1005)" % dtype_name,
+    return {"workload": batch_workload_label(dtype_name),
             "nnz_in": nnz_in, "batched_ms": ms_b, "per_matrix_ms": ms_s,
             "speedup": ms_s / ms_b, "batched_nnz_per_s": nnz_in / (ms_b * 1e-3),
             "bitwise_equal": same, "pack_s": gen_s}
+
+
+def batch_workload_label(dtype_name):
+    return ("4096 matrices, n log-uniform [64, 8192], 16 triplets/column, 10 percent "
+            "duplicates, %s, k=32 (seed 1005)" % dtype_name)
 
 
 def stored_traffic(phase, tuning):

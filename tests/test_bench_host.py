@@ -1,0 +1,35 @@
+"""Host-side pieces of bench.py (no GPU): the exit for more than one GPU, the algorithmic
+byte model and the workload labels that go into its JSON line."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_batch_labels_format():
+    for dt in ("float32", "bfloat16"):
+        s = bench.batch_workload_label(dt)
+        assert dt in s and "4096 matrices" in s and "seed 1005" in s
+
+
+def test_model_bytes_uniform_f32():
+    n, nnz_in, nnz, k = 100_000, 1_000_000, 950_000, 64
+    b = bench.model_bytes(n, n, nnz_in, nnz, k, 4, 4, 4, 4, 4)
+    assert b["assemble"] == nnz_in * 12 + nnz * 8 + 4 * (n + 1)
+    # the fused call writes the plan's outputs but never re-reads the CSC it assembled
+    assert b["assemble_plan"] == b["assemble"] + 4 * (n + 1) + nnz * 12
+    assert b["plan"] == 4 * (n + 1) + nnz * 8 + 4 * (n + 1) + nnz * 12
+    assert b["forward"] == 4 * (n + 1) + nnz * 8 + 2 * n * k * 4
+    assert b["backward"] == 4 * (n + 1) + nnz * 8 + 3 * n * k * 4 + nnz * 4
+
+
+def test_more_than_one_gpu_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
