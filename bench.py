@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip batched vs per-matrix")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--value-dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="steps timed one by one after writing 1 GiB of scratch (cold caches)")
     ap.add_argument("--separate", action="store_true",
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -137,24 +139,70 @@ def batch_workload_label(dtype_name):
             "duplicates, %s, k=32 (seed 1005)" % dtype_name)
 
 
-def stored_traffic(phase, tuning):
-    """HBM bytes per launch of the SpMM kernel of `phase`, from the committed counter runs
-    (profiles/traffic_uniform_1e5_f32_k64.json) -- None unless the kernel sources and the
-    launch tuning are still the ones the counters were taken with."""
-    from paper_1805_03380_amd import profiling
+def _traffic_record():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                         "traffic_uniform_1e5_f32_k64.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        tr = json.load(f)
-    if tr.get("spmm_source_sha256") != profiling.spmm_source_hash():
+        return json.load(f)
+
+
+def _tuning_matches(tr, tuning, prefix):
+    return all(tuning.get(k) == v for k, v in (tr.get("tuning") or {}).items()
+               if k.startswith(prefix))
+
+
+def stored_traffic(phase, tuning):
+    """HBM bytes per launch of the SpMM kernel of `phase`, from the committed counter runs
+    (profiles/traffic_uniform_1e5_f32_k64.json) -- None unless the kernel sources and the
+    launch tuning are still the ones the counters were taken with."""
+    from paper_1805_03380_amd import profiling
+    tr = _traffic_record()
+    if tr is None or tr.get("spmm_source_sha256") != profiling.spmm_source_hash():
         return None
-    for k, v in (tr.get("tuning") or {}).items():
-        if tuning.get(k) != v:
-            return None
+    if not _tuning_matches(tr, tuning, "spmm_"):
+        return None
     entry = tr.get(phase)
     return None if entry is None else float(entry["bytes_per_launch"])
+
+
+def stored_step_traffic(tuning):
+    """HBM bytes of the assembly-and-plan kernels of one step (one call), from the same
+    counter runs -- None unless their sources and the grouping tuning still match."""
+    from paper_1805_03380_amd import profiling
+    tr = _traffic_record()
+    if tr is None or tr.get("partition_source_sha256") != profiling.partition_source_hash():
+        return None
+    if not _tuning_matches(tr, tuning, "part_"):
+        return None
+    entry = tr.get("assemble_plan")
+    return None if entry is None else float(entry["bytes_per_step"])
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def rbt_context(p):
+    """The paper's own assembly (red-black tree, one insertion per triplet; the oracle's
+    "rbt" read) timed once on the same triplets: context for the bulk method, not a target."""
+    import oracle
+    t0 = time.perf_counter()
+    st, _ = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val, method="rbt")
+    el = time.perf_counter() - t0
+    return {"value": p.nnz_in / el, "unit": "nnz/s", "cores": 1, "kind": "oracle (rbt)",
+            "sample": "one assembly of the 1e6-triplet workload, %.2f s" % el,
+            "status": int(st)}
 
 
 def copy_calibration(mib):
@@ -222,6 +270,28 @@ def main():
     phase_ms = {ph: float(np.mean([evs[i][j].elapsed_time(evs[i][j + 1])
                                    for i in range(args.steps)]))
                 for j, ph in enumerate(phases)}
+    step_ms = np.array([evs[i][0].elapsed_time(evs[i][-1]) for i in range(args.steps)])
+
+    # cold caches: 1 GiB written before each step evicts the 256 MB MALL and every L2, so the
+    # step's inputs come from HBM
+    cold = None
+    if args.cold_steps > 0:
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        c_step, c_ph = [], []
+        for i in range(args.cold_steps):
+            flush.fill_(i & 0xFF)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)]
+            pipe.step(row, col, val, X, G, stream, events=ev)
+            torch.cuda.synchronize()
+            c_step.append(ev[0].elapsed_time(ev[-1]))
+            c_ph.append([ev[j].elapsed_time(ev[j + 1]) for j in range(len(phases))])
+        del flush
+        c_step = np.array(c_step)
+        cold = {"steps": args.cold_steps, "ms_per_step_median": float(np.median(c_step)),
+                "value": p.nnz_in / (float(np.median(c_step)) * 1e-3),
+                "phase_ms_median": {ph: float(np.median([c[j] for c in c_ph]))
+                                    for j, ph in enumerate(phases)},
+                "flush": "1 GiB device fill before each step"}
 
     s_vin = p.val.dtype.itemsize
     s_v = pipe.values.element_size()
@@ -235,7 +305,20 @@ def main():
     ach = bytes_[dominant] / (phase_ms[dominant] * 1e-3) / 1e9
     spmm_ms = phase_ms["forward"] + phase_ms["backward"]
     spmm_gbps = (bytes_["forward"] + bytes_["backward"]) / (spmm_ms * 1e-3) / 1e9
-    traffic = stored_traffic(dominant, tuning_used) if args.value_dtype == "float32" else None
+    f32 = args.value_dtype == "float32"
+    traffic = stored_traffic(dominant, tuning_used) if f32 else None
+    spmm_measured = {}
+    for ph in ("forward", "backward"):
+        tb = stored_traffic(ph, tuning_used) if f32 else None
+        gbps = None if tb is None else tb / (phase_ms[ph] * 1e-3) / 1e9
+        spmm_measured[ph] = {"bytes": tb, "GBps": gbps,
+                             "frac": None if gbps is None else gbps / HBM_PEAK_GBPS,
+                             "B_min_GBps": bytes_[ph] / (phase_ms[ph] * 1e-3) / 1e9,
+                             "B_gat_GBps": (bytes_[ph] + gather_bytes(nnz, p.k, 4))
+                             / (phase_ms[ph] * 1e-3) / 1e9}
+    asm_t = phase_ms[phases[0]] * 1e-3
+    asm_traffic = stored_step_traffic(tuning_used) if (f32 and phases[0] == "assemble_plan") \
+        else None
 
     out = {
         "metric": "COO->CSC nnz/s; SpMM fwd+bwd HBM GB/s and % of roofline, batched vs single",
@@ -256,8 +339,16 @@ def main():
                    "dense_dtype": "float32", "accumulate": "binary64",
                    "step": "assemble+plan+forward+adjoint", "parallelism": "single GPU"},
         "phase_ms": phase_ms,
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_p10": float(np.percentile(step_ms, 10)),
+        "step_ms_p90": float(np.percentile(step_ms, 90)),
+        "cold": cold,
         "assembly_nnz_per_s": p.nnz_in / (phase_ms[phases[0]] * 1e-3),
         "assembly_phase": phases[0],
+        "assembly_compulsory_GBps": bytes_[phases[0]] / asm_t / 1e9,
+        "assembly_measured": {"bytes": asm_traffic,
+                              "GBps": None if asm_traffic is None else asm_traffic / asm_t / 1e9},
+        "spmm_measured": spmm_measured,
         "spmm_fwd_bwd_GBps": spmm_gbps,
         "spmm_fwd_bwd_frac": spmm_gbps / HBM_PEAK_GBPS,
         "spmm_gather_GBps": (bytes_["forward"] + bytes_["backward"]
@@ -284,6 +375,8 @@ def main():
         out["batched_vs_single"]["generate_s"] = gen_s
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline"]["host"] = host_cpu()
+        out["cpu_rbt_context"] = rbt_context(p)
     print(json.dumps(out), flush=True)
 
 
