@@ -197,8 +197,9 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
 
 /* ------------------------------------------------------------------------------------------
  * Batched path: many independent matrices assembled, planned, multiplied forward and
- * backward in ONE persistent launch (one workgroup per matrix at a time, matrices taken
- * from a device queue in the order given, largest first recommended).
+ * backward by two persistent launches on the stream (grouping, then products), each with
+ * one workgroup per matrix at a time, matrices taken from a device queue in the order
+ * given (largest first recommended).
  * All per-matrix arrays are packed; item b describes where matrix b lives.  Element offsets
  * are in elements of the respective array.  For matrix b with nnz_in triplets:
  *   triplets       row/col/val[trip_off .. trip_off + nnz_in)
@@ -255,7 +256,9 @@ typedef struct spm_tuning {
                                   (256..2048, power of two) */
   int32_t part_max_tiles;      /* assembly / plan grouping: at most this many first-level
                                   tiles (64..4096, power of two) */
-  int32_t reserved[3];
+  int32_t batch_spmm_wg_per_cu; /* persistent workgroups per compute unit of the batch's
+                                   products launch (1..32; 0 = the library's default, 8) */
+  int32_t reserved[2];
 } spm_tuning;
 
 spm_status spm_tuning_get(spm_tuning *out);

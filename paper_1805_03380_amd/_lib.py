@@ -39,10 +39,11 @@ class Tuning(ctypes.Structure):
     """spm_tuning."""
     _fields_ = [("spmm_block", ctypes.c_int32), ("spmm_blocks_per_cu", ctypes.c_int32),
                 ("batch_wg_per_cu", ctypes.c_int32), ("part_bucket_target", ctypes.c_int32),
-                ("part_max_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("part_max_tiles", ctypes.c_int32), ("batch_spmm_wg_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     FIELDS = ("spmm_block", "spmm_blocks_per_cu", "batch_wg_per_cu", "part_bucket_target",
-              "part_max_tiles")
+              "part_max_tiles", "batch_spmm_wg_per_cu")
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f in self.FIELDS}

@@ -24,7 +24,7 @@ DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.json")
 
 SPMM_SPACE = {"spmm_block": [64, 128, 256], "spmm_blocks_per_cu": [8, 16, 32, 64]}
 PART_SPACE = {"part_bucket_target": [512, 1024, 2048], "part_max_tiles": [64, 128, 256, 512]}
-BATCH_SPACE = {"batch_wg_per_cu": [1, 2, 3, 4]}
+BATCH_SPACE = {"batch_wg_per_cu": [1, 2, 3, 4], "batch_spmm_wg_per_cu": [4, 8, 16]}
 
 
 def table_path() -> str:

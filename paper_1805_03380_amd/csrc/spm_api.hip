@@ -43,7 +43,7 @@ struct Carve {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-spm_tuning g_tuning = {256, 64, 2, 2048, 512, {0, 0, 0}};
+spm_tuning g_tuning = {256, 64, 2, 2048, 512, 0, {0, 0}};
 std::mutex g_tuning_mu;
 
 spm_tuning tuning() {
@@ -908,6 +908,7 @@ spm_status spm_tuning_set(const spm_tuning* in) {
   if (in->spmm_block != 64 && in->spmm_block != 128 && in->spmm_block != 256) return SPM_EINVAL;
   if (in->spmm_blocks_per_cu < 1 || in->spmm_blocks_per_cu > 64) return SPM_EINVAL;
   if (in->batch_wg_per_cu < 1 || in->batch_wg_per_cu > 8) return SPM_EINVAL;
+  if (in->batch_spmm_wg_per_cu < 0 || in->batch_spmm_wg_per_cu > 32) return SPM_EINVAL;
   if (!pow2(in->part_bucket_target) || in->part_bucket_target < 256 ||
       in->part_bucket_target > 2048)
     return SPM_EINVAL;
@@ -937,23 +938,41 @@ int batch_workers(int32_t workers, int32_t batch) {
   return w < 1 ? 1 : w;
 }
 
-template <int NT, typename VIN, typename XT, typename ACC>
-void launch_batch(const BatchArgs& a, int workers, hipStream_t s) {
-#define SPM_CALL(GW) k_batch<NT, VIN, XT, ACC, GW><<<dim3(workers), dim3(NT), 0, s>>>(a)
-  SPM_GW_SWITCH(a.G, SPM_CALL)
+// Persistent workgroups of the products launch: it holds no LDS and few registers, so
+// several times the grouping launch's workgroups fit a CU.
+constexpr int kBatchSpmmDefaultWgPerCu = 8;
+
+int batch_spmm_workers(int32_t batch) {
+  const spm_tuning tu = tuning();
+  const int per_cu = tu.batch_spmm_wg_per_cu > 0 ? tu.batch_spmm_wg_per_cu
+                                                 : kBatchSpmmDefaultWgPerCu;
+  int w = cu_count() * per_cu;
+  if (batch > 0 && w > batch) w = batch;
+  return w < 1 ? 1 : w;
+}
+
+template <int NT, typename XT, typename ACC>
+void launch_batch_spmm(const BatchArgs& a, int workers, hipStream_t s) {
+  // the full path for k = 32, 64, 128 with aligned rows, as in the single-matrix launches
+  const bool full = a.k == 4 * (int64_t)a.G && a.xal && a.yal;
+#define SPM_CALL_F(GW, F) k_batch_spmm<NT, XT, ACC, GW, F><<<dim3(workers), dim3(NT), 0, s>>>(a)
+#define SPM_CALL(GW) SPM_CALL_F(GW, false)
+  if (full && a.G == 8) SPM_CALL_F(8, true);
+  else if (full && a.G == 16) SPM_CALL_F(16, true);
+  else if (full && a.G == 32) SPM_CALL_F(32, true);
+  else SPM_GW_SWITCH(a.G, SPM_CALL)
 #undef SPM_CALL
+#undef SPM_CALL_F
 }
 
 template <int NT>
 void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers,
-                     hipStream_t s) {
-  if (vt == SPM_F32) {
-    if (xt == SPM_F32) launch_batch<NT, float, float, double>(a, workers, s);
-    else launch_batch<NT, float, bf16_t, float>(a, workers, s);
-  } else {
-    if (xt == SPM_F32) launch_batch<NT, bf16_t, float, double>(a, workers, s);
-    else launch_batch<NT, bf16_t, bf16_t, float>(a, workers, s);
-  }
+                     int spmm_workers, hipStream_t s) {
+  if (vt == SPM_F32) k_batch<NT, float><<<dim3(workers), dim3(NT), 0, s>>>(a);
+  else k_batch<NT, bf16_t><<<dim3(workers), dim3(NT), 0, s>>>(a);
+  // values are assembled into binary32; bfloat16 dense operands accumulate in binary32
+  if (xt == SPM_F32) launch_batch_spmm<NT, float, double>(a, spmm_workers, s);
+  else launch_batch_spmm<NT, bf16_t, float>(a, spmm_workers, s);
 }
 
 }  // namespace
@@ -1040,8 +1059,8 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   k_zero2<<<dim3(1), dim3(64), 0, s>>>(
-      a.queue, (int64_t)1, (uint32_t*)nullptr, (int64_t)0);
-  launch_batch_nt<256>(a, val_type, x_type, w, s);
+      a.queue, (int64_t)2, (uint32_t*)nullptr, (int64_t)0);
+  launch_batch_nt<256>(a, val_type, x_type, w, batch_spmm_workers(batch), s);
   return launch_status();
 }
 

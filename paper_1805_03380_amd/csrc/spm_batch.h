@@ -1,10 +1,14 @@
-// Batched path: one persistent launch assembles, plans, multiplies forward and backward many
-// independent matrices.  Each workgroup takes whole matrices from a device queue (in the
-// order the caller gives, largest first) and runs every phase of one matrix itself, with its
-// per-column / per-row counters in LDS and its keys in a per-workgroup slice of the workspace
-// (so one matrix's working set stays in the L2 of the XCD that runs it).  The phases call the
-// same device functions as the per-matrix kernels (segment sort, fold, spmm_row,
-// spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
+// Batched path: two persistent launches assemble, plan, multiply forward and backward many
+// independent matrices.  In each, a workgroup takes whole matrices from a device queue (in
+// the order the caller gives, largest first) and runs one matrix at a time.
+//   k_batch       assembly and plan, with the matrix's per-column / per-row counters in LDS
+//                 and its keys in a per-workgroup slice of the workspace (one matrix's
+//                 working set stays in the L2 of the XCD that runs it);
+//   k_batch_spmm  forward and adjoint.  It needs no LDS and few registers, so many more
+//                 workgroups share a CU than the grouping phases allow, which hides the
+//                 latency of the dense-row gathers.
+// The phases call the same device functions as the per-matrix kernels (segment sort, fold,
+// spmm_row, spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
 #pragma once
 
 #include "spm_partition.h"
@@ -41,12 +45,19 @@ struct BatchArgs {
   int64_t max_nnz;
   char* ws;           // per-worker slices
   size_t ws_stride;   // bytes per worker
-  uint32_t* queue;    // zeroed before the launch
+  uint32_t* queue;    // [0]: grouping queue, [1]: products queue; zeroed before the launches
   int xal;            // X / G rows start on 4-element boundaries (vector loads allowed)
   int yal;            // Y / dX rows likewise (vector stores allowed)
 };
 
-template <int NT, typename VIN, typename XT, typename ACC, int GW>
+// The item's sizes against the batch's limits (an item beyond them is skipped by both
+// launches; the grouping launch reports SPM_EINVAL for it).
+__device__ __forceinline__ bool batch_item_ok(const BatchArgs& a, const spm_batch_item& it) {
+  return !(it.n_rows < 0 || it.n_cols < 0 || it.nnz_in < 0 || it.n_rows > a.max_dim ||
+           it.n_cols > a.max_dim || it.nnz_in > a.max_nnz);
+}
+
+template <int NT, typename VIN>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
   constexpr int T = NT * kBatchFoldIPT;
@@ -63,8 +74,6 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   uint64_t* scratch = bucket + a.max_nnz;
   uint32_t* gcnt = reinterpret_cast<uint32_t*>(scratch + a.max_nnz);
   const VIN* vin = static_cast<const VIN*>(a.val);
-  const XT* Xa = static_cast<const XT*>(a.X);
-  const XT* Ga = static_cast<const XT*>(a.Gm);
 
   while (true) {
     if (threadIdx.x == 0) {
@@ -86,8 +95,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     }
     const spm_batch_item it = a.items[b];
     const int64_t n_r = it.n_rows, n_c = it.n_cols, nnz_in = it.nnz_in;
-    if (n_r < 0 || n_c < 0 || nnz_in < 0 || n_r > a.max_dim || n_c > a.max_dim ||
-        nnz_in > a.max_nnz) {
+    if (!batch_item_ok(a, it)) {
       if (threadIdx.x == 0) {
         a.info[2 * (int64_t)b] = 0;
         a.info[2 * (int64_t)b + 1] = kStEinval;
@@ -211,36 +219,69 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     sort_segments<NT, kBatchCap, true>(bucket, cnt, 0, n_r, scratch, a.col_t + to, a.perm + to,
                                        s_key, s_pre, &s_b[0]);
     __syncthreads();
-    // ---- 7. forward Y = A.X and 8. adjoint dX, dval ---------------------------------------
-    {
-      const int lg = threadIdx.x & (GW - 1);
-      const int64_t groups = NT / GW;
-      const int64_t gid = threadIdx.x / GW;
-      const XT* Xb = Xa + it.x_off;
-      const XT* Gb = Ga + it.g_off;
-      const bool full = a.k == 4 * GW && a.xal && a.yal;
-      for (int64_t r = gid; r < n_r; r += groups) {
-        if (full)
-          spmm_row_full<float, XT, ACC, GW>(r, lg, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
-                                            Xb, a.k, a.Y + it.g_off, a.k, false);
-        else
-          spmm_row<float, XT, ACC, GW, false>(r, lg, a.k, n_c, nnz, rp, a.col_t + to,
-                                              a.perm + to, vo, Xb, a.k, a.xal != 0,
-                                              a.Y + it.g_off, a.k, false, a.yal != 0);
+  }
+}
+
+// Forward and adjoint of every matrix, after k_batch.  nnz comes from info[2b], written by
+// k_batch for the same matrix.  FULL (k == 4 * GW, aligned rows) is chosen on the host, so
+// each instantiation holds only the registers of its own path.
+template <int NT, typename XT, typename ACC, int GW, bool FULL>
+__global__ __launch_bounds__(NT) void k_batch_spmm(BatchArgs a) {
+  __shared__ int32_t s_item;
+  const XT* Xa = static_cast<const XT*>(a.X);
+  const XT* Ga = static_cast<const XT*>(a.Gm);
+  const int lg = threadIdx.x & (GW - 1);
+  const int64_t groups = NT / GW;
+  const int64_t gid = threadIdx.x / GW;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t q = atomicAdd(a.queue + 1, 1u);
+      int32_t m = -1;  // -1: queue drained
+      if (q < (uint32_t)a.batch) {
+        m = a.order[q];
+        if (m < 0 || m >= a.batch) m = -2;  // not a matrix index: skipped
       }
-      for (int64_t c = gid; c < n_c; c += groups) {
-        const int64_t p0 = cp[c], p1 = cp[c + 1];
-        if (full)
-          spmm_col_bwd_full<float, XT, ACC, GW>(c, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
-                                                a.dX + it.x_off, a.k, false, a.dval + to, false);
-        else
-          spmm_col_bwd<float, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
-                                                  a.xal != 0, Xb, a.k, a.xal != 0,
-                                                  a.dX + it.x_off, a.k, false, a.yal != 0,
-                                                  a.dval + to, false);
-      }
+      s_item = m;
     }
     __syncthreads();
+    const int32_t b = s_item;
+    __syncthreads();  // every thread has read s_item before thread 0 takes the next one
+    if (b == -1) break;  // every workgroup leaves through here once the queue is drained
+    if (b == -2) continue;
+    const spm_batch_item it = a.items[b];
+    if (!batch_item_ok(a, it)) continue;
+    const int64_t n_r = it.n_rows, n_c = it.n_cols;
+    int64_t nnz = a.info[2 * (int64_t)b];
+    nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
+    const int64_t to = it.trip_off;
+    const int32_t* cp = a.col_ptr + it.colptr_off;
+    const int32_t* ri = a.row_idx + to;
+    const float* vo = a.val_out + to;
+    const int32_t* rp = a.row_ptr + it.rowptr_off;
+    const XT* Xb = Xa + it.x_off;
+    const XT* Gb = Ga + it.g_off;
+    // ---- forward Y = A.X --------------------------------------------------------------
+    for (int64_t r = gid; r < n_r; r += groups) {
+      if constexpr (FULL)
+        spmm_row_full<float, XT, ACC, GW>(r, lg, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
+                                          Xb, a.k, a.Y + it.g_off, a.k, false);
+      else
+        spmm_row<float, XT, ACC, GW, false>(r, lg, a.k, n_c, nnz, rp, a.col_t + to,
+                                            a.perm + to, vo, Xb, a.k, a.xal != 0,
+                                            a.Y + it.g_off, a.k, false, a.yal != 0);
+    }
+    // ---- adjoint dX, dval ---------------------------------------------------------------
+    for (int64_t c = gid; c < n_c; c += groups) {
+      const int64_t p0 = cp[c], p1 = cp[c + 1];
+      if constexpr (FULL)
+        spmm_col_bwd_full<float, XT, ACC, GW>(c, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
+                                              a.dX + it.x_off, a.k, false, a.dval + to, false);
+      else
+        spmm_col_bwd<float, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
+                                                a.xal != 0, Xb, a.k, a.xal != 0,
+                                                a.dX + it.x_off, a.k, false, a.yal != 0,
+                                                a.dval + to, false);
+    }
   }
 }
 

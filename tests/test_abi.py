@@ -136,6 +136,9 @@ def test_tuning_roundtrip():
     bad.part_bucket_target = 1000  # not a power of two
     assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
     bad = _lib.Tuning.from_buffer_copy(t)
+    bad.batch_spmm_wg_per_cu = 33
+    assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
+    bad = _lib.Tuning.from_buffer_copy(t)
     bad.part_max_tiles = 8192
     assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
     good = _lib.Tuning.from_buffer_copy(t)

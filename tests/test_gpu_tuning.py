@@ -68,8 +68,8 @@ def test_batch_invariant_under_workers():
     torch.cuda.synchronize()
     saved = _lib.get_tuning().as_dict()
     try:
-        for w in (1, 4):
-            _lib.set_tuning(batch_wg_per_cu=w)
+        for w, ws in ((1, 1), (4, 0), (2, 16)):
+            _lib.set_tuning(batch_wg_per_cu=w, batch_spmm_wg_per_cu=ws)
             out = pb.run_batched(out=pb.new_outputs())
             torch.cuda.synchronize()
             for key in ("col_ptr", "Y", "dX", "info"):
