@@ -84,7 +84,8 @@ def cpu_baseline(p, seconds):
 
 
 def batched_vs_single(bt, dtype_name="float32", reps_batched=5, reps_single=3):
-    """The 4096-matrix workload: one persistent launch vs 4096 x 4 per-matrix calls of the
+    """The 4096-matrix workload: the batched entry point (one grouping launch, a prefix launch,
+    two flat product launches) vs 4096 x 4 per-matrix calls of the
     same kernels; outputs compared bitwise.  dtype_name "bfloat16" is the variant with values,
     X and G in bfloat16 and binary32 accumulation."""
     import numpy as np

@@ -197,9 +197,11 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
 
 /* ------------------------------------------------------------------------------------------
  * Batched path: many independent matrices assembled, planned, multiplied forward and
- * backward by two persistent launches on the stream (grouping, then products), each with
- * one workgroup per matrix at a time, matrices taken from a device queue in the order
- * given (largest first recommended).
+ * backward by launches on the stream: a persistent grouping launch (one workgroup per matrix
+ * at a time, matrices taken from a device queue in the order given, largest first
+ * recommended), then the products, as one grid over all rows (forward) and all columns
+ * (adjoint) of all matrices.  When the workspace cannot hold the batch's row and column
+ * prefixes (16 bytes per matrix), the products run one workgroup per matrix instead.
  * All per-matrix arrays are packed; item b describes where matrix b lives.  Element offsets
  * are in elements of the respective array.  For matrix b with nnz_in triplets:
  *   triplets       row/col/val[trip_off .. trip_off + nnz_in)

@@ -1,5 +1,6 @@
 """Batched assembly + SpMM over the C ABI: many independent matrices packed into flat device
-arrays, run either as ONE persistent launch (spm_batch_run) or as per-matrix calls of the four
+arrays, run either by the batched entry point (spm_batch_run: a grouping launch, then the
+product launches) or as per-matrix calls of the four
 single-matrix entry points (for comparison; same kernels' device functions, bitwise-equal
 results)."""
 from __future__ import annotations
@@ -114,7 +115,7 @@ class PackedBatch:
             self.ws = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
 
     def run_batched(self, out=None, stream=None):
-        """All matrices in one persistent launch."""
+        """All matrices: the grouping launch, then the product launches (spm_batch_run)."""
         self._ensure_workspace()
         o = self.out if out is None else out
         s = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -965,12 +965,45 @@ void launch_batch_spmm(const BatchArgs& a, int workers, hipStream_t s) {
 #undef SPM_CALL_F
 }
 
+// Flat products: the forward over all rows, then the adjoint over all columns.
+template <int NT, typename XT, typename ACC>
+void launch_batch_flat(const BatchArgs& a, const int64_t* rpre, const int64_t* cpre, int grid,
+                       hipStream_t s) {
+  const bool full = a.k == 4 * (int64_t)a.G && a.xal && a.yal;
+#define SPM_CALL_F(GW, F)                                                                      \
+  do {                                                                                         \
+    k_batch_flat<NT, XT, ACC, GW, F, true><<<dim3(grid), dim3(NT), 0, s>>>(a, rpre);           \
+    k_batch_flat<NT, XT, ACC, GW, F, false><<<dim3(grid), dim3(NT), 0, s>>>(a, cpre);          \
+  } while (0)
+#define SPM_CALL(GW) SPM_CALL_F(GW, false)
+  if (full && a.G == 8) SPM_CALL_F(8, true);
+  else if (full && a.G == 16) SPM_CALL_F(16, true);
+  else if (full && a.G == 32) SPM_CALL_F(32, true);
+  else SPM_GW_SWITCH(a.G, SPM_CALL)
+#undef SPM_CALL
+#undef SPM_CALL_F
+}
+
+// Grouping launch, then the products: flat when the (now free) worker slices can hold the
+// row and column prefixes, else one persistent workgroup per matrix.
 template <int NT>
 void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers,
-                     int spmm_workers, hipStream_t s) {
+                     int spmm_workers, size_t slices_bytes, hipStream_t s) {
   if (vt == SPM_F32) k_batch<NT, float><<<dim3(workers), dim3(NT), 0, s>>>(a);
   else k_batch<NT, bf16_t><<<dim3(workers), dim3(NT), 0, s>>>(a);
-  // values are assembled into binary32; bfloat16 dense operands accumulate in binary32
+  const size_t pre_bytes = 2 * sizeof(int64_t) * ((size_t)a.batch + 1);
+  if (slices_bytes >= pre_bytes) {
+    int64_t* rpre = reinterpret_cast<int64_t*>(a.ws);
+    int64_t* cpre = rpre + a.batch + 1;
+    k_batch_prefix<NT><<<dim3(1), dim3(NT), 0, s>>>(a, rpre, cpre);
+    const int grid = cu_count() * (tuning().batch_spmm_wg_per_cu > 0
+                                       ? tuning().batch_spmm_wg_per_cu
+                                       : kBatchSpmmDefaultWgPerCu);
+    // values are assembled into binary32; bfloat16 dense operands accumulate in binary32
+    if (xt == SPM_F32) launch_batch_flat<NT, float, double>(a, rpre, cpre, grid, s);
+    else launch_batch_flat<NT, bf16_t, float>(a, rpre, cpre, grid, s);
+    return;
+  }
   if (xt == SPM_F32) launch_batch_spmm<NT, float, double>(a, spmm_workers, s);
   else launch_batch_spmm<NT, bf16_t, float>(a, spmm_workers, s);
 }
@@ -1060,7 +1093,8 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
   (void)hipGetLastError();
   k_zero2<<<dim3(1), dim3(64), 0, s>>>(
       a.queue, (int64_t)2, (uint32_t*)nullptr, (int64_t)0);
-  launch_batch_nt<256>(a, val_type, x_type, w, batch_spmm_workers(batch), s);
+  launch_batch_nt<256>(a, val_type, x_type, w, batch_spmm_workers(batch), (size_t)w * stride,
+                       s);
   return launch_status();
 }
 

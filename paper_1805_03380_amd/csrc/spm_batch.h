@@ -1,12 +1,14 @@
-// Batched path: two persistent launches assemble, plan, multiply forward and backward many
-// independent matrices.  In each, a workgroup takes whole matrices from a device queue (in
-// the order the caller gives, largest first) and runs one matrix at a time.
-//   k_batch       assembly and plan, with the matrix's per-column / per-row counters in LDS
-//                 and its keys in a per-workgroup slice of the workspace (one matrix's
-//                 working set stays in the L2 of the XCD that runs it);
-//   k_batch_spmm  forward and adjoint.  It needs no LDS and few registers, so many more
-//                 workgroups share a CU than the grouping phases allow, which hides the
-//                 latency of the dense-row gathers.
+// Batched path: launches that assemble, plan, multiply forward and backward many
+// independent matrices.
+//   k_batch       assembly and plan: a persistent workgroup takes whole matrices from a
+//                 device queue (in the order the caller gives, largest first) and keeps the
+//                 matrix's per-column / per-row counters in LDS and its keys in a
+//                 per-workgroup slice of the workspace;
+//   k_batch_prefix, k_batch_flat
+//                 forward over all rows and adjoint over all columns of all matrices, one
+//                 grid each, at the occupancy of the single-matrix kernels;
+//   k_batch_spmm  the same products one workgroup per matrix, when the workspace cannot hold
+//                 the prefixes the flat launches need.
 // The phases call the same device functions as the per-matrix kernels (segment sort, fold,
 // spmm_row, spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
 #pragma once
@@ -281,6 +283,152 @@ __global__ __launch_bounds__(NT) void k_batch_spmm(BatchArgs a) {
                                                 a.xal != 0, Xb, a.k, a.xal != 0,
                                                 a.dX + it.x_off, a.k, false, a.yal != 0,
                                                 a.dval + to, false);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Flat products.  Matrices of the batch run concurrently by the dozen on every XCD, so their
+// dense rows come from MALL / HBM, not from one XCD's L2; the products are then best run as
+// one grid over all rows (forward) or all columns (adjoint) of all matrices, at the
+// occupancy of the single-matrix kernels.  k_batch_prefix lays out the rows and columns in
+// schedule order; k_batch_flat hands out chunks of consecutive rows (columns).  Every row
+// (column) is computed by the same device function as in the per-matrix kernels.
+// ------------------------------------------------------------------------------------------
+
+// Inclusive scan of one int64 per thread across the workgroup; s_w holds NT/64 + 1 words.
+template <int NT>
+__device__ __forceinline__ int64_t wg_incl_scan_i64(int64_t x, int64_t* s_w) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) s_w[wave_id()] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < NW; ++w) {
+      const int64_t t = s_w[w];
+      s_w[w] = run;
+      run += t;
+    }
+    s_w[NW] = run;
+  }
+  __syncthreads();
+  const int64_t r = x + s_w[wave_id()];
+  __syncthreads();
+  return r;
+}
+
+// rpre[q] / cpre[q] = rows / columns of the valid matrices order[0 .. q), q = 0 .. batch.
+// One workgroup.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_prefix(BatchArgs a, int64_t* __restrict__ rpre,
+                                                     int64_t* __restrict__ cpre) {
+  __shared__ int64_t s_w[NT / kWave + 1];
+  int64_t rc = 0, cc = 0;
+  if (threadIdx.x == 0) {
+    rpre[0] = 0;
+    cpre[0] = 0;
+  }
+  for (int64_t base = 0; base < a.batch; base += NT) {
+    const int64_t q = base + threadIdx.x;
+    int64_t r = 0, c = 0;
+    if (q < a.batch) {
+      const int32_t m = a.order[q];
+      if (m >= 0 && m < a.batch) {
+        const spm_batch_item it = a.items[m];
+        if (batch_item_ok(a, it)) {
+          r = it.n_rows;
+          c = it.n_cols;
+        }
+      }
+    }
+    const int64_t ri = wg_incl_scan_i64<NT>(r, s_w) + rc;
+    const int64_t ci = wg_incl_scan_i64<NT>(c, s_w) + cc;
+    if (q < a.batch) {
+      rpre[q + 1] = ri;
+      cpre[q + 1] = ci;
+    }
+    // carry: the last thread's inclusive value, shared through s_w
+    if (threadIdx.x == NT - 1) {
+      s_w[0] = ri;
+      s_w[1] = ci;
+    }
+    __syncthreads();
+    rc = s_w[0];
+    cc = s_w[1];
+    __syncthreads();
+  }
+}
+
+// FWD: rows of all matrices (pre = rpre), forward product.  !FWD: columns (pre = cpre),
+// adjoint.  Each group takes kPerGroup rows (columns) of a chunk, kGroups apart.
+template <int NT, typename XT, typename ACC, int GW, bool FULL, bool FWD>
+__global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* __restrict__ pre) {
+  constexpr int64_t kGroups = NT / GW;
+  constexpr int kPerGroup = 8;
+  constexpr int64_t kChunk = kGroups * kPerGroup;
+  __shared__ int32_t s_q;
+  const XT* Xa = static_cast<const XT*>(a.X);
+  const XT* Ga = static_cast<const XT*>(a.Gm);
+  const int lg = threadIdx.x & (GW - 1);
+  const int64_t gid = threadIdx.x / GW;
+  const int64_t total = pre[a.batch];
+  const int64_t nchunks = (total + kChunk - 1) / kChunk;
+  for (int64_t round = 0; round < nchunks; round += gridDim.x) {
+    const int64_t chunk = round + xcd_tile(blockIdx.x, gridDim.x);
+    if (chunk >= nchunks) break;  // the same for every thread of the workgroup
+    const int64_t g0 = chunk * kChunk;
+    if (threadIdx.x == 0) s_q = (int32_t)(upper_bound(pre, (int64_t)a.batch + 1, g0) - 1);
+    __syncthreads();
+    int64_t q = s_q;
+    __syncthreads();  // s_q is read before thread 0 rewrites it
+    int64_t qb = -1;  // schedule slot whose item is loaded below
+    spm_batch_item it{};
+    int64_t nnz = 0;
+    for (int j = 0; j < kPerGroup; ++j) {
+      const int64_t g = g0 + (int64_t)j * kGroups + gid;
+      if (g >= total) break;
+      while (pre[q + 1] <= g) ++q;  // q < batch: g < total = pre[batch]
+      if (q != qb) {
+        qb = q;
+        it = a.items[a.order[q]];
+        nnz = a.info[2 * (int64_t)a.order[q]];
+        nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
+      }
+      const int64_t e = g - pre[q];  // row (column) within the matrix
+      const int64_t to = it.trip_off;
+      const int64_t n_r = it.n_rows, n_c = it.n_cols;
+      const float* vo = a.val_out + to;
+      const XT* Xb = Xa + it.x_off;
+      if constexpr (FWD) {
+        const int32_t* rp = a.row_ptr + it.rowptr_off;
+        if constexpr (FULL)
+          spmm_row_full<float, XT, ACC, GW>(e, lg, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
+                                            Xb, a.k, a.Y + it.g_off, a.k, false);
+        else
+          spmm_row<float, XT, ACC, GW, false>(e, lg, a.k, n_c, nnz, rp, a.col_t + to,
+                                              a.perm + to, vo, Xb, a.k, a.xal != 0,
+                                              a.Y + it.g_off, a.k, false, a.yal != 0);
+      } else {
+        const int32_t* cp = a.col_ptr + it.colptr_off;
+        const int32_t* ri = a.row_idx + to;
+        const XT* Gb = Ga + it.g_off;
+        const int64_t p0 = cp[e], p1 = cp[e + 1];
+        if constexpr (FULL)
+          spmm_col_bwd_full<float, XT, ACC, GW>(e, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
+                                                a.dX + it.x_off, a.k, false, a.dval + to,
+                                                false);
+        else
+          spmm_col_bwd<float, XT, ACC, GW, false>(e, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
+                                                  a.xal != 0, Xb, a.k, a.xal != 0,
+                                                  a.dX + it.x_off, a.k, false, a.yal != 0,
+                                                  a.dval + to, false);
+      }
     }
   }
 }

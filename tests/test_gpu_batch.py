@@ -128,3 +128,33 @@ def test_deterministic_rerun():
     o2 = pb.run_batched(out=pb.new_outputs())
     torch.cuda.synchronize()
     _bitwise_equal(pb, o1, o2)
+
+
+def test_flat_and_per_matrix_products_agree():
+    """The products run flat over all rows / columns when the grouping workspace can hold the
+    batch's row and column prefixes (16 bytes per matrix), else one workgroup per matrix.
+    Many tiny matrices with one grouping workgroup per CU take the per-matrix form, the
+    default tuning the flat one; both are bitwise equal to the per-matrix calls."""
+    from paper_1805_03380_amd import _lib
+    bt = _small_batch(2008, 5000, 2, 6, per_col=2)
+    pb = PackedBatch(bt.problems)
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    max_nnz = max(p.nnz_in for p in bt.problems)
+    max_dim = max(max(p.n_rows, p.n_cols) for p in bt.problems)
+    stride = (16 * max_nnz + 4 * (max_dim + 1) + 255) // 256 * 256
+    saved = _lib.get_tuning().as_dict()
+    seen = set()
+    try:
+        for wpc in (1, 2):
+            _lib.set_tuning(batch_wg_per_cu=wpc)
+            w = min(cus * wpc, pb.B)
+            seen.add(w * stride >= 16 * (pb.B + 1))
+            pb2 = PackedBatch(bt.problems)
+            o_b = pb2.run_batched(out=pb2.new_outputs())
+            torch.cuda.synchronize()
+            _bitwise_equal(pb2, o_b, o_s)
+    finally:
+        _lib.set_tuning(**saved)
+    assert seen == {True, False}, "both product forms must be exercised"
