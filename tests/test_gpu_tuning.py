@@ -1,5 +1,6 @@
 """Tuning never changes results: every spm_tuning choice gives bitwise the same CSC, plan,
-forward and adjoint (single-matrix path) and the same batched outputs."""
+plan-order values, forward and adjoint (single-matrix path, with assembly and plan in one
+call or in two) and the same batched outputs."""
 import numpy as np
 import pytest
 import torch
@@ -18,13 +19,14 @@ TUNINGS = [
 ]
 
 
-def _run(p, dev="cuda:0"):
+def _run(p, dev="cuda:0", fused=True):
     row = torch.from_numpy(p.row).to(dev)
     col = torch.from_numpy(p.col).to(dev)
     val = torch.from_numpy(p.val).to(dev)
     X = torch.from_numpy(p.X).to(dev)
     G = torch.from_numpy(p.G).to(dev)
-    pipe = Pipeline(p.n_rows, p.n_cols, p.nnz_in, p.k, val_dtype=val.dtype, x_dtype=X.dtype)
+    pipe = Pipeline(p.n_rows, p.n_cols, p.nnz_in, p.k, val_dtype=val.dtype, x_dtype=X.dtype,
+                    fused=fused)
     pipe.step(row, col, val, X, G)
     torch.cuda.synchronize()
     nnz, sa, sp = pipe.status()
@@ -32,8 +34,8 @@ def _run(p, dev="cuda:0"):
     rp, ct, pm = plan_arrays(pipe.plan, p.n_rows, p.nnz_in)
     return dict(col_ptr=pipe.col_ptr.clone(), row_idx=pipe.row_idx[:nnz].clone(),
                 values=pipe.values[:nnz].clone(), row_ptr=rp.clone(), col_t=ct[:nnz].clone(),
-                perm=pm[:nnz].clone(), Y=pipe.Y.clone(), dX=pipe.dX.clone(),
-                dval=pipe.dval[:nnz].clone())
+                perm=pm[:nnz].clone(), values_plan=pipe.values_plan[:nnz].clone(),
+                Y=pipe.Y.clone(), dX=pipe.dX.clone(), dval=pipe.dval[:nnz].clone())
 
 
 def _same(a, b):
@@ -52,11 +54,13 @@ def test_pipeline_invariant_under_tuning(dims):
     p = synth.random_coo(900 + k, n_rows, n_cols, nnz, dup_frac=0.2, dtype=np.float32,
                          dist="normal", k=k)
     ref = _run(p)
+    _same(ref, _run(p, fused=False))  # assembly and plan as two calls
     saved = _lib.get_tuning().as_dict()
     try:
         for tu in TUNINGS:
             _lib.set_tuning(**tu)
             _same(ref, _run(p))
+            _same(ref, _run(p, fused=False))
     finally:
         _lib.set_tuning(**saved)
 
