@@ -1,4 +1,4 @@
-"""GPU tests of the batched persistent path (spm_batch_run): bitwise equal to the per-matrix
+"""GPU tests of the batched path (spm_batch_run): bitwise equal to the per-matrix
 entry points, and per matrix equal to the oracle (assembly bit-exact, products within the
 a-priori bound)."""
 import numpy as np
@@ -108,7 +108,7 @@ def full_batch():
 def test_full_batch_workload_bitwise_and_sampled_oracle(full_batch, dtype):
     """The 4096-matrix workload (n log-uniform in [64, 8192], 16 triplets per column, 10 %
     duplicates, k = 32), in float32 and in the bfloat16 variant (values, X and G rounded to
-    bfloat16, binary32 accumulation): one persistent launch is bitwise equal to 4096
+    bfloat16, binary32 accumulation): the batched entry point is bitwise equal to 4096
     per-matrix calls, and sampled matrices match the oracle."""
     bt = full_batch
     pb = PackedBatch(bt.problems, val_dtype=dtype, x_dtype=dtype)
