@@ -147,6 +147,24 @@ class Pipeline:
                                              _DT[self.dx_dtype], self.dval.data_ptr(),
                                              _DT[self.csc_dtype], h), "spm_csc_spmm_backward")
 
+    def capture(self, row, col, val, X, G, warmup: int = 1):
+        """Record one step into a HIP graph (torch.cuda.CUDAGraph) over these tensors, so that
+        graph.replay() submits the step's kernels at once.  The step holds no host
+        synchronisation, allocation or memset, so it captures as it runs.  The tensors'
+        addresses are part of the graph: to change the data, refill the same tensors."""
+        dev = self.device
+        s = torch.cuda.Stream(dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step(row, col, val, X, G, stream=s)
+        torch.cuda.current_stream(dev).wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.step(row, col, val, X, G, stream=s)
+        torch.cuda.synchronize(dev)
+        return g
+
     def status(self):
         """(nnz_out, assembly status, plan status) -- synchronises."""
         a = self.info.cpu()
