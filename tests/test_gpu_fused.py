@@ -75,7 +75,8 @@ def _check_plan_oracle(B, p):
 
 @pytest.mark.parametrize("val_dtype,out_dtype", [
     (torch.float32, torch.float32), (torch.float64, torch.float64),
-    (torch.float64, torch.float32), (torch.bfloat16, torch.float32)])
+    (torch.float64, torch.float32), (torch.float32, torch.float64),
+    (torch.bfloat16, torch.float32)])
 def test_fused_random(val_dtype, out_dtype):
     p = synth.random_coo(41, 1000, 1200, 20_000, dup_frac=0.2, zero_frac=0.05, dist="normal")
     B, _, _, st = _both(p, val_dtype, out_dtype)
