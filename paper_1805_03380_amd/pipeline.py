@@ -176,3 +176,4 @@ class Pipeline:
                       self.values[: self.nnz_in], self.info)
         A._plan = self.plan
         return A.sync()
+
