@@ -22,8 +22,10 @@
  *   Errors.   Arguments that can be checked on the host are checked before anything is
  *             enqueued; on failure the call returns that status and enqueues nothing.
  *             Conditions only the device can see (an out-of-range triplet, a malformed CSC)
- *             are written to the device status word info[1]; outputs are then unspecified,
- *             but no kernel ever reads or writes outside the buffers described here.
+ *             are written to the device status word info[1].  Out-of-range triplets are
+ *             skipped and the outputs describe the others; a plan built from a malformed CSC
+ *             is unspecified.  Either way no kernel reads or writes outside the buffers
+ *             described here.
  *             A failed HIP launch returns SPM_EHIP.
  *   Sizes.    Dimensions and counts are int64_t on the ABI; n_rows, n_cols, nnz and every
  *             offset must fit in int32 (SPM_EOVERFLOW otherwise).
