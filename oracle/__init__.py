@@ -62,6 +62,8 @@ def configure(lib):
         f = getattr(lib, name)
         f.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
         f.restype = ctypes.c_int
+    lib.oracle_csc_insert.argtypes = [i64, i64, p, p, p, i64, p, p, p, p, p, p, p]
+    lib.oracle_csc_insert.restype = ctypes.c_int
     lib.oracle_spmm.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
     lib.oracle_spmm.restype = None
     lib.oracle_spmm_backward.argtypes = [i64, i64, i64, p, p, p, p, p, p, p, p, p]
@@ -124,6 +126,34 @@ def coo_to_csc(n_rows, n_cols, row, col, val, method: str = "sort"):
         return st, None
     m = nnz.value
     return OK, CSC(n_rows, n_cols, col_ptr, row_idx[:m].copy(), out[:m].copy())
+
+
+def csc_insert(A: CSC, row, col, val):
+    """Batch insertion of new triplets into the existing CSC A (Section 3.1: sort the new
+    elements, then merge with the existing arrays), accumulating like X(r,c) += v (Fig. 1):
+    at each location the existing value comes first, then the new values in input order, in
+    binary64; zero sums are not stored.  Returns (status, CSC or None)."""
+    lib = _load()
+    row = np.ascontiguousarray(row, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    v = widen(val)
+    n = row.shape[0]
+    assert col.shape[0] == n and v.shape[0] == n
+    a_cp = np.ascontiguousarray(A.col_ptr, dtype=np.int32)
+    a_ri = np.ascontiguousarray(A.row_idx, dtype=np.int32)
+    a_v = np.ascontiguousarray(A.values, dtype=np.float64)
+    cap = max(int(a_cp[-1]) + n, 1)
+    col_ptr = np.zeros(A.n_cols + 1, dtype=np.int32)
+    row_idx = np.zeros(cap, dtype=np.int32)
+    out = np.zeros(cap, dtype=np.float64)
+    nnz = ctypes.c_int64(0)
+    st = lib.oracle_csc_insert(A.n_rows, A.n_cols, _ptr(a_cp), _ptr(a_ri), _ptr(a_v), n,
+                               _ptr(row), _ptr(col), _ptr(v), _ptr(col_ptr), _ptr(row_idx),
+                               _ptr(out), ctypes.byref(nnz))
+    if st != OK:
+        return st, None
+    m = nnz.value
+    return OK, CSC(A.n_rows, A.n_cols, col_ptr, row_idx[:m].copy(), out[:m].copy())
 
 
 def spmm(A: CSC, X, values=None):

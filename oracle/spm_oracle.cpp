@@ -20,6 +20,7 @@
 #include <map>
 #include <vector>
 #include <algorithm>
+#include <climits>
 
 namespace {
 
@@ -125,6 +126,77 @@ int oracle_coo_to_csc_sort(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const
       ++n;
     }
     i = j;
+  }
+  offsets_from_columns(n_cols, emitted_cols, col_ptr);
+  *nnz_out = n;
+  return 0;
+}
+
+// Batch insertion into an existing CSC (Section 3.1: sort the elements to be inserted, then
+// merge them with the existing arrays), with the accumulating update of Fig. 1, X(r,c) += v:
+//   the new triplets are stably sorted by (column, row), so that those at one location stay in
+//   input order; every column of the result is the merge of the existing column (rows
+//   strictly increasing) with the sorted new triplets of that column; at each location the
+//   existing value, if any, comes first and the new values are added to it left to right in
+//   binary64, s = ((a + v_t1) + v_t2) + ... (a location without an existing element starts
+//   from its first new value); the location is stored iff s != 0.0.
+// Existing CSC: a_col_ptr[n_cols+1] with a_col_ptr[0] = 0 and non-decreasing offsets, and
+// a_row_idx / a_val holding a_col_ptr[n_cols] elements.  Outputs as for assembly, with
+// capacity a_col_ptr[n_cols] + nnz_in.
+// Returns 0, 1 (bad sizes, null pointers, or an existing CSC not of that form) or 2 (a new
+// triplet out of range; outputs untouched).
+int oracle_csc_insert(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
+                      const int32_t* a_row_idx, const double* a_val, int64_t nnz_in,
+                      const int32_t* row, const int32_t* col, const double* val,
+                      int32_t* col_ptr, int32_t* row_idx, double* val_out, int64_t* nnz_out) {
+  if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || !a_col_ptr || !col_ptr || !nnz_out) return 1;
+  if (nnz_in > 0 && (!row || !col || !val)) return 1;
+  if (a_col_ptr[0] != 0) return 1;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    if (a_col_ptr[c + 1] < a_col_ptr[c]) return 1;
+    for (int64_t p = a_col_ptr[c]; p < a_col_ptr[c + 1]; ++p) {
+      if (a_row_idx[p] < 0 || (int64_t)a_row_idx[p] >= n_rows) return 1;
+      if (p > a_col_ptr[c] && a_row_idx[p] <= a_row_idx[p - 1]) return 1;
+    }
+  }
+  for (int64_t t = 0; t < nnz_in; ++t)
+    if (!in_range(n_rows, n_cols, row[t], col[t])) return 2;
+
+  std::vector<int64_t> order(nnz_in);
+  for (int64_t t = 0; t < nnz_in; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return col[a] < col[b] || (col[a] == col[b] && row[a] < row[b]);
+  });
+
+  std::vector<int64_t> emitted_cols;
+  int64_t n = 0;
+  int64_t j = 0;  // next sorted new triplet
+  for (int64_t c = 0; c < n_cols; ++c) {
+    int64_t p = a_col_ptr[c];
+    const int64_t pe = a_col_ptr[c + 1];
+    while (p < pe || (j < nnz_in && col[order[j]] == c)) {
+      // the next location of the merged column: the smaller of the two next rows
+      int64_t r = p < pe ? a_row_idx[p] : INT64_MAX;
+      if (j < nnz_in && col[order[j]] == c && row[order[j]] < r) r = row[order[j]];
+      bool started = false;
+      double acc = 0.0;
+      if (p < pe && a_row_idx[p] == r) {  // the existing element first
+        acc = a_val[p];
+        started = true;
+        ++p;
+      }
+      while (j < nnz_in && col[order[j]] == c && row[order[j]] == r) {
+        acc = started ? acc + val[order[j]] : val[order[j]];
+        started = true;
+        ++j;
+      }
+      if (acc != 0.0) {
+        row_idx[n] = (int32_t)r;
+        val_out[n] = acc;
+        emitted_cols.push_back(c);
+        ++n;
+      }
+    }
   }
   offsets_from_columns(n_cols, emitted_cols, col_ptr);
   *nnz_out = n;

@@ -369,8 +369,78 @@ def pin_central_fd(samples: int = 24):
         assert abs(fd - dX[c, j]) <= 1e-8 * abs(dX[c, j]) + 1e-10, (c, j, fd, dX[c, j])
 
 
+# ----------------------------------------------------------------------- batch insertion pins
+
+def pin_golden_insert():
+    """The hand-computed insertion of tests/golden/insert_small.json (existing value first)."""
+    g = load_golden("insert_small.json")
+    A = oracle.CSC(g["n_rows"], g["n_cols"], np.array(g["a_col_ptr"], np.int32),
+                   np.array(g["a_row_idx"], np.int32), np.array(g["a_val"], np.float64))
+    st, R = oracle.csc_insert(A, np.array(g["row"], np.int32), np.array(g["col"], np.int32),
+                              np.array(g["val"], np.float64))
+    assert st == oracle.OK
+    assert R.col_ptr.tolist() == g["expect_col_ptr"]
+    assert R.row_idx.tolist() == g["expect_row_idx"]
+    assert same_floats(R.values, np.array(g["expect_val"], np.float64))
+
+
+def pin_brute_force_insert(seeds=range(12)):
+    """Dense brute force: start from the existing matrix, D[r, c] = D[r, c] + v for the new
+    triplets in input order, store the non-zero entries column by column."""
+    for seed in seeds:
+        rng = np.random.Generator(np.random.PCG64(6000 + seed))
+        n_rows = int(rng.integers(1, 9))
+        n_cols = int(rng.integers(1, 9))
+        D0 = rng.choice(np.array([-2.0, -1.0, 0.5, 1.5, 3.0]), (n_rows, n_cols))
+        D0 = D0 * (rng.random((n_rows, n_cols)) < 0.5)
+        D0 = D0 + rng.standard_normal((n_rows, n_cols)) * (D0 != 0) * (rng.random(D0.shape) < 0.3)
+        A = csc_from_dense(D0)
+        nnz = int(rng.integers(0, 40))
+        row = rng.integers(0, n_rows, nnz).astype(np.int32)
+        col = rng.integers(0, n_cols, nnz).astype(np.int32)
+        val = rng.choice(np.array([-1.5, -1.0, -0.5, 0.25, 0.5, 1.0, 2.0]), nnz)
+        cancel = rng.random(nnz) < 0.3  # some new values cancel the existing ones exactly
+        val = np.where(cancel & (D0[row, col] != 0), -D0[row, col], val)
+        D = D0.copy()
+        for r, c, v in zip(row.tolist(), col.tolist(), val.tolist()):
+            D[r, c] = D[r, c] + v
+        E = csc_from_dense(D)
+        st, R = oracle.csc_insert(A, row, col, val)
+        assert st == oracle.OK
+        assert np.array_equal(R.col_ptr, E.col_ptr), seed
+        assert np.array_equal(R.row_idx, E.row_idx), seed
+        assert same_floats(R.values, E.values), seed
+
+
+def pin_insert_special_cases():
+    """Nothing to insert leaves A as it is; inserting into an empty matrix is assembly; a
+    new triplet out of range is rejected; a malformed existing CSC is rejected."""
+    rng = np.random.Generator(np.random.PCG64(6100))
+    D0 = rng.standard_normal((5, 4)) * (rng.random((5, 4)) < 0.5)
+    A = csc_from_dense(D0)
+    st, R = oracle.csc_insert(A, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert st == oracle.OK and np.array_equal(R.col_ptr, A.col_ptr)
+    assert np.array_equal(R.row_idx, A.row_idx) and same_floats(R.values, A.values)
+    E = oracle.CSC(5, 4, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    row = np.array([4, 0, 4, 2], np.int32)
+    col = np.array([3, 0, 3, 1], np.int32)
+    val = np.array([1.0, -2.0, 0.5, 3.0])
+    st, R = oracle.csc_insert(E, row, col, val)
+    ecp, er, ev = brute_force_csc(5, 4, row, col, val)
+    assert st == oracle.OK and np.array_equal(R.col_ptr, ecp)
+    assert np.array_equal(R.row_idx, er) and same_floats(R.values, ev)
+    st, _ = oracle.csc_insert(A, np.array([5], np.int32), np.array([0], np.int32),
+                              np.array([1.0]))
+    assert st == oracle.EBOUNDS
+    bad = oracle.CSC(5, 4, np.array([0, 2, 2, 2, 2], np.int32), np.array([3, 1], np.int32),
+                     np.array([1.0, 2.0]))  # rows not increasing in column 0
+    st, _ = oracle.csc_insert(bad, row, col, val)
+    assert st == oracle.EINVAL
+
+
 ASSEMBLY_PINS = [pin_golden_assembly, pin_brute_force, pin_scipy_dyadic, pin_invariants_and_totals,
-                 pin_index_encoding, pin_special_cases]
+                 pin_index_encoding, pin_special_cases, pin_golden_insert, pin_brute_force_insert,
+                 pin_insert_special_cases]
 SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
              pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
 ALL_PINS = ASSEMBLY_PINS + SPMM_PINS

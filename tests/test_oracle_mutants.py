@@ -15,6 +15,30 @@ import pytest
 import oracle
 import pins
 
+# the existing value of a location folded last instead of first
+INSERT_FOLD = """      if (p < pe && a_row_idx[p] == r) {  // the existing element first
+        acc = a_val[p];
+        started = true;
+        ++p;
+      }
+      while (j < nnz_in && col[order[j]] == c && row[order[j]] == r) {
+        acc = started ? acc + val[order[j]] : val[order[j]];
+        started = true;
+        ++j;
+      }
+"""
+INSERT_FOLD_NEW_FIRST = """      while (j < nnz_in && col[order[j]] == c && row[order[j]] == r) {
+        acc = started ? acc + val[order[j]] : val[order[j]];
+        started = true;
+        ++j;
+      }
+      if (p < pe && a_row_idx[p] == r) {
+        acc = started ? acc + a_val[p] : a_val[p];
+        started = true;
+        ++p;
+      }
+"""
+
 MUTANTS = {
     "fold_sign_sort": ("s = s + val[order[j]];", "s = s - val[order[j]];"),
     "fold_last_wins_rbt": ("it->second = it->second + val[t];", "it->second = val[t];"),
@@ -35,6 +59,9 @@ MUTANTS = {
     "dval_sign": ("d = d + G[r * k + j] * X[c * k + j];", "d = d - G[r * k + j] * X[c * k + j];"),
     "dval_dropped_term": ("d = d + G[r * k + j] * X[c * k + j];",
                           "if (j) d = d + G[r * k + j] * X[c * k + j];"),
+    "insert_existing_ignored": ("acc = a_val[p];", "acc = 0.0;"),
+    "insert_keep_zero": ("if (acc != 0.0) {", "if (true) {"),
+    "insert_new_first": (INSERT_FOLD, INSERT_FOLD_NEW_FIRST),
 }
 
 

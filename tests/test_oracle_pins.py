@@ -65,3 +65,22 @@ def test_float32_fold_never_rounds_to_zero():
     r = rng.integers(0, 5, 4000).astype(np.int32)
     s, A = oracle.coo_to_csc(5, 1, r, np.zeros(4000, np.int32), v)
     assert not np.any(A.rounded(np.float32) == 0)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_insert_equals_concatenated_assembly(seed):
+    """Insertion folds the existing value first, then the new ones in input order: the same as
+    assembling the existing elements (in CSC order) followed by the new triplets."""
+    from paper_1805_03380_amd import synth
+    p = synth.random_coo(seed, 400, 300, 20_000, dup_frac=0.2, dist="normal")
+    q = synth.random_coo(seed + 10, 400, 300, 8_000, dup_frac=0.2, dist="normal")
+    s0, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    assert s0 == oracle.OK
+    s1, R = oracle.csc_insert(A, q.row, q.col, q.val)
+    a_col = np.repeat(np.arange(A.n_cols), np.diff(A.col_ptr)).astype(np.int32)
+    s2, C = oracle.coo_to_csc(A.n_rows, A.n_cols, np.concatenate([A.row_idx, q.row]),
+                              np.concatenate([a_col, q.col]), np.concatenate([A.values, q.val]))
+    assert s1 == s2 == oracle.OK
+    assert np.array_equal(R.col_ptr, C.col_ptr)
+    assert np.array_equal(R.row_idx, C.row_idx)
+    assert pins.same_floats(R.values, C.values)
