@@ -16,7 +16,7 @@ recorded in a HIP graph are reported under "graph";
 oracle timed on the host cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch] [--separate]
-                    [--no-graph] [--cold-steps 10]
+                    [--no-graph] [--no-insert] [--cold-steps 10]
 """
 from __future__ import annotations
 
@@ -42,6 +42,8 @@ def parse():
                     help="steps timed one by one after writing 1 GiB of scratch (cold caches)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the K steps timed as replays of the step recorded in a HIP graph")
+    ap.add_argument("--no-insert", action="store_true",
+                    help="skip the batch-insertion measurement")
     ap.add_argument("--separate", action="store_true",
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -305,6 +307,44 @@ def main():
                  "value": p.nnz_in / (g_ms * 1e-3)}
         del g
 
+    # batch insertion (Section 3.1): 10^5 new triplets merged into the step's CSC
+    insert = None
+    if not args.no_insert:
+        from paper_1805_03380_amd import ops
+        A = pipe.csc()
+        q = synth.random_coo(1006, p.n_rows, p.n_cols, 100_000, dup_frac=0.05,
+                             dtype=np.float64 if pipe.values.dtype == torch.float64
+                             else np.float32)
+        qr, qc, qv = (torch.from_numpy(a).to(dev) for a in (q.row, q.col, q.val))
+        B = ops.csc_insert(A, qr, qc, qv)  # warm-up, and the workspace for the timed calls
+        out = (B.col_ptr, B.row_idx_buf, B.values_buf, B.info)
+        lib = _lib.load()
+        cap_a = A.nnz_cap
+
+        def run_insert():
+            for _ in range(args.steps):
+                lib.spm_csc_insert(A.n_rows, A.n_cols, cap_a, A.col_ptr.data_ptr(),
+                                   A.row_idx_buf.data_ptr(), A.values_buf.data_ptr(), q.nnz_in,
+                                   qr.data_ptr(), qc.data_ptr(), qv.data_ptr(),
+                                   ops._dtype_code(qv.dtype), out[0].data_ptr(),
+                                   out[1].data_ptr(), out[2].data_ptr(),
+                                   ops._dtype_code(out[2].dtype), out[3].data_ptr(),
+                                   B._ws.data_ptr(), B._ws.numel(), stream.cuda_stream)
+        i_ms = timed(run_insert)
+        nnz_out, st_i = (int(x) for x in out[3].cpu())
+        if st_i:
+            raise RuntimeError("spm_csc_insert reported status %d" % st_i)
+        sv = A.values_buf.element_size()
+        i_bytes = (4 * (p.n_cols + 1) + nnz * (4 + sv) + q.nnz_in * (8 + sv)
+                   + 4 * (p.n_cols + 1) + nnz_out * (4 + sv))
+        insert = {"workload": "10^5 new triplets (5 percent duplicates, seed 1006) into the "
+                              "assembled 1e5 x 1e5 CSC", "existing": nnz, "new": q.nnz_in,
+                  "nnz_out": nnz_out, "ms": i_ms,
+                  "elements_per_s": (nnz + q.nnz_in) / (i_ms * 1e-3),
+                  "new_triplets_per_s": q.nnz_in / (i_ms * 1e-3),
+                  "compulsory_bytes": i_bytes,
+                  "compulsory_GBps": i_bytes / (i_ms * 1e-3) / 1e9}
+
     # headline: the K eager steps on one stream, nothing recorded between them
     head_ms, timing = ms_step, "eager library calls on one stream"
 
@@ -383,6 +423,7 @@ def main():
         "step_ms_p90": float(np.percentile(step_ms, 90)),
         "cold": cold,
         "graph": graph,
+        "insert": insert,
         "assembly_nnz_per_s": p.nnz_in / (phase_ms[phases[0]] * 1e-3),
         "assembly_phase": phases[0],
         "assembly_compulsory_GBps": bytes_[phases[0]] / asm_t / 1e9,

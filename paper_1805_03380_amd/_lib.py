@@ -83,6 +83,10 @@ SIGNATURES = {
                                            c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                            ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
                                            c_p]),
+    "spm_csc_insert_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
+    "spm_csc_insert": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
+                                      ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
+                                      ctypes.c_size_t, c_p]),
     "spm_csc_spmm": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int,
                                     ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p, c_i64,
                                     ctypes.c_int, c_p]),

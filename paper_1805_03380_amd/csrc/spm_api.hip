@@ -711,6 +711,88 @@ void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t
   }
 }
 
+// Batch insertion: the assembly's layout over the cap_a + nnz_t positions of the virtual
+// input, plus the existing elements' columns, the virtual values (8 bytes each, for either
+// value type) and the status flags (column expansion, then level-1 tiles).
+struct InsertLayout {
+  AsmLayout A;
+  size_t colarr, vcat, flags, total;
+};
+
+InsertLayout insert_layout(int64_t n_cols, int64_t cap_a, int64_t nnz_t) {
+  InsertLayout L;
+  L.A = asm_layout(n_cols, cap_a + nnz_t);
+  Carve c;
+  c.off = L.A.total;
+  L.colarr = c.take(sizeof(int32_t) * (size_t)cap_a);
+  L.vcat = c.take(sizeof(double) * (size_t)(cap_a + nnz_t));
+  L.flags = c.take(sizeof(uint32_t) *
+                   (size_t)(expand_grid(n_cols) + (L.A.pp.ok ? L.A.pp.ntiles : 0)));
+  L.total = c.off;
+  return L;
+}
+
+// The merge as the assembly of the virtual input (PartSrcMerge), on the partition path.
+template <typename VT>
+void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_col_ptr,
+              const int32_t* a_row_idx, const VT* a_val, int64_t nnz_t, const int32_t* row,
+              const int32_t* col, const VT* val, int32_t* col_ptr, int32_t* row_idx,
+              void* val_out, int out_f64, int32_t* info, char* w, const InsertLayout& IL,
+              hipStream_t s) {
+  const AsmLayout& L = IL.A;
+  const PartParams& P = L.pp;
+  int32_t* colarr = reinterpret_cast<int32_t*>(w + IL.colarr);
+  VT* vcat = reinterpret_cast<VT*>(w + IL.vcat);
+  uint32_t* flags = reinterpret_cast<uint32_t*>(w + IL.flags);
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
+  uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
+  uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
+  uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
+  uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
+  int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
+  uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
+  uint32_t* bvhi = reinterpret_cast<uint32_t*>(w + L.bvhi);
+  uint32_t* trow = reinterpret_cast<uint32_t*>(w + L.trow);
+  double* tval = reinterpret_cast<double*>(w + L.tval);
+  uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
+  const int cap = cu_count() * 16;
+  const int64_t n = cap_a + nnz_t;
+  if (n > 0)
+    k_concat_values<kNT, VT><<<dim3(grid_for(n, kNT * 4, cap)), dim3(kNT), 0, s>>>(
+        a_val, cap_a, val, nnz_t, vcat);
+  const int eg = expand_grid(n_cols);
+  k_expand_columns<kNT><<<dim3(eg), dim3(kNT), 0, s>>>(a_col_ptr, n_cols, cap_a, colarr, info,
+                                                       flags);
+  PartSrcMerge src{a_row_idx, colarr, a_col_ptr, row, col, (int32_t)n_rows, (int32_t)n_cols,
+                   cap_a, nnz_t};
+  k_part_hist<kPartNT, PartSrcMerge>
+      <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
+          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg);
+  k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
+      (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
+      (int64_t)eg + P.ntiles, info);
+  k_part_scatter<kPartNT, PartSrcMerge, VT>
+      <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
+          src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
+          bstart, brec, (const VT*)vcat, bvhi);
+  k_part_level2<kNT, kPartCap, false, VT>
+      <<<dim3((unsigned)P.CB), dim3(kNT), part_level2_lds_bytes(P.b, kPartCap), s>>>(
+          P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi,
+          bucket, scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+          (const VT*)vcat, (VT*)nullptr, col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b),
+          L2RowCount{nullptr, 0, 0, 0});
+  int32_t* boff = nullptr;
+  if (P.CB > kEmitReduceMax) {
+    boff = reinterpret_cast<int32_t*>(w + L.boff);
+    k_small_scan<kNT><<<dim3(1), dim3(kNT), 0, s>>>((const uint32_t*)bkept, (int64_t)P.CB,
+                                                    boff);
+  }
+  k_part_emit<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
+      P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint32_t*)bkept, (const int32_t*)boff,
+      (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out, out_f64, info,
+      EmitPlan{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+}
+
 }  // namespace
 
 extern "C" {
@@ -790,6 +872,52 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
     plan_build_t<float>(n_rows, n_cols, nnz_in, col_ptr, row_idx,
                         static_cast<const float*>(val_out), static_cast<float*>(val_plan),
                         static_cast<char*>(plan), plan_info, w, P, PL, s);
+  return launch_status();
+}
+
+spm_status spm_csc_insert_workspace(int64_t n_rows, int64_t n_cols, int64_t cap_a,
+                                    int64_t nnz_t, size_t* ws_bytes) {
+  if (!ws_bytes || cap_a < 0 || nnz_t < 0) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, cap_a);
+  if (st != SPM_OK) return st;
+  if (!fits_i32(nnz_t) || !fits_i32(cap_a + nnz_t)) return SPM_EOVERFLOW;
+  *ws_bytes = insert_layout(n_cols, cap_a, nnz_t).total;
+  return SPM_OK;
+}
+
+spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
+                          const int32_t* a_col_ptr, const int32_t* a_row_idx, const void* a_val,
+                          int64_t nnz_t, const int32_t* row, const int32_t* col,
+                          const void* val, spm_dtype val_type, int32_t* col_ptr,
+                          int32_t* row_idx, void* val_out, spm_dtype out_type, int32_t* info,
+                          void* ws, size_t ws_bytes, void* stream) {
+  if (cap_a < 0 || nnz_t < 0) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, cap_a);
+  if (st != SPM_OK) return st;
+  if (!fits_i32(nnz_t) || !fits_i32(cap_a + nnz_t)) return SPM_EOVERFLOW;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (out_type != SPM_F64 && out_type != SPM_F32) return SPM_EDTYPE;
+  if (!a_col_ptr || !col_ptr || !info || !ws) return SPM_EINVAL;
+  if (cap_a > 0 && (!a_row_idx || !a_val)) return SPM_EINVAL;
+  if (nnz_t > 0 && (!row || !col || !val)) return SPM_EINVAL;
+  if (cap_a + nnz_t > 0 && (!row_idx || !val_out)) return SPM_EINVAL;
+  if (!aligned(ws, 256)) return SPM_EINVAL;
+  const InsertLayout L = insert_layout(n_cols, cap_a, nnz_t);
+  if (!L.A.pp.ok) return SPM_EINVAL;  // no columns, or more than the partition covers
+  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const int out_f64 = out_type == SPM_F64 ? 1 : 0;
+  if (val_type == SPM_F64)
+    insert_t<double>(n_rows, n_cols, cap_a, a_col_ptr, a_row_idx,
+                     static_cast<const double*>(a_val), nnz_t, row, col,
+                     static_cast<const double*>(val), col_ptr, row_idx, val_out, out_f64, info,
+                     static_cast<char*>(ws), L, s);
+  else
+    insert_t<float>(n_rows, n_cols, cap_a, a_col_ptr, a_row_idx,
+                    static_cast<const float*>(a_val), nnz_t, row, col,
+                    static_cast<const float*>(val), col_ptr, row_idx, val_out, out_f64, info,
+                    static_cast<char*>(ws), L, s);
   return launch_status();
 }
 

@@ -35,7 +35,13 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
 }
 constexpr int kPartMaxWidth = 4096;     // segments per coarse bucket (LDS counters)
 
-// Element sources.  part_elem returns false for an element that is skipped (out of range).
+// Element sources.  elem() reports kElemOk (seg and key set), kElemBad (an index out of
+// range: skipped and reported in the status) or kElemSkip (an unused position: skipped
+// silently); a bool source's true / false read as ok / bad.
+constexpr int kElemBad = 0;
+constexpr int kElemOk = 1;
+constexpr int kElemSkip = 2;
+
 struct PartSrcCoo {  // assembly: segment = column, key = row << 32 | input position
   const int32_t* row;
   const int32_t* col;
@@ -72,6 +78,54 @@ struct PartSrcCsc {  // plan: segment = row, key = column << 32 | CSC slot
     return false;
   }
 };
+
+// Batch insertion into an existing CSC: the existing stored elements take the positions
+// 0 .. cap_a of one virtual input (slot p; slots at or past a_col_ptr[n_cols] are unused and
+// skipped silently), the new triplets follow at cap_a + t.  Keys carry the position, so at a
+// location the existing element folds first, then the new triplets in input order; the
+// assembly of this virtual input is the merge.
+struct PartSrcMerge {
+  const int32_t* a_row;      // existing row indices, by CSC slot
+  const int32_t* a_colarr;   // column of every existing slot (k_expand_columns)
+  const int32_t* a_col_ptr;  // a_col_ptr[n_cols] = number of existing elements
+  const int32_t* row;        // new triplets
+  const int32_t* col;
+  int32_t n_rows, n_cols;
+  int64_t cap_a, n_t;
+  __device__ __forceinline__ int64_t count() const { return cap_a + n_t; }
+  __device__ __forceinline__ int elem(int64_t e, uint32_t& seg, uint64_t& key) const {
+    int32_t r, c;
+    if (e < cap_a) {
+      const int64_t raw = a_col_ptr[n_cols];
+      const int64_t nnz_a = raw < 0 ? 0 : (raw > cap_a ? cap_a : raw);
+      if (e >= nnz_a) return kElemSkip;
+      r = a_row[e];
+      c = a_colarr[e];
+    } else {
+      r = row[e - cap_a];
+      c = col[e - cap_a];
+    }
+    if ((uint32_t)r < (uint32_t)n_rows && (uint32_t)c < (uint32_t)n_cols) {
+      seg = (uint32_t)c;
+      key = ((uint64_t)(uint32_t)r << 32) | (uint32_t)e;
+      return kElemOk;
+    }
+    return kElemBad;
+  }
+};
+
+// Values of the virtual input of a batch insertion: vcat[e] = a_val[e] for e < cap_a (slots
+// past the existing elements are copied but never read), val[e - cap_a] after.
+template <int NT, typename VT>
+__global__ __launch_bounds__(NT) void k_concat_values(const VT* __restrict__ a_val,
+                                                      int64_t cap_a,
+                                                      const VT* __restrict__ val, int64_t n_t,
+                                                      VT* __restrict__ vcat) {
+  const int64_t n = cap_a + n_t;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * NT)
+    vcat[e] = e < cap_a ? a_val[e] : val[e - cap_a];
+}
 
 // Status without a cleared word: every workgroup of a checking kernel writes its own flag
 // word (kFlagShape | kFlagIndex bits, 0 if clean) and k_rows_scan folds them into info[1],
@@ -162,8 +216,9 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
       uint64_t key;
       ok[u] = false;
       if (e < end) {
-        ok[u] = src.elem(e, seg[u], key);
-        bad |= !ok[u];
+        const int st = (int)src.elem(e, seg[u], key);
+        ok[u] = st == kElemOk;
+        bad |= st == kElemBad;
       }
     }
 #pragma unroll
@@ -302,7 +357,7 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + (int64_t)u * NT;
-      ok[u] = (e < end) ? src.elem(e, seg[u], key[u]) : false;
+      ok[u] = (e < end) && (int)src.elem(e, seg[u], key[u]) == kElemOk;
       if (carry && e < end) v[u] = vin[e];
     }
 #pragma unroll

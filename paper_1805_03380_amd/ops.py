@@ -178,6 +178,51 @@ def coo_to_csc_plan(row: torch.Tensor, col: torch.Tensor, val: torch.Tensor, sha
     return A, vplan
 
 
+def csc_insert(A: CSCMatrix, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor,
+               out_dtype: torch.dtype | None = None, sync: bool = True) -> CSCMatrix:
+    """Batch insertion of triplets into A (spm_csc_insert): a new CSC in which every location
+    holds A's value (if any) plus the new values in input order, zero sums dropped.  `val`
+    must have A's value type (float32 or float64)."""
+    _require_cuda(row, col, val, A.col_ptr)
+    row = row.contiguous()
+    col = col.contiguous()
+    val = val.contiguous()
+    if row.dtype != torch.int32 or col.dtype != torch.int32:
+        raise ValueError("row and col must be int32")
+    if val.dtype != A.values_buf.dtype:
+        raise ValueError("new values must have the matrix's value type %s" % A.values_buf.dtype)
+    nnz_t = int(row.numel())
+    if col.numel() != nnz_t or val.numel() != nnz_t:
+        raise ValueError("row, col and val must have the same length")
+    if out_dtype is None:
+        out_dtype = A.values_buf.dtype
+    lib = _lib.load()
+    dev = row.device
+    cap_a = A.nnz_cap
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_csc_insert_workspace(A.n_rows, A.n_cols, cap_a, nnz_t,
+                                            _lib.ctypes.byref(wb)), "spm_csc_insert_workspace")
+    ws = _workspace(wb.value, dev)
+    cap = cap_a + nnz_t
+    col_ptr = torch.empty(A.n_cols + 1, dtype=torch.int32, device=dev)
+    row_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    vout = torch.empty(max(cap, 1), dtype=out_dtype, device=dev)
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.spm_csc_insert(A.n_rows, A.n_cols, cap_a, _ptr(A.col_ptr),
+                            _ptr(A.row_idx_buf) if cap_a else None,
+                            _ptr(A.values_buf) if cap_a else None, nnz_t, _ptr(row), _ptr(col),
+                            _ptr(val), _dtype_code(val.dtype), _ptr(col_ptr), _ptr(row_idx),
+                            _ptr(vout), _dtype_code(out_dtype), _ptr(info), _ptr(ws),
+                            ws.numel(), _stream(dev))
+    _lib.check(st, "spm_csc_insert")
+    B = CSCMatrix(A.n_rows, A.n_cols, col_ptr, row_idx[:cap] if cap else row_idx[:0],
+                  vout[:cap] if cap else vout[:0], info)
+    B._ws = ws
+    if sync:
+        B.sync()
+    return B
+
+
 def plan_size(n_rows: int, n_cols: int, nnz_cap: int):
     lib = _lib.load()
     pb = _lib.ctypes.c_size_t(0)

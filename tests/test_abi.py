@@ -122,6 +122,22 @@ def test_host_validation_rejects_before_launch():
     assert c2cp(plan=ctypes.c_void_p(0x1010)) == _lib.EINVAL  # not 256-byte aligned
     assert c2cp(pb=16) == _lib.EWORKSPACE
     assert c2cp(wsb=16) == _lib.EWORKSPACE
+    # batch insertion
+
+    def ins(n_rows=4, n_cols=4, cap=8, nt=3, vt=_lib.F64, ot=_lib.F64, acp=fake, cp=fake,
+            info=fake, w=ws, wsb=1 << 30):
+        return lib.spm_csc_insert(n_rows, n_cols, cap, acp, fake, fake, nt, fake, fake, fake, vt,
+                                  cp, fake, fake, ot, info, w, wsb, None)
+
+    assert ins(cap=-1) == _lib.EINVAL
+    assert ins(nt=2 ** 31) == _lib.EOVERFLOW
+    assert ins(cap=2 ** 30, nt=2 ** 30) == _lib.EOVERFLOW
+    assert ins(vt=_lib.BF16) == _lib.EDTYPE
+    assert ins(ot=_lib.BF16) == _lib.EDTYPE
+    assert ins(acp=None) == _lib.EINVAL
+    assert ins(info=None) == _lib.EINVAL
+    assert ins(n_cols=0) == _lib.EINVAL  # no columns: nothing for the partition to group
+    assert ins(wsb=16) == _lib.EWORKSPACE
 
 
 def test_tuning_roundtrip():
