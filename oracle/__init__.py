@@ -64,6 +64,8 @@ def configure(lib):
         f.restype = ctypes.c_int
     lib.oracle_csc_insert.argtypes = [i64, i64, p, p, p, i64, p, p, p, p, p, p, p]
     lib.oracle_csc_insert.restype = ctypes.c_int
+    lib.oracle_csc_transpose.argtypes = [i64, i64, p, p, p, p, p, p]
+    lib.oracle_csc_transpose.restype = ctypes.c_int
     lib.oracle_spmm.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
     lib.oracle_spmm.restype = None
     lib.oracle_spmm_backward.argtypes = [i64, i64, i64, p, p, p, p, p, p, p, p, p]
@@ -154,6 +156,24 @@ def csc_insert(A: CSC, row, col, val):
         return st, None
     m = nnz.value
     return OK, CSC(A.n_rows, A.n_cols, col_ptr, row_idx[:m].copy(), out[:m].copy())
+
+
+def csc_transpose(A: CSC):
+    """A^T as a CSC (X.t() of Table 1): element (r, c, v) of A becomes (c, r, v); each column
+    of the result lists one row of A by increasing column.  Returns (status, CSC or None)."""
+    lib = _load()
+    a_cp = np.ascontiguousarray(A.col_ptr, dtype=np.int32)
+    a_ri = np.ascontiguousarray(A.row_idx, dtype=np.int32)
+    a_v = np.ascontiguousarray(A.values, dtype=np.float64)
+    m = int(a_cp[-1])
+    t_cp = np.zeros(A.n_rows + 1, dtype=np.int32)
+    t_ri = np.zeros(max(m, 1), dtype=np.int32)
+    t_v = np.zeros(max(m, 1), dtype=np.float64)
+    st = lib.oracle_csc_transpose(A.n_rows, A.n_cols, _ptr(a_cp), _ptr(a_ri), _ptr(a_v),
+                                  _ptr(t_cp), _ptr(t_ri), _ptr(t_v))
+    if st != OK:
+        return st, None
+    return OK, CSC(A.n_cols, A.n_rows, t_cp, t_ri[:m].copy(), t_v[:m].copy())
 
 
 def spmm(A: CSC, X, values=None):

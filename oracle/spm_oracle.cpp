@@ -203,6 +203,38 @@ int oracle_csc_insert(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
   return 0;
 }
 
+// Transpose X.t() (Table 1) of a CSC, written as a CSC of the n_cols x n_rows result:
+//   every stored element (r, c, v) of A becomes (c, r, v) of A^T.  Column r of A^T lists the
+//   elements of row r of A in increasing column order (a counting pass over the rows of A,
+//   then the columns of A walked in order, so each row receives its elements by increasing
+//   column).  Values are moved, not changed.
+// Output: t_col_ptr[n_rows+1], t_row_idx / t_val with capacity a_col_ptr[n_cols].
+// Returns 0, or 1 (bad sizes, null pointers, or an existing CSC that is not valid).
+int oracle_csc_transpose(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
+                         const int32_t* a_row_idx, const double* a_val, int32_t* t_col_ptr,
+                         int32_t* t_row_idx, double* t_val) {
+  if (n_rows < 0 || n_cols < 0 || !a_col_ptr || !t_col_ptr) return 1;
+  if (a_col_ptr[0] != 0) return 1;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    if (a_col_ptr[c + 1] < a_col_ptr[c]) return 1;
+    for (int64_t p = a_col_ptr[c]; p < a_col_ptr[c + 1]; ++p)
+      if (a_row_idx[p] < 0 || (int64_t)a_row_idx[p] >= n_rows) return 1;
+  }
+  std::vector<int64_t> per_row(n_rows + 1, 0);
+  for (int64_t p = 0; p < a_col_ptr[n_cols]; ++p) per_row[a_row_idx[p] + 1] += 1;
+  t_col_ptr[0] = 0;
+  for (int64_t r = 0; r < n_rows; ++r) t_col_ptr[r + 1] = (int32_t)(t_col_ptr[r] + per_row[r + 1]);
+  std::vector<int64_t> next(n_rows);
+  for (int64_t r = 0; r < n_rows; ++r) next[r] = t_col_ptr[r];
+  for (int64_t c = 0; c < n_cols; ++c)
+    for (int64_t p = a_col_ptr[c]; p < a_col_ptr[c + 1]; ++p) {
+      const int64_t q = next[a_row_idx[p]]++;
+      t_row_idx[q] = (int32_t)c;
+      t_val[q] = a_val[p];
+    }
+  return 0;
+}
+
 // Sparse x dense product, Section 3 use case (iv) and the CSC traversal of Section 3.1:
 //   Y[r, j] = sum over stored (r, c) of  v * X[c, j],   X is n_cols x k, Y is n_rows x k,
 // both dense row-major.  The loop walks columns in ascending order and, within a column, the

@@ -438,9 +438,37 @@ def pin_insert_special_cases():
     assert st == oracle.EINVAL
 
 
+# ------------------------------------------------------------------------------ transpose pins
+
+def pin_transpose_dense(seeds=range(10)):
+    """The transpose equals the CSC of the transposed dense matrix (values moved bit for bit),
+    transposing twice gives A back, and the identity is its own transpose."""
+    for seed in seeds:
+        rng = np.random.Generator(np.random.PCG64(6200 + seed))
+        n_rows = int(rng.integers(1, 10))
+        n_cols = int(rng.integers(1, 10))
+        D = rng.standard_normal((n_rows, n_cols)) * (rng.random((n_rows, n_cols)) < 0.4)
+        A = csc_from_dense(D)
+        st, T = oracle.csc_transpose(A)
+        assert st == oracle.OK
+        E = csc_from_dense(D.T.copy())
+        assert T.n_rows == n_cols and T.n_cols == n_rows
+        assert np.array_equal(T.col_ptr, E.col_ptr), seed
+        assert np.array_equal(T.row_idx, E.row_idx), seed
+        assert same_floats(T.values, E.values), seed
+        st, TT = oracle.csc_transpose(T)
+        assert st == oracle.OK
+        assert np.array_equal(TT.col_ptr, A.col_ptr) and np.array_equal(TT.row_idx, A.row_idx)
+        assert same_floats(TT.values, A.values)
+    eye = csc_from_dense(np.eye(7))
+    st, T = oracle.csc_transpose(eye)
+    assert st == oracle.OK and np.array_equal(T.col_ptr, eye.col_ptr)
+    assert np.array_equal(T.row_idx, eye.row_idx)
+
+
 ASSEMBLY_PINS = [pin_golden_assembly, pin_brute_force, pin_scipy_dyadic, pin_invariants_and_totals,
                  pin_index_encoding, pin_special_cases, pin_golden_insert, pin_brute_force_insert,
-                 pin_insert_special_cases]
+                 pin_insert_special_cases, pin_transpose_dense]
 SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
              pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
 ALL_PINS = ASSEMBLY_PINS + SPMM_PINS

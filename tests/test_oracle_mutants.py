@@ -62,6 +62,9 @@ MUTANTS = {
     "insert_existing_ignored": ("acc = a_val[p];", "acc = 0.0;"),
     "insert_keep_zero": ("if (acc != 0.0) {", "if (true) {"),
     "insert_new_first": (INSERT_FOLD, INSERT_FOLD_NEW_FIRST),
+    "transpose_index_kept": ("t_row_idx[q] = (int32_t)c;",
+                             "t_row_idx[q] = (int32_t)a_row_idx[p];"),
+    "transpose_value_from_wrong_slot": ("t_val[q] = a_val[p];", "t_val[q] = a_val[q];"),
 }
 
 
