@@ -16,7 +16,8 @@ recorded in a HIP graph are reported under "graph";
 oracle timed on the host cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch] [--separate]
-                    [--no-graph] [--no-insert] [--cold-steps 10]
+                    [--no-graph] [--no-insert] [--no-transpose]
+                    [--cold-steps 10]
 """
 from __future__ import annotations
 
@@ -44,6 +45,8 @@ def parse():
                     help="skip the K steps timed as replays of the step recorded in a HIP graph")
     ap.add_argument("--no-insert", action="store_true",
                     help="skip the batch-insertion measurement")
+    ap.add_argument("--no-transpose", action="store_true",
+                    help="skip the transpose and row-vector product measurement")
     ap.add_argument("--separate", action="store_true",
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -345,6 +348,42 @@ def main():
                   "compulsory_bytes": i_bytes,
                   "compulsory_GBps": i_bytes / (i_ms * 1e-3) / 1e9}
 
+    # transpose X.t() (Table 1) of the step's CSC, and the row-vector product V.A (Fig. 1)
+    transpose = None
+    if not args.no_transpose:
+        from paper_1805_03380_amd import ops
+        A = pipe.csc()
+        T = ops.csc_transpose(A)  # warm-up, and the buffers for the timed calls
+        lib = _lib.load()
+        t_info = T.info
+
+        def run_transpose():
+            for _ in range(args.steps):
+                lib.spm_csc_transpose(A.n_rows, A.n_cols, A.nnz_cap, A.col_ptr.data_ptr(),
+                                      A.row_idx_buf.data_ptr(), A.values_buf.data_ptr(),
+                                      ops._dtype_code(A.values_buf.dtype), T.col_ptr.data_ptr(),
+                                      T.row_idx_buf.data_ptr(), T.values_buf.data_ptr(),
+                                      t_info.data_ptr(), T._ws.data_ptr(), T._ws.numel(),
+                                      stream.cuda_stream)
+        t_ms = timed(run_transpose)
+        if int(t_info[1].item()):
+            raise RuntimeError("spm_csc_transpose reported status %d" % int(t_info[1]))
+        sv = A.values_buf.element_size()
+        t_bytes = 4 * (p.n_cols + 1) + 4 * (p.n_rows + 1) + 2 * nnz * (4 + sv)
+        V = torch.randn(p.n_rows, dtype=X.dtype, device=dev)
+        ops.rowvec_spmm(V, A)
+
+        def run_rowvec():
+            with torch.cuda.stream(stream):
+                for _ in range(args.steps):
+                    ops.rowvec_spmm(V, A)
+        r_ms = timed(run_rowvec)
+        transpose = {"workload": "transpose of the assembled 1e5 x 1e5 CSC", "nnz": nnz,
+                     "ms": t_ms, "elements_per_s": nnz / (t_ms * 1e-3),
+                     "compulsory_bytes": t_bytes,
+                     "compulsory_GBps": t_bytes / (t_ms * 1e-3) / 1e9,
+                     "rowvec_ms": r_ms, "rowvec_elements_per_s": nnz / (r_ms * 1e-3)}
+
     # headline: the K eager steps on one stream, nothing recorded between them
     head_ms, timing = ms_step, "eager library calls on one stream"
 
@@ -424,6 +463,7 @@ def main():
         "cold": cold,
         "graph": graph,
         "insert": insert,
+        "transpose": transpose,
         "assembly_nnz_per_s": p.nnz_in / (phase_ms[phases[0]] * 1e-3),
         "assembly_phase": phases[0],
         "assembly_compulsory_GBps": bytes_[phases[0]] / asm_t / 1e9,

@@ -166,6 +166,30 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
                                size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Transpose X.t() (Table 1) as a CSC of the n_cols x n_rows result: the row index of A that
+ * spm_csc_plan_build derives is the CSC of A^T, here written into separate arrays with the
+ * values carried along (moved, not changed).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Workspace of spm_csc_transpose. */
+spm_status spm_csc_transpose_workspace(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                                       size_t *ws_bytes);
+
+/* A^T of the CSC (col_ptr[n_cols+1], row_idx / val of capacity nnz_cap; nnz =
+ * col_ptr[n_cols] is read on the device).
+ *   val_type   F64 or F32, also the type of t_val.
+ *   t_col_ptr  int32[n_rows + 1], fully written; t_row_idx / t_val have capacity nnz_cap,
+ *              the first nnz entries are written (column r of A^T lists row r of A by
+ *              increasing column).
+ *   info       int32[2] as for spm_csc_plan_build (nnz; 0, SPM_EINVAL or SPM_EBOUNDS).
+ *   ws         at least spm_csc_transpose_workspace() bytes, 256-byte aligned. */
+spm_status spm_csc_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                             const int32_t *col_ptr, const int32_t *row_idx, const void *val,
+                             spm_dtype val_type, int32_t *t_col_ptr, int32_t *t_row_idx,
+                             void *t_val, int32_t *info, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
  * location the existing value comes first, then the new values in input order, folded in

@@ -83,6 +83,9 @@ SIGNATURES = {
                                            c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                            ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
                                            c_p]),
+    "spm_csc_transpose_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p]),
+    "spm_csc_transpose": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p,
+                                         c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
     "spm_csc_insert_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_insert": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                       ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,

@@ -643,18 +643,17 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
   return launch_status();
 }
 
-// Plan build for one value type VT (the type of the optional values carried to plan order).
+// Plan build for one value type VT (the type of the optional values carried to plan order),
+// into row_ptr[n_rows+1], col_t[nnz_cap], perm[nnz_cap] wherever they are.
 template <typename VT>
-void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t* col_ptr,
-                  const int32_t* row_idx, const VT* val, VT* val_plan, char* pl, int32_t* info,
-                  char* w, const PlanParts& P, const PlanLayout& L, hipStream_t s) {
+void plan_build_into(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t* col_ptr,
+                     const int32_t* row_idx, const VT* val, VT* val_plan, int32_t* row_ptr,
+                     int32_t* col_t, int32_t* perm, int32_t* info, char* w,
+                     const PlanLayout& L, hipStream_t s) {
   uint64_t* scan_state = reinterpret_cast<uint64_t*>(w + L.scan_state);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
   uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
   uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
-  int32_t* row_ptr = reinterpret_cast<int32_t*>(pl + P.row_ptr);
-  int32_t* col_t = reinterpret_cast<int32_t*>(pl + P.col_t);
-  int32_t* perm = reinterpret_cast<int32_t*>(pl + P.perm);
   const int cap = cu_count() * 16;
   if (L.pp.ok) {
     // two-level partition by row: no device-wide atomics, no inter-workgroup waiting; the
@@ -709,6 +708,28 @@ void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t
             col_ptr, n_cols, nnz_cap, perm, val, val_plan);
     }
   }
+}
+
+// Plan build into one plan buffer (layout of include/spm.h).
+template <typename VT>
+void plan_build_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int32_t* col_ptr,
+                  const int32_t* row_idx, const VT* val, VT* val_plan, char* pl, int32_t* info,
+                  char* w, const PlanParts& P, const PlanLayout& L, hipStream_t s) {
+  plan_build_into<VT>(n_rows, n_cols, nnz_cap, col_ptr, row_idx, val, val_plan,
+                      reinterpret_cast<int32_t*>(pl + P.row_ptr),
+                      reinterpret_cast<int32_t*>(pl + P.col_t),
+                      reinterpret_cast<int32_t*>(pl + P.perm), info, w, L, s);
+}
+
+// Transpose: the plan build writes the row index of A, which is the CSC of A^T, straight
+// into the caller's arrays; the CSC slot of each element (perm) goes to the workspace, after
+// the plan build's own layout.
+size_t transpose_ws_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_t* perm_off) {
+  const PlanLayout L = plan_ws_layout(n_rows, n_cols, nnz_cap);
+  Carve c;
+  c.off = L.total;
+  *perm_off = c.take(sizeof(int32_t) * (size_t)nnz_cap);
+  return c.off;
 }
 
 // Batch insertion: the assembly's layout over the cap_a + nnz_t positions of the virtual
@@ -872,6 +893,50 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
     plan_build_t<float>(n_rows, n_cols, nnz_in, col_ptr, row_idx,
                         static_cast<const float*>(val_out), static_cast<float*>(val_plan),
                         static_cast<char*>(plan), plan_info, w, P, PL, s);
+  return launch_status();
+}
+
+spm_status spm_csc_transpose_workspace(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                                       size_t* ws_bytes) {
+  if (!ws_bytes) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  size_t perm_off;
+  *ws_bytes = transpose_ws_bytes(n_rows, n_cols, nnz_cap, &perm_off);
+  return SPM_OK;
+}
+
+spm_status spm_csc_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                             const int32_t* col_ptr, const int32_t* row_idx, const void* val,
+                             spm_dtype val_type, int32_t* t_col_ptr, int32_t* t_row_idx,
+                             void* t_val, int32_t* info, void* ws, size_t ws_bytes,
+                             void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_cap);
+  if (st != SPM_OK) return st;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (!col_ptr || !t_col_ptr || !info || !ws) return SPM_EINVAL;
+  if (nnz_cap > 0 && (!row_idx || !val || !t_row_idx || !t_val)) return SPM_EINVAL;
+  if (!aligned(ws, 256)) return SPM_EINVAL;
+  size_t perm_off;
+  if (ws_bytes < transpose_ws_bytes(n_rows, n_cols, nnz_cap, &perm_off))
+    return SPM_EWORKSPACE;
+  const PlanLayout L = plan_ws_layout(n_rows, n_cols, nnz_cap);
+  char* w = static_cast<char*>(ws);
+  int32_t* perm = reinterpret_cast<int32_t*>(w + perm_off);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  // a CSC with no stored element still needs its (all-zero) offsets; the plan build writes
+  // them, and carries the values only when there are some
+  if (val_type == SPM_F64)
+    plan_build_into<double>(n_rows, n_cols, nnz_cap, col_ptr, row_idx,
+                            nnz_cap ? static_cast<const double*>(val) : nullptr,
+                            nnz_cap ? static_cast<double*>(t_val) : nullptr, t_col_ptr,
+                            t_row_idx, perm, info, w, L, s);
+  else
+    plan_build_into<float>(n_rows, n_cols, nnz_cap, col_ptr, row_idx,
+                           nnz_cap ? static_cast<const float*>(val) : nullptr,
+                           nnz_cap ? static_cast<float*>(t_val) : nullptr, t_col_ptr,
+                           t_row_idx, perm, info, w, L, s);
   return launch_status();
 }
 

@@ -223,6 +223,49 @@ def csc_insert(A: CSCMatrix, row: torch.Tensor, col: torch.Tensor, val: torch.Te
     return B
 
 
+def csc_transpose(A: CSCMatrix, sync: bool = True) -> CSCMatrix:
+    """A^T as a CSC (spm_csc_transpose; X.t() of Table 1)."""
+    _require_cuda(A.col_ptr)
+    lib = _lib.load()
+    dev = A.device
+    cap = A.nnz_cap
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_csc_transpose_workspace(A.n_rows, A.n_cols, cap, _lib.ctypes.byref(wb)),
+               "spm_csc_transpose_workspace")
+    ws = _workspace(wb.value, dev)
+    t_cp = torch.empty(A.n_rows + 1, dtype=torch.int32, device=dev)
+    t_ri = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    t_v = torch.empty(max(cap, 1), dtype=A.values_buf.dtype, device=dev)
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.spm_csc_transpose(A.n_rows, A.n_cols, cap, _ptr(A.col_ptr),
+                               _ptr(A.row_idx_buf) if cap else None,
+                               _ptr(A.values_buf) if cap else None,
+                               _dtype_code(A.values_buf.dtype), _ptr(t_cp), _ptr(t_ri),
+                               _ptr(t_v), _ptr(info), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(st, "spm_csc_transpose")
+    T = CSCMatrix(A.n_cols, A.n_rows, t_cp, t_ri[:cap] if cap else t_ri[:0],
+                  t_v[:cap] if cap else t_v[:0], info)
+    T._ws = ws
+    if sync:
+        h = info.cpu()
+        _lib.check(int(h[1]), "spm_csc_transpose (device)")
+        T._nnz = int(h[0])
+    return T
+
+
+def rowvec_spmm(V: torch.Tensor, A: CSCMatrix, out_dtype: torch.dtype | None = None):
+    """W = V.A for row vectors V (n_rows, or m x n_rows for m of them): the product of Section
+    3's use case (iv) written as in Fig. 1.  It is the column walk of the adjoint with the
+    vectors as its upstream operand (spm_csc_spmm_backward, dX only), so W[i] sums column i of
+    A in increasing row order."""
+    V2 = V.reshape(1, -1) if V.dim() == 1 else V
+    Vt = V2.t().contiguous()  # n_rows x m
+    X_dummy = torch.zeros(A.n_cols, Vt.shape[1], dtype=Vt.dtype, device=Vt.device)
+    dX, _ = spmm_backward(A, Vt, X_dummy, need_dval=False, dx_dtype=out_dtype)
+    W = dX.t()
+    return W.reshape(-1) if V.dim() == 1 else W
+
+
 def plan_size(n_rows: int, n_cols: int, nnz_cap: int):
     lib = _lib.load()
     pb = _lib.ctypes.c_size_t(0)

@@ -138,6 +138,25 @@ def test_host_validation_rejects_before_launch():
     assert ins(info=None) == _lib.EINVAL
     assert ins(n_cols=0) == _lib.EINVAL  # no columns: nothing for the partition to group
     assert ins(wsb=16) == _lib.EWORKSPACE
+    # transpose
+
+    def tr(n_rows=4, n_cols=4, cap=8, vt=_lib.F64, cp=fake, tcp=fake, tri=fake, info=fake, w=ws,
+           wsb=1 << 30):
+        return lib.spm_csc_transpose(n_rows, n_cols, cap, cp, fake, fake, vt, tcp, tri, fake,
+                                     info, w, wsb, None)
+
+    wb = ctypes.c_size_t(0)
+    assert lib.spm_csc_transpose_workspace(4, 4, 8, ctypes.byref(wb)) == _lib.OK and wb.value
+    assert lib.spm_csc_transpose_workspace(4, -1, 8, ctypes.byref(wb)) == _lib.EINVAL
+    assert tr(cap=-1) == _lib.EINVAL
+    assert tr(n_rows=2 ** 31) == _lib.EOVERFLOW
+    assert tr(vt=_lib.BF16) == _lib.EDTYPE
+    assert tr(cp=None) == _lib.EINVAL
+    assert tr(tcp=None) == _lib.EINVAL
+    assert tr(tri=None) == _lib.EINVAL
+    assert tr(info=None) == _lib.EINVAL
+    assert tr(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
+    assert tr(wsb=16) == _lib.EWORKSPACE
 
 
 def test_tuning_roundtrip():
