@@ -10,7 +10,7 @@ round-to-nearest-even cast.
 
 Paper: Sanderson & Curtin, "A User-Friendly Hybrid Sparse Matrix Class in C++", arXiv:1805.03380.
 Sections cited in each function: 3.1 (CSC), 3.2 (COO), 3.3 (red-black tree, index encoding),
-3 use case (iv) (dense x sparse products), Table 1 (speye, sum).
+3 use case (iv) (dense x sparse products), Table 1 (speye, sum, X.t(), trace(A.t()*B)).
 """
 from __future__ import annotations
 
@@ -66,6 +66,8 @@ def configure(lib):
     lib.oracle_csc_insert.restype = ctypes.c_int
     lib.oracle_csc_transpose.argtypes = [i64, i64, p, p, p, p, p, p]
     lib.oracle_csc_transpose.restype = ctypes.c_int
+    lib.oracle_trace_atb.argtypes = [i64, i64, p, p, p, p, p, p, p, p]
+    lib.oracle_trace_atb.restype = ctypes.c_int
     lib.oracle_spmm.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
     lib.oracle_spmm.restype = None
     lib.oracle_spmm_backward.argtypes = [i64, i64, i64, p, p, p, p, p, p, p, p, p]
@@ -174,6 +176,27 @@ def csc_transpose(A: CSC):
     if st != OK:
         return st, None
     return OK, CSC(A.n_cols, A.n_rows, t_cp, t_ri[:m].copy(), t_v[:m].copy())
+
+
+def trace_atb(A: CSC, B: CSC):
+    """trace(A^T B) without forming A^T or the product (Section 2, Table 1): the sum over
+    locations stored in both A and B of A[i,j] * B[i,j], columns ascending and A's rows
+    ascending within each, binary64 products added left to right.
+    Returns (status, trace, hits) with hits = locations stored in both."""
+    lib = _load()
+    assert (A.n_rows, A.n_cols) == (B.n_rows, B.n_cols)
+    arrs = []
+    for M in (A, B):
+        arrs += [np.ascontiguousarray(M.col_ptr, dtype=np.int32),
+                 np.ascontiguousarray(M.row_idx, dtype=np.int32),
+                 np.ascontiguousarray(widen(M.values), dtype=np.float64)]
+    out = ctypes.c_double(0.0)
+    hits = ctypes.c_int64(0)
+    st = lib.oracle_trace_atb(A.n_rows, A.n_cols, *(_ptr(a) for a in arrs), ctypes.byref(out),
+                              ctypes.byref(hits))
+    if st != OK:
+        return st, None, None
+    return OK, out.value, hits.value
 
 
 def spmm(A: CSC, X, values=None):

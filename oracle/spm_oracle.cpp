@@ -3,7 +3,7 @@
 // A plain, slow, deliberately unoptimised CPU reference for what the sparse path computes:
 // bulk assembly of coordinate (COO) triplets into compressed sparse column (CSC) form, the CSC
 // sparse x dense product Y = A.X, and its adjoint (dX = A^T.G, dvalues = G.X sampled on A's
-// pattern).  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
+// pattern); batch insertion into an existing CSC, the transpose, and trace(A^T B).  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
 // so every '+' and '*' below is one correctly rounded binary64 operation, in the order written.
 //
 // Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may load this
@@ -38,6 +38,21 @@ void offsets_from_columns(int64_t n_cols, const std::vector<int64_t>& emitted_co
   for (int64_t c : emitted_cols) count[c + 1] += 1;
   col_ptr[0] = 0;
   for (int64_t i = 0; i < n_cols; ++i) col_ptr[i + 1] = (int32_t)(col_ptr[i] + count[i + 1]);
+}
+
+// A CSC whose offsets start at 0 and never decrease, and whose stored rows lie in the matrix and
+// strictly increase down each column (Section 3.1: each column lists its rows in order).
+bool valid_sorted_csc(int64_t n_rows, int64_t n_cols, const int32_t* col_ptr,
+                      const int32_t* row_idx) {
+  if (!col_ptr || col_ptr[0] != 0) return false;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    if (col_ptr[c + 1] < col_ptr[c]) return false;
+    for (int64_t p = col_ptr[c]; p < col_ptr[c + 1]; ++p) {
+      if (row_idx[p] < 0 || (int64_t)row_idx[p] >= n_rows) return false;
+      if (p > col_ptr[c] && row_idx[p] <= row_idx[p - 1]) return false;
+    }
+  }
+  return true;
 }
 
 }  // namespace
@@ -232,6 +247,41 @@ int oracle_csc_transpose(int64_t n_rows, int64_t n_cols, const int32_t* a_col_pt
       t_row_idx[q] = (int32_t)c;
       t_val[q] = a_val[p];
     }
+  return 0;
+}
+
+// trace(A^T B) (Section 2's example of an expression evaluated without forming the transpose
+// or the product; Table 1).  Entry (j, j) of A^T B is the dot product of column j of A with
+// column j of B, so the trace is the sum, over every location stored in both A and B, of
+// A[i,j] * B[i,j].  A location stored in only one of them meets a structural zero and adds
+// nothing.  Columns are taken in ascending order and, within a column, A's stored rows in
+// ascending order; B's element at the same row is found by binary search in B's sorted
+// column.  Each product is one binary64 multiply, and the products are added left to right.
+// Outputs: *out = the trace, *hits = the number of locations stored in both.
+// Returns 0, or 1 (bad sizes, null pointers, or a CSC that is not valid and sorted).
+int oracle_trace_atb(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
+                     const int32_t* a_row_idx, const double* a_val, const int32_t* b_col_ptr,
+                     const int32_t* b_row_idx, const double* b_val, double* out,
+                     int64_t* hits) {
+  if (n_rows < 0 || n_cols < 0 || !out || !hits) return 1;
+  if (!valid_sorted_csc(n_rows, n_cols, a_col_ptr, a_row_idx)) return 1;
+  if (!valid_sorted_csc(n_rows, n_cols, b_col_ptr, b_row_idx)) return 1;
+  double trace = 0.0;
+  int64_t matched = 0;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    const int32_t* b_first = b_row_idx + b_col_ptr[c];
+    const int32_t* b_last = b_row_idx + b_col_ptr[c + 1];
+    for (int64_t p = a_col_ptr[c]; p < a_col_ptr[c + 1]; ++p) {
+      const int32_t r = a_row_idx[p];
+      const int32_t* it = std::lower_bound(b_first, b_last, r);
+      if (it == b_last || *it != r) continue;  // B has no element at (r, c)
+      const int64_t q = it - b_row_idx;
+      trace = trace + a_val[p] * b_val[q];
+      matched += 1;
+    }
+  }
+  *out = trace;
+  *hits = matched;
   return 0;
 }
 

@@ -466,9 +466,118 @@ def pin_transpose_dense(seeds=range(10)):
     assert np.array_equal(T.row_idx, eye.row_idx)
 
 
+# -------------------------------------------------------------------------- trace(A^T B) pins
+
+def _trace_pair(rng, n_rows, n_cols, density, values):
+    """Two independent random sparse matrices (dense form) of one shape."""
+    out = []
+    for _ in range(2):
+        mask = rng.random((n_rows, n_cols)) < density
+        out.append(np.where(mask, values(rng, (n_rows, n_cols)), 0.0))
+    return out
+
+
+def _dyadic(rng, shape):
+    """Non-zero multiples of 1/4 in [-4, 4]: products and their sums are exact in binary64."""
+    v = rng.integers(1, 17, size=shape) * rng.choice([-1, 1], size=shape)
+    return v / 4.0
+
+
+def pin_golden_trace():
+    g = load_golden("trace_small.json")
+    for case in g["cases"]:
+        A = oracle.CSC(case["n_rows"], case["n_cols"], np.array(case["a_col_ptr"], np.int32),
+                       np.array(case["a_row_idx"], np.int32), np.array(case["a_val"]))
+        B = oracle.CSC(case["n_rows"], case["n_cols"], np.array(case["b_col_ptr"], np.int32),
+                       np.array(case["b_row_idx"], np.int32), np.array(case["b_val"]))
+        st, t, hits = oracle.trace_atb(A, B)
+        assert st == oracle.OK
+        assert same_floats([t], [case["expect_trace"]]), (case["name"], t)
+        assert hits == case["expect_hits"], (case["name"], hits)
+
+
+def pin_trace_dense(seeds=range(12)):
+    """Brute force on small dense matrices: with dyadic values every product and sum is exact,
+    so the trace equals numpy's trace of the dense A^T B exactly, and trace(A^T B) equals
+    trace(B^T A); the matched count is the size of the pattern intersection.  With normal
+    values the trace is within the a-priori bound of the exact (Fraction) sum."""
+    for seed in seeds:
+        rng = np.random.Generator(np.random.PCG64(6300 + seed))
+        n_rows = int(rng.integers(1, 12))
+        n_cols = int(rng.integers(1, 12))
+        Da, Db = _trace_pair(rng, n_rows, n_cols, 0.5, _dyadic)
+        A, B = csc_from_dense(Da), csc_from_dense(Db)
+        st, t, hits = oracle.trace_atb(A, B)
+        assert st == oracle.OK
+        assert t == float(np.trace(Da.T @ Db)), seed
+        assert hits == int(np.count_nonzero((Da != 0) & (Db != 0))), seed
+        st, t2, hits2 = oracle.trace_atb(B, A)
+        assert st == oracle.OK and t2 == t and hits2 == hits
+        Na, Nb = _trace_pair(rng, n_rows, n_cols, 0.5, lambda r, sh: r.standard_normal(sh))
+        st, t, hits = oracle.trace_atb(csc_from_dense(Na), csc_from_dense(Nb))
+        assert st == oracle.OK
+        exact = sum((Fraction(float(a)) * Fraction(float(b))
+                     for a, b in zip(Na.ravel(), Nb.ravel()) if a != 0 and b != 0), Fraction(0))
+        s_abs = float(np.sum(np.abs(Na * Nb)))
+        assert abs(Fraction(t) - exact) <= Fraction(oracle.gamma(hits + 1) * s_abs), seed
+
+
+def pin_trace_closed_forms():
+    """trace(A^T A) is the squared Frobenius norm; trace(I^T B) (speye, Table 1) is the sum of
+    B's diagonal; matrices with disjoint patterns give 0 with no match."""
+    rng = np.random.Generator(np.random.PCG64(6400))
+    D = np.where(rng.random((9, 6)) < 0.5, _dyadic(rng, (9, 6)), 0.0)
+    A = csc_from_dense(D)
+    st, t, hits = oracle.trace_atb(A, A)
+    assert st == oracle.OK
+    assert t == float(sum(Fraction(float(v)) ** 2 for v in D.ravel()))
+    assert hits == int(np.count_nonzero(D))
+    Db = np.where(rng.random((8, 8)) < 0.6, _dyadic(rng, (8, 8)), 0.0)
+    st, t, hits = oracle.trace_atb(csc_from_dense(np.eye(8)), csc_from_dense(Db))
+    assert st == oracle.OK
+    assert t == float(sum(Fraction(float(Db[i, i])) for i in range(8)))
+    assert hits == int(np.count_nonzero(np.diag(Db)))
+    even = np.zeros((6, 5))
+    odd = np.zeros((6, 5))
+    even[0::2, :] = 1.5
+    odd[1::2, :] = -2.0
+    st, t, hits = oracle.trace_atb(csc_from_dense(even), csc_from_dense(odd))
+    assert st == oracle.OK and t == 0.0 and hits == 0
+
+
+def pin_trace_special_cases():
+    """IEEE rules at matched locations only: an infinity of A facing a structural zero of B
+    adds nothing, facing a stored 0.0 gives NaN; a NaN at a matched location propagates.
+    Empty shapes give 0; an unsorted column is rejected."""
+    A = oracle.CSC(3, 2, np.array([0, 2, 3], np.int32), np.array([0, 2, 1], np.int32),
+                   np.array([np.inf, 2.0, 3.0]))
+    B = oracle.CSC(3, 2, np.array([0, 1, 2], np.int32), np.array([2, 1], np.int32),
+                   np.array([0.5, 4.0]))
+    st, t, hits = oracle.trace_atb(A, B)
+    assert st == oracle.OK and t == 13.0 and hits == 2
+    Bz = oracle.CSC(3, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32),
+                    np.array([0.0, 4.0]))
+    st, t, hits = oracle.trace_atb(A, Bz)
+    assert st == oracle.OK and math.isnan(t) and hits == 2
+    An = oracle.CSC(3, 2, np.array([0, 0, 1], np.int32), np.array([1], np.int32),
+                    np.array([np.nan]))
+    st, t, hits = oracle.trace_atb(An, B)
+    assert st == oracle.OK and math.isnan(t) and hits == 1
+    for shape in ((0, 4), (4, 0)):
+        E = oracle.CSC(shape[0], shape[1], np.zeros(shape[1] + 1, np.int32),
+                       np.zeros(0, np.int32), np.zeros(0))
+        st, t, hits = oracle.trace_atb(E, E)
+        assert st == oracle.OK and t == 0.0 and hits == 0
+    bad = oracle.CSC(3, 2, np.array([0, 2, 3], np.int32), np.array([2, 0, 1], np.int32),
+                     np.array([1.0, 2.0, 3.0]))
+    st, _, _ = oracle.trace_atb(bad, B)
+    assert st == oracle.EINVAL
+
+
 ASSEMBLY_PINS = [pin_golden_assembly, pin_brute_force, pin_scipy_dyadic, pin_invariants_and_totals,
                  pin_index_encoding, pin_special_cases, pin_golden_insert, pin_brute_force_insert,
                  pin_insert_special_cases, pin_transpose_dense]
 SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
              pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
-ALL_PINS = ASSEMBLY_PINS + SPMM_PINS
+TRACE_PINS = [pin_golden_trace, pin_trace_dense, pin_trace_closed_forms, pin_trace_special_cases]
+ALL_PINS = ASSEMBLY_PINS + SPMM_PINS + TRACE_PINS

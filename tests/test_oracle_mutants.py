@@ -65,6 +65,15 @@ MUTANTS = {
     "transpose_index_kept": ("t_row_idx[q] = (int32_t)c;",
                              "t_row_idx[q] = (int32_t)a_row_idx[p];"),
     "transpose_value_from_wrong_slot": ("t_val[q] = a_val[p];", "t_val[q] = a_val[q];"),
+    "trace_last_row_skipped": ("""    for (int64_t p = a_col_ptr[c]; p < a_col_ptr[c + 1]; ++p) {
+      const int32_t r = a_row_idx[p];""", """    for (int64_t p = a_col_ptr[c]; p + 1 < a_col_ptr[c + 1]; ++p) {
+      const int32_t r = a_row_idx[p];"""),
+    "trace_match_unchecked": ("if (it == b_last || *it != r) continue;",
+                              "if (it == b_last) continue;"),
+    "trace_search_all_columns": ("std::lower_bound(b_first, b_last, r);",
+                                 "std::lower_bound(b_row_idx, b_row_idx + b_col_ptr[n_cols], r);"),
+    "trace_b_value_replaced": ("trace = trace + a_val[p] * b_val[q];",
+                               "trace = trace + a_val[p] * a_val[p];"),
 }
 
 
