@@ -190,6 +190,37 @@ spm_status spm_csc_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                              void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * trace(A^T B) of two CSC matrices of one shape without forming A^T or the product (Section 2's
+ * example of an expression evaluated from its parts; Table 1): entry (j, j) of A^T B is the
+ * dot product of column j of A with column j of B, so the trace is the sum, over locations
+ * stored in both, of A[i,j] * B[i,j].  A location stored in only one matrix meets a structural
+ * zero and adds nothing (an Inf or NaN there does not reach the result).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Workspace of spm_csc_trace_atb (about 16 bytes per 16 columns). */
+spm_status spm_csc_trace_atb_workspace(int64_t n_cols, size_t *ws_bytes);
+
+/* A and B: n_rows x n_cols CSCs (col_ptr[n_cols+1]; row_idx / val of capacity a_cap, b_cap),
+ * rows strictly increasing down each column, as spm_coo_to_csc writes them.
+ *   val_type  F64 or F32, the type of both a_val and b_val; products and sums in binary64.
+ *   out       double[1] (device): the trace.
+ *   info      int32[2] (device): info[0] = number of locations stored in both, info[1] = 0,
+ *             SPM_EINVAL (offsets not starting at 0, decreasing or beyond the capacity, or
+ *             rows not increasing in a column) or SPM_EBOUNDS (a stored row outside the
+ *             matrix); on a nonzero status out is unspecified.
+ *   ws        at least spm_csc_trace_atb_workspace() bytes, 256-byte aligned.
+ * Summation order: in each column A's elements by increasing position, dealt round-robin to
+ * 64 partial sums that combine by halving; columns in chunks of 16 added in order; the chunk
+ * sums in a fixed two-level order.  The result depends on n_cols and the data only, never on
+ * the tuning, and is within the a-priori bound of a dot product of the matched terms. */
+spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
+                             const int32_t *a_col_ptr, const int32_t *a_row_idx,
+                             const void *a_val, int64_t b_cap, const int32_t *b_col_ptr,
+                             const int32_t *b_row_idx, const void *b_val, spm_dtype val_type,
+                             double *out, int32_t *info, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
  * location the existing value comes first, then the new values in input order, folded in
@@ -319,7 +350,9 @@ typedef struct spm_tuning {
                                   tiles (64..4096, power of two) */
   int32_t batch_spmm_wg_per_cu; /* persistent workgroups per compute unit of the batch's
                                    products launch (1..32; 0 = the library's default, 8) */
-  int32_t reserved[2];
+  int32_t trace_group_width;   /* lanes per column of spm_csc_trace_atb: 16, 32 or 64
+                                  (0 = chosen from the average column length) */
+  int32_t reserved;
 } spm_tuning;
 
 spm_status spm_tuning_get(spm_tuning *out);

@@ -40,10 +40,10 @@ class Tuning(ctypes.Structure):
     _fields_ = [("spmm_block", ctypes.c_int32), ("spmm_blocks_per_cu", ctypes.c_int32),
                 ("batch_wg_per_cu", ctypes.c_int32), ("part_bucket_target", ctypes.c_int32),
                 ("part_max_tiles", ctypes.c_int32), ("batch_spmm_wg_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("trace_group_width", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     FIELDS = ("spmm_block", "spmm_blocks_per_cu", "batch_wg_per_cu", "part_bucket_target",
-              "part_max_tiles", "batch_spmm_wg_per_cu")
+              "part_max_tiles", "batch_spmm_wg_per_cu", "trace_group_width")
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f in self.FIELDS}
@@ -86,6 +86,9 @@ SIGNATURES = {
     "spm_csc_transpose_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_transpose": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p,
                                          c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
+    "spm_csc_trace_atb_workspace": (ctypes.c_int, [c_i64, c_size_p]),
+    "spm_csc_trace_atb": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
+                                         ctypes.c_int, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
     "spm_csc_insert_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_insert": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                       ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,

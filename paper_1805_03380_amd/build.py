@@ -2,8 +2,9 @@
 
     python -m paper_1805_03380_amd.build
 
-Produces paper_1805_03380_amd/lib/libspm.so from csrc/spm_api.hip (one translation unit that
-includes every kernel header) and include/spm.h.
+Produces paper_1805_03380_amd/lib/libspm.so from csrc/spm_api.hip (the translation unit that
+includes every kernel header of the assembly, plan, products and batch), csrc/spm_trace.hip
+(trace(A^T B)) and include/spm.h.
 """
 from __future__ import annotations
 
@@ -39,7 +40,7 @@ def hipcc() -> str:
 
 
 def sources():
-    return [os.path.join(CSRC, "spm_api.hip")]
+    return [os.path.join(CSRC, "spm_api.hip"), os.path.join(CSRC, "spm_trace.hip")]
 
 
 def build(verbose: bool = False) -> str:

@@ -43,7 +43,7 @@ struct Carve {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-spm_tuning g_tuning = {256, 64, 2, 2048, 512, 0, {0, 0}};
+spm_tuning g_tuning = {256, 64, 2, 2048, 512, 0, 0, 0};
 std::mutex g_tuning_mu;
 
 spm_tuning tuning() {
@@ -1102,6 +1102,9 @@ spm_status spm_tuning_set(const spm_tuning* in) {
   if (in->spmm_blocks_per_cu < 1 || in->spmm_blocks_per_cu > 64) return SPM_EINVAL;
   if (in->batch_wg_per_cu < 1 || in->batch_wg_per_cu > 8) return SPM_EINVAL;
   if (in->batch_spmm_wg_per_cu < 0 || in->batch_spmm_wg_per_cu > 32) return SPM_EINVAL;
+  if (in->trace_group_width != 0 && in->trace_group_width != 16 &&
+      in->trace_group_width != 32 && in->trace_group_width != 64)
+    return SPM_EINVAL;
   if (!pow2(in->part_bucket_target) || in->part_bucket_target < 256 ||
       in->part_bucket_target > 2048)
     return SPM_EINVAL;

@@ -253,6 +253,40 @@ def csc_transpose(A: CSCMatrix, sync: bool = True) -> CSCMatrix:
     return T
 
 
+def trace_atb(A: CSCMatrix, B: CSCMatrix, sync: bool = True):
+    """trace(A^T B) without forming A^T or the product (spm_csc_trace_atb; Section 2, Table 1).
+    With sync, returns (trace as a Python float, number of locations stored in both); without,
+    the device tensors (out float64[1], info int32[2]) with the call only enqueued."""
+    _require_cuda(A.col_ptr, B.col_ptr)
+    if (A.n_rows, A.n_cols) != (B.n_rows, B.n_cols):
+        raise ValueError("A is %dx%d, B is %dx%d" % (A.n_rows, A.n_cols, B.n_rows, B.n_cols))
+    if A.values_buf.dtype != B.values_buf.dtype:
+        raise ValueError("A and B must share one value type")
+    lib = _lib.load()
+    dev = A.device
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_csc_trace_atb_workspace(A.n_cols, _lib.ctypes.byref(wb)),
+               "spm_csc_trace_atb_workspace")
+    ws = _workspace(wb.value, dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    ca, cb = A.nnz_cap, B.nnz_cap
+    st = lib.spm_csc_trace_atb(A.n_rows, A.n_cols, ca, _ptr(A.col_ptr),
+                               _ptr(A.row_idx_buf) if ca else None,
+                               _ptr(A.values_buf) if ca else None, cb, _ptr(B.col_ptr),
+                               _ptr(B.row_idx_buf) if cb else None,
+                               _ptr(B.values_buf) if cb else None,
+                               _dtype_code(A.values_buf.dtype), _ptr(out), _ptr(info), _ptr(ws),
+                               ws.numel(), _stream(dev))
+    _lib.check(st, "spm_csc_trace_atb")
+    if not sync:
+        out._ws = ws
+        return out, info
+    h = info.cpu()
+    _lib.check(int(h[1]), "spm_csc_trace_atb (device)")
+    return float(out.item()), int(h[0])
+
+
 def rowvec_spmm(V: torch.Tensor, A: CSCMatrix, out_dtype: torch.dtype | None = None):
     """W = V.A for row vectors V (n_rows, or m x n_rows for m of them): the product of Section
     3's use case (iv) written as in Fig. 1.  It is the column walk of the adjoint with the

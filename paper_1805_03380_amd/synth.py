@@ -208,6 +208,18 @@ def diff_2e5(seed: int = 1004, n: int = 200_000, nnz_in: int = 5_000_000, k: int
     return COOProblem(name, n, n, row, col, val, X, G, meta=dict(seed=seed))
 
 
+def trace_pair(seed: int = 1007, n: int = 10_000, density: float = 0.001,
+               value_dtype=np.float64) -> tuple[COOProblem, COOProblem]:
+    """The trace(A^T B) workload of the paper's evaluation: two independent n x n matrices,
+    each with round(density * n^2) distinct uniform locations (no duplicates) and values
+    U[-1,1]; the paper uses 10,000 x 10,000 at densities 0.01 %, 0.1 %, 1 % and 10 %."""
+    nnz = int(round(density * n * n))
+    tag = "trace_%dx%d_d%g" % (n, n, density)
+    a = random_coo(seed, n, n, nnz, dup_frac=0.0, dtype=value_dtype, name=tag + "_A")
+    b = random_coo(seed + 1, n, n, nnz, dup_frac=0.0, dtype=value_dtype, name=tag + "_B")
+    return a, b
+
+
 def diff_fd(seed: int = 1014) -> COOProblem:
     """Finite-difference instance: 2,000 x 2,000, 20,000 i.i.d. uniform triplets, k = 16,
     everything float64 N(0,1)."""

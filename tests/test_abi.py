@@ -157,6 +157,27 @@ def test_host_validation_rejects_before_launch():
     assert tr(info=None) == _lib.EINVAL
     assert tr(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
     assert tr(wsb=16) == _lib.EWORKSPACE
+    # trace(A^T B)
+
+    def ta(n_rows=4, n_cols=4, ca=8, cb=8, vt=_lib.F64, acp=fake, bcp=fake, ari=fake, out=fake,
+           info=fake, w=ws, wsb=1 << 30):
+        return lib.spm_csc_trace_atb(n_rows, n_cols, ca, acp, ari, fake, cb, bcp, fake, fake, vt,
+                                     out, info, w, wsb, None)
+
+    assert lib.spm_csc_trace_atb_workspace(4, ctypes.byref(wb)) == _lib.OK and wb.value >= 256
+    assert lib.spm_csc_trace_atb_workspace(-1, ctypes.byref(wb)) == _lib.EINVAL
+    assert lib.spm_csc_trace_atb_workspace(2 ** 31, ctypes.byref(wb)) == _lib.EOVERFLOW
+    assert ta(ca=-1) == _lib.EINVAL
+    assert ta(n_rows=2 ** 31) == _lib.EOVERFLOW
+    assert ta(cb=2 ** 31) == _lib.EOVERFLOW
+    assert ta(vt=_lib.BF16) == _lib.EDTYPE
+    assert ta(acp=None) == _lib.EINVAL
+    assert ta(bcp=None) == _lib.EINVAL
+    assert ta(ari=None) == _lib.EINVAL
+    assert ta(out=None) == _lib.EINVAL
+    assert ta(info=None) == _lib.EINVAL
+    assert ta(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
+    assert ta(wsb=16) == _lib.EWORKSPACE
 
 
 def test_tuning_roundtrip():
@@ -172,6 +193,9 @@ def test_tuning_roundtrip():
     assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
     bad = _lib.Tuning.from_buffer_copy(t)
     bad.batch_spmm_wg_per_cu = 33
+    assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
+    bad = _lib.Tuning.from_buffer_copy(t)
+    bad.trace_group_width = 8
     assert lib.spm_tuning_set(ctypes.byref(bad)) == _lib.EINVAL
     bad = _lib.Tuning.from_buffer_copy(t)
     bad.part_max_tiles = 8192
