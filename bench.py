@@ -17,7 +17,7 @@ oracle timed on the host cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch] [--separate]
                     [--no-graph] [--no-insert] [--no-transpose]
-                    [--cold-steps 10]
+                    [--no-trace] [--cold-steps 10]
 """
 from __future__ import annotations
 
@@ -47,6 +47,8 @@ def parse():
                     help="skip the batch-insertion measurement")
     ap.add_argument("--no-transpose", action="store_true",
                     help="skip the transpose and row-vector product measurement")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="skip the trace(A^T B) measurement")
     ap.add_argument("--separate", action="store_true",
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -384,6 +386,49 @@ def main():
                      "compulsory_GBps": t_bytes / (t_ms * 1e-3) / 1e9,
                      "rowvec_ms": r_ms, "rowvec_elements_per_s": nnz / (r_ms * 1e-3)}
 
+    # trace(A^T B) without forming the product (Section 2, Table 1), on the paper's evaluation
+    # workload: two independent 10,000 x 10,000 matrices at four densities
+    trace = None
+    if not args.no_trace:
+        from paper_1805_03380_amd import ops
+        lib = _lib.load()
+        trace = []
+        for dens in (0.0001, 0.001, 0.01, 0.1):
+            qa, qb = synth.trace_pair(seed=1007, density=dens)
+            TA, TB = (ops.coo_to_csc(*(torch.from_numpy(x).to(dev) for x in (q.row, q.col, q.val)),
+                                     (q.n_rows, q.n_cols)) for q in (qa, qb))
+            t_val, hits = ops.trace_atb(TA, TB)
+            wb = _lib.ctypes.c_size_t(0)
+            lib.spm_csc_trace_atb_workspace(TA.n_cols, _lib.ctypes.byref(wb))
+            t_ws = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=dev)
+            t_out = torch.empty(1, dtype=torch.float64, device=dev)
+            t_inf = torch.empty(2, dtype=torch.int32, device=dev)
+
+            def run_trace():
+                for _ in range(args.steps):
+                    lib.spm_csc_trace_atb(TA.n_rows, TA.n_cols, TA.nnz_cap, TA.col_ptr.data_ptr(),
+                                          TA.row_idx_buf.data_ptr(), TA.values_buf.data_ptr(),
+                                          TB.nnz_cap, TB.col_ptr.data_ptr(),
+                                          TB.row_idx_buf.data_ptr(), TB.values_buf.data_ptr(),
+                                          _lib.F64, t_out.data_ptr(), t_inf.data_ptr(),
+                                          t_ws.data_ptr(), t_ws.numel(), stream.cuda_stream)
+            tr_ms = timed(run_trace)
+            if int(t_inf[1].item()) or int(t_inf[0].item()) != hits:
+                raise RuntimeError("spm_csc_trace_atb: status %d" % int(t_inf[1].item()))
+            na, nb = TA.nnz, TB.nnz
+            # compulsory: both offset arrays and both row-index arrays once, values where rows
+            # match; the full-read model reads every value too
+            c_bytes = 2 * 4 * (qa.n_cols + 1) + 4 * (na + nb) + 2 * 8 * hits
+            f_bytes = 2 * 4 * (qa.n_cols + 1) + (4 + 8) * (na + nb)
+            trace.append({"workload": "trace(A^T B), 10^4 x 10^4, density %g, float64 (seed 1007)"
+                                      % dens, "nnz_a": na, "nnz_b": nb, "hits": hits,
+                          "ms": tr_ms, "elements_per_s": (na + nb) / (tr_ms * 1e-3),
+                          "compulsory_bytes": c_bytes,
+                          "compulsory_GBps": c_bytes / (tr_ms * 1e-3) / 1e9,
+                          "full_read_GBps": f_bytes / (tr_ms * 1e-3) / 1e9,
+                          "frac_hbm_full_read": f_bytes / (tr_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS})
+            del TA, TB, t_ws
+
     # headline: the K eager steps on one stream, nothing recorded between them
     head_ms, timing = ms_step, "eager library calls on one stream"
 
@@ -464,6 +509,7 @@ def main():
         "graph": graph,
         "insert": insert,
         "transpose": transpose,
+        "trace_atb": trace,
         "assembly_nnz_per_s": p.nnz_in / (phase_ms[phases[0]] * 1e-3),
         "assembly_phase": phases[0],
         "assembly_compulsory_GBps": bytes_[phases[0]] / asm_t / 1e9,

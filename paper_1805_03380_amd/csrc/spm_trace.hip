@@ -26,10 +26,15 @@
 
 namespace spm {
 
-constexpr int kTraceNT = 256;        // threads per workgroup of the column kernel
 constexpr int kTraceChunk = 16;      // columns per workgroup (one partial sum each)
 constexpr int kTraceVL = 64;         // virtual lanes per column
 constexpr int kTraceFinishNT = 256;  // threads of the single finishing workgroup
+constexpr int kTraceU = 8;           // A elements per lane in flight (a multiple of 64 / GW)
+constexpr int kTraceUB = 8;          // B rows per lane in flight
+constexpr int kTraceBmRows = 16384;  // largest row count of the bitmap form (at most 3 KiB of
+                                     // LDS per column)
+constexpr int kTraceLdsPerLane = 19; // B rows per lane of the LDS slice (1216 at 64 lanes: two
+                                     // workgroups of 16 columns fit in 160 KiB)
 
 constexpr uint32_t kFlagInval = 1u;   // a malformed CSC (offsets, or rows not increasing)
 constexpr uint32_t kFlagBounds = 2u;  // a stored row outside the matrix
@@ -65,88 +70,209 @@ __device__ __forceinline__ uint32_t group_sum_u32(uint32_t v) {
   return v;
 }
 
-// One workgroup per chunk of kTraceChunk columns; groups of GW lanes walk its columns.
-// Writes the chunk's sum, matched count and status flags at index blockIdx.x.
-template <typename VT, int GW>
-__global__ __launch_bounds__(kTraceNT) void k_trace_atb(
+// Lower bound of r in the sorted rows b[lo, lo + n): a fixed number of halving steps for the
+// whole group (n is the same for every lane), so the lanes stay converged.
+__device__ __forceinline__ int lower_row_fixed(const int32_t* __restrict__ b, int n, int32_t r) {
+  int lo = 0;
+  int step = 1;
+  while (step <= n / 2) step <<= 1;
+  for (; step > 0; step >>= 1)
+    if (lo + step <= n && b[lo + step - 1] < r) lo += step;
+  return lo;
+}
+
+// Rows of one column, read U per lane at a time (element j = j0 + u GW + lg), checked
+// to lie in the matrix and to increase strictly (the previous element's row comes from the
+// neighbouring lane, or from the last lane's previous read).
+template <int GW, int U>
+__device__ __forceinline__ void check_rows(const int32_t (&r)[U], int j0, int n, int lg,
+                                           int64_t n_rows, int32_t& prev, uint32_t& flags) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = j0 + u * GW + lg;
+    const int32_t up = __shfl_up(r[u], 1, GW);
+    const int32_t before = lg == 0 ? prev : up;
+    prev = __shfl(r[u], GW - 1, GW);
+    if (j < n) {
+      if (r[u] < 0 || (int64_t)r[u] >= n_rows) flags |= kFlagBounds;
+      if (j > 0 && before >= r[u]) flags |= kFlagInval;
+    }
+  }
+}
+
+// Exclusive prefix sum over the GW lanes of a group.
+template <int GW>
+__device__ __forceinline__ uint32_t group_excl_scan(uint32_t x, int lg) {
+  uint32_t incl = x;
+#pragma unroll
+  for (int d = 1; d < GW; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, GW);
+    if (lg >= d) incl += t;
+  }
+  return incl - x;
+}
+
+// One workgroup per chunk of kTraceChunk columns, one group of GW lanes per column.  Per
+// column, B's rows are read once (coalesced) and checked, then made searchable in LDS:
+//   BM (n_rows <= kTraceBmRows): a bitmap of B's rows with the set-bit count before each
+//     32-row word, so that a row's presence and its position in B's column (the rank) take
+//     two LDS reads and a popcount;
+//   otherwise: B's rows themselves (when they fit the group's slice of kTraceLdsPerLane * GW
+//     rows; a longer column is searched in global memory), looked up by binary search.
+// A's rows are then read in batches of kTraceU per lane, checked, and looked up; a match adds
+// A's value times B's value (binary64) to the lane's accumulator of that element's virtual
+// lane.  Writes the chunk's sum, matched count and status flags at index blockIdx.x.
+template <typename VT, int GW, bool BM>
+__global__ __launch_bounds__(kTraceChunk * GW) void k_trace_atb(
     int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* __restrict__ a_col_ptr,
     const int32_t* __restrict__ a_row_idx, const VT* __restrict__ a_val, int64_t b_cap,
     const int32_t* __restrict__ b_col_ptr, const int32_t* __restrict__ b_row_idx,
     const VT* __restrict__ b_val, double* __restrict__ part_sum,
-    uint32_t* __restrict__ part_hits, uint32_t* __restrict__ part_flags) {
-  constexpr int G = kTraceNT / GW;  // columns in flight per workgroup
-  constexpr int A = kTraceVL / GW;  // virtual lanes per physical lane
-  static_assert(G <= kTraceChunk && kTraceChunk % G == 0, "groups tile the chunk");
+    uint32_t* __restrict__ part_hits, uint32_t* __restrict__ part_flags, int slice) {
+  constexpr int A = kTraceVL / GW;              // virtual lanes per physical lane
+  constexpr int CAP = kTraceLdsPerLane * GW;    // B rows per LDS slice (search form)
+  static_assert(kTraceU % A == 0, "a batch of GW * kTraceU elements spans whole virtual rounds");
+  extern __shared__ __align__(16) unsigned char s_raw[];  // kTraceChunk slices of `slice` bytes
   __shared__ double s_col[kTraceChunk];
   __shared__ uint32_t s_hits[kTraceChunk];
   __shared__ uint32_t s_flags;
   const int lg = threadIdx.x % GW;
-  const int g = threadIdx.x / GW;
-  const int64_t c0 = (int64_t)blockIdx.x * kTraceChunk;
+  const int ci = threadIdx.x / GW;
+  const int nw = (int)((n_rows + 31) >> 5);  // bitmap words (bitmap form)
+  // search form: up to CAP of B's rows; bitmap form: nw words, then nw 16-bit ranks
+  int32_t* sb = reinterpret_cast<int32_t*>(s_raw + ci * slice);
+  uint32_t* bm = reinterpret_cast<uint32_t*>(s_raw + ci * slice);
+  uint16_t* pre = reinterpret_cast<uint16_t*>(s_raw + ci * slice + nw * 4);
+  const int64_t c = (int64_t)blockIdx.x * kTraceChunk + ci;
   if (threadIdx.x == 0) s_flags = 0;
-  __syncthreads();
   uint32_t flags = 0;
-  for (int ci = g; ci < kTraceChunk; ci += G) {
-    const int64_t c = c0 + ci;
-    double acc[A];
+  int64_t pa0 = 0, pa1 = 0, pb0 = 0, pb1 = 0;
+  if (c < n_cols) {
+    pa0 = a_col_ptr[c];
+    pa1 = a_col_ptr[c + 1];
+    pb0 = b_col_ptr[c];
+    pb1 = b_col_ptr[c + 1];
+    bool ok = pa0 >= 0 && pa0 <= pa1 && pa1 <= a_cap && pb0 >= 0 && pb0 <= pb1 && pb1 <= b_cap;
+    if (c == 0 && (pa0 != 0 || pb0 != 0)) ok = false;
+    if (!ok) {
+      flags |= kFlagInval;
+      pa0 = pa1 = pb0 = pb1 = 0;
+    }
+  }
+  const int nb = (int)(pb1 - pb0), na = (int)(pa1 - pa0);
+  const bool lds = BM || nb <= CAP;
+  const int32_t* bcol = b_row_idx + pb0;
+  const int32_t* acol = a_row_idx + pa0;
+  if (BM) {
+    for (int w = lg; w < nw; w += GW) bm[w] = 0u;
+    __syncthreads();
+  }
+  // B's rows: checked once, kTraceUB loads in flight per lane, then into LDS
+  int32_t prev = INT32_MIN;
+  for (int q0 = 0; q0 < nb; q0 += GW * kTraceUB) {
+    int32_t rb[kTraceUB];
 #pragma unroll
-    for (int a = 0; a < A; ++a) acc[a] = 0.0;
-    uint32_t hits = 0;
-    if (c < n_cols) {
-      const int64_t pa0 = a_col_ptr[c], pa1 = a_col_ptr[c + 1];
-      const int64_t pb0 = b_col_ptr[c], pb1 = b_col_ptr[c + 1];
-      bool ok = pa0 >= 0 && pa0 <= pa1 && pa1 <= a_cap && pb0 >= 0 && pb0 <= pb1 &&
-                pb1 <= b_cap;
-      if (c == 0 && (pa0 != 0 || pb0 != 0)) ok = false;
-      if (!ok) {
-        flags |= kFlagInval;
-      } else {
-        // B's column: rows inside the matrix and strictly increasing
-        for (int64_t q = pb0 + lg; q < pb1; q += GW) {
-          const int32_t rb = b_row_idx[q];
-          if (rb < 0 || (int64_t)rb >= n_rows) flags |= kFlagBounds;
-          if (q > pb0 && b_row_idx[q - 1] >= rb) flags |= kFlagInval;
-        }
-        // A's column: element j = p - pa0 goes to virtual lane j mod 64, which is this
-        // lane's accumulator (j / GW) mod A
-        int a = 0;
-        for (int64_t p = pa0 + lg; p < pa1; p += GW) {
-          const int32_t r = a_row_idx[p];
-          if (r < 0 || (int64_t)r >= n_rows) flags |= kFlagBounds;
-          if (p > pa0 && a_row_idx[p - 1] >= r) flags |= kFlagInval;
-          const int64_t q = lower_row(b_row_idx, pb0, pb1, r);
-          if (q < pb1 && b_row_idx[q] == r) {
-            const double prod = widen_val(a_val[p]) * widen_val(b_val[q]);
+    for (int u = 0; u < kTraceUB; ++u) {
+      const int q = q0 + u * GW + lg;
+      rb[u] = q < nb ? bcol[q] : INT32_MAX;
+    }
+    check_rows<GW, kTraceUB>(rb, q0, nb, lg, n_rows, prev, flags);
 #pragma unroll
-            for (int u = 0; u < A; ++u)
-              if (u == a) acc[u] += prod;
-            ++hits;
-          }
-          a = (a + 1 == A) ? 0 : a + 1;
+    for (int u = 0; u < kTraceUB; ++u) {
+      const int q = q0 + u * GW + lg;
+      if (q < nb) {
+        if (BM) {
+          if (rb[u] >= 0 && (int64_t)rb[u] < n_rows)
+            atomicOr(&bm[rb[u] >> 5], 1u << (rb[u] & 31));
+        } else if (lds) {
+          sb[q] = rb[u];
         }
       }
     }
-    // halving over the 64 virtual lanes: strides >= GW inside the lane, the rest across lanes
+  }
+  __syncthreads();  // B in LDS (and s_flags cleared) before any lookup
+  if (BM) {
+    // rank of each word: set bits in the words before it (a run of words per lane)
+    const int per = (nw + GW - 1) / GW;
+    const int w0 = lg * per;
+    uint32_t run = 0;
+    for (int k = 0; k < per; ++k)
+      if (w0 + k < nw) run += __popc(bm[w0 + k]);
+    uint32_t before = group_excl_scan<GW>(run, lg);
+    for (int k = 0; k < per; ++k)
+      if (w0 + k < nw) {
+        pre[w0 + k] = (uint16_t)before;
+        before += __popc(bm[w0 + k]);
+      }
+    __syncthreads();
+  }
+  const int32_t* sc = lds ? sb : bcol;  // where the searches read B's rows (search form)
+  double acc[A];
 #pragma unroll
-    for (int s = A / 2; s >= 1; s >>= 1) {
+  for (int u = 0; u < A; ++u) acc[u] = 0.0;
+  uint32_t hits = 0;
+  prev = INT32_MIN;
+  // A's rows in batches of kTraceU per lane.  A batch starts at a multiple of GW * kTraceU,
+  // a multiple of 64, so element j's virtual lane j mod 64 is this lane's accumulator u mod A.
+  for (int j0 = 0; j0 < na; j0 += GW * kTraceU) {
+    int32_t r[kTraceU];
 #pragma unroll
-      for (int u = 0; u < s; ++u) acc[u] += acc[u + s];
+    for (int u = 0; u < kTraceU; ++u) {
+      const int j = j0 + u * GW + lg;
+      r[u] = j < na ? acol[j] : INT32_MAX;
     }
-    const double col = group_halving<GW>(acc[0]);
-    hits = group_sum_u32<GW>(hits);
-    if (lg == 0) {
-      s_col[ci] = col;
-      s_hits[ci] = hits;
+    check_rows<GW, kTraceU>(r, j0, na, lg, n_rows, prev, flags);
+    int32_t qb[kTraceU];  // B position of a match (offset from pb0), or -1
+#pragma unroll
+    for (int u = 0; u < kTraceU; ++u) {
+      qb[u] = -1;
+      if (j0 + u * GW + lg < na) {
+        if (BM) {
+          if (r[u] >= 0 && (int64_t)r[u] < n_rows) {
+            const uint32_t word = bm[r[u] >> 5];
+            const uint32_t bit = (uint32_t)r[u] & 31u;
+            if ((word >> bit) & 1u)
+              qb[u] = (int32_t)pre[r[u] >> 5] + __popc(word & ((1u << bit) - 1u));
+          }
+        } else {
+          const int lo = lower_row_fixed(sc, nb, r[u]);
+          if (lo < nb && sc[lo] == r[u]) qb[u] = lo;
+        }
+      }
     }
+    double av[kTraceU], bv[kTraceU];
+#pragma unroll
+    for (int u = 0; u < kTraceU; ++u) {
+      av[u] = qb[u] >= 0 ? widen_val(a_val[pa0 + j0 + u * GW + lg]) : 0.0;
+      bv[u] = qb[u] >= 0 ? widen_val(b_val[pb0 + qb[u]]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kTraceU; ++u)
+      if (qb[u] >= 0) {
+        acc[u % A] += av[u] * bv[u];
+        ++hits;
+      }
+  }
+  // halving over the 64 virtual lanes: strides >= GW inside the lane, the rest across lanes
+#pragma unroll
+  for (int s = A / 2; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int u = 0; u < s; ++u) acc[u] += acc[u + s];
+  }
+  const double col = group_halving<GW>(acc[0]);
+  hits = group_sum_u32<GW>(hits);
+  if (lg == 0) {
+    s_col[ci] = col;
+    s_hits[ci] = hits;
   }
   if (flags) atomicOr(&s_flags, flags);
   __syncthreads();
   if (threadIdx.x == 0) {
     double sum = 0.0;
     uint32_t h = 0;
-    for (int ci = 0; ci < kTraceChunk; ++ci) {
-      sum += s_col[ci];
-      h += s_hits[ci];
+    for (int k = 0; k < kTraceChunk; ++k) {
+      sum += s_col[k];
+      h += s_hits[k];
     }
     part_sum[blockIdx.x] = sum;
     part_hits[blockIdx.x] = h;
@@ -229,23 +355,43 @@ int trace_group_width(int64_t n_cols, int64_t a_cap, int64_t b_cap) {
   return 16;
 }
 
+template <typename VT, int GW>
+void launch_trace_gw(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a_cp,
+                     const int32_t* a_ri, const VT* av, int64_t b_cap, const int32_t* b_cp,
+                     const int32_t* b_ri, const VT* bv, double* ps, uint32_t* ph, uint32_t* pf,
+                     hipStream_t s) {
+  const dim3 grid((unsigned)trace_chunks(n_cols)), block(kTraceChunk * GW);
+  const int nw = (int)((n_rows + 31) >> 5);
+  // the bitmap costs nw words of set-up per column: worth it once B's columns are long
+  // enough (average from the capacity) to make binary searches the larger cost
+  const bool bitmap = n_rows <= kTraceBmRows && 4 * (b_cap / (n_cols > 0 ? n_cols : 1)) >= nw;
+  if (bitmap) {
+    const int slice = (nw * 6 + 15) & ~15;  // nw words and nw 16-bit ranks, 16-byte aligned
+    k_trace_atb<VT, GW, true><<<grid, block, (size_t)kTraceChunk * slice, s>>>(
+        n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap, b_cp, b_ri, bv, ps, ph, pf, slice);
+  } else {
+    const int slice = kTraceLdsPerLane * GW * 4;
+    k_trace_atb<VT, GW, false><<<grid, block, (size_t)kTraceChunk * slice, s>>>(
+        n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap, b_cp, b_ri, bv, ps, ph, pf, slice);
+  }
+}
+
 template <typename VT>
 void launch_trace(int gw, int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a_cp,
                   const int32_t* a_ri, const void* a_v, int64_t b_cap, const int32_t* b_cp,
                   const int32_t* b_ri, const void* b_v, double* ps, uint32_t* ph, uint32_t* pf,
                   hipStream_t s) {
-  const dim3 grid((unsigned)trace_chunks(n_cols)), block(kTraceNT);
   const VT* av = static_cast<const VT*>(a_v);
   const VT* bv = static_cast<const VT*>(b_v);
   if (gw == 64)
-    k_trace_atb<VT, 64><<<grid, block, 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap,
-                                               b_cp, b_ri, bv, ps, ph, pf);
+    launch_trace_gw<VT, 64>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap, b_cp, b_ri, bv, ps,
+                            ph, pf, s);
   else if (gw == 32)
-    k_trace_atb<VT, 32><<<grid, block, 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap,
-                                               b_cp, b_ri, bv, ps, ph, pf);
+    launch_trace_gw<VT, 32>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap, b_cp, b_ri, bv, ps,
+                            ph, pf, s);
   else
-    k_trace_atb<VT, 16><<<grid, block, 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap,
-                                               b_cp, b_ri, bv, ps, ph, pf);
+    launch_trace_gw<VT, 16>(n_rows, n_cols, a_cap, a_cp, a_ri, av, b_cap, b_cp, b_ri, bv, ps,
+                            ph, pf, s);
 }
 
 }  // namespace
