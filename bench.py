@@ -49,6 +49,9 @@ def parse():
                     help="skip the transpose and row-vector product measurement")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the trace(A^T B) measurement")
+    ap.add_argument("--trace-densities", type=lambda t: [float(x) for x in t.split(",")],
+                    default=[0.0001, 0.001, 0.01, 0.1],
+                    help="densities of the trace(A^T B) workload (comma-separated)")
     ap.add_argument("--separate", action="store_true",
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -393,7 +396,7 @@ def main():
         from paper_1805_03380_amd import ops
         lib = _lib.load()
         trace = []
-        for dens in (0.0001, 0.001, 0.01, 0.1):
+        for dens in args.trace_densities:
             qa, qb = synth.trace_pair(seed=1007, density=dens)
             TA, TB = (ops.coo_to_csc(*(torch.from_numpy(x).to(dev) for x in (q.row, q.col, q.val)),
                                      (q.n_rows, q.n_cols)) for q in (qa, qb))
