@@ -68,6 +68,8 @@ def configure(lib):
     lib.oracle_csc_transpose.restype = ctypes.c_int
     lib.oracle_trace_atb.argtypes = [i64, i64, p, p, p, p, p, p, p, p]
     lib.oracle_trace_atb.restype = ctypes.c_int
+    lib.oracle_triplet_grad.argtypes = [i64, i64, i64, i64, p, p, p, p, p, p]
+    lib.oracle_triplet_grad.restype = None
     lib.oracle_spmm.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
     lib.oracle_spmm.restype = None
     lib.oracle_spmm_backward.argtypes = [i64, i64, i64, p, p, p, p, p, p, p, p, p]
@@ -197,6 +199,29 @@ def trace_atb(A: CSC, B: CSC):
     if st != OK:
         return st, None, None
     return OK, out.value, hits.value
+
+
+def triplet_grad(n_rows, n_cols, row, col, G, X):
+    """dL/dv_t for every input triplet of an assembly followed by Y = A.X, with dL/dY = G:
+    sum_j G[row_t, j] X[col_t, j] in binary64 (ascending j), also for triplets whose location
+    summed to zero; 0 for a triplet outside the matrix.  Returns (dv, S), S = sum |G||X|."""
+    lib = _load()
+    row = np.ascontiguousarray(row, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    Gd, Xd = widen(G), widen(X)
+    if Gd.ndim == 1:
+        Gd = Gd[:, None]
+    if Xd.ndim == 1:
+        Xd = Xd[:, None]
+    Gd, Xd = np.ascontiguousarray(Gd), np.ascontiguousarray(Xd)
+    k = Xd.shape[1]
+    assert Gd.shape == (n_rows, k) and Xd.shape == (n_cols, k)
+    n = row.shape[0]
+    dv = np.zeros(max(n, 1), dtype=np.float64)
+    S = np.zeros(max(n, 1), dtype=np.float64)
+    lib.oracle_triplet_grad(n_rows, n_cols, n, k, _ptr(row), _ptr(col), _ptr(Gd), _ptr(Xd),
+                            _ptr(dv), _ptr(S))
+    return dv[:n].copy(), S[:n].copy()
 
 
 def spmm(A: CSC, X, values=None):

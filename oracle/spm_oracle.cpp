@@ -3,7 +3,8 @@
 // A plain, slow, deliberately unoptimised CPU reference for what the sparse path computes:
 // bulk assembly of coordinate (COO) triplets into compressed sparse column (CSC) form, the CSC
 // sparse x dense product Y = A.X, and its adjoint (dX = A^T.G, dvalues = G.X sampled on A's
-// pattern); batch insertion into an existing CSC, the transpose, and trace(A^T B).  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
+// pattern); batch insertion into an existing CSC, the transpose, trace(A^T B), and the gradient
+// with respect to each input triplet.  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
 // so every '+' and '*' below is one correctly rounded binary64 operation, in the order written.
 //
 // Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may load this
@@ -283,6 +284,32 @@ int oracle_trace_atb(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
   *out = trace;
   *hits = matched;
   return 0;
+}
+
+// Gradient with respect to each input triplet's value (the triplet-level adjoint of assembly
+// followed by Y = A.X, for a loss with dL/dY = G).  Assembly makes A[r,c] the sum of the values
+// of the triplets at (r, c) (Fig. 1's +=; a zero sum is merely not stored, the entry is still
+// that sum), and L depends on A[r,c] through sum_j G[r,j] A[r,c] X[c,j]; so every triplet t
+// at (r, c) has dL/dv_t = sum_j G[r,j] * X[c,j], whether or not its location survived, and
+// duplicates share it.  A triplet outside the matrix takes no part in A: its gradient is 0.
+// One binary64 multiply per term, added left to right in ascending j; S[t] = sum |G||X|.
+void oracle_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
+                         const int32_t* row, const int32_t* col, const double* G,
+                         const double* X, double* dv, double* S) {
+  for (int64_t t = 0; t < nnz_in; ++t) {
+    dv[t] = 0.0;
+    S[t] = 0.0;
+    if (!in_range(n_rows, n_cols, row[t], col[t])) continue;
+    const double* g = G + (int64_t)row[t] * k;
+    const double* x = X + (int64_t)col[t] * k;
+    double d = 0.0, a = 0.0;
+    for (int64_t j = 0; j < k; ++j) {
+      d = d + g[j] * x[j];
+      a = a + std::fabs(g[j]) * std::fabs(x[j]);
+    }
+    dv[t] = d;
+    S[t] = a;
+  }
 }
 
 // Sparse x dense product, Section 3 use case (iv) and the CSC traversal of Section 3.1:

@@ -574,10 +574,85 @@ def pin_trace_special_cases():
     assert st == oracle.EINVAL
 
 
+# ----------------------------------------------------------------- triplet-level adjoint pins
+
+def _small_triplets(seed, n_rows=7, n_cols=6, n_t=40, k=5):
+    """Dyadic triplets with duplicates, an exactly cancelling pair, and dyadic G and X: every
+    sum below is exact in binary64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    row = rng.integers(0, n_rows, size=n_t).astype(np.int32)
+    col = rng.integers(0, n_cols, size=n_t).astype(np.int32)
+    val = _dyadic(rng, n_t)
+    # a location whose two triplets cancel, so assembly drops it
+    row[-2:], col[-2:] = 3, 4
+    keep = ~((row[:-2] == 3) & (col[:-2] == 4))
+    row = np.concatenate([row[:-2][keep], row[-2:]])
+    col = np.concatenate([col[:-2][keep], col[-2:]])
+    val = np.concatenate([val[:-2][keep], [1.25, -1.25]])
+    G = _dyadic(rng, (n_rows, k))
+    X = _dyadic(rng, (n_cols, k))
+    return n_rows, n_cols, row, col, val, G, X
+
+
+def pin_triplet_grad_fd():
+    """Central differences of L = sum((assemble(v).X) * G) in each triplet's value: L is linear
+    in v_t, the data are dyadic, so the quotient with h = 2^-4 is exact and must equal the
+    gradient, for unique triplets, duplicates and both triplets of the cancelling pair."""
+    n_rows, n_cols, row, col, val, G, X = _small_triplets(6500)
+    dv, _ = oracle.triplet_grad(n_rows, n_cols, row, col, G, X)
+    h = 2.0 ** -4
+
+    def L(v):
+        st, A = oracle.coo_to_csc(n_rows, n_cols, row, col, v)
+        assert st == oracle.OK
+        Y, _, _ = oracle.spmm(A, X)
+        return float(sum(Fraction(float(y)) * Fraction(float(g))
+                         for y, g in zip(Y.ravel(), G.ravel())))
+
+    st, A0 = oracle.coo_to_csc(n_rows, n_cols, row, col, val)
+    assert not np.any((A0.row_idx == 3) & (np.repeat(np.arange(n_cols), np.diff(A0.col_ptr)) == 4))
+    for t in range(len(row)):
+        vp, vm = val.copy(), val.copy()
+        vp[t] += h
+        vm[t] -= h
+        fd = (L(vp) - L(vm)) / (2 * h)
+        assert fd == dv[t], (t, fd, dv[t])
+
+
+def pin_triplet_grad_matches_dvalues():
+    """Without duplicates or zero sums every triplet has its own CSC slot, and its gradient is
+    the adjoint's dvalues at that slot (the same binary64 sum in ascending j); a triplet
+    outside the matrix has gradient 0; the gradient is within the a-priori bound of the exact
+    (Fraction) dot product."""
+    rng = np.random.Generator(np.random.PCG64(6501))
+    n_rows, n_cols, k = 9, 8, 6
+    pos = rng.choice(n_rows * n_cols, size=30, replace=False)
+    row = (pos % n_rows).astype(np.int32)
+    col = (pos // n_rows).astype(np.int32)
+    val = rng.standard_normal(30) + 3.0
+    G = rng.standard_normal((n_rows, k))
+    X = rng.standard_normal((n_cols, k))
+    st, A = oracle.coo_to_csc(n_rows, n_cols, row, col, val)
+    assert st == oracle.OK and A.nnz == 30
+    _, dval, _, _ = oracle.spmm_backward(A, G, X)
+    dv, S = oracle.triplet_grad(n_rows, n_cols, row, col, G, X)
+    a_col = np.repeat(np.arange(n_cols), np.diff(A.col_ptr))
+    for t in range(30):
+        slot = int(np.nonzero((A.row_idx == row[t]) & (a_col == col[t]))[0][0])
+        assert same_floats([dv[t]], [dval[slot]]), t
+        exact = sum((Fraction(float(G[row[t], j])) * Fraction(float(X[col[t], j]))
+                     for j in range(k)), Fraction(0))
+        assert abs(Fraction(float(dv[t])) - exact) <= Fraction(float(oracle.gamma(k) * S[t]))
+    out = oracle.triplet_grad(n_rows, n_cols, np.array([n_rows, 0, -1], np.int32),
+                              np.array([0, n_cols, 0], np.int32), G, X)[0]
+    assert np.array_equal(out, np.zeros(3))
+
+
 ASSEMBLY_PINS = [pin_golden_assembly, pin_brute_force, pin_scipy_dyadic, pin_invariants_and_totals,
                  pin_index_encoding, pin_special_cases, pin_golden_insert, pin_brute_force_insert,
                  pin_insert_special_cases, pin_transpose_dense]
 SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
              pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
 TRACE_PINS = [pin_golden_trace, pin_trace_dense, pin_trace_closed_forms, pin_trace_special_cases]
-ALL_PINS = ASSEMBLY_PINS + SPMM_PINS + TRACE_PINS
+TRIPLET_GRAD_PINS = [pin_triplet_grad_fd, pin_triplet_grad_matches_dvalues]
+ALL_PINS = ASSEMBLY_PINS + SPMM_PINS + TRACE_PINS + TRIPLET_GRAD_PINS

@@ -74,6 +74,11 @@ MUTANTS = {
                                  "std::lower_bound(b_row_idx, b_row_idx + b_col_ptr[n_cols], r);"),
     "trace_b_value_replaced": ("trace = trace + a_val[p] * b_val[q];",
                                "trace = trace + a_val[p] * a_val[p];"),
+    "tgrad_last_term_dropped": ("""    for (int64_t j = 0; j < k; ++j) {
+      d = d + g[j] * x[j];""", """    for (int64_t j = 0; j + 1 < k; ++j) {
+      d = d + g[j] * x[j];"""),
+    "tgrad_wrong_operand": ("d = d + g[j] * x[j];", "d = d + g[j] * g[j];"),
+    "tgrad_sign": ("dv[t] = d;", "dv[t] = -d;"),
 }
 
 
