@@ -17,7 +17,7 @@ oracle timed on the host cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-batch] [--separate]
                     [--no-graph] [--no-insert] [--no-transpose]
-                    [--no-trace] [--cold-steps 10]
+                    [--no-tgrad] [--no-trace] [--cold-steps 10]
 """
 from __future__ import annotations
 
@@ -47,6 +47,8 @@ def parse():
                     help="skip the batch-insertion measurement")
     ap.add_argument("--no-transpose", action="store_true",
                     help="skip the transpose and row-vector product measurement")
+    ap.add_argument("--no-tgrad", action="store_true",
+                    help="skip the per-triplet gradient measurement")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the trace(A^T B) measurement")
     ap.add_argument("--trace-densities", type=lambda t: [float(x) for x in t.split(",")],
@@ -389,6 +391,34 @@ def main():
                      "compulsory_GBps": t_bytes / (t_ms * 1e-3) / 1e9,
                      "rowvec_ms": r_ms, "rowvec_elements_per_s": nnz / (r_ms * 1e-3)}
 
+    # gradient with respect to each input triplet (dropped locations included) for the step's
+    # triplets and dense operands
+    tgrad = None
+    if not args.no_tgrad:
+        lib = _lib.load()
+        tg_dv = torch.empty(p.nnz_in, dtype=torch.float32, device=dev)
+        k_ = X.shape[1]
+        vt_code = _lib.F64 if val.dtype == torch.float64 else _lib.F32
+        x_code = _lib.F64 if X.dtype == torch.float64 else _lib.F32
+
+        def run_tgrad():
+            for _ in range(args.steps):
+                lib.spm_coo_triplet_grad(p.n_rows, p.n_cols, p.nnz_in, k_, row.data_ptr(),
+                                         col.data_ptr(), vt_code, G.data_ptr(), G.stride(0),
+                                         X.data_ptr(), X.stride(0), x_code, tg_dv.data_ptr(),
+                                         _lib.F32, stream.cuda_stream)
+        run_tgrad()
+        tg_ms = timed(run_tgrad)
+        xs = X.element_size()
+        # compulsory: the triplet indices, every G and X row once, the gradients; the gather
+        # model reads a G row and an X row per triplet
+        tg_c = p.nnz_in * (8 + 4) + (p.n_rows + p.n_cols) * k_ * xs
+        tg_g = p.nnz_in * (8 + 4 + 2 * k_ * xs)
+        tgrad = {"workload": "dL/dv for the %d input triplets of the step, k=%d" % (p.nnz_in, k_),
+                 "ms": tg_ms, "triplets_per_s": p.nnz_in / (tg_ms * 1e-3),
+                 "compulsory_bytes": tg_c, "compulsory_GBps": tg_c / (tg_ms * 1e-3) / 1e9,
+                 "gather_GBps": tg_g / (tg_ms * 1e-3) / 1e9}
+
     # trace(A^T B) without forming the product (Section 2, Table 1), on the paper's evaluation
     # workload: two independent 10,000 x 10,000 matrices at four densities
     trace = None
@@ -512,6 +542,7 @@ def main():
         "graph": graph,
         "insert": insert,
         "transpose": transpose,
+        "triplet_grad": tgrad,
         "trace_atb": trace,
         "assembly_nnz_per_s": p.nnz_in / (phase_ms[phases[0]] * 1e-3),
         "assembly_phase": phases[0],

@@ -221,6 +221,28 @@ spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
                              void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Gradient with respect to each input triplet's value, for assembly (spm_coo_to_csc) followed
+ * by Y = A . X and a loss with dL/dY = G.  A[r,c] is the sum of the values of the triplets at
+ * (r, c) (the += of Fig. 1; a zero sum is only not stored), so every triplet t at (r, c) has
+ *     dv[t] = sum_j G[r, j] * X[c, j],
+ * shared by duplicates and defined also where the location summed to zero; a triplet outside
+ * the matrix (skipped by assembly) gets 0.
+ * ------------------------------------------------------------------------------------------ */
+
+/* row, col  int32[nnz_in], the triplets' locations as given to assembly.
+ * val_type  F64 or F32: the assembled values' type; with x_type BF16 and val_type F32 the dot
+ *           products accumulate in binary32 (as the adjoint's dvalues), otherwise binary64.
+ * G         n_rows x k, X n_cols x k (x_type F64, F32 or BF16, leading dimensions ldg, ldx >= k).
+ * dv        nnz_in elements of dv_type (F64 or F32), rounded once.
+ * Summation order: the adjoint's dvalues order (lane pieces of 4 in ascending order, then a
+ * fixed lane tree that depends on k alone).  No workspace, no device status (a triplet out
+ * of range is not an error here). */
+spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
+                                const int32_t *row, const int32_t *col, spm_dtype val_type,
+                                const void *G, int64_t ldg, const void *X, int64_t ldx,
+                                spm_dtype x_type, void *dv, spm_dtype dv_type, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
  * location the existing value comes first, then the new values in input order, folded in

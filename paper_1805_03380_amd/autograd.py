@@ -1,7 +1,12 @@
-"""torch.autograd.Function over the CSC product: forward Y = A.X (spm_csc_spmm), backward
-dX = A^T.G and dvalues = G.X^T sampled on A's pattern (spm_csc_spmm_backward), both hand
-written kernels.  Gradients are taken with respect to the stored CSC values and X; the
-pattern (col_ptr, row_idx) is constant.
+"""torch.autograd.Functions over the CSC product, every step in hand-written kernels.
+
+CscSpmm: forward Y = A.X (spm_csc_spmm), backward dX = A^T.G and dvalues = G.X^T sampled on
+A's pattern (spm_csc_spmm_backward); gradients with respect to the stored CSC values and X,
+the pattern (col_ptr, row_idx) constant.
+
+CooSpmm: assembly and product together, Y = assemble(row, col, val).X; the backward gives
+every input triplet its gradient (spm_coo_triplet_grad), duplicates and locations that summed
+to zero included, and dX from the adjoint.
 """
 from __future__ import annotations
 
@@ -38,3 +43,37 @@ class CscSpmm(torch.autograd.Function):
 def csc_spmm(A: ops.CSCMatrix, values: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """Differentiable Y = A(values) . X."""
     return CscSpmm.apply(values, X, A)
+
+
+class CooSpmm(torch.autograd.Function):
+    """Y = assemble(row, col, val) . X, differentiable in the triplet values and X."""
+
+    @staticmethod
+    def forward(ctx, val: torch.Tensor, X: torch.Tensor, row: torch.Tensor, col: torch.Tensor,
+                shape):
+        A = ops.coo_to_csc(row, col, val, shape)
+        ctx.A, ctx.shape = A, (int(shape[0]), int(shape[1]))
+        ctx.val_dtype = val.dtype
+        ctx.save_for_backward(row, col, X)
+        return ops.spmm(A, X)
+
+    @staticmethod
+    def backward(ctx, G: torch.Tensor):
+        row, col, X = ctx.saved_tensors
+        need_v, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        G = G.to(X.dtype) if G.dtype != X.dtype else G
+        G = G.contiguous()
+        dval = dX = None
+        if need_v:
+            dval = ops.triplet_grad(row, col, G, X, ctx.shape,
+                                    val_dtype=ctx.A.values_buf.dtype).to(ctx.val_dtype)
+        if need_x:
+            dX, _ = ops.spmm_backward(ctx.A, G, X, need_dX=True, need_dval=False,
+                                      dx_dtype=X.dtype)
+        return dval, dX, None, None, None
+
+
+def coo_spmm(row: torch.Tensor, col: torch.Tensor, val: torch.Tensor, X: torch.Tensor,
+             shape) -> torch.Tensor:
+    """Differentiable Y = assemble(row, col, val) . X (gradients per input triplet)."""
+    return CooSpmm.apply(val, X, row, col, shape)

@@ -4,7 +4,7 @@
 
 Produces paper_1805_03380_amd/lib/libspm.so from csrc/spm_api.hip (the translation unit that
 includes every kernel header of the assembly, plan, products and batch), csrc/spm_trace.hip
-(trace(A^T B)) and include/spm.h.
+(trace(A^T B)), csrc/spm_tgrad.hip (the gradient per input triplet) and include/spm.h.
 """
 from __future__ import annotations
 
@@ -40,7 +40,8 @@ def hipcc() -> str:
 
 
 def sources():
-    return [os.path.join(CSRC, "spm_api.hip"), os.path.join(CSRC, "spm_trace.hip")]
+    return [os.path.join(CSRC, "spm_api.hip"), os.path.join(CSRC, "spm_trace.hip"),
+            os.path.join(CSRC, "spm_tgrad.hip")]
 
 
 def build(verbose: bool = False) -> str:

@@ -287,6 +287,41 @@ def trace_atb(A: CSCMatrix, B: CSCMatrix, sync: bool = True):
     return float(out.item()), int(h[0])
 
 
+def triplet_grad(row: torch.Tensor, col: torch.Tensor, G: torch.Tensor, X: torch.Tensor, shape,
+                 val_dtype: torch.dtype = torch.float32,
+                 out_dtype: torch.dtype | None = None) -> torch.Tensor:
+    """dL/dv_t = G[row_t, :] . X[col_t, :] for every input triplet of an assembly followed by
+    Y = A.X (spm_coo_triplet_grad): duplicates share it, a location that summed to zero still
+    has it, a triplet outside the matrix gets 0.  `val_dtype` is the assembled values' type
+    (it picks the accumulation, as for the adjoint)."""
+    n_rows, n_cols = int(shape[0]), int(shape[1])
+    G2 = G.reshape(-1, 1) if G.dim() == 1 else G
+    X2 = X.reshape(-1, 1) if X.dim() == 1 else X
+    _require_cuda(row, col, G2, X2)
+    if G2.dtype != X2.dtype:
+        raise ValueError("G and X must share one element type")
+    if G2.shape[0] != n_rows or X2.shape[0] != n_cols or G2.shape[1] != X2.shape[1]:
+        raise ValueError("G %s and X %s do not fit a %dx%d matrix" % (tuple(G2.shape),
+                         tuple(X2.shape), n_rows, n_cols))
+    if G2.stride(1) != 1:
+        G2 = G2.contiguous()
+    if X2.stride(1) != 1:
+        X2 = X2.contiguous()
+    if row.dtype != torch.int32 or col.dtype != torch.int32:
+        raise ValueError("row and col must be int32")
+    n = int(row.shape[0])
+    if out_dtype is None:
+        out_dtype = val_dtype if val_dtype in (torch.float32, torch.float64) else torch.float32
+    dv = torch.empty(max(n, 1), dtype=out_dtype, device=row.device)
+    lib = _lib.load()
+    st = lib.spm_coo_triplet_grad(n_rows, n_cols, n, int(X2.shape[1]), _ptr(row), _ptr(col),
+                                  _dtype_code(val_dtype), _ptr(G2), G2.stride(0), _ptr(X2),
+                                  X2.stride(0), _dtype_code(X2.dtype), _ptr(dv),
+                                  _dtype_code(out_dtype), _stream(row.device))
+    _lib.check(st, "spm_coo_triplet_grad")
+    return dv[:n]
+
+
 def rowvec_spmm(V: torch.Tensor, A: CSCMatrix, out_dtype: torch.dtype | None = None):
     """W = V.A for row vectors V (n_rows, or m x n_rows for m of them): the product of Section
     3's use case (iv) written as in Fig. 1.  It is the column walk of the adjoint with the

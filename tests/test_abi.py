@@ -178,6 +178,24 @@ def test_host_validation_rejects_before_launch():
     assert ta(info=None) == _lib.EINVAL
     assert ta(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
     assert ta(wsb=16) == _lib.EWORKSPACE
+    # gradient per input triplet
+
+    def tg(n_rows=4, n_cols=4, n=8, k=4, row=fake, vt=_lib.F32, ldg=4, ldx=4, xt=_lib.F32,
+           dv=fake, dvt=_lib.F32):
+        return lib.spm_coo_triplet_grad(n_rows, n_cols, n, k, row, fake, vt, fake, ldg, fake,
+                                        ldx, xt, dv, dvt, None)
+
+    assert tg(n=0) == _lib.OK  # nothing to do, nothing enqueued
+    assert tg(k=0) == _lib.EINVAL
+    assert tg(ldg=3) == _lib.EINVAL
+    assert tg(ldx=3) == _lib.EINVAL
+    assert tg(n=-1) == _lib.EINVAL
+    assert tg(n=2 ** 31) == _lib.EOVERFLOW
+    assert tg(vt=_lib.BF16) == _lib.EDTYPE
+    assert tg(xt=7) == _lib.EDTYPE
+    assert tg(dvt=_lib.BF16) == _lib.EDTYPE
+    assert tg(row=None) == _lib.EINVAL
+    assert tg(dv=None) == _lib.EINVAL
 
 
 def test_tuning_roundtrip():
