@@ -224,6 +224,22 @@ def rbt_context(p):
             "status": int(st)}
 
 
+def host_csc(A):
+    """The device CSC's arrays on the host, as the oracle takes them."""
+    import oracle
+    n = A.nnz
+    return oracle.CSC(A.n_rows, A.n_cols, A.col_ptr.cpu().numpy(),
+                      A.row_idx_buf[:n].cpu().numpy(),
+                      oracle.widen(A.values_buf[:n].cpu()))
+
+
+def oracle_ms(fn):
+    """One call of an oracle function on the host (single thread), in ms."""
+    t0 = time.perf_counter()
+    fn()
+    return (time.perf_counter() - t0) * 1e3
+
+
 def copy_calibration(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -347,7 +363,13 @@ def main():
         sv = A.values_buf.element_size()
         i_bytes = (4 * (p.n_cols + 1) + nnz * (4 + sv) + q.nnz_in * (8 + sv)
                    + 4 * (p.n_cols + 1) + nnz_out * (4 + sv))
-        insert = {"workload": "10^5 new triplets (5 percent duplicates, seed 1006) into the "
+        cpu_ms = None
+        if not args.no_cpu:
+            import oracle
+            Ah = host_csc(A)
+            cpu_ms = oracle_ms(lambda: oracle.csc_insert(Ah, q.row, q.col, q.val))
+        insert = {"cpu_oracle_ms": cpu_ms,
+                  "workload": "10^5 new triplets (5 percent duplicates, seed 1006) into the "
                               "assembled 1e5 x 1e5 CSC", "existing": nnz, "new": q.nnz_in,
                   "nnz_out": nnz_out, "ms": i_ms,
                   "elements_per_s": (nnz + q.nnz_in) / (i_ms * 1e-3),
@@ -385,7 +407,13 @@ def main():
                 for _ in range(args.steps):
                     ops.rowvec_spmm(V, A)
         r_ms = timed(run_rowvec)
-        transpose = {"workload": "transpose of the assembled 1e5 x 1e5 CSC", "nnz": nnz,
+        cpu_ms = None
+        if not args.no_cpu:
+            import oracle
+            Ah = host_csc(A)
+            cpu_ms = oracle_ms(lambda: oracle.csc_transpose(Ah))
+        transpose = {"cpu_oracle_ms": cpu_ms,
+                     "workload": "transpose of the assembled 1e5 x 1e5 CSC", "nnz": nnz,
                      "ms": t_ms, "elements_per_s": nnz / (t_ms * 1e-3),
                      "compulsory_bytes": t_bytes,
                      "compulsory_GBps": t_bytes / (t_ms * 1e-3) / 1e9,
@@ -414,7 +442,13 @@ def main():
         # model reads a G row and an X row per triplet
         tg_c = p.nnz_in * (8 + 4) + (p.n_rows + p.n_cols) * k_ * xs
         tg_g = p.nnz_in * (8 + 4 + 2 * k_ * xs)
-        tgrad = {"workload": "dL/dv for the %d input triplets of the step, k=%d" % (p.nnz_in, k_),
+        cpu_ms = None
+        if not args.no_cpu:
+            import oracle
+            cpu_ms = oracle_ms(lambda: oracle.triplet_grad(p.n_rows, p.n_cols, p.row, p.col,
+                                                           p.G, p.X))
+        tgrad = {"cpu_oracle_ms": cpu_ms,
+                 "workload": "dL/dv for the %d input triplets of the step, k=%d" % (p.nnz_in, k_),
                  "ms": tg_ms, "triplets_per_s": p.nnz_in / (tg_ms * 1e-3),
                  "compulsory_bytes": tg_c, "compulsory_GBps": tg_c / (tg_ms * 1e-3) / 1e9,
                  "gather_GBps": tg_g / (tg_ms * 1e-3) / 1e9}
@@ -453,7 +487,13 @@ def main():
             # match; the full-read model reads every value too
             c_bytes = 2 * 4 * (qa.n_cols + 1) + 4 * (na + nb) + 2 * 8 * hits
             f_bytes = 2 * 4 * (qa.n_cols + 1) + (4 + 8) * (na + nb)
-            trace.append({"workload": "trace(A^T B), 10^4 x 10^4, density %g, float64 (seed 1007)"
+            cpu_ms = None
+            if not args.no_cpu:
+                import oracle
+                Ah, Bh = host_csc(TA), host_csc(TB)
+                cpu_ms = oracle_ms(lambda: oracle.trace_atb(Ah, Bh))
+            trace.append({"cpu_oracle_ms": cpu_ms,
+                          "workload": "trace(A^T B), 10^4 x 10^4, density %g, float64 (seed 1007)"
                                       % dens, "nnz_a": na, "nnz_b": nb, "hits": hits,
                           "ms": tr_ms, "elements_per_s": (na + nb) / (tr_ms * 1e-3),
                           "compulsory_bytes": c_bytes,

@@ -68,6 +68,8 @@ def configure(lib):
     lib.oracle_csc_transpose.restype = ctypes.c_int
     lib.oracle_trace_atb.argtypes = [i64, i64, p, p, p, p, p, p, p, p]
     lib.oracle_trace_atb.restype = ctypes.c_int
+    lib.oracle_csc_add.argtypes = [i64, i64, p, p, p, p, p, p, p, p, p, p]
+    lib.oracle_csc_add.restype = ctypes.c_int
     lib.oracle_triplet_grad.argtypes = [i64, i64, i64, i64, p, p, p, p, p, p]
     lib.oracle_triplet_grad.restype = None
     lib.oracle_spmm.argtypes = [i64, i64, i64, p, p, p, p, p, p, p]
@@ -156,6 +158,30 @@ def csc_insert(A: CSC, row, col, val):
     st = lib.oracle_csc_insert(A.n_rows, A.n_cols, _ptr(a_cp), _ptr(a_ri), _ptr(a_v), n,
                                _ptr(row), _ptr(col), _ptr(v), _ptr(col_ptr), _ptr(row_idx),
                                _ptr(out), ctypes.byref(nnz))
+    if st != OK:
+        return st, None
+    m = nnz.value
+    return OK, CSC(A.n_rows, A.n_cols, col_ptr, row_idx[:m].copy(), out[:m].copy())
+
+
+def csc_add(A: CSC, B: CSC):
+    """A + B (both CSCs of one shape): per column, the sorted row lists merged; a row in both
+    gives A's value plus B's in binary64; a 0.0 result is not stored.  Returns (status, CSC or
+    None)."""
+    lib = _load()
+    assert (A.n_rows, A.n_cols) == (B.n_rows, B.n_cols)
+    arrs = []
+    for M in (A, B):
+        arrs += [np.ascontiguousarray(M.col_ptr, dtype=np.int32),
+                 np.ascontiguousarray(M.row_idx, dtype=np.int32),
+                 np.ascontiguousarray(widen(M.values), dtype=np.float64)]
+    cap = max(int(arrs[0][-1]) + int(arrs[3][-1]), 1)
+    col_ptr = np.zeros(A.n_cols + 1, dtype=np.int32)
+    row_idx = np.zeros(cap, dtype=np.int32)
+    out = np.zeros(cap, dtype=np.float64)
+    nnz = ctypes.c_int64(0)
+    st = lib.oracle_csc_add(A.n_rows, A.n_cols, *(_ptr(a) for a in arrs), _ptr(col_ptr),
+                            _ptr(row_idx), _ptr(out), ctypes.byref(nnz))
     if st != OK:
         return st, None
     m = nnz.value

@@ -3,8 +3,8 @@
 // A plain, slow, deliberately unoptimised CPU reference for what the sparse path computes:
 // bulk assembly of coordinate (COO) triplets into compressed sparse column (CSC) form, the CSC
 // sparse x dense product Y = A.X, and its adjoint (dX = A^T.G, dvalues = G.X sampled on A's
-// pattern); batch insertion into an existing CSC, the transpose, trace(A^T B), and the gradient
-// with respect to each input triplet.  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
+// pattern); batch insertion into an existing CSC, the sum of two CSCs, the transpose,
+// trace(A^T B), and the gradient with respect to each input triplet.  Everything is IEEE binary64; the build uses -O2 -ffp-contract=off and no fast-math,
 // so every '+' and '*' below is one correctly rounded binary64 operation, in the order written.
 //
 // Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may load this
@@ -215,6 +215,53 @@ int oracle_csc_insert(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
     }
   }
   offsets_from_columns(n_cols, emitted_cols, col_ptr);
+  *nnz_out = n;
+  return 0;
+}
+
+// Sparse sum A + B of two CSCs of one shape (the addition of two sparse matrices, built, like
+// batch insertion, by merging sorted columns; Section 3.1).  Column by column, the two sorted
+// row lists are merged: a row stored in both gives A's value plus B's value (binary64, A's
+// first), a row stored in one gives that value; a result equal to 0.0 is not stored (the rule
+// of the assembly).  Output capacity: nnz(A) + nnz(B).
+// Returns 0, or 1 (bad sizes, null pointers, or a CSC that is not valid and sorted).
+int oracle_csc_add(int64_t n_rows, int64_t n_cols, const int32_t* a_col_ptr,
+                   const int32_t* a_row_idx, const double* a_val, const int32_t* b_col_ptr,
+                   const int32_t* b_row_idx, const double* b_val, int32_t* col_ptr,
+                   int32_t* row_idx, double* val_out, int64_t* nnz_out) {
+  if (n_rows < 0 || n_cols < 0 || !col_ptr || !nnz_out) return 1;
+  if (!valid_sorted_csc(n_rows, n_cols, a_col_ptr, a_row_idx)) return 1;
+  if (!valid_sorted_csc(n_rows, n_cols, b_col_ptr, b_row_idx)) return 1;
+  int64_t n = 0;
+  col_ptr[0] = 0;
+  for (int64_t c = 0; c < n_cols; ++c) {
+    int64_t p = a_col_ptr[c], q = b_col_ptr[c];
+    const int64_t pe = a_col_ptr[c + 1], qe = b_col_ptr[c + 1];
+    while (p < pe || q < qe) {
+      int32_t r;
+      double v;
+      if (q >= qe || (p < pe && a_row_idx[p] < b_row_idx[q])) {
+        r = a_row_idx[p];
+        v = a_val[p];
+        ++p;
+      } else if (p >= pe || b_row_idx[q] < a_row_idx[p]) {
+        r = b_row_idx[q];
+        v = b_val[q];
+        ++q;
+      } else {  // the row is stored in both
+        r = a_row_idx[p];
+        v = a_val[p] + b_val[q];
+        ++p;
+        ++q;
+      }
+      if (v != 0.0) {
+        row_idx[n] = r;
+        val_out[n] = v;
+        ++n;
+      }
+    }
+    col_ptr[c + 1] = (int32_t)n;
+  }
   *nnz_out = n;
   return 0;
 }

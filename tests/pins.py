@@ -466,6 +466,54 @@ def pin_transpose_dense(seeds=range(10)):
     assert np.array_equal(T.row_idx, eye.row_idx)
 
 
+# ------------------------------------------------------------------------------ sum A + B pins
+
+def pin_add_dense(seeds=range(12)):
+    """A + B equals the CSC of the dense sum (dyadic values: every sum exact), zeros dropped;
+    A + B = B + A; A + (-A) is empty; A + empty = A."""
+    for seed in seeds:
+        rng = np.random.Generator(np.random.PCG64(6600 + seed))
+        n_rows = int(rng.integers(1, 10))
+        n_cols = int(rng.integers(1, 10))
+        Da, Db = _trace_pair(rng, n_rows, n_cols, 0.5, _dyadic)
+        # some exact cancellations
+        Db = np.where(rng.random((n_rows, n_cols)) < 0.2, -Da, Db)
+        A, B = csc_from_dense(Da), csc_from_dense(Db)
+        st, R = oracle.csc_add(A, B)
+        assert st == oracle.OK
+        E = csc_from_dense(Da + Db)
+        assert np.array_equal(R.col_ptr, E.col_ptr), seed
+        assert np.array_equal(R.row_idx, E.row_idx), seed
+        assert same_floats(R.values, E.values), seed
+        st, R2 = oracle.csc_add(B, A)
+        assert st == oracle.OK and np.array_equal(R2.row_idx, R.row_idx)
+        assert same_floats(R2.values, R.values)
+        st, Z = oracle.csc_add(A, csc_from_dense(-Da))
+        assert st == oracle.OK and Z.nnz == 0 and np.all(Z.col_ptr == 0)
+        st, S = oracle.csc_add(A, csc_from_dense(np.zeros_like(Da)))
+        assert st == oracle.OK and np.array_equal(S.row_idx, A.row_idx)
+        assert same_floats(S.values, A.values)
+    bad = oracle.CSC(3, 2, np.array([0, 2, 2], np.int32), np.array([2, 0], np.int32),
+                     np.array([1.0, 2.0]))
+    st, _ = oracle.csc_add(bad, bad)
+    assert st == oracle.EINVAL
+
+
+def pin_add_is_insertion():
+    """A + B equals the batch insertion of B's elements (as triplets, in CSC order) into A:
+    at a shared location both fold A's value first."""
+    rng = np.random.Generator(np.random.PCG64(6700))
+    D1 = rng.standard_normal((30, 20)) * (rng.random((30, 20)) < 0.3)
+    D2 = rng.standard_normal((30, 20)) * (rng.random((30, 20)) < 0.3)
+    A, B = csc_from_dense(D1), csc_from_dense(D2)
+    st, R = oracle.csc_add(A, B)
+    b_col = np.repeat(np.arange(20), np.diff(B.col_ptr)).astype(np.int32)
+    st2, I = oracle.csc_insert(A, B.row_idx, b_col, B.values)
+    assert st == st2 == oracle.OK
+    assert np.array_equal(R.col_ptr, I.col_ptr) and np.array_equal(R.row_idx, I.row_idx)
+    assert same_floats(R.values, I.values)
+
+
 # -------------------------------------------------------------------------- trace(A^T B) pins
 
 def _trace_pair(rng, n_rows, n_cols, density, values):
@@ -655,4 +703,5 @@ SPMM_PINS = [pin_golden_spmm, pin_fraction_exact, pin_identity_and_permutation,
              pin_ones_closed_form, pin_dense_crosscheck, pin_adjoint_identity, pin_central_fd]
 TRACE_PINS = [pin_golden_trace, pin_trace_dense, pin_trace_closed_forms, pin_trace_special_cases]
 TRIPLET_GRAD_PINS = [pin_triplet_grad_fd, pin_triplet_grad_matches_dvalues]
-ALL_PINS = ASSEMBLY_PINS + SPMM_PINS + TRACE_PINS + TRIPLET_GRAD_PINS
+ADD_PINS = [pin_add_dense, pin_add_is_insertion]
+ALL_PINS = ASSEMBLY_PINS + SPMM_PINS + TRACE_PINS + TRIPLET_GRAD_PINS + ADD_PINS

@@ -79,6 +79,10 @@ MUTANTS = {
       d = d + g[j] * x[j];"""),
     "tgrad_wrong_operand": ("d = d + g[j] * x[j];", "d = d + g[j] * g[j];"),
     "tgrad_sign": ("dv[t] = d;", "dv[t] = -d;"),
+    "add_b_dropped_when_shared": ("v = a_val[p] + b_val[q];", "v = a_val[p];"),
+    "add_keep_zero": ("""      if (v != 0.0) {
+        row_idx[n] = r;""", """      if (true) {
+        row_idx[n] = r;"""),
 }
 
 
