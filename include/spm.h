@@ -166,6 +166,32 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
                                size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Sum A + B of two CSCs of one shape, by the merge of batch insertion: B's stored elements are
+ * inserted into A, so a location stored in both holds A's value plus B's (binary64, A's
+ * first), and a 0.0 result is not stored.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Workspace of spm_csc_add. */
+spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, int64_t b_cap,
+                                 size_t *ws_bytes);
+
+/* A (a_col_ptr, a_row_idx, a_val; capacity a_cap) and B (b_*; capacity b_cap): valid CSCs,
+ * n_rows x n_cols, rows increasing down each column; the stored counts are read on the device.
+ *   val_type   F64 or F32, the type of a_val and b_val.
+ *   col_ptr    int32[n_cols + 1]; row_idx / val_out (out_type F64 or F32) have capacity
+ *              a_cap + b_cap.
+ *   info       int32[2]: info[0] = nnz of the sum, info[1] = 0, SPM_EINVAL (a malformed
+ *              CSC) or SPM_EBOUNDS (a stored row outside the matrix).
+ *   ws         at least spm_csc_add_workspace() bytes, 256-byte aligned.
+ * n_cols must be at least 1 (SPM_EINVAL otherwise, as for spm_csc_insert). */
+spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t *a_col_ptr,
+                       const int32_t *a_row_idx, const void *a_val, int64_t b_cap,
+                       const int32_t *b_col_ptr, const int32_t *b_row_idx, const void *b_val,
+                       spm_dtype val_type, int32_t *col_ptr, int32_t *row_idx, void *val_out,
+                       spm_dtype out_type, int32_t *info, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Transpose X.t() (Table 1) as a CSC of the n_cols x n_rows result: the row index of A that
  * spm_csc_plan_build derives is the CSC of A^T, here written into separate arrays with the
  * values carried along (moved, not changed).

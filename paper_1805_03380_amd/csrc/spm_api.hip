@@ -737,18 +737,20 @@ size_t transpose_ws_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_
 // value type) and the status flags (column expansion, then level-1 tiles).
 struct InsertLayout {
   AsmLayout A;
-  size_t colarr, vcat, flags, total;
+  size_t colarr, tcolarr, vcat, flags, total;
 };
 
-InsertLayout insert_layout(int64_t n_cols, int64_t cap_a, int64_t nnz_t) {
+// sum: the new elements are a second CSC's nnz_t slots, whose columns are expanded too
+InsertLayout insert_layout(int64_t n_cols, int64_t cap_a, int64_t nnz_t, bool sum = false) {
   InsertLayout L;
   L.A = asm_layout(n_cols, cap_a + nnz_t);
   Carve c;
   c.off = L.A.total;
   L.colarr = c.take(sizeof(int32_t) * (size_t)cap_a);
+  L.tcolarr = c.take(sizeof(int32_t) * (size_t)(sum ? nnz_t : 0));
   L.vcat = c.take(sizeof(double) * (size_t)(cap_a + nnz_t));
-  L.flags = c.take(sizeof(uint32_t) *
-                   (size_t)(expand_grid(n_cols) + (L.A.pp.ok ? L.A.pp.ntiles : 0)));
+  L.flags = c.take(sizeof(uint32_t) * (size_t)((sum ? 2 : 1) * expand_grid(n_cols) +
+                                               (L.A.pp.ok ? L.A.pp.ntiles : 0)));
   L.total = c.off;
   return L;
 }
@@ -759,7 +761,7 @@ void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_co
               const int32_t* a_row_idx, const VT* a_val, int64_t nnz_t, const int32_t* row,
               const int32_t* col, const VT* val, int32_t* col_ptr, int32_t* row_idx,
               void* val_out, int out_f64, int32_t* info, char* w, const InsertLayout& IL,
-              hipStream_t s) {
+              hipStream_t s, const int32_t* t_col_ptr = nullptr) {
   const AsmLayout& L = IL.A;
   const PartParams& P = L.pp;
   int32_t* colarr = reinterpret_cast<int32_t*>(w + IL.colarr);
@@ -781,11 +783,18 @@ void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_co
   if (n > 0)
     k_concat_values<kNT, VT><<<dim3(grid_for(n, kNT * 4, cap)), dim3(kNT), 0, s>>>(
         a_val, cap_a, val, nnz_t, vcat);
-  const int eg = expand_grid(n_cols);
+  int eg = expand_grid(n_cols);
   k_expand_columns<kNT><<<dim3(eg), dim3(kNT), 0, s>>>(a_col_ptr, n_cols, cap_a, colarr, info,
                                                        flags);
+  if (t_col_ptr) {  // the second CSC's columns, checked like the first's
+    int32_t* tcolarr = reinterpret_cast<int32_t*>(w + IL.tcolarr);
+    k_expand_columns<kNT><<<dim3(eg), dim3(kNT), 0, s>>>(t_col_ptr, n_cols, nnz_t, tcolarr,
+                                                         info, flags + eg);
+    col = tcolarr;
+    eg *= 2;  // both expansions' flags come before the tiles'
+  }
   PartSrcMerge src{a_row_idx, colarr, a_col_ptr, row, col, (int32_t)n_rows, (int32_t)n_cols,
-                   cap_a, nnz_t};
+                   cap_a, nnz_t, t_col_ptr};
   k_part_hist<kPartNT, PartSrcMerge>
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
           src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg);
@@ -983,6 +992,53 @@ spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
                     static_cast<const float*>(a_val), nnz_t, row, col,
                     static_cast<const float*>(val), col_ptr, row_idx, val_out, out_f64, info,
                     static_cast<char*>(ws), L, s);
+  return launch_status();
+}
+
+spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, int64_t b_cap,
+                                 size_t* ws_bytes) {
+  if (!ws_bytes || a_cap < 0 || b_cap < 0) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, a_cap);
+  if (st != SPM_OK) return st;
+  if (!fits_i32(b_cap) || !fits_i32(a_cap + b_cap)) return SPM_EOVERFLOW;
+  *ws_bytes = insert_layout(n_cols, a_cap, b_cap, true).total;
+  return SPM_OK;
+}
+
+spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a_col_ptr,
+                       const int32_t* a_row_idx, const void* a_val, int64_t b_cap,
+                       const int32_t* b_col_ptr, const int32_t* b_row_idx, const void* b_val,
+                       spm_dtype val_type, int32_t* col_ptr, int32_t* row_idx, void* val_out,
+                       spm_dtype out_type, int32_t* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (a_cap < 0 || b_cap < 0) return SPM_EINVAL;
+  spm_status st = check_dims(n_rows, n_cols, a_cap);
+  if (st != SPM_OK) return st;
+  if (!fits_i32(b_cap) || !fits_i32(a_cap + b_cap)) return SPM_EOVERFLOW;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (out_type != SPM_F64 && out_type != SPM_F32) return SPM_EDTYPE;
+  if (!a_col_ptr || !b_col_ptr || !col_ptr || !info || !ws) return SPM_EINVAL;
+  if (a_cap > 0 && (!a_row_idx || !a_val)) return SPM_EINVAL;
+  if (b_cap > 0 && (!b_row_idx || !b_val)) return SPM_EINVAL;
+  if (a_cap + b_cap > 0 && (!row_idx || !val_out)) return SPM_EINVAL;
+  if (!aligned(ws, 256)) return SPM_EINVAL;
+  const InsertLayout L = insert_layout(n_cols, a_cap, b_cap, true);
+  if (!L.A.pp.ok) return SPM_EINVAL;  // no columns, or more than the partition covers
+  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const int out_f64 = out_type == SPM_F64 ? 1 : 0;
+  // B's slots are the new elements (rows b_row_idx, columns expanded from b_col_ptr)
+  if (val_type == SPM_F64)
+    insert_t<double>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
+                     static_cast<const double*>(a_val), b_cap, b_row_idx, nullptr,
+                     static_cast<const double*>(b_val), col_ptr, row_idx, val_out, out_f64,
+                     info, static_cast<char*>(ws), L, s, b_col_ptr);
+  else
+    insert_t<float>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
+                    static_cast<const float*>(a_val), b_cap, b_row_idx, nullptr,
+                    static_cast<const float*>(b_val), col_ptr, row_idx, val_out, out_f64, info,
+                    static_cast<char*>(ws), L, s, b_col_ptr);
   return launch_status();
 }
 

@@ -79,8 +79,8 @@ struct PartSrcCsc {  // plan: segment = row, key = column << 32 | CSC slot
   }
 };
 
-// Batch insertion into an existing CSC: the existing stored elements take the positions
-// 0 .. cap_a of one virtual input (slot p; slots at or past a_col_ptr[n_cols] are unused and
+// Batch insertion into an existing CSC (and the sum of two CSCs): the existing stored
+// elements take the positions 0 .. cap_a of one virtual input (slot p; slots at or past a_col_ptr[n_cols] are unused and
 // skipped silently), the new triplets follow at cap_a + t.  Keys carry the position, so at a
 // location the existing element folds first, then the new triplets in input order; the
 // assembly of this virtual input is the merge.
@@ -92,6 +92,9 @@ struct PartSrcMerge {
   const int32_t* col;
   int32_t n_rows, n_cols;
   int64_t cap_a, n_t;
+  // non-null: the new elements are the n_t slots of a second CSC (the sum A + B), col its
+  // k_expand_columns; slots at or past t_col_ptr[n_cols] are unused and skipped silently
+  const int32_t* t_col_ptr;
   __device__ __forceinline__ int64_t count() const { return cap_a + n_t; }
   __device__ __forceinline__ int elem(int64_t e, uint32_t& seg, uint64_t& key) const {
     int32_t r, c;
@@ -102,6 +105,11 @@ struct PartSrcMerge {
       r = a_row[e];
       c = a_colarr[e];
     } else {
+      if (t_col_ptr) {
+        const int64_t raw = t_col_ptr[n_cols];
+        const int64_t nnz_t = raw < 0 ? 0 : (raw > n_t ? n_t : raw);
+        if (e - cap_a >= nnz_t) return kElemSkip;
+      }
       r = row[e - cap_a];
       c = col[e - cap_a];
     }

@@ -223,6 +223,46 @@ def csc_insert(A: CSCMatrix, row: torch.Tensor, col: torch.Tensor, val: torch.Te
     return B
 
 
+def csc_add(A: CSCMatrix, B: CSCMatrix, out_dtype: torch.dtype | None = None,
+            sync: bool = True) -> CSCMatrix:
+    """A + B (spm_csc_add): B's stored elements inserted into A, a shared location holding A's
+    value plus B's, zero sums dropped.  A and B share one shape and value type."""
+    _require_cuda(A.col_ptr, B.col_ptr)
+    if (A.n_rows, A.n_cols) != (B.n_rows, B.n_cols):
+        raise ValueError("A is %dx%d, B is %dx%d" % (A.n_rows, A.n_cols, B.n_rows, B.n_cols))
+    if A.values_buf.dtype != B.values_buf.dtype:
+        raise ValueError("A and B must share one value type")
+    if out_dtype is None:
+        out_dtype = A.values_buf.dtype
+    lib = _lib.load()
+    dev = A.device
+    ca, cb = A.nnz_cap, B.nnz_cap
+    wb = _lib.ctypes.c_size_t(0)
+    _lib.check(lib.spm_csc_add_workspace(A.n_rows, A.n_cols, ca, cb, _lib.ctypes.byref(wb)),
+               "spm_csc_add_workspace")
+    ws = _workspace(wb.value, dev)
+    cap = ca + cb
+    col_ptr = torch.empty(A.n_cols + 1, dtype=torch.int32, device=dev)
+    row_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    vout = torch.empty(max(cap, 1), dtype=out_dtype, device=dev)
+    info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.spm_csc_add(A.n_rows, A.n_cols, ca, _ptr(A.col_ptr),
+                         _ptr(A.row_idx_buf) if ca else None, _ptr(A.values_buf) if ca else None,
+                         cb, _ptr(B.col_ptr), _ptr(B.row_idx_buf) if cb else None,
+                         _ptr(B.values_buf) if cb else None, _dtype_code(A.values_buf.dtype),
+                         _ptr(col_ptr), _ptr(row_idx), _ptr(vout), _dtype_code(out_dtype),
+                         _ptr(info), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(st, "spm_csc_add")
+    C = CSCMatrix(A.n_rows, A.n_cols, col_ptr, row_idx[:cap] if cap else row_idx[:0],
+                  vout[:cap] if cap else vout[:0], info)
+    C._ws = ws
+    if sync:
+        h = info.cpu()
+        _lib.check(int(h[1]), "spm_csc_add (device)")
+        C._nnz = int(h[0])
+    return C
+
+
 def csc_transpose(A: CSCMatrix, sync: bool = True) -> CSCMatrix:
     """A^T as a CSC (spm_csc_transpose; X.t() of Table 1)."""
     _require_cuda(A.col_ptr)

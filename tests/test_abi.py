@@ -178,6 +178,24 @@ def test_host_validation_rejects_before_launch():
     assert ta(info=None) == _lib.EINVAL
     assert ta(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
     assert ta(wsb=16) == _lib.EWORKSPACE
+    # sum of two CSCs
+
+    def ad(n_rows=4, n_cols=4, ca=8, cb=8, vt=_lib.F64, ot=_lib.F64, acp=fake, bcp=fake,
+           info=fake, w=ws, wsb=1 << 30):
+        return lib.spm_csc_add(n_rows, n_cols, ca, acp, fake, fake, cb, bcp, fake, fake, vt,
+                               fake, fake, fake, ot, info, w, wsb, None)
+
+    assert lib.spm_csc_add_workspace(4, 4, 8, 8, ctypes.byref(wb)) == _lib.OK and wb.value
+    assert ad(ca=-1) == _lib.EINVAL
+    assert ad(cb=2 ** 31) == _lib.EOVERFLOW
+    assert ad(ca=2 ** 30, cb=2 ** 30) == _lib.EOVERFLOW
+    assert ad(vt=_lib.BF16) == _lib.EDTYPE
+    assert ad(ot=_lib.BF16) == _lib.EDTYPE
+    assert ad(acp=None) == _lib.EINVAL
+    assert ad(bcp=None) == _lib.EINVAL
+    assert ad(info=None) == _lib.EINVAL
+    assert ad(n_cols=0) == _lib.EINVAL
+    assert ad(wsb=16) == _lib.EWORKSPACE
     # gradient per input triplet
 
     def tg(n_rows=4, n_cols=4, n=8, k=4, row=fake, vt=_lib.F32, ldg=4, ldx=4, xt=_lib.F32,

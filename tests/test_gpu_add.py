@@ -1,0 +1,96 @@
+"""GPU parity of the sum of two CSCs (spm_csc_add) with the oracle's column merge: structure
+and values bit-exact (a shared location is A's value plus B's in binary64, zero sums
+dropped), and equal to inserting B's elements into A."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1805_03380_amd import _lib, ops, synth
+from gpu_util import DEV, assemble_gpu, assert_csc_equal, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(A_gpu):
+    n = A_gpu.nnz
+    return oracle.CSC(A_gpu.n_rows, A_gpu.n_cols, A_gpu.col_ptr.cpu().numpy(),
+                      A_gpu.row_idx_buf[:n].cpu().numpy(),
+                      oracle.widen(A_gpu.values_buf[:n].cpu()))
+
+
+def _add_case(A, B, out_np=np.float64, out_dtype=None):
+    C = ops.csc_add(A, B, out_dtype=out_dtype)
+    st, R = oracle.csc_add(_host(A), _host(B))
+    assert st == oracle.OK
+    assert_csc_equal(C, R, out_np)
+    return C
+
+
+@pytest.mark.parametrize("val_dtype", [torch.float64, torch.float32])
+def test_add_random(val_dtype):
+    pa = synth.random_coo(3100, 2500, 1800, 50_000, dup_frac=0.2, dist="normal")
+    pb = synth.random_coo(3101, 2500, 1800, 40_000, dup_frac=0.2, dist="normal")
+    print("case add %s" % val_dtype, flush=True)
+    A, B = assemble_gpu(pa, val_dtype=val_dtype), assemble_gpu(pb, val_dtype=val_dtype)
+    out_np = np.float64 if val_dtype == torch.float64 else np.float32
+    C = _add_case(A, B, out_np)
+    # the same as inserting B's elements (CSC order) into A
+    b_col = torch.repeat_interleave(torch.arange(B.n_cols, device=DEV, dtype=torch.int32),
+                                    torch.diff(B.col_ptr).long())
+    I = ops.csc_insert(A, B.row_idx.contiguous(), b_col, B.values.contiguous())
+    assert torch.equal(C.col_ptr, I.col_ptr) and torch.equal(C.row_idx, I.row_idx)
+    assert torch.equal(C.values.view(torch.int32 if out_np == np.float32 else torch.int64),
+                       I.values.view(torch.int32 if out_np == np.float32 else torch.int64))
+
+
+def test_add_cancellation_and_empty():
+    pa = synth.random_coo(3102, 600, 500, 8000, dup_frac=0.0, dist="normal")
+    neg = synth.COOProblem("neg", pa.n_rows, pa.n_cols, pa.row, pa.col, -pa.val)
+    A, N = assemble_gpu(pa), assemble_gpu(neg)
+    C = _add_case(A, N)
+    assert C.nnz == 0
+    e = synth.COOProblem("empty", 600, 500, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                         np.zeros(0))
+    E = assemble_gpu(e)
+    C = _add_case(A, E)
+    assert torch.equal(C.row_idx, A.row_idx)
+    _add_case(E, A)
+    _add_case(E, E)
+
+
+def test_add_spare_capacity():
+    """Both operands with capacity above their nnz (duplicates folded on assembly)."""
+    pa = synth.random_coo(3103, 900, 700, 20_000, dup_frac=0.5, dist="normal")
+    pb = synth.random_coo(3104, 900, 700, 20_000, dup_frac=0.5, dist="normal")
+    A, B = assemble_gpu(pa), assemble_gpu(pb)
+    assert A.nnz_cap > A.nnz and B.nnz_cap > B.nnz
+    _add_case(A, B)
+
+
+def test_add_uniform_1e5():
+    p = synth.uniform_1e5(k=1)
+    q = synth.random_coo(1006, p.n_rows, p.n_cols, 1_000_000, dup_frac=0.05, dtype=np.float32)
+    print("case add uniform 1e5", flush=True)
+    A, B = assemble_gpu(p), assemble_gpu(q)
+    _add_case(A, B, np.float32)
+    _add_case(A, B, np.float64, out_dtype=torch.float64)
+
+
+def _csc_dev(n_rows, n_cols, col_ptr, row_idx, val):
+    return ops.CSCMatrix(n_rows, n_cols, dev(np.array(col_ptr, np.int32)),
+                         dev(np.array(row_idx, np.int32)), dev(np.array(val, np.float64)),
+                         torch.zeros(2, dtype=torch.int32, device=DEV))
+
+
+def test_add_reports_malformed_inputs():
+    good = _csc_dev(4, 3, [0, 2, 3, 4], [0, 2, 1, 3], [1.0, 2.0, 3.0, 4.0])
+    out_of_range = _csc_dev(4, 3, [0, 2, 3, 4], [0, 2, 1, 4], [1.0, 2.0, 3.0, 4.0])
+    bad_offsets = _csc_dev(4, 3, [0, 3, 2, 4], [0, 2, 1, 3], [1.0, 2.0, 3.0, 4.0])
+    for bad, exc in ((out_of_range, IndexError), (bad_offsets, ValueError)):
+        with pytest.raises(exc):
+            ops.csc_add(good, bad)
+        with pytest.raises(exc):
+            ops.csc_add(bad, good)
+    C = ops.csc_add(good, good)
+    assert C.values.cpu().tolist() == [2.0, 4.0, 6.0, 8.0]
