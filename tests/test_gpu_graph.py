@@ -66,3 +66,55 @@ def test_graph_replays_equal_eager(fused):
     g.replay()
     ref_pipe.step(row, col, val, X, G)
     _equal(_snap(ref_pipe), _snap(pipe))
+
+
+def test_graph_trace_and_triplet_grad():
+    """trace(A^T B) and the gradient per input triplet recorded into one graph: every replay,
+    with eager work between, equals the eager calls bit for bit (neither allocates, clears
+    memory with a memset or synchronises)."""
+    from paper_1805_03380_amd import _lib, ops
+    p = synth.random_coo(4100, 3000, 2500, 60_000, dup_frac=0.2, dist="normal")
+    q = synth.random_coo(4101, 3000, 2500, 60_000, dup_frac=0.2, dist="normal")
+    A = ops.coo_to_csc(dev(p.row), dev(p.col), dev(p.val), (p.n_rows, p.n_cols))
+    B = ops.coo_to_csc(dev(q.row), dev(q.col), dev(q.val), (q.n_rows, q.n_cols))
+    rng = np.random.Generator(np.random.PCG64(4102))
+    G = dev(rng.standard_normal((p.n_rows, 32)))
+    X = dev(rng.standard_normal((p.n_cols, 32)))
+    row, col = dev(p.row), dev(p.col)
+    lib = _lib.load()
+    wb = _lib.ctypes.c_size_t(0)
+    assert lib.spm_csc_trace_atb_workspace(p.n_cols, _lib.ctypes.byref(wb)) == _lib.OK
+    ws = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=DEV)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    info = torch.empty(2, dtype=torch.int32, device=DEV)
+    dv = torch.empty(p.nnz_in, dtype=torch.float64, device=DEV)
+
+    def calls(stream):
+        assert lib.spm_csc_trace_atb(
+            A.n_rows, A.n_cols, A.nnz_cap, A.col_ptr.data_ptr(), A.row_idx_buf.data_ptr(),
+            A.values_buf.data_ptr(), B.nnz_cap, B.col_ptr.data_ptr(), B.row_idx_buf.data_ptr(),
+            B.values_buf.data_ptr(), _lib.F64, out.data_ptr(), info.data_ptr(), ws.data_ptr(),
+            ws.numel(), stream) == _lib.OK
+        assert lib.spm_coo_triplet_grad(
+            p.n_rows, p.n_cols, p.nnz_in, 32, row.data_ptr(), col.data_ptr(), _lib.F64,
+            G.data_ptr(), 32, X.data_ptr(), 32, _lib.F64, dv.data_ptr(), _lib.F64,
+            stream) == _lib.OK
+
+    s = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(s):
+        calls(s.cuda_stream)
+    torch.cuda.synchronize(DEV)
+    want = (out.clone(), info.clone(), dv.clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        calls(s.cuda_stream)
+    for i in range(3):
+        out.fill_(float(i + 7))
+        info.fill_(-1)
+        dv.fill_(1.5)
+        torch.cuda.synchronize(DEV)
+        g.replay()
+        torch.cuda.synchronize(DEV)
+        assert torch.equal(_bits(out), _bits(want[0])), i
+        assert torch.equal(info, want[1]), i
+        assert torch.equal(_bits(dv), _bits(want[2])), i
