@@ -447,7 +447,24 @@ def main():
             import oracle
             cpu_ms = oracle_ms(lambda: oracle.triplet_grad(p.n_rows, p.n_cols, p.row, p.col,
                                                            p.G, p.X))
-        tgrad = {"cpu_oracle_ms": cpu_ms,
+        # the dvalues form: each triplet reads the step's dvalues at its location's slot
+        A_t = pipe.csc()
+        dval_t = pipe.dval
+        dval_code = _lib.F64 if dval_t.dtype == torch.float64 else _lib.F32
+
+        def run_tgrad_csc():
+            for _ in range(args.steps):
+                lib.spm_coo_triplet_grad_csc(p.n_rows, p.n_cols, p.nnz_in, k_, row.data_ptr(),
+                                             col.data_ptr(), A_t.nnz_cap, A_t.col_ptr.data_ptr(),
+                                             A_t.row_idx_buf.data_ptr(), dval_t.data_ptr(),
+                                             dval_code, vt_code, G.data_ptr(), G.stride(0),
+                                             X.data_ptr(), X.stride(0), x_code,
+                                             tg_dv.data_ptr(), _lib.F32, stream.cuda_stream)
+        run_tgrad_csc()
+        tgc_ms = timed(run_tgrad_csc)
+        tgrad = {"cpu_oracle_ms": cpu_ms, "ms_from_dvalues": tgc_ms,
+                 "from_dvalues": "each triplet reads the adjoint's dvalue at its slot (the "
+                                 "dot product only where the location summed to zero)",
                  "workload": "dL/dv for the %d input triplets of the step, k=%d" % (p.nnz_in, k_),
                  "ms": tg_ms, "triplets_per_s": p.nnz_in / (tg_ms * 1e-3),
                  "compulsory_bytes": tg_c, "compulsory_GBps": tg_c / (tg_ms * 1e-3) / 1e9,

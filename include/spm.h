@@ -268,6 +268,20 @@ spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, 
                                 const void *G, int64_t ldg, const void *X, int64_t ldx,
                                 spm_dtype x_type, void *dv, spm_dtype dv_type, void *stream);
 
+/* The same gradients read from the adjoint's dvalues (spm_csc_spmm_backward on the CSC that
+ * assembly produced from these triplets: col_ptr, row_idx of capacity nnz_cap, dval of type
+ * dval_type F64 or F32): a binary search in the triplet's column finds its slot p and
+ * dv[t] = dval[p] (rounded to dv_type).  A triplet whose location is not stored (its values
+ * summed to zero) gets the dot product as in spm_coo_triplet_grad, one outside the matrix 0.
+ * Only dropped locations read rows of G and X, so this form costs a lookup per triplet. */
+spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
+                                    const int32_t *row, const int32_t *col, int64_t nnz_cap,
+                                    const int32_t *col_ptr, const int32_t *row_idx,
+                                    const void *dval, spm_dtype dval_type, spm_dtype val_type,
+                                    const void *G, int64_t ldg, const void *X, int64_t ldx,
+                                    spm_dtype x_type, void *dv, spm_dtype dv_type,
+                                    void *stream);
+
 /* ------------------------------------------------------------------------------------------
  * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a

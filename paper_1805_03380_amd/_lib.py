@@ -96,6 +96,10 @@ SIGNATURES = {
     "spm_csc_add": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                    ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                    ctypes.c_size_t, c_p]),
+    "spm_coo_triplet_grad_csc": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, c_i64,
+                                                c_p, c_p, c_p, ctypes.c_int, ctypes.c_int, c_p,
+                                                c_i64, c_p, c_i64, ctypes.c_int, c_p,
+                                                ctypes.c_int, c_p]),
     "spm_csc_insert_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_insert": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                       ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,

@@ -4,9 +4,9 @@ CscSpmm: forward Y = A.X (spm_csc_spmm), backward dX = A^T.G and dvalues = G.X^T
 A's pattern (spm_csc_spmm_backward); gradients with respect to the stored CSC values and X,
 the pattern (col_ptr, row_idx) constant.
 
-CooSpmm: assembly and product together, Y = assemble(row, col, val).X; the backward gives
-every input triplet its gradient (spm_coo_triplet_grad), duplicates and locations that summed
-to zero included, and dX from the adjoint.
+CooSpmm: assembly and product together, Y = assemble(row, col, val).X; the backward runs the
+adjoint once (dX and the dvalues) and gives every input triplet the dvalue of its location
+(spm_coo_triplet_grad_csc), duplicates and locations that summed to zero included.
 """
 from __future__ import annotations
 
@@ -63,13 +63,15 @@ class CooSpmm(torch.autograd.Function):
         need_v, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         G = G.to(X.dtype) if G.dtype != X.dtype else G
         G = G.contiguous()
-        dval = dX = None
+        if not (need_v or need_x):
+            return None, None, None, None, None
+        # one adjoint pass gives dX and the dvalues; each triplet then reads its location's
+        # dvalue (the dot product only where the location summed to zero)
+        dX, dslot = ops.spmm_backward(ctx.A, G, X, need_dX=need_x, need_dval=need_v,
+                                      dx_dtype=X.dtype, dval_dtype=torch.float64)
+        dval = None
         if need_v:
-            dval = ops.triplet_grad(row, col, G, X, ctx.shape,
-                                    val_dtype=ctx.A.values_buf.dtype).to(ctx.val_dtype)
-        if need_x:
-            dX, _ = ops.spmm_backward(ctx.A, G, X, need_dX=True, need_dval=False,
-                                      dx_dtype=X.dtype)
+            dval = ops.triplet_grad_csc(row, col, ctx.A, dslot, G, X).to(ctx.val_dtype)
         return dval, dX, None, None, None
 
 

@@ -74,6 +74,76 @@ __global__ __launch_bounds__(kTgNT) void k_triplet_grad(
   }
 }
 
+// The same gradients, read from the adjoint's dvalues where the triplet's location is stored
+// in the assembled CSC (col_ptr, row_idx of capacity nnz_cap, rows increasing down each
+// column).  One lane per triplet: a binary search in the triplet's column finds its slot p
+// and dv[t] = dval[p], bit for bit; a triplet outside the matrix gets 0.  A triplet whose
+// location was dropped (its values summed to zero) has no slot: the wave then computes the
+// dot product above for it, on its first GW lanes (the same lane pieces and group_sum tree),
+// one such triplet at a time.
+template <typename XT, typename ACC, int GW, typename DT>
+__global__ __launch_bounds__(kTgNT) void k_triplet_grad_csc(
+    int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* __restrict__ row,
+    const int32_t* __restrict__ col, int64_t nnz_cap, const int32_t* __restrict__ col_ptr,
+    const int32_t* __restrict__ row_idx, const DT* __restrict__ dval,
+    const XT* __restrict__ Gm, int64_t ldg, bool gal, const XT* __restrict__ X, int64_t ldx,
+    bool xal, void* __restrict__ dv, bool dv_f64) {
+  const int lane = threadIdx.x % kWave;
+  const int nch = (int)((k + 4 * GW - 1) / (4 * GW));
+  const int64_t stride = (int64_t)gridDim.x * kTgNT;
+  for (int64_t base = (int64_t)blockIdx.x * kTgNT + (threadIdx.x - lane); base < nnz_in;
+       base += stride) {
+    const int64_t t = base + lane;
+    const bool live = t < nnz_in;
+    const int32_t r = live ? row[t] : -1;
+    const int32_t c = live ? col[t] : -1;
+    const bool ok = r >= 0 && c >= 0 && (int64_t)r < n_rows && (int64_t)c < n_cols;
+    int64_t lo = ok ? col_ptr[c] : 0;
+    int64_t hi = ok ? col_ptr[c + 1] : 0;
+    lo = lo < 0 ? 0 : (lo > nnz_cap ? nnz_cap : lo);
+    hi = hi < lo ? lo : (hi > nnz_cap ? nnz_cap : hi);
+    // [lo, hi) shrinks to the one slot whose row can equal r: rows before lo are below r,
+    // and once hi has moved, the slot before hi holds a row not below r
+    while (hi - lo > 1) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (row_idx[mid - 1] < r) lo = mid;
+      else hi = mid;
+    }
+    const bool hit = ok && lo < hi && row_idx[lo] == r;
+    if (live && (hit || !ok)) {
+      const double v = hit ? (double)dval[lo] : 0.0;
+      if (dv_f64) static_cast<double*>(dv)[t] = v;
+      else static_cast<float*>(dv)[t] = (float)v;
+    }
+    // dropped locations: the dot product, one triplet at a time on lanes 0 .. GW-1
+    uint64_t miss = __ballot(live && ok && !hit);
+    while (miss) {
+      const int j = __ffsll((unsigned long long)miss) - 1;
+      miss &= miss - 1;
+      const int32_t rj = __shfl(r, j, kWave);
+      const int32_t cj = __shfl(c, j, kWave);
+      if (lane < GW) {
+        ACC d = (ACC)0;
+        for (int m = 0; m < nch; ++m) {
+          const int64_t j0 = ((int64_t)m * GW + lane) * 4;
+          const int avail = j0 >= k ? 0 : (int)((k - j0) < 4 ? (k - j0) : 4);
+          const int64_t off = avail ? j0 : 0;
+          ACC g[4], x[4];
+          load4<ACC>(Gm + (int64_t)rj * ldg + off, avail, gal, g);
+          load4<ACC>(X + (int64_t)cj * ldx + off, avail, xal, x);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) d = fma_acc<ACC>(g[e], x[e], d);
+        }
+        d = group_sum<GW, ACC>(d);
+        if (lane == 0) {
+          if (dv_f64) static_cast<double*>(dv)[base + j] = (double)d;
+          else static_cast<float*>(dv)[base + j] = (float)d;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace spm
 
 namespace {
@@ -131,6 +201,49 @@ void launch_tg_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_
 #undef SPM_TG
 }
 
+template <typename XT, typename ACC, int GW>
+void launch_tg_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* row,
+                   const int32_t* col, int64_t nnz_cap, const int32_t* col_ptr,
+                   const int32_t* row_idx, const void* dval, bool dval_f64, const void* Gm,
+                   int64_t ldg, bool gal, const void* X, int64_t ldx, bool xal, void* dv,
+                   bool dv_f64, hipStream_t s) {
+  int64_t grid = (nnz_in + kTgNT - 1) / kTgNT;  // one lane per triplet
+  const int64_t cap = (int64_t)device_cus() * 32;
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+  const XT* g = static_cast<const XT*>(Gm);
+  const XT* x = static_cast<const XT*>(X);
+  if (dval_f64)
+    k_triplet_grad_csc<XT, ACC, GW, double><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
+        n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx,
+        static_cast<const double*>(dval), g, ldg, gal, x, ldx, xal, dv, dv_f64);
+  else
+    k_triplet_grad_csc<XT, ACC, GW, float><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
+        n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx,
+        static_cast<const float*>(dval), g, ldg, gal, x, ldx, xal, dv, dv_f64);
+}
+
+template <typename XT, typename ACC>
+void launch_tg_csc_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
+                      const int32_t* row, const int32_t* col, int64_t nnz_cap,
+                      const int32_t* col_ptr, const int32_t* row_idx, const void* dval,
+                      bool dval_f64, const void* Gm, int64_t ldg, bool gal, const void* X,
+                      int64_t ldx, bool xal, void* dv, bool dv_f64, hipStream_t s) {
+#define SPM_TGC(W)                                                                          \
+  launch_tg_csc<XT, ACC, W>(n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx, \
+                            dval, dval_f64, Gm, ldg, gal, X, ldx, xal, dv, dv_f64, s)
+  switch (gw) {
+    case 1: SPM_TGC(1); break;
+    case 2: SPM_TGC(2); break;
+    case 4: SPM_TGC(4); break;
+    case 8: SPM_TGC(8); break;
+    case 16: SPM_TGC(16); break;
+    case 32: SPM_TGC(32); break;
+    default: SPM_TGC(64); break;
+  }
+#undef SPM_TGC
+}
+
 }  // namespace
 
 extern "C" {
@@ -170,6 +283,49 @@ spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, 
   else
     launch_tg_gw<bf16_t, float>(gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx,
                                 xal, dv, f64, s);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPM_OK : SPM_EHIP;
+}
+
+spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
+                                    const int32_t* row, const int32_t* col, int64_t nnz_cap,
+                                    const int32_t* col_ptr, const int32_t* row_idx,
+                                    const void* dval, spm_dtype dval_type, spm_dtype val_type,
+                                    const void* Gm, int64_t ldg, const void* X, int64_t ldx,
+                                    spm_dtype x_type, void* dv, spm_dtype dv_type,
+                                    void* stream) {
+  if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || nnz_cap < 0) return SPM_EINVAL;
+  if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz_in) || !fits_i32(nnz_cap) ||
+      n_rows == INT32_MAX || n_cols == INT32_MAX)
+    return SPM_EOVERFLOW;
+  if (k < 1 || ldg < k || ldx < k) return SPM_EINVAL;
+  if (!fits_i32(k)) return SPM_EOVERFLOW;
+  if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (dval_type != SPM_F64 && dval_type != SPM_F32) return SPM_EDTYPE;
+  if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
+  if (dv_type != SPM_F64 && dv_type != SPM_F32) return SPM_EDTYPE;
+  if (nnz_in > 0 && (!row || !col || !dv || !col_ptr)) return SPM_EINVAL;
+  if (nnz_cap > 0 && (!row_idx || !dval)) return SPM_EINVAL;
+  if ((n_rows > 0 && !Gm) || (n_cols > 0 && !X)) return SPM_EINVAL;
+  if (nnz_in == 0) return SPM_OK;
+  const int gw = group_width(k);
+  const bool gal = aligned_to(Gm, 4 * dsize(x_type)) && (ldg % 4) == 0;
+  const bool xal = aligned_to(X, 4 * dsize(x_type)) && (ldx % 4) == 0;
+  const bool f64 = dv_type == SPM_F64, d64 = dval_type == SPM_F64;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (x_type == SPM_F64)
+    launch_tg_csc_gw<double, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
+                                      row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
+  else if (x_type == SPM_F32)
+    launch_tg_csc_gw<float, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
+                                     row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
+  else if (val_type == SPM_F64)
+    launch_tg_csc_gw<bf16_t, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
+                                      row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
+  else
+    launch_tg_csc_gw<bf16_t, float>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
+                                     row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPM_OK : SPM_EHIP;
 }

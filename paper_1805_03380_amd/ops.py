@@ -362,6 +362,43 @@ def triplet_grad(row: torch.Tensor, col: torch.Tensor, G: torch.Tensor, X: torch
     return dv[:n]
 
 
+def triplet_grad_csc(row: torch.Tensor, col: torch.Tensor, A: CSCMatrix, dval: torch.Tensor,
+                     G: torch.Tensor, X: torch.Tensor,
+                     out_dtype: torch.dtype | None = None) -> torch.Tensor:
+    """The gradient per input triplet read from the adjoint's dvalues `dval` of the CSC `A`
+    assembled from these triplets (spm_coo_triplet_grad_csc): dv[t] = dval[slot of t], the dot
+    product only where the location was dropped."""
+    G2 = G.reshape(-1, 1) if G.dim() == 1 else G
+    X2 = X.reshape(-1, 1) if X.dim() == 1 else X
+    _require_cuda(row, col, A.col_ptr, dval, G2, X2)
+    if G2.dtype != X2.dtype:
+        raise ValueError("G and X must share one element type")
+    if G2.shape[0] != A.n_rows or X2.shape[0] != A.n_cols or G2.shape[1] != X2.shape[1]:
+        raise ValueError("G %s and X %s do not fit a %dx%d matrix" % (tuple(G2.shape),
+                         tuple(X2.shape), A.n_rows, A.n_cols))
+    if G2.stride(1) != 1:
+        G2 = G2.contiguous()
+    if X2.stride(1) != 1:
+        X2 = X2.contiguous()
+    if row.dtype != torch.int32 or col.dtype != torch.int32:
+        raise ValueError("row and col must be int32")
+    n = int(row.shape[0])
+    cap = A.nnz_cap
+    if out_dtype is None:
+        out_dtype = dval.dtype
+    dv = torch.empty(max(n, 1), dtype=out_dtype, device=row.device)
+    lib = _lib.load()
+    st = lib.spm_coo_triplet_grad_csc(A.n_rows, A.n_cols, n, int(X2.shape[1]), _ptr(row),
+                                      _ptr(col), cap, _ptr(A.col_ptr),
+                                      _ptr(A.row_idx_buf) if cap else None,
+                                      _ptr(dval) if cap else None, _dtype_code(dval.dtype),
+                                      _dtype_code(A.values_buf.dtype), _ptr(G2), G2.stride(0),
+                                      _ptr(X2), X2.stride(0), _dtype_code(X2.dtype), _ptr(dv),
+                                      _dtype_code(out_dtype), _stream(row.device))
+    _lib.check(st, "spm_coo_triplet_grad_csc")
+    return dv[:n]
+
+
 def rowvec_spmm(V: torch.Tensor, A: CSCMatrix, out_dtype: torch.dtype | None = None):
     """W = V.A for row vectors V (n_rows, or m x n_rows for m of them): the product of Section
     3's use case (iv) written as in Fig. 1.  It is the column walk of the adjoint with the

@@ -215,6 +215,18 @@ def test_host_validation_rejects_before_launch():
     assert tg(row=None) == _lib.EINVAL
     assert tg(dv=None) == _lib.EINVAL
 
+    def tgc(n=8, cap=8, cp=fake, ri=fake, dvt=_lib.F64, k=4):
+        return lib.spm_coo_triplet_grad_csc(4, 4, n, k, fake, fake, cap, cp, ri, fake, dvt,
+                                            _lib.F32, fake, 4, fake, 4, _lib.F32, fake,
+                                            _lib.F32, None)
+
+    assert tgc(n=0) == _lib.OK
+    assert tgc(k=0) == _lib.EINVAL
+    assert tgc(cap=-1) == _lib.EINVAL
+    assert tgc(cp=None) == _lib.EINVAL
+    assert tgc(ri=None) == _lib.EINVAL
+    assert tgc(dvt=_lib.BF16) == _lib.EDTYPE
+
 
 def test_tuning_roundtrip():
     lib = _lib_or_build()

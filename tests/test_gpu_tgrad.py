@@ -132,3 +132,47 @@ def test_coo_spmm_gradcheck():
     assert torch.autograd.gradcheck(
         lambda v, x: autograd.coo_spmm(r, c, v, x, (n_rows, n_cols)), (val, X),
         eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+@pytest.mark.parametrize("k", [1, 16, 64, 100])
+def test_triplet_grad_csc_reads_dvalues(k):
+    """The dvalues form: a triplet whose location is stored gets the adjoint's dvalue there bit
+    for bit; a dropped location gets the dot product of the direct form bit for bit; outside
+    the matrix 0; all within the bound of the oracle."""
+    p, G, X = _with_specials(2600 + k, 1500, 1100, 30_000, k)
+    inside = (p.row >= 0) & (p.row < p.n_rows) & (p.col >= 0) & (p.col < p.n_cols)
+    row, col = dev(p.row), dev(p.col)
+    Gd, Xd = dev(G), dev(X)
+    A = ops.coo_to_csc(row, col, dev(p.val), (p.n_rows, p.n_cols), sync=False)
+    info = A.info.cpu()
+    assert int(info[1]) == oracle.EBOUNDS  # the out-of-range triplets, skipped
+    A._nnz = int(info[0])
+    _, dval = ops.spmm_backward(A, Gd, Xd, need_dX=False)
+    dv = ops.triplet_grad_csc(row, col, A, dval, Gd, Xd)
+    direct = ops.triplet_grad(row, col, Gd, Xd, (p.n_rows, p.n_cols), val_dtype=torch.float64)
+    cp = A.col_ptr.cpu().numpy()
+    ri = A.row_idx.cpu().numpy()
+    key = np.repeat(np.arange(p.n_cols, dtype=np.int64), np.diff(cp)) * p.n_rows + ri
+    tkey = p.col.astype(np.int64) * p.n_rows + p.row
+    slot = np.searchsorted(key, tkey)
+    slot_c = np.minimum(slot, max(len(key) - 1, 0))
+    stored = inside & (slot < len(key)) & (key[slot_c] == tkey)
+    got = dv.cpu().numpy()
+    assert np.array_equal(got[stored].view(np.int64), dval.cpu().numpy()[slot[stored]].view(np.int64))
+    dropped = inside & ~stored
+    assert dropped.sum() >= 2  # the cancelling pair
+    assert np.array_equal(got[dropped].view(np.int64), direct.cpu().numpy()[dropped].view(np.int64))
+    assert np.all(got[~inside] == 0)
+    want, S = oracle.triplet_grad(p.n_rows, p.n_cols, p.row, p.col, G, X)
+    assert_close(dv, want, S, k, torch.float64, what="csc form k=%d" % k)
+
+
+def test_triplet_grad_csc_uniform_1e5():
+    p = synth.uniform_1e5()
+    row, col = dev(p.row), dev(p.col)
+    Gd, Xd = dev(p.G), dev(p.X)
+    A = ops.coo_to_csc(row, col, dev(p.val), (p.n_rows, p.n_cols))
+    _, dval = ops.spmm_backward(A, Gd, Xd, need_dX=False, dval_dtype=torch.float64)
+    dv = ops.triplet_grad_csc(row, col, A, dval, Gd, Xd)
+    want, S = oracle.triplet_grad(p.n_rows, p.n_cols, p.row, p.col, p.G, p.X)
+    assert_close(dv, want, S, 64, torch.float64, what="csc form uniform")
