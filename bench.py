@@ -101,6 +101,34 @@ def cpu_baseline(p, seconds):
                        " workload, k=64, binary64 oracle, single thread, %.1f s" % (reps, el))
 
 
+def cpu_all_cores(p, seconds, threads):
+    """The same oracle passes on all the host cores given: `threads` Python threads each run
+    whole passes (the oracle's C code runs without the interpreter lock) on the shared
+    read-only inputs; the rate is the total over the threads."""
+    import threading
+    import oracle
+    done = [0] * threads
+    t0 = time.perf_counter()
+
+    def work(i):
+        while time.perf_counter() - t0 < seconds:
+            st, A = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+            oracle.spmm(A, p.X)
+            oracle.spmm_backward(A, p.G, p.X)
+            done[i] += 1
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    el = time.perf_counter() - t0
+    reps = sum(done)
+    return dict(value=p.nnz_in * reps / el, unit="nnz/s", cores=threads, kind="oracle",
+                sample="%d full passes on %d threads (one independent pass per thread) of the "
+                       "1e6-triplet workload, k=64, binary64 oracle, %.1f s" % (reps, threads, el))
+
+
 def batched_vs_single(bt, dtype_name="float32", reps_batched=5, reps_single=3):
     """The 4096-matrix workload: the batched entry point (one grouping launch, a prefix launch,
     two flat product launches) vs 4096 x 4 per-matrix calls of the
@@ -633,6 +661,9 @@ def main():
         out["batched_vs_single"]["generate_s"] = gen_s
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        # every host core this process may use (the scheduler's set), at most 16
+        n_thr = max(1, min(16, len(os.sched_getaffinity(0))))
+        out["cpu_baseline_all_cores"] = cpu_all_cores(p, args.cpu_seconds, n_thr)
         out["cpu_baseline"]["host"] = host_cpu()
         out["cpu_rbt_context"] = rbt_context(p)
     print(json.dumps(out), flush=True)
