@@ -414,6 +414,38 @@ def main():
                   "new_triplets_per_s": q.nnz_in / (i_ms * 1e-3),
                   "compulsory_bytes": i_bytes,
                   "compulsory_GBps": i_bytes / (i_ms * 1e-3) / 1e9}
+        # the sum A + B with B the same 10^5 triplets assembled (spm_csc_add)
+        Bq = ops.coo_to_csc(qr, qc, qv, (p.n_rows, p.n_cols))
+        S = ops.csc_add(A, Bq)  # warm-up, and the buffers for the timed calls
+        s_out = (S.col_ptr, S.row_idx_buf, S.values_buf, S.info)
+
+        def run_add():
+            for _ in range(args.steps):
+                lib.spm_csc_add(A.n_rows, A.n_cols, cap_a, A.col_ptr.data_ptr(),
+                                A.row_idx_buf.data_ptr(), A.values_buf.data_ptr(), Bq.nnz_cap,
+                                Bq.col_ptr.data_ptr(), Bq.row_idx_buf.data_ptr(),
+                                Bq.values_buf.data_ptr(), ops._dtype_code(qv.dtype),
+                                s_out[0].data_ptr(), s_out[1].data_ptr(), s_out[2].data_ptr(),
+                                ops._dtype_code(s_out[2].dtype), s_out[3].data_ptr(),
+                                S._ws.data_ptr(), S._ws.numel(), stream.cuda_stream)
+        a_ms = timed(run_add)
+        nnz_s, st_s = (int(x) for x in s_out[3].cpu())
+        if st_s:
+            raise RuntimeError("spm_csc_add reported status %d" % st_s)
+        nb = Bq.nnz
+        a_bytes = (2 * 4 * (p.n_cols + 1) + (nnz + nb) * (4 + sv) + 4 * (p.n_cols + 1)
+                   + nnz_s * (4 + sv))
+        cpu_ms = None
+        if not args.no_cpu:
+            import oracle
+            Ah, Bh = host_csc(A), host_csc(Bq)
+            cpu_ms = oracle_ms(lambda: oracle.csc_add(Ah, Bh))
+        insert["sum"] = {"workload": "A + B, A the assembled 1e5 x 1e5 CSC, B the same 10^5 "
+                                     "triplets assembled", "nnz_a": nnz, "nnz_b": nb,
+                         "nnz_out": nnz_s, "ms": a_ms, "cpu_oracle_ms": cpu_ms,
+                         "elements_per_s": (nnz + nb) / (a_ms * 1e-3),
+                         "compulsory_bytes": a_bytes,
+                         "compulsory_GBps": a_bytes / (a_ms * 1e-3) / 1e9}
 
     # transpose X.t() (Table 1) of the step's CSC, and the row-vector product V.A (Fig. 1)
     transpose = None
