@@ -183,7 +183,10 @@ spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, 
  *   info       int32[2]: info[0] = nnz of the sum, info[1] = 0, SPM_EINVAL (a malformed
  *              CSC) or SPM_EBOUNDS (a stored row outside the matrix).
  *   ws         at least spm_csc_add_workspace() bytes, 256-byte aligned.
- * n_cols must be at least 1 (SPM_EINVAL otherwise, as for spm_csc_insert). */
+ * n_cols must be at least 1 (SPM_EINVAL otherwise, as for spm_csc_insert).
+ * With short columns (capacities at most 64 per column on average) the columns are merged
+ * directly, and rows not increasing down a column are also reported as SPM_EINVAL; otherwise
+ * B's elements go through the insertion path.  Both give the same bits. */
 spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t *a_col_ptr,
                        const int32_t *a_row_idx, const void *a_val, int64_t b_cap,
                        const int32_t *b_col_ptr, const int32_t *b_row_idx, const void *b_val,

@@ -11,6 +11,7 @@
 #include "spm_assemble.h"
 #include "spm_spmm.h"
 #include "spm_batch.h"
+#include "spm_merge.h"
 #include <algorithm>
 #include <vector>
 
@@ -995,13 +996,74 @@ spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
   return launch_status();
 }
 
+}  // extern "C"
+
+namespace {
+
+// A + B by the direct column merge (spm_merge.h) when the columns are short: at most
+// kAddMergeMaxAvg stored elements per column on average (from the capacities); longer columns
+// take the insertion path, whose work does not grow with the column length.
+constexpr int64_t kAddMergeMaxAvg = 64;
+
+bool add_uses_merge(int64_t n_cols, int64_t a_cap, int64_t b_cap) {
+  return n_cols > 0 && a_cap + b_cap <= kAddMergeMaxAvg * n_cols;
+}
+
+struct MergeLayout {
+  size_t scan_state, ticket, flag, zero_bytes, counts, total;
+};
+
+// The first region (look-back states, the scan ticket, the status flag) is zeroed by one
+// kernel at the start of every call.
+MergeLayout merge_layout(int64_t n_cols) {
+  MergeLayout L;
+  Carve c;
+  L.scan_state = c.take(sizeof(uint64_t) * (size_t)ceil_div(n_cols > 0 ? n_cols : 1, kScanTile));
+  L.ticket = c.take(sizeof(uint32_t) * 4);
+  L.flag = c.take(sizeof(uint32_t) * 4);
+  L.zero_bytes = c.off;
+  L.counts = c.take(sizeof(uint32_t) * (size_t)(n_cols > 0 ? n_cols : 1));
+  L.total = c.off;
+  return L;
+}
+
+template <typename VT>
+void add_merge_t(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a_cp,
+                 const int32_t* a_ri, const VT* a_v, int64_t b_cap, const int32_t* b_cp,
+                 const int32_t* b_ri, const VT* b_v, int32_t* col_ptr, int32_t* row_idx,
+                 void* val_out, int out_f64, int32_t* info, char* w, const MergeLayout& L,
+                 hipStream_t s) {
+  uint64_t* state = reinterpret_cast<uint64_t*>(w + L.scan_state);
+  uint32_t* ticket = reinterpret_cast<uint32_t*>(w + L.ticket);
+  uint32_t* flag = reinterpret_cast<uint32_t*>(w + L.flag);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
+  const int cap = cu_count() * 16;
+  k_zero2<<<dim3(1), dim3(kNT), 0, s>>>(reinterpret_cast<uint32_t*>(w),
+                                         (int64_t)(L.zero_bytes / 4), nullptr, 0);
+  const int grid = grid_for(n_cols, kNT, cap);
+  k_add_count<kNT, VT><<<dim3(grid), dim3(kNT), 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, a_v,
+                                                        b_cap, b_cp, b_ri, b_v, counts, flag);
+  launch_scan<kNT, kScanIPT>(counts, n_cols, col_ptr, state, ticket, s);
+  k_add_write<kNT, VT><<<dim3(grid), dim3(kNT), 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, a_v,
+                                                        b_cap, b_cp, b_ri, b_v, col_ptr,
+                                                        row_idx, val_out, out_f64);
+  k_add_finish<<<dim3(1), dim3(64), 0, s>>>(n_cols, col_ptr, flag, info, (int32_t)SPM_EINVAL,
+                                            (int32_t)SPM_EBOUNDS);
+}
+
+}  // namespace
+
+extern "C" {
+
 spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, int64_t b_cap,
                                  size_t* ws_bytes) {
   if (!ws_bytes || a_cap < 0 || b_cap < 0) return SPM_EINVAL;
   spm_status st = check_dims(n_rows, n_cols, a_cap);
   if (st != SPM_OK) return st;
   if (!fits_i32(b_cap) || !fits_i32(a_cap + b_cap)) return SPM_EOVERFLOW;
-  *ws_bytes = insert_layout(n_cols, a_cap, b_cap, true).total;
+  *ws_bytes = add_uses_merge(n_cols, a_cap, b_cap)
+                  ? merge_layout(n_cols).total
+                  : insert_layout(n_cols, a_cap, b_cap, true).total;
   return SPM_OK;
 }
 
@@ -1022,12 +1084,29 @@ spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int3
   if (b_cap > 0 && (!b_row_idx || !b_val)) return SPM_EINVAL;
   if (a_cap + b_cap > 0 && (!row_idx || !val_out)) return SPM_EINVAL;
   if (!aligned(ws, 256)) return SPM_EINVAL;
-  const InsertLayout L = insert_layout(n_cols, a_cap, b_cap, true);
-  if (!L.A.pp.ok) return SPM_EINVAL;  // no columns, or more than the partition covers
-  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  if (n_cols == 0) return SPM_EINVAL;  // as for the insertion
   hipStream_t s = static_cast<hipStream_t>(stream);
-  (void)hipGetLastError();
   const int out_f64 = out_type == SPM_F64 ? 1 : 0;
+  if (add_uses_merge(n_cols, a_cap, b_cap)) {
+    const MergeLayout M = merge_layout(n_cols);
+    if (ws_bytes < M.total) return SPM_EWORKSPACE;
+    (void)hipGetLastError();
+    if (val_type == SPM_F64)
+      add_merge_t<double>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
+                          static_cast<const double*>(a_val), b_cap, b_col_ptr, b_row_idx,
+                          static_cast<const double*>(b_val), col_ptr, row_idx, val_out, out_f64,
+                          info, static_cast<char*>(ws), M, s);
+    else
+      add_merge_t<float>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
+                         static_cast<const float*>(a_val), b_cap, b_col_ptr, b_row_idx,
+                         static_cast<const float*>(b_val), col_ptr, row_idx, val_out, out_f64,
+                         info, static_cast<char*>(ws), M, s);
+    return launch_status();
+  }
+  const InsertLayout L = insert_layout(n_cols, a_cap, b_cap, true);
+  if (!L.A.pp.ok) return SPM_EINVAL;  // more than the partition covers
+  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  (void)hipGetLastError();
   // B's slots are the new elements (rows b_row_idx, columns expanded from b_col_ptr)
   if (val_type == SPM_F64)
     insert_t<double>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,

@@ -94,3 +94,31 @@ def test_add_reports_malformed_inputs():
             ops.csc_add(bad, good)
     C = ops.csc_add(good, good)
     assert C.values.cpu().tolist() == [2.0, 4.0, 6.0, 8.0]
+
+
+def _with_capacity(A, cap):
+    """The same CSC in buffers of a larger capacity (the extra slots hold garbage)."""
+    ri = torch.full((cap,), 7, dtype=torch.int32, device=DEV)
+    v = torch.full((cap,), 3.5, dtype=A.values_buf.dtype, device=DEV)
+    ri[:A.nnz] = A.row_idx
+    v[:A.nnz] = A.values
+    return ops.CSCMatrix(A.n_rows, A.n_cols, A.col_ptr.clone(), ri, v, A.info)
+
+
+def test_add_merge_and_insertion_paths_agree():
+    """Short columns take the direct merge, long ones (by capacity) the insertion path: both
+    give the same bits, and both match the oracle."""
+    pa = synth.random_coo(3105, 4000, 3000, 60_000, dup_frac=0.1, dist="normal")
+    pb = synth.random_coo(3106, 4000, 3000, 50_000, dup_frac=0.1, dist="normal")
+    A, B = assemble_gpu(pa), assemble_gpu(pb)
+    C1 = _add_case(A, B)  # average capacity per column well under 64: merge
+    big = 70 * A.n_cols
+    C2 = _add_case(_with_capacity(A, big), _with_capacity(B, big))  # insertion path
+    assert torch.equal(C1.col_ptr, C2.col_ptr) and torch.equal(C1.row_idx, C2.row_idx)
+    assert torch.equal(C1.values.view(torch.int64), C2.values.view(torch.int64))
+
+
+def test_add_long_columns():
+    pa = synth.random_coo(3107, 20_000, 60, 120_000, dup_frac=0.1, dist="normal")
+    pb = synth.random_coo(3108, 20_000, 60, 100_000, dup_frac=0.1, dist="normal")
+    _add_case(assemble_gpu(pa), assemble_gpu(pb))
