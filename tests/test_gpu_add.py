@@ -122,3 +122,13 @@ def test_add_long_columns():
     pa = synth.random_coo(3107, 20_000, 60, 120_000, dup_frac=0.1, dist="normal")
     pb = synth.random_coo(3108, 20_000, 60, 100_000, dup_frac=0.1, dist="normal")
     _add_case(assemble_gpu(pa), assemble_gpu(pb))
+
+
+@pytest.mark.parametrize("shape", [(0, 5), (1, 1), (7, 1), (1, 9)])
+def test_add_degenerate_shapes(shape):
+    n_rows, n_cols = shape
+    n = 0 if n_rows == 0 else min(n_rows * n_cols, 5)
+    pa = synth.random_coo(3109, n_rows, n_cols, n, dup_frac=0.0) if n else synth.COOProblem(
+        "empty", n_rows, n_cols, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    pb = synth.random_coo(3110, n_rows, n_cols, n, dup_frac=0.0) if n else pa
+    _add_case(assemble_gpu(pa), assemble_gpu(pb))
