@@ -295,7 +295,7 @@ def main():
         copy_calibration(args.copy_calib_mib)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
+        print("bench.py runs on one GPU only: it measures the single-GPU kernels "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
