@@ -166,6 +166,71 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
                                size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
+ * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
+ * location the existing value comes first, then the new values in input order, folded in
+ * binary64 and rounded once to out_type; a location whose result compares equal to 0.0 is
+ * not stored.  The result is a new CSC (outputs must not overlap the existing arrays).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Host only.  Workspace of spm_csc_insert for an existing CSC of capacity cap_a and nnz_t new
+ * triplets. */
+spm_status spm_csc_insert_workspace(int64_t n_rows, int64_t n_cols, int64_t cap_a,
+                                    int64_t nnz_t, size_t *ws_bytes);
+
+/* Insert nnz_t triplets (row[t], col[t], val[t]) into the n_rows x n_cols CSC
+ * (a_col_ptr[n_cols+1], a_row_idx / a_val with capacity cap_a; the number of existing
+ * elements a_col_ptr[n_cols] is read on the device).
+ *   val_type   type of a_val and val alike: F64 or F32.
+ *   col_ptr    int32[n_cols + 1], fully written; row_idx / val_out (out_type F64 or F32) have
+ *              capacity cap_a + nnz_t, the first nnz_out entries are written.
+ *   info       int32[2]: info[0] = nnz_out, info[1] = 0, SPM_EBOUNDS (a new triplet, or an
+ *              existing row index, outside the matrix; skipped) or SPM_EINVAL (a_col_ptr not
+ *              monotone, a_col_ptr[0] != 0 or more than cap_a elements).
+ *   ws         at least spm_csc_insert_workspace() bytes, 256-byte aligned.
+ * The existing rows must increase strictly within each column (a valid CSC).  n_cols >= 1;
+ * shapes the assembly's partition does not cover return SPM_EINVAL.  cap_a + nnz_t must fit
+ * in int32 (SPM_EOVERFLOW). */
+spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
+                          const int32_t *a_col_ptr, const int32_t *a_row_idx, const void *a_val,
+                          int64_t nnz_t, const int32_t *row, const int32_t *col, const void *val,
+                          spm_dtype val_type, int32_t *col_ptr, int32_t *row_idx, void *val_out,
+                          spm_dtype out_type, int32_t *info, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Forward product Y = A . X  (Section 3 use case (iv), through the plan of A's pattern).
+ *   val      values of A, val_type F64 or F32, in val_order: CSC order (indexed through
+ *            plan.perm) or plan order (read contiguously; from spm_csc_plan_build).
+ *   X        n_cols x k, x_type F64, F32 or BF16, leading dimension ldx >= k.
+ *   Y        n_rows x k, y_type F64 or F32, leading dimension ldy >= k; fully written
+ *            (rows with no stored element are 0).
+ * Y[r, j] = sum over q in row r, ascending column, of val[perm[q]] * X[col_t[q], j]; the
+ * order of the values changes where they are read from, never the result.
+ * ------------------------------------------------------------------------------------------ */
+spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                        const void *plan, const void *val, spm_dtype val_type,
+                        spm_val_order val_order, const void *X, int64_t ldx, spm_dtype x_type,
+                        void *Y, int64_t ldy, spm_dtype y_type, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Adjoint of Y = A . X for a loss with dL/dY = G (n_rows x k):
+ *   dX[c, j]  = sum over p in column c (ascending row) of val[p] * G[row_idx[p], j]
+ *               -- A^T . G by a walk down each CSC column, the traversal of the row-vector
+ *               times CSC product of Fig. 1;
+ *   dval[p]   = sum_j G[row_idx[p], j] * X[c, j]  -- G . X^T sampled on A's pattern.
+ * G and X share g_type = x_type (F64, F32 or BF16).  dX (n_cols x k, ld lddx, dx_type F64 or
+ * F32) and dval (nnz elements, dval_type F64 or F32) may each be NULL to skip that output;
+ * nnz = col_ptr[n_cols] is read on the device and clamped to nnz_cap.
+ * ------------------------------------------------------------------------------------------ */
+spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
+                                 const int32_t *col_ptr, const int32_t *row_idx,
+                                 const void *val, spm_dtype val_type, const void *G,
+                                 int64_t ldg, const void *X, int64_t ldx, spm_dtype x_type,
+                                 void *dX, int64_t lddx, spm_dtype dx_type, void *dval,
+                                 spm_dtype dval_type, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Sum A + B of two CSCs of one shape, by the merge of batch insertion: B's stored elements are
  * inserted into A, so a location stored in both holds A's value plus B's (binary64, A's
  * first), and a 0.0 result is not stored.
@@ -284,71 +349,6 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
                                     const void *G, int64_t ldg, const void *X, int64_t ldx,
                                     spm_dtype x_type, void *dv, spm_dtype dv_type,
                                     void *stream);
-
-/* ------------------------------------------------------------------------------------------
- * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
- * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
- * location the existing value comes first, then the new values in input order, folded in
- * binary64 and rounded once to out_type; a location whose result compares equal to 0.0 is
- * not stored.  The result is a new CSC (outputs must not overlap the existing arrays).
- * ------------------------------------------------------------------------------------------ */
-
-/* Host only.  Workspace of spm_csc_insert for an existing CSC of capacity cap_a and nnz_t new
- * triplets. */
-spm_status spm_csc_insert_workspace(int64_t n_rows, int64_t n_cols, int64_t cap_a,
-                                    int64_t nnz_t, size_t *ws_bytes);
-
-/* Insert nnz_t triplets (row[t], col[t], val[t]) into the n_rows x n_cols CSC
- * (a_col_ptr[n_cols+1], a_row_idx / a_val with capacity cap_a; the number of existing
- * elements a_col_ptr[n_cols] is read on the device).
- *   val_type   type of a_val and val alike: F64 or F32.
- *   col_ptr    int32[n_cols + 1], fully written; row_idx / val_out (out_type F64 or F32) have
- *              capacity cap_a + nnz_t, the first nnz_out entries are written.
- *   info       int32[2]: info[0] = nnz_out, info[1] = 0, SPM_EBOUNDS (a new triplet, or an
- *              existing row index, outside the matrix; skipped) or SPM_EINVAL (a_col_ptr not
- *              monotone, a_col_ptr[0] != 0 or more than cap_a elements).
- *   ws         at least spm_csc_insert_workspace() bytes, 256-byte aligned.
- * The existing rows must increase strictly within each column (a valid CSC).  n_cols >= 1;
- * shapes the assembly's partition does not cover return SPM_EINVAL.  cap_a + nnz_t must fit
- * in int32 (SPM_EOVERFLOW). */
-spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
-                          const int32_t *a_col_ptr, const int32_t *a_row_idx, const void *a_val,
-                          int64_t nnz_t, const int32_t *row, const int32_t *col, const void *val,
-                          spm_dtype val_type, int32_t *col_ptr, int32_t *row_idx, void *val_out,
-                          spm_dtype out_type, int32_t *info, void *ws, size_t ws_bytes,
-                          void *stream);
-
-/* ------------------------------------------------------------------------------------------
- * Forward product Y = A . X  (Section 3 use case (iv), through the plan of A's pattern).
- *   val      values of A, val_type F64 or F32, in val_order: CSC order (indexed through
- *            plan.perm) or plan order (read contiguously; from spm_csc_plan_build).
- *   X        n_cols x k, x_type F64, F32 or BF16, leading dimension ldx >= k.
- *   Y        n_rows x k, y_type F64 or F32, leading dimension ldy >= k; fully written
- *            (rows with no stored element are 0).
- * Y[r, j] = sum over q in row r, ascending column, of val[perm[q]] * X[col_t[q], j]; the
- * order of the values changes where they are read from, never the result.
- * ------------------------------------------------------------------------------------------ */
-spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
-                        const void *plan, const void *val, spm_dtype val_type,
-                        spm_val_order val_order, const void *X, int64_t ldx, spm_dtype x_type,
-                        void *Y, int64_t ldy, spm_dtype y_type, void *stream);
-
-/* ------------------------------------------------------------------------------------------
- * Adjoint of Y = A . X for a loss with dL/dY = G (n_rows x k):
- *   dX[c, j]  = sum over p in column c (ascending row) of val[p] * G[row_idx[p], j]
- *               -- A^T . G by a walk down each CSC column, the traversal of the row-vector
- *               times CSC product of Fig. 1;
- *   dval[p]   = sum_j G[row_idx[p], j] * X[c, j]  -- G . X^T sampled on A's pattern.
- * G and X share g_type = x_type (F64, F32 or BF16).  dX (n_cols x k, ld lddx, dx_type F64 or
- * F32) and dval (nnz elements, dval_type F64 or F32) may each be NULL to skip that output;
- * nnz = col_ptr[n_cols] is read on the device and clamped to nnz_cap.
- * ------------------------------------------------------------------------------------------ */
-spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
-                                 const int32_t *col_ptr, const int32_t *row_idx,
-                                 const void *val, spm_dtype val_type, const void *G,
-                                 int64_t ldg, const void *X, int64_t ldx, spm_dtype x_type,
-                                 void *dX, int64_t lddx, spm_dtype dx_type, void *dval,
-                                 spm_dtype dval_type, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Batched path: many independent matrices assembled, planned, multiplied forward and
