@@ -1046,7 +1046,8 @@ void add_merge_t(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a
   launch_scan<kNT, kScanIPT>(counts, n_cols, col_ptr, state, ticket, s);
   k_add_write<kNT, VT><<<dim3(grid), dim3(kNT), 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, a_v,
                                                         b_cap, b_cp, b_ri, b_v, col_ptr,
-                                                        row_idx, val_out, out_f64);
+                                                        row_idx, val_out, out_f64,
+                                                        a_cap + b_cap);
   k_add_finish<<<dim3(1), dim3(64), 0, s>>>(n_cols, col_ptr, flag, info, (int32_t)SPM_EINVAL,
                                             (int32_t)SPM_EBOUNDS);
 }

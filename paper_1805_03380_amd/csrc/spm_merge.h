@@ -97,16 +97,22 @@ __global__ __launch_bounds__(NT) void k_add_write(
     const int32_t* __restrict__ a_ri, const VT* __restrict__ a_v, int64_t b_cap,
     const int32_t* __restrict__ b_cp, const int32_t* __restrict__ b_ri,
     const VT* __restrict__ b_v, const int32_t* __restrict__ col_ptr,
-    int32_t* __restrict__ row_idx, void* __restrict__ val_out, int out_f64) {
+    int32_t* __restrict__ row_idx, void* __restrict__ val_out, int out_f64, int64_t out_cap) {
+  // A malformed pair of CSCs (offsets that pass each column's own checks but overlap between
+  // columns) can make the counts total more than the outputs hold, and the int32 scan of such
+  // counts can wrap: every store is therefore checked against [0, out_cap).  The count pass
+  // has already reported the malformed input.
   for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < n_cols;
        c += (int64_t)gridDim.x * NT) {
     int64_t o = col_ptr[c];
     uint32_t flags = 0;  // already reported by the count pass
     merge_column<VT>(c, n_rows, a_cap, a_cp, a_ri, a_v, b_cap, b_cp, b_ri, b_v, flags,
                      [&](int32_t r, double v) {
-                       row_idx[o] = r;
-                       if (out_f64) static_cast<double*>(val_out)[o] = v;
-                       else static_cast<float*>(val_out)[o] = (float)v;
+                       if (o >= 0 && o < out_cap) {
+                         row_idx[o] = r;
+                         if (out_f64) static_cast<double*>(val_out)[o] = v;
+                         else static_cast<float*>(val_out)[o] = (float)v;
+                       }
                        ++o;
                      });
   }

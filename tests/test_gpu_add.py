@@ -132,3 +132,42 @@ def test_add_degenerate_shapes(shape):
         "empty", n_rows, n_cols, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
     pb = synth.random_coo(3110, n_rows, n_cols, n, dup_frac=0.0) if n else pa
     _add_case(assemble_gpu(pa), assemble_gpu(pb))
+
+
+def test_add_overlapping_offsets_stay_in_bounds():
+    """Offsets [0, cap, 0, cap, ...]: every even column passes its own checks and covers the
+    whole capacity again, so the per-column counts total far more than the outputs hold.  The
+    call must report SPM_EINVAL and write nothing past the capacity (a sentinel region right
+    after it stays as it was)."""
+    import ctypes
+    n_rows, n_cols, a_cap = 16, 64, 8
+    cp = np.array([0 if c % 2 == 0 else a_cap for c in range(n_cols + 1)], np.int32)
+    a_cp, a_ri = dev(cp), dev(np.arange(a_cap, dtype=np.int32))
+    a_v = dev(np.arange(1, a_cap + 1, dtype=np.float64))
+    good = _csc_dev(n_rows, n_cols, [0] + [1] * 4 + [4] * (n_cols - 4), [0, 3, 5, 9],
+                    [1.0, 2.0, 3.0, 4.0])
+    b_cap = 4
+    out_cap, spare = a_cap + b_cap, 4096
+    lib = _lib.load()
+    wb = ctypes.c_size_t(0)
+    assert lib.spm_csc_add_workspace(n_rows, n_cols, a_cap, b_cap, ctypes.byref(wb)) == _lib.OK
+    ws = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=DEV)
+    col_ptr = torch.empty(n_cols + 1, dtype=torch.int32, device=DEV)
+    row_idx = torch.full((out_cap + spare,), -77, dtype=torch.int32, device=DEV)
+    val_out = torch.full((out_cap + spare,), 1234.5, dtype=torch.float64, device=DEV)
+    info = torch.zeros(2, dtype=torch.int32, device=DEV)
+    for a_first in (True, False):
+        A = (a_cp, a_ri, a_v, a_cap) if a_first else (good.col_ptr, good.row_idx_buf,
+                                                      good.values_buf, b_cap)
+        B = (good.col_ptr, good.row_idx_buf, good.values_buf, b_cap) if a_first else \
+            (a_cp, a_ri, a_v, a_cap)
+        st = lib.spm_csc_add(n_rows, n_cols, A[3], A[0].data_ptr(), A[1].data_ptr(),
+                             A[2].data_ptr(), B[3], B[0].data_ptr(), B[1].data_ptr(),
+                             B[2].data_ptr(), _lib.F64, col_ptr.data_ptr(), row_idx.data_ptr(),
+                             val_out.data_ptr(), _lib.F64, info.data_ptr(), ws.data_ptr(),
+                             ws.numel(), None)
+        assert st == _lib.OK
+        torch.cuda.synchronize()
+        assert int(info[1]) == _lib.EINVAL
+        assert torch.all(row_idx[out_cap:] == -77)
+        assert torch.all(val_out[out_cap:] == 1234.5)
