@@ -436,6 +436,13 @@ spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
   if (!aligned256(ws)) return SPM_EINVAL;
   size_t oh, of;
   if (ws_bytes < trace_ws_bytes(n_cols, &oh, &of)) return SPM_EWORKSPACE;
+  // One workgroup of kTraceChunk * gw lanes per chunk of columns: the launch's lane count
+  // must stay below 2^32.  The lane count per column does not enter the summation order, so
+  // a huge n_cols takes narrower groups first; beyond 16-lane groups the shape is rejected.
+  int gw = n_cols > 0 ? trace_group_width(n_rows, n_cols, a_cap, b_cap) : 16;
+  const uint64_t lanes_per_gw = (uint64_t)trace_chunks(n_cols) * kTraceChunk;
+  while (gw > 16 && lanes_per_gw * (uint64_t)gw > 0xFFFFFFFFull) gw >>= 1;
+  if (lanes_per_gw * (uint64_t)gw > 0xFFFFFFFFull) return SPM_EOVERFLOW;
   char* w = static_cast<char*>(ws);
   double* ps = reinterpret_cast<double*>(w);
   uint32_t* ph = reinterpret_cast<uint32_t*>(w + oh);
@@ -443,7 +450,6 @@ spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   if (n_cols > 0) {
-    const int gw = trace_group_width(n_rows, n_cols, a_cap, b_cap);
     if (val_type == SPM_F64)
       launch_trace<double>(gw, n_rows, n_cols, a_cap, a_col_ptr, a_row_idx, a_val, b_cap,
                            b_col_ptr, b_row_idx, b_val, ps, ph, pf, s);
