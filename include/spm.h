@@ -35,10 +35,10 @@
  *             once to the output type; a location whose fold compares equal to 0.0 is not
  *             stored (so -0.0 and cancelled sums are dropped; NaN and Inf are kept).  SpMM
  *             accumulates every output sequentially in a fixed order (ascending column for Y,
- *             ascending row for dX) in binary64, or in binary32 when an operand is bfloat16
- *             and none is binary64, and rounds once.  Results do not depend on tuning,
- *             launch shape or batching: the batched entry point is bitwise equal to the
- *             per-matrix entry points.
+ *             ascending row for dX) in binary64, or in binary32 when a dense operand is
+ *             bfloat16 and no operand is binary64, and rounds once.  Results do not depend
+ *             on tuning, launch shape or batching: the batched entry point is bitwise equal
+ *             to the per-matrix entry points.
  */
 #ifndef SPM_H
 #define SPM_H
@@ -219,16 +219,20 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
  *               -- A^T . G by a walk down each CSC column, the traversal of the row-vector
  *               times CSC product of Fig. 1;
  *   dval[p]   = sum_j G[row_idx[p], j] * X[c, j]  -- G . X^T sampled on A's pattern.
- * G and X share g_type = x_type (F64, F32 or BF16).  dX (n_cols x k, ld lddx, dx_type F64 or
- * F32) and dval (nnz elements, dval_type F64 or F32) may each be NULL to skip that output;
- * nnz = col_ptr[n_cols] is read on the device and clamped to nnz_cap.
+ * G has an element type of its own, g_type (F64, F32 or BF16), independent of x_type (F64,
+ * F32 or BF16): G arrives in Y's type (binary64 when the values are binary64, whatever X is)
+ * and is read as such, never narrowed.  Sums run in binary64, or in binary32 when one of
+ * G and X is bfloat16 and none of the values, G and X is binary64.
+ * dX (n_cols x k, ld lddx, dx_type F64 or F32) and dval (nnz elements, dval_type F64 or F32)
+ * may each be NULL to skip that output; nnz = col_ptr[n_cols] is read on the device and
+ * clamped to nnz_cap.
  * ------------------------------------------------------------------------------------------ */
 spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
                                  const int32_t *col_ptr, const int32_t *row_idx,
                                  const void *val, spm_dtype val_type, const void *G,
-                                 int64_t ldg, const void *X, int64_t ldx, spm_dtype x_type,
-                                 void *dX, int64_t lddx, spm_dtype dx_type, void *dval,
-                                 spm_dtype dval_type, void *stream);
+                                 int64_t ldg, spm_dtype g_type, const void *X, int64_t ldx,
+                                 spm_dtype x_type, void *dX, int64_t lddx, spm_dtype dx_type,
+                                 void *dval, spm_dtype dval_type, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Sum A + B of two CSCs of one shape, by the merge of batch insertion: B's stored elements are
@@ -303,6 +307,7 @@ spm_status spm_csc_trace_atb_workspace(int64_t n_cols, size_t *ws_bytes);
  *             rows not increasing in a column) or SPM_EBOUNDS (a stored row outside the
  *             matrix); on a nonzero status out is unspecified.
  *   ws        at least spm_csc_trace_atb_workspace() bytes, 256-byte aligned.
+ * n_cols above 2^28 returns SPM_EOVERFLOW (one launch covers at most 2^32 lanes).
  * Summation order: in each column A's elements by increasing position, dealt round-robin to
  * 64 partial sums that combine by halving; columns in chunks of 16 added in order; the chunk
  * sums in a fixed two-level order.  The result depends on n_cols and the data only, never on
@@ -324,17 +329,20 @@ spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
  * ------------------------------------------------------------------------------------------ */
 
 /* row, col  int32[nnz_in], the triplets' locations as given to assembly.
- * val_type  F64 or F32: the assembled values' type; with x_type BF16 and val_type F32 the dot
- *           products accumulate in binary32 (as the adjoint's dvalues), otherwise binary64.
- * G         n_rows x k, X n_cols x k (x_type F64, F32 or BF16, leading dimensions ldg, ldx >= k).
+ * val_type  F64 or F32: the assembled values' type; it takes part in the accumulation rule
+ *           of the adjoint (binary32 only when one of G and X is bfloat16 and none of the
+ *           values, G and X is binary64; otherwise binary64).
+ * G         n_rows x k of g_type, X n_cols x k of x_type (each F64, F32 or BF16, leading
+ *           dimensions ldg, ldx >= k).
  * dv        nnz_in elements of dv_type (F64 or F32), rounded once.
  * Summation order: the adjoint's dvalues order (lane pieces of 4 in ascending order, then a
  * fixed lane tree that depends on k alone).  No workspace, no device status (a triplet out
  * of range is not an error here). */
 spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
                                 const int32_t *row, const int32_t *col, spm_dtype val_type,
-                                const void *G, int64_t ldg, const void *X, int64_t ldx,
-                                spm_dtype x_type, void *dv, spm_dtype dv_type, void *stream);
+                                const void *G, int64_t ldg, spm_dtype g_type, const void *X,
+                                int64_t ldx, spm_dtype x_type, void *dv, spm_dtype dv_type,
+                                void *stream);
 
 /* The same gradients read from the adjoint's dvalues (spm_csc_spmm_backward on the CSC that
  * assembly produced from these triplets: col_ptr, row_idx of capacity nnz_cap, dval of type
@@ -346,9 +354,9 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
                                     const int32_t *row, const int32_t *col, int64_t nnz_cap,
                                     const int32_t *col_ptr, const int32_t *row_idx,
                                     const void *dval, spm_dtype dval_type, spm_dtype val_type,
-                                    const void *G, int64_t ldg, const void *X, int64_t ldx,
-                                    spm_dtype x_type, void *dv, spm_dtype dv_type,
-                                    void *stream);
+                                    const void *G, int64_t ldg, spm_dtype g_type,
+                                    const void *X, int64_t ldx, spm_dtype x_type, void *dv,
+                                    spm_dtype dv_type, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Batched path: many independent matrices assembled, planned, multiplied forward and

@@ -90,16 +90,16 @@ SIGNATURES = {
     "spm_csc_trace_atb": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                          ctypes.c_int, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
     "spm_coo_triplet_grad": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, ctypes.c_int,
-                                            c_p, c_i64, c_p, c_i64, ctypes.c_int, c_p,
-                                            ctypes.c_int, c_p]),
+                                            c_p, c_i64, ctypes.c_int, c_p, c_i64, ctypes.c_int,
+                                            c_p, ctypes.c_int, c_p]),
     "spm_csc_add_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_add": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                    ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                    ctypes.c_size_t, c_p]),
     "spm_coo_triplet_grad_csc": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, c_i64,
                                                 c_p, c_p, c_p, ctypes.c_int, ctypes.c_int, c_p,
-                                                c_i64, c_p, c_i64, ctypes.c_int, c_p,
-                                                ctypes.c_int, c_p]),
+                                                c_i64, ctypes.c_int, c_p, c_i64, ctypes.c_int,
+                                                c_p, ctypes.c_int, c_p]),
     "spm_csc_insert_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_insert": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
                                       ctypes.c_int, c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
@@ -108,8 +108,9 @@ SIGNATURES = {
                                     ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p, c_i64,
                                     ctypes.c_int, c_p]),
     "spm_csc_spmm_backward": (ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_p, c_p, c_p,
-                                             ctypes.c_int, c_p, c_i64, c_p, c_i64, ctypes.c_int,
-                                             c_p, c_i64, ctypes.c_int, c_p, ctypes.c_int, c_p]),
+                                             ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p, c_i64,
+                                             ctypes.c_int, c_p, c_i64, ctypes.c_int, c_p,
+                                             ctypes.c_int, c_p]),
     "spm_batch_workspace": (ctypes.c_int, [c_i64, c_i64, c_i32, c_size_p]),
     "spm_batch_schedule": (ctypes.c_int, [c_p, c_i32, c_i64, c_p]),
     "spm_batch_run": (ctypes.c_int, [c_i32, c_i64, c_p, c_p, c_p, c_p, c_p, ctypes.c_int, c_p,

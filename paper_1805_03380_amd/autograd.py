@@ -15,6 +15,11 @@ import torch
 from . import ops
 
 
+def _grad_dtype(dt: torch.dtype) -> torch.dtype:
+    """Element type the adjoint writes a gradient in: binary64 or binary32."""
+    return torch.float64 if dt == torch.float64 else torch.float32
+
+
 class CscSpmm(torch.autograd.Function):
     """Y = A(values) . X  with A's pattern fixed by ``A`` (an ops.CSCMatrix)."""
 
@@ -31,9 +36,11 @@ class CscSpmm(torch.autograd.Function):
         need_v, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_v or need_x):
             return None, None, None
-        G = G.to(X.dtype) if G.dtype != X.dtype else G
+        # G keeps the element type it arrives in (Y's: binary64 with binary64 values); the
+        # adjoint reads it as such.  A bfloat16 X gets its gradient in binary32 (autograd
+        # rounds it to X's type).
         dX, dval = ops.spmm_backward(A, G.contiguous(), X, values=values, need_dX=need_x,
-                                     need_dval=need_v, dx_dtype=X.dtype,
+                                     need_dval=need_v, dx_dtype=_grad_dtype(X.dtype),
                                      dval_dtype=values.dtype)
         if dval is not None:
             dval = dval[: values.shape[0]]
@@ -61,17 +68,17 @@ class CooSpmm(torch.autograd.Function):
     def backward(ctx, G: torch.Tensor):
         row, col, X = ctx.saved_tensors
         need_v, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        G = G.to(X.dtype) if G.dtype != X.dtype else G
-        G = G.contiguous()
+        G = G.contiguous()  # in its own element type, never narrowed to X's
         if not (need_v or need_x):
             return None, None, None, None, None
         # one adjoint pass gives dX and the dvalues; each triplet then reads its location's
         # dvalue (the dot product only where the location summed to zero)
         dX, dslot = ops.spmm_backward(ctx.A, G, X, need_dX=need_x, need_dval=need_v,
-                                      dx_dtype=X.dtype, dval_dtype=torch.float64)
+                                      dx_dtype=_grad_dtype(X.dtype), dval_dtype=torch.float64)
         dval = None
         if need_v:
-            dval = ops.triplet_grad_csc(row, col, ctx.A, dslot, G, X).to(ctx.val_dtype)
+            dval = ops.triplet_grad_csc(row, col, ctx.A, dslot, G, X,
+                                        out_dtype=_grad_dtype(ctx.val_dtype))
         return dval, dX, None, None, None
 
 

@@ -171,7 +171,7 @@ class PackedBatch:
                                   _lib.ORDER_CSC, xp, k, xt,
                                   o["Y"].data_ptr() + 4 * int(self.g_off[b]), k, _lib.F32, h)
             _lib.check(st, "spm_csc_spmm[%d]" % b)
-            st = lib.spm_csc_spmm_backward(nr, nc, nz, k, cp, ri, vo, _lib.F32, gp, k, xp, k, xt,
+            st = lib.spm_csc_spmm_backward(nr, nc, nz, k, cp, ri, vo, _lib.F32, gp, k, xt, xp, k, xt,
                                            o["dX"].data_ptr() + 4 * int(self.x_off[b]), k,
                                            _lib.F32, o["dval"].data_ptr() + 4 * to, _lib.F32, h)
             _lib.check(st, "spm_csc_spmm_backward[%d]" % b)

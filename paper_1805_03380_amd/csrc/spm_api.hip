@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "spm.h"
 #include "spm_assemble.h"
@@ -400,16 +401,16 @@ void launch_fwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, in
 #undef SPM_CALL_F
 }
 
-template <typename VT, typename XT, typename ACC>
+template <typename VT, typename GT, typename XT, typename ACC>
 void launch_bwd_t(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k, int G, bool full,
                   const int32_t* col_ptr, const int32_t* row_idx, const void* val, const void* Gm,
                   int64_t ldg, int gal, const void* X, int64_t ldx, int xal, void* dX,
                   int64_t lddx, int dx_f64, int dxal, void* dval, int dv_f64, int grid,
                   int block, hipStream_t s) {
 #define SPM_CALL_F(GW, F)                                                                      \
-  k_spmm_bwd<VT, XT, ACC, GW, F><<<dim3(grid), dim3(block), 0, s>>>(                           \
+  k_spmm_bwd<VT, GT, XT, ACC, GW, F><<<dim3(grid), dim3(block), 0, s>>>(                       \
       n_rows, n_cols, nnz_cap, k, col_ptr, row_idx, static_cast<const VT*>(val),               \
-      static_cast<const XT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal, dX, lddx,     \
+      static_cast<const GT*>(Gm), ldg, gal, static_cast<const XT*>(X), ldx, xal, dX, lddx,     \
       dx_f64, dxal, dval, dv_f64)
 #define SPM_CALL(GW) SPM_CALL_F(GW, false)
   if (full && G == 8) SPM_CALL_F(8, true);
@@ -1177,15 +1178,16 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
 
 spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t k,
                                  const int32_t* col_ptr, const int32_t* row_idx, const void* val,
-                                 spm_dtype val_type, const void* Gm, int64_t ldg, const void* X,
-                                 int64_t ldx, spm_dtype x_type, void* dX, int64_t lddx,
-                                 spm_dtype dx_type, void* dval, spm_dtype dval_type,
-                                 void* stream) {
+                                 spm_dtype val_type, const void* Gm, int64_t ldg,
+                                 spm_dtype g_type, const void* X, int64_t ldx, spm_dtype x_type,
+                                 void* dX, int64_t lddx, spm_dtype dx_type, void* dval,
+                                 spm_dtype dval_type, void* stream) {
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (k < 1 || ldg < k || ldx < k || (dX && lddx < k)) return SPM_EINVAL;
   if (!fits_i32(k)) return SPM_EOVERFLOW;
   if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (g_type != SPM_F64 && g_type != SPM_F32 && g_type != SPM_BF16) return SPM_EDTYPE;
   if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
   if (dX && dx_type != SPM_F64 && dx_type != SPM_F32) return SPM_EDTYPE;
   if (dval && dval_type != SPM_F64 && dval_type != SPM_F32) return SPM_EDTYPE;
@@ -1198,29 +1200,35 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
   const spm_tuning tu = tuning();
   const int block = tu.spmm_block;
   const int grid = spmm_grid(n_cols, G, block);
-  const int gal = (aligned(Gm, 4 * dsize(x_type)) && (ldg % 4) == 0) ? 1 : 0;
+  const int gal = (aligned(Gm, 4 * dsize(g_type)) && (ldg % 4) == 0) ? 1 : 0;
   const int xal = (aligned(X, 4 * dsize(x_type)) && (ldx % 4) == 0) ? 1 : 0;
   const int dxal = dX ? ((aligned(dX, 4 * dsize(dx_type)) && (lddx % 4) == 0) ? 1 : 0) : 0;
   const int dx_f64 = dx_type == SPM_F64;
   const int dv_f64 = dval_type == SPM_F64;
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
-  const bool f32acc = acc_is_f32(val_type, x_type);
   const bool full = k == 4 * (int64_t)G && gal && xal && (!dX || dxal) && n_rows > 0;
-#define SPM_BWD(VT, XT, ACC)                                                                  \
-  launch_bwd_t<VT, XT, ACC>(n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm,    \
-                            ldg, gal, X, ldx, xal, dX, lddx, dx_f64, dxal, dval, dv_f64, grid, \
-                            block, s)
+#define SPM_BWD(VT, GT, XT)                                                                   \
+  launch_bwd_t<VT, GT, XT, typename AccOf<VT, GT, XT>::type>(                                 \
+      n_rows, n_cols, nnz_cap, k, G, full, col_ptr, row_idx, val, Gm, ldg, gal, X, ldx, xal,  \
+      dX, lddx, dx_f64, dxal, dval, dv_f64, grid, block, s)
+#define SPM_BWD_X(VT, GT)                                         \
+  do {                                                            \
+    if (x_type == SPM_F64) SPM_BWD(VT, GT, double);               \
+    else if (x_type == SPM_F32) SPM_BWD(VT, GT, float);           \
+    else SPM_BWD(VT, GT, bf16_t);                                 \
+  } while (0)
+  // G's element type is dispatched on its own, never converted to X's.
   if (val_type == SPM_F64) {
-    if (x_type == SPM_F64) SPM_BWD(double, double, double);
-    else if (x_type == SPM_F32) SPM_BWD(double, float, double);
-    else SPM_BWD(double, bf16_t, double);
+    if (g_type == SPM_F64) SPM_BWD_X(double, double);
+    else if (g_type == SPM_F32) SPM_BWD_X(double, float);
+    else SPM_BWD_X(double, bf16_t);
   } else {
-    if (x_type == SPM_F64) SPM_BWD(float, double, double);
-    else if (x_type == SPM_F32) SPM_BWD(float, float, double);
-    else if (f32acc) SPM_BWD(float, bf16_t, float);
-    else SPM_BWD(float, bf16_t, double);
+    if (g_type == SPM_F64) SPM_BWD_X(float, double);
+    else if (g_type == SPM_F32) SPM_BWD_X(float, float);
+    else SPM_BWD_X(float, bf16_t);
   }
+#undef SPM_BWD_X
 #undef SPM_BWD
   return launch_status();
 }

@@ -276,10 +276,10 @@ __global__ __launch_bounds__(NT) void k_batch_spmm(BatchArgs a) {
     for (int64_t c = gid; c < n_c; c += groups) {
       const int64_t p0 = cp[c], p1 = cp[c + 1];
       if constexpr (FULL)
-        spmm_col_bwd_full<float, XT, ACC, GW>(c, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
+        spmm_col_bwd_full<float, XT, XT, ACC, GW>(c, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
                                               a.dX + it.x_off, a.k, false, a.dval + to, false);
       else
-        spmm_col_bwd<float, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
+        spmm_col_bwd<float, XT, XT, ACC, GW, false>(c, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
                                                 a.xal != 0, Xb, a.k, a.xal != 0,
                                                 a.dX + it.x_off, a.k, false, a.yal != 0,
                                                 a.dval + to, false);
@@ -420,11 +420,11 @@ __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* _
         const XT* Gb = Ga + it.g_off;
         const int64_t p0 = cp[e], p1 = cp[e + 1];
         if constexpr (FULL)
-          spmm_col_bwd_full<float, XT, ACC, GW>(e, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
+          spmm_col_bwd_full<float, XT, XT, ACC, GW>(e, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
                                                 a.dX + it.x_off, a.k, false, a.dval + to,
                                                 false);
         else
-          spmm_col_bwd<float, XT, ACC, GW, false>(e, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
+          spmm_col_bwd<float, XT, XT, ACC, GW, false>(e, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
                                                   a.xal != 0, Xb, a.k, a.xal != 0,
                                                   a.dX + it.x_off, a.k, false, a.yal != 0,
                                                   a.dval + to, false);

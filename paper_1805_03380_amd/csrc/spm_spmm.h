@@ -13,6 +13,8 @@
 // The batched kernel calls the same device functions, so its results are bitwise equal.
 #pragma once
 
+#include <type_traits>
+
 #include "spm_device.h"
 
 namespace spm {
@@ -24,6 +26,19 @@ __host__ __device__ inline int group_width(int64_t k) {
   while (g < need && g < kWave) g <<= 1;
   return g;
 }
+
+// Accumulator type of a product over operands of element types VT, GT, XT: binary64 when
+// any operand is binary64, else binary32 when any is bfloat16, else binary64.
+template <typename VT, typename GT, typename XT>
+struct AccOf {
+  static constexpr bool any64 = std::is_same<VT, double>::value ||
+                                std::is_same<GT, double>::value ||
+                                std::is_same<XT, double>::value;
+  static constexpr bool any16 = std::is_same<VT, bf16_t>::value ||
+                                std::is_same<GT, bf16_t>::value ||
+                                std::is_same<XT, bf16_t>::value;
+  using type = typename std::conditional<!any64 && any16, float, double>::type;
+};
 
 template <typename ACC>
 __device__ __forceinline__ ACC fma_acc(ACC a, ACC b, ACC c);
@@ -207,19 +222,20 @@ __device__ __forceinline__ void spmm_row_full(int64_t r, int lg, int64_t n_cols,
   store_n<ACC>(Y, r * ldy + (int64_t)lg * 4, 4, y_f64, true, acc);
 }
 
-// Adjoint, full aligned pieces (k == 4*GW).
-template <typename VT, typename XT, typename ACC, int GW>
+// Adjoint, full aligned pieces (k == 4*GW).  G (GT) and X (XT) have element types of their
+// own: a binary64 G is read as binary64, never narrowed to X's type.
+template <typename VT, typename GT, typename XT, typename ACC, int GW>
 __device__ __forceinline__ void spmm_col_bwd_full(int64_t c, int64_t p0, int64_t p1, int lg,
                                                   int64_t n_rows,
                                                   const int32_t* __restrict__ row_idx,
                                                   const VT* __restrict__ val,
-                                                  const XT* __restrict__ Gm, int64_t ldg,
+                                                  const GT* __restrict__ Gm, int64_t ldg,
                                                   const XT* __restrict__ X, int64_t ldx,
                                                   void* __restrict__ dX, int64_t lddx,
                                                   bool dx_f64, void* __restrict__ dval,
                                                   bool dv_f64) {
   static_assert(kU == 4, "the dvalues store selects among four sums");
-  const XT* Gl = Gm + (int64_t)lg * 4;
+  const GT* Gl = Gm + (int64_t)lg * 4;
   ACC x[4];
   vload4<ACC>(X + c * ldx + (int64_t)lg * 4, x);
   ACC dx[4] = {(ACC)0, (ACC)0, (ACC)0, (ACC)0};
@@ -361,12 +377,12 @@ __device__ __forceinline__ void spmm_row(int64_t r, int lg, int64_t k, int64_t n
 // When k > 4*GW a lane owns several pieces; its dval partial then runs over its pieces in
 // order before the group sum.
 // ------------------------------------------------------------------------------------------
-template <typename VT, typename XT, typename ACC, int GW, bool FULL>
+template <typename VT, typename GT, typename XT, typename ACC, int GW, bool FULL>
 __device__ __forceinline__ void spmm_col_bwd(int64_t c, int64_t p0, int64_t p1, int lg,
                                              int64_t k, int64_t n_rows,
                                              const int32_t* __restrict__ row_idx,
                                              const VT* __restrict__ val,
-                                             const XT* __restrict__ Gm, int64_t ldg, bool gal,
+                                             const GT* __restrict__ Gm, int64_t ldg, bool gal,
                                              const XT* __restrict__ X, int64_t ldx, bool xal,
                                              void* __restrict__ dX, int64_t lddx, bool dx_f64,
                                              bool dxal, void* __restrict__ dval, bool dv_f64) {
@@ -498,12 +514,12 @@ __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols
                                        ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);
 }
 
-template <typename VT, typename XT, typename ACC, int GW, bool FULL>
+template <typename VT, typename GT, typename XT, typename ACC, int GW, bool FULL>
 __global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                                                   int64_t k, const int32_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ row_idx,
                                                   const VT* __restrict__ val,
-                                                  const XT* __restrict__ Gm, int64_t ldg, int gal,
+                                                  const GT* __restrict__ Gm, int64_t ldg, int gal,
                                                   const XT* __restrict__ X, int64_t ldx, int xal,
                                                   void* __restrict__ dX, int64_t lddx, int dx_f64,
                                                   int dxal, void* __restrict__ dval, int dv_f64) {
@@ -518,10 +534,10 @@ __global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols
     p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
     p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
     if constexpr (FULL)
-      spmm_col_bwd_full<VT, XT, ACC, GW>(c, p0, p1, lg, n_rows, row_idx, val, Gm, ldg, X, ldx,
+      spmm_col_bwd_full<VT, GT, XT, ACC, GW>(c, p0, p1, lg, n_rows, row_idx, val, Gm, ldg, X, ldx,
                                          dX, lddx, dx_f64 != 0, dval, dv_f64 != 0);
     else
-      spmm_col_bwd<VT, XT, ACC, GW, false>(c, p0, p1, lg, k, n_rows, row_idx, val, Gm, ldg,
+      spmm_col_bwd<VT, GT, XT, ACC, GW, false>(c, p0, p1, lg, k, n_rows, row_idx, val, Gm, ldg,
                                            gal != 0, X, ldx, xal != 0, dX, lddx, dx_f64 != 0,
                                            dxal != 0, dval, dv_f64 != 0);
   }

@@ -23,10 +23,10 @@ namespace spm {
 constexpr int kTgNT = 256;  // threads per workgroup
 constexpr int kTgU = 4;     // triplets per group in flight
 
-template <typename XT, typename ACC, int GW>
+template <typename GT, typename XT, typename ACC, int GW>
 __global__ __launch_bounds__(kTgNT) void k_triplet_grad(
     int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* __restrict__ row,
-    const int32_t* __restrict__ col, const XT* __restrict__ Gm, int64_t ldg, bool gal,
+    const int32_t* __restrict__ col, const GT* __restrict__ Gm, int64_t ldg, bool gal,
     const XT* __restrict__ X, int64_t ldx, bool xal, void* __restrict__ dv, bool dv_f64) {
   constexpr int NG = kTgNT / GW;  // groups per workgroup
   const int lg = threadIdx.x % GW;
@@ -81,12 +81,12 @@ __global__ __launch_bounds__(kTgNT) void k_triplet_grad(
 // location was dropped (its values summed to zero) has no slot: the wave then computes the
 // dot product above for it, on its first GW lanes (the same lane pieces and group_sum tree),
 // one such triplet at a time.
-template <typename XT, typename ACC, int GW, typename DT>
+template <typename GT, typename XT, typename ACC, int GW, typename DT>
 __global__ __launch_bounds__(kTgNT) void k_triplet_grad_csc(
     int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* __restrict__ row,
     const int32_t* __restrict__ col, int64_t nnz_cap, const int32_t* __restrict__ col_ptr,
     const int32_t* __restrict__ row_idx, const DT* __restrict__ dval,
-    const XT* __restrict__ Gm, int64_t ldg, bool gal, const XT* __restrict__ X, int64_t ldx,
+    const GT* __restrict__ Gm, int64_t ldg, bool gal, const XT* __restrict__ X, int64_t ldx,
     bool xal, void* __restrict__ dv, bool dv_f64) {
   const int lane = threadIdx.x % kWave;
   const int nch = (int)((k + 4 * GW - 1) / (4 * GW));
@@ -168,7 +168,7 @@ int device_cus() {
   return cached[dev];
 }
 
-template <typename XT, typename ACC, int GW>
+template <typename GT, typename XT, typename ACC, int GW>
 void launch_tg(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* row,
                const int32_t* col, const void* Gm, int64_t ldg, bool gal, const void* X,
                int64_t ldx, bool xal, void* dv, bool dv_f64, hipStream_t s) {
@@ -177,17 +177,17 @@ void launch_tg(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const 
   const int64_t cap = (int64_t)device_cus() * 32;
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  k_triplet_grad<XT, ACC, GW><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
-      n_rows, n_cols, nnz_in, k, row, col, static_cast<const XT*>(Gm), ldg, gal,
+  k_triplet_grad<GT, XT, ACC, GW><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
+      n_rows, n_cols, nnz_in, k, row, col, static_cast<const GT*>(Gm), ldg, gal,
       static_cast<const XT*>(X), ldx, xal, dv, dv_f64);
 }
 
-template <typename XT, typename ACC>
+template <typename GT, typename XT, typename ACC>
 void launch_tg_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
                   const int32_t* row, const int32_t* col, const void* Gm, int64_t ldg, bool gal,
                   const void* X, int64_t ldx, bool xal, void* dv, bool dv_f64, hipStream_t s) {
 #define SPM_TG(W)                                                                            \
-  launch_tg<XT, ACC, W>(n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx, xal, dv, \
+  launch_tg<GT, XT, ACC, W>(n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx, xal, dv, \
                         dv_f64, s)
   switch (gw) {
     case 1: SPM_TG(1); break;
@@ -201,7 +201,7 @@ void launch_tg_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_
 #undef SPM_TG
 }
 
-template <typename XT, typename ACC, int GW>
+template <typename GT, typename XT, typename ACC, int GW>
 void launch_tg_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, const int32_t* row,
                    const int32_t* col, int64_t nnz_cap, const int32_t* col_ptr,
                    const int32_t* row_idx, const void* dval, bool dval_f64, const void* Gm,
@@ -211,26 +211,26 @@ void launch_tg_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k, co
   const int64_t cap = (int64_t)device_cus() * 32;
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  const XT* g = static_cast<const XT*>(Gm);
+  const GT* g = static_cast<const GT*>(Gm);
   const XT* x = static_cast<const XT*>(X);
   if (dval_f64)
-    k_triplet_grad_csc<XT, ACC, GW, double><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
+    k_triplet_grad_csc<GT, XT, ACC, GW, double><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
         n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx,
         static_cast<const double*>(dval), g, ldg, gal, x, ldx, xal, dv, dv_f64);
   else
-    k_triplet_grad_csc<XT, ACC, GW, float><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
+    k_triplet_grad_csc<GT, XT, ACC, GW, float><<<dim3((unsigned)grid), dim3(kTgNT), 0, s>>>(
         n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx,
         static_cast<const float*>(dval), g, ldg, gal, x, ldx, xal, dv, dv_f64);
 }
 
-template <typename XT, typename ACC>
+template <typename GT, typename XT, typename ACC>
 void launch_tg_csc_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
                       const int32_t* row, const int32_t* col, int64_t nnz_cap,
                       const int32_t* col_ptr, const int32_t* row_idx, const void* dval,
                       bool dval_f64, const void* Gm, int64_t ldg, bool gal, const void* X,
                       int64_t ldx, bool xal, void* dv, bool dv_f64, hipStream_t s) {
 #define SPM_TGC(W)                                                                          \
-  launch_tg_csc<XT, ACC, W>(n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx, \
+  launch_tg_csc<GT, XT, ACC, W>(n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr, row_idx, \
                             dval, dval_f64, Gm, ldg, gal, X, ldx, xal, dv, dv_f64, s)
   switch (gw) {
     case 1: SPM_TGC(1); break;
@@ -244,14 +244,48 @@ void launch_tg_csc_gw(int gw, int64_t n_rows, int64_t n_cols, int64_t nnz_in, in
 #undef SPM_TGC
 }
 
+// Element-type dispatch of G and X: each has a type of its own.  The accumulator follows the
+// adjoint's rule over the values, G and X (AccOf): binary32 only when bfloat16 is involved and
+// binary64 is not.
+template <template <typename, typename, typename> class F, typename... A>
+void dispatch_gx(spm_dtype vt, spm_dtype gt, spm_dtype xt, A&&... args) {
+  auto with_x = [&](auto g_tag) {
+    using GT = decltype(g_tag);
+    auto go = [&](auto x_tag) {
+      using XT = decltype(x_tag);
+      if (vt == SPM_F64) F<GT, XT, double>::run(args...);
+      else F<GT, XT, typename AccOf<float, GT, XT>::type>::run(args...);
+    };
+    if (xt == SPM_F64) go(double{});
+    else if (xt == SPM_F32) go(float{});
+    else go(bf16_t{});
+  };
+  if (gt == SPM_F64) with_x(double{});
+  else if (gt == SPM_F32) with_x(float{});
+  else with_x(bf16_t{});
+}
+
+template <typename GT, typename XT, typename ACC>
+struct RunTg {
+  template <typename... A>
+  static void run(A&&... args) { launch_tg_gw<GT, XT, ACC>(args...); }
+};
+
+template <typename GT, typename XT, typename ACC>
+struct RunTgCsc {
+  template <typename... A>
+  static void run(A&&... args) { launch_tg_csc_gw<GT, XT, ACC>(args...); }
+};
+
 }  // namespace
 
 extern "C" {
 
 spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, int64_t k,
                                 const int32_t* row, const int32_t* col, spm_dtype val_type,
-                                const void* Gm, int64_t ldg, const void* X, int64_t ldx,
-                                spm_dtype x_type, void* dv, spm_dtype dv_type, void* stream) {
+                                const void* Gm, int64_t ldg, spm_dtype g_type, const void* X,
+                                int64_t ldx, spm_dtype x_type, void* dv, spm_dtype dv_type,
+                                void* stream) {
   if (n_rows < 0 || n_cols < 0 || nnz_in < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz_in) || n_rows == INT32_MAX ||
       n_cols == INT32_MAX)
@@ -259,30 +293,20 @@ spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, 
   if (k < 1 || ldg < k || ldx < k) return SPM_EINVAL;
   if (!fits_i32(k)) return SPM_EOVERFLOW;
   if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
+  if (g_type != SPM_F64 && g_type != SPM_F32 && g_type != SPM_BF16) return SPM_EDTYPE;
   if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
   if (dv_type != SPM_F64 && dv_type != SPM_F32) return SPM_EDTYPE;
   if (nnz_in > 0 && (!row || !col || !dv)) return SPM_EINVAL;
   if ((n_rows > 0 && !Gm) || (n_cols > 0 && !X)) return SPM_EINVAL;
   if (nnz_in == 0) return SPM_OK;
   const int gw = group_width(k);
-  const bool gal = aligned_to(Gm, 4 * dsize(x_type)) && (ldg % 4) == 0;
+  const bool gal = aligned_to(Gm, 4 * dsize(g_type)) && (ldg % 4) == 0;
   const bool xal = aligned_to(X, 4 * dsize(x_type)) && (ldx % 4) == 0;
   const bool f64 = dv_type == SPM_F64;
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
-  // accumulation as in the adjoint: binary32 for bfloat16 operands with binary32 values
-  if (x_type == SPM_F64)
-    launch_tg_gw<double, double>(gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx,
-                                 xal, dv, f64, s);
-  else if (x_type == SPM_F32)
-    launch_tg_gw<float, double>(gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx,
-                                xal, dv, f64, s);
-  else if (val_type == SPM_F64)
-    launch_tg_gw<bf16_t, double>(gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx,
-                                 xal, dv, f64, s);
-  else
-    launch_tg_gw<bf16_t, float>(gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg, gal, X, ldx,
-                                xal, dv, f64, s);
+  dispatch_gx<RunTg>(val_type, g_type, x_type, gw, n_rows, n_cols, nnz_in, k, row, col, Gm, ldg,
+                     gal, X, ldx, xal, dv, f64, s);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPM_OK : SPM_EHIP;
 }
@@ -291,9 +315,9 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
                                     const int32_t* row, const int32_t* col, int64_t nnz_cap,
                                     const int32_t* col_ptr, const int32_t* row_idx,
                                     const void* dval, spm_dtype dval_type, spm_dtype val_type,
-                                    const void* Gm, int64_t ldg, const void* X, int64_t ldx,
-                                    spm_dtype x_type, void* dv, spm_dtype dv_type,
-                                    void* stream) {
+                                    const void* Gm, int64_t ldg, spm_dtype g_type,
+                                    const void* X, int64_t ldx, spm_dtype x_type, void* dv,
+                                    spm_dtype dv_type, void* stream) {
   if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || nnz_cap < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz_in) || !fits_i32(nnz_cap) ||
       n_rows == INT32_MAX || n_cols == INT32_MAX)
@@ -302,6 +326,7 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
   if (!fits_i32(k)) return SPM_EOVERFLOW;
   if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
   if (dval_type != SPM_F64 && dval_type != SPM_F32) return SPM_EDTYPE;
+  if (g_type != SPM_F64 && g_type != SPM_F32 && g_type != SPM_BF16) return SPM_EDTYPE;
   if (x_type != SPM_F64 && x_type != SPM_F32 && x_type != SPM_BF16) return SPM_EDTYPE;
   if (dv_type != SPM_F64 && dv_type != SPM_F32) return SPM_EDTYPE;
   if (nnz_in > 0 && (!row || !col || !dv || !col_ptr)) return SPM_EINVAL;
@@ -309,23 +334,14 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
   if ((n_rows > 0 && !Gm) || (n_cols > 0 && !X)) return SPM_EINVAL;
   if (nnz_in == 0) return SPM_OK;
   const int gw = group_width(k);
-  const bool gal = aligned_to(Gm, 4 * dsize(x_type)) && (ldg % 4) == 0;
+  const bool gal = aligned_to(Gm, 4 * dsize(g_type)) && (ldg % 4) == 0;
   const bool xal = aligned_to(X, 4 * dsize(x_type)) && (ldx % 4) == 0;
   const bool f64 = dv_type == SPM_F64, d64 = dval_type == SPM_F64;
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
-  if (x_type == SPM_F64)
-    launch_tg_csc_gw<double, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
-                                      row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
-  else if (x_type == SPM_F32)
-    launch_tg_csc_gw<float, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
-                                     row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
-  else if (val_type == SPM_F64)
-    launch_tg_csc_gw<bf16_t, double>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
-                                      row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
-  else
-    launch_tg_csc_gw<bf16_t, float>(gw, n_rows, n_cols, nnz_in, k, row, col, nnz_cap, col_ptr,
-                                     row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64, s);
+  dispatch_gx<RunTgCsc>(val_type, g_type, x_type, gw, n_rows, n_cols, nnz_in, k, row, col,
+                        nnz_cap, col_ptr, row_idx, dval, d64, Gm, ldg, gal, X, ldx, xal, dv, f64,
+                        s);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPM_OK : SPM_EHIP;
 }

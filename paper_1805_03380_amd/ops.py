@@ -338,8 +338,6 @@ def triplet_grad(row: torch.Tensor, col: torch.Tensor, G: torch.Tensor, X: torch
     G2 = G.reshape(-1, 1) if G.dim() == 1 else G
     X2 = X.reshape(-1, 1) if X.dim() == 1 else X
     _require_cuda(row, col, G2, X2)
-    if G2.dtype != X2.dtype:
-        raise ValueError("G and X must share one element type")
     if G2.shape[0] != n_rows or X2.shape[0] != n_cols or G2.shape[1] != X2.shape[1]:
         raise ValueError("G %s and X %s do not fit a %dx%d matrix" % (tuple(G2.shape),
                          tuple(X2.shape), n_rows, n_cols))
@@ -355,8 +353,9 @@ def triplet_grad(row: torch.Tensor, col: torch.Tensor, G: torch.Tensor, X: torch
     dv = torch.empty(max(n, 1), dtype=out_dtype, device=row.device)
     lib = _lib.load()
     st = lib.spm_coo_triplet_grad(n_rows, n_cols, n, int(X2.shape[1]), _ptr(row), _ptr(col),
-                                  _dtype_code(val_dtype), _ptr(G2), G2.stride(0), _ptr(X2),
-                                  X2.stride(0), _dtype_code(X2.dtype), _ptr(dv),
+                                  _dtype_code(val_dtype), _ptr(G2), G2.stride(0),
+                                  _dtype_code(G2.dtype), _ptr(X2), X2.stride(0),
+                                  _dtype_code(X2.dtype), _ptr(dv),
                                   _dtype_code(out_dtype), _stream(row.device))
     _lib.check(st, "spm_coo_triplet_grad")
     return dv[:n]
@@ -371,8 +370,6 @@ def triplet_grad_csc(row: torch.Tensor, col: torch.Tensor, A: CSCMatrix, dval: t
     G2 = G.reshape(-1, 1) if G.dim() == 1 else G
     X2 = X.reshape(-1, 1) if X.dim() == 1 else X
     _require_cuda(row, col, A.col_ptr, dval, G2, X2)
-    if G2.dtype != X2.dtype:
-        raise ValueError("G and X must share one element type")
     if G2.shape[0] != A.n_rows or X2.shape[0] != A.n_cols or G2.shape[1] != X2.shape[1]:
         raise ValueError("G %s and X %s do not fit a %dx%d matrix" % (tuple(G2.shape),
                          tuple(X2.shape), A.n_rows, A.n_cols))
@@ -393,7 +390,8 @@ def triplet_grad_csc(row: torch.Tensor, col: torch.Tensor, A: CSCMatrix, dval: t
                                       _ptr(A.row_idx_buf) if cap else None,
                                       _ptr(dval) if cap else None, _dtype_code(dval.dtype),
                                       _dtype_code(A.values_buf.dtype), _ptr(G2), G2.stride(0),
-                                      _ptr(X2), X2.stride(0), _dtype_code(X2.dtype), _ptr(dv),
+                                      _dtype_code(G2.dtype), _ptr(X2), X2.stride(0),
+                                      _dtype_code(X2.dtype), _ptr(dv),
                                       _dtype_code(out_dtype), _stream(row.device))
     _lib.check(st, "spm_coo_triplet_grad_csc")
     return dv[:n]
@@ -504,13 +502,12 @@ def spmm_backward(A: CSCMatrix, G: torch.Tensor, X: torch.Tensor,
                   values: torch.Tensor | None = None, need_dX: bool = True,
                   need_dval: bool = True, dx_dtype: torch.dtype | None = None,
                   dval_dtype: torch.dtype | None = None):
-    """(dX, dval) of Y = A.X for dL/dY = G (spm_csc_spmm_backward); None where not needed."""
+    """(dX, dval) of Y = A.X for dL/dY = G (spm_csc_spmm_backward); None where not needed.
+    G and X keep their own element types (G usually arrives in Y's type)."""
     vec = X.dim() == 1
     X2 = X.reshape(-1, 1) if vec else X
     G2 = G.reshape(-1, 1) if G.dim() == 1 else G
     _require_cuda(X2, G2, A.col_ptr)
-    if G2.dtype != X2.dtype:
-        raise ValueError("G and X must share one element type")
     if X2.stride(1) != 1:
         X2 = X2.contiguous()
     if G2.stride(1) != 1:
@@ -531,8 +528,8 @@ def spmm_backward(A: CSCMatrix, G: torch.Tensor, X: torch.Tensor,
     st = lib.spm_csc_spmm_backward(A.n_rows, A.n_cols, A.nnz_cap, k, _ptr(A.col_ptr),
                                    _ptr(A.row_idx_buf) if A.nnz_cap else None,
                                    _ptr(v) if A.nnz_cap else None, _dtype_code(v.dtype),
-                                   _ptr(G2), G2.stride(0), _ptr(X2), X2.stride(0),
-                                   _dtype_code(X2.dtype), _ptr(dX),
+                                   _ptr(G2), G2.stride(0), _dtype_code(G2.dtype), _ptr(X2),
+                                   X2.stride(0), _dtype_code(X2.dtype), _ptr(dX),
                                    dX.stride(0) if dX is not None else k,
                                    _dtype_code(dx_dtype), _ptr(dval), _dtype_code(dval_dtype),
                                    _stream(dev))

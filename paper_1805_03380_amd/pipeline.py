@@ -88,7 +88,8 @@ class Pipeline:
         _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
                                              self.row_idx.data_ptr(), self.values.data_ptr(),
                                              _DT[self.csc_dtype], G.data_ptr(), G.stride(0),
-                                             X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                             _DT[G.dtype], X.data_ptr(), X.stride(0),
+                                             _DT[X.dtype],
                                              self.dX.data_ptr(), self.dX.stride(0),
                                              _DT[self.dx_dtype], self.dval.data_ptr(),
                                              _DT[self.csc_dtype], h), "spm_csc_spmm_backward")
@@ -142,7 +143,8 @@ class Pipeline:
         _lib.check(lib.spm_csc_spmm_backward(n_rows, n_cols, nnz, k, self.col_ptr.data_ptr(),
                                              self.row_idx.data_ptr(), self.values.data_ptr(),
                                              _DT[self.csc_dtype], G.data_ptr(), G.stride(0),
-                                             X.data_ptr(), X.stride(0), _DT[X.dtype],
+                                             _DT[G.dtype], X.data_ptr(), X.stride(0),
+                                             _DT[X.dtype],
                                              self.dX.data_ptr(), self.dX.stride(0),
                                              _DT[self.dx_dtype], self.dval.data_ptr(),
                                              _DT[self.csc_dtype], h), "spm_csc_spmm_backward")

@@ -97,9 +97,19 @@ def test_host_validation_rejects_before_launch():
                             _lib.F32, None) == _lib.EDTYPE
     assert lib.spm_csc_spmm(4, 4, 8, 4, fake, fake, _lib.F32, 7, fake, 4, _lib.F32, fake, 4,
                             _lib.F32, None) == _lib.EINVAL  # unknown value order
-    assert lib.spm_csc_spmm_backward(4, 4, 8, 4, None, fake, fake, _lib.F32, fake, 4, fake, 4,
-                                     _lib.F32, fake, 4, _lib.F32, fake, _lib.F32,
+    assert lib.spm_csc_spmm_backward(4, 4, 8, 4, None, fake, fake, _lib.F32, fake, 4, _lib.F32,
+                                     fake, 4, _lib.F32, fake, 4, _lib.F32, fake, _lib.F32,
                                      None) == _lib.EINVAL
+
+    def bw(gt=_lib.F64, xt=_lib.F32, dxt=_lib.F32, dvt=_lib.F64, ldg=4):
+        return lib.spm_csc_spmm_backward(4, 4, 8, 4, None, fake, fake, _lib.F64, fake, ldg, gt,
+                                         fake, 4, xt, fake, 4, dxt, fake, dvt, None)
+
+    # G's element type is checked on its own (a NULL col_ptr is reported only after it)
+    assert bw(gt=7) == _lib.EDTYPE
+    assert bw(gt=_lib.F64, xt=_lib.F32) == _lib.EINVAL
+    assert bw(gt=_lib.BF16, xt=_lib.F64) == _lib.EINVAL
+    assert bw(ldg=3) == _lib.EINVAL
     assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, None, _lib.F32, fake, 16, None, fake, ws,
                                   1 << 30, None) == _lib.EWORKSPACE
     assert lib.spm_csc_plan_build(4, 4, 8, fake, fake, fake, _lib.F32, fake, 1 << 20, None,
@@ -178,6 +188,8 @@ def test_host_validation_rejects_before_launch():
     assert ta(info=None) == _lib.EINVAL
     assert ta(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
     assert ta(wsb=16) == _lib.EWORKSPACE
+    # more columns than one launch of 16-lane groups covers (2^32 lanes): rejected on the host
+    assert ta(n_cols=2 ** 28 + 16, wsb=1 << 40) == _lib.EOVERFLOW
     # sum of two CSCs
 
     def ad(n_rows=4, n_cols=4, ca=8, cb=8, vt=_lib.F64, ot=_lib.F64, acp=fake, bcp=fake,
@@ -198,9 +210,9 @@ def test_host_validation_rejects_before_launch():
     assert ad(wsb=16) == _lib.EWORKSPACE
     # gradient per input triplet
 
-    def tg(n_rows=4, n_cols=4, n=8, k=4, row=fake, vt=_lib.F32, ldg=4, ldx=4, xt=_lib.F32,
-           dv=fake, dvt=_lib.F32):
-        return lib.spm_coo_triplet_grad(n_rows, n_cols, n, k, row, fake, vt, fake, ldg, fake,
+    def tg(n_rows=4, n_cols=4, n=8, k=4, row=fake, vt=_lib.F32, ldg=4, gt=_lib.F32, ldx=4,
+           xt=_lib.F32, dv=fake, dvt=_lib.F32):
+        return lib.spm_coo_triplet_grad(n_rows, n_cols, n, k, row, fake, vt, fake, ldg, gt, fake,
                                         ldx, xt, dv, dvt, None)
 
     assert tg(n=0) == _lib.OK  # nothing to do, nothing enqueued
@@ -211,13 +223,14 @@ def test_host_validation_rejects_before_launch():
     assert tg(n=2 ** 31) == _lib.EOVERFLOW
     assert tg(vt=_lib.BF16) == _lib.EDTYPE
     assert tg(xt=7) == _lib.EDTYPE
+    assert tg(gt=7) == _lib.EDTYPE
     assert tg(dvt=_lib.BF16) == _lib.EDTYPE
     assert tg(row=None) == _lib.EINVAL
     assert tg(dv=None) == _lib.EINVAL
 
-    def tgc(n=8, cap=8, cp=fake, ri=fake, dvt=_lib.F64, k=4):
+    def tgc(n=8, cap=8, cp=fake, ri=fake, dvt=_lib.F64, k=4, gt=_lib.F64):
         return lib.spm_coo_triplet_grad_csc(4, 4, n, k, fake, fake, cap, cp, ri, fake, dvt,
-                                            _lib.F32, fake, 4, fake, 4, _lib.F32, fake,
+                                            _lib.F32, fake, 4, gt, fake, 4, _lib.F32, fake,
                                             _lib.F32, None)
 
     assert tgc(n=0) == _lib.OK
@@ -226,6 +239,7 @@ def test_host_validation_rejects_before_launch():
     assert tgc(cp=None) == _lib.EINVAL
     assert tgc(ri=None) == _lib.EINVAL
     assert tgc(dvt=_lib.BF16) == _lib.EDTYPE
+    assert tgc(gt=9) == _lib.EDTYPE
 
 
 def test_tuning_roundtrip():

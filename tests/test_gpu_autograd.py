@@ -103,3 +103,34 @@ def test_needs_input_grad_skips_outputs():
     X2 = dev(p.X)
     csc_spmm(A, v2, X2).sum().backward()
     assert v2.grad is not None
+
+
+def test_gradcheck_f64_values_f32_x():
+    """Binary64 values with a binary32 X: Y and so G are binary64, and the adjoint reads G as
+    binary64 (no narrowing to X's type), so the dvalues pass gradcheck at binary64 tolerances."""
+    p = synth.random_coo(503, 24, 18, 60, dup_frac=0.1, dist="normal", k=5)
+    A = assemble_gpu(p)
+    v = A.values.clone().requires_grad_(True)
+    X = dev(p.X, torch.float32)
+    assert v.dtype == torch.float64
+    assert torch.autograd.gradcheck(lambda vv: csc_spmm(A, vv, X), (v,), eps=1e-6, atol=1e-9,
+                                    rtol=1e-7)
+
+
+def test_f64_values_f32_x_oracle_gradient():
+    """The same mixed case against the oracle: a binary64 G, unrounded, gives binary64
+    dvalues within 1e-12 relative plus the oracle's own a-priori slack."""
+    p = synth.random_coo(504, 3000, 2500, 40_000, dup_frac=0.05, dist="normal", k=64)
+    A = assemble_gpu(p)
+    v = A.values.clone().requires_grad_(True)
+    X = dev(p.X, torch.float32).requires_grad_(True)
+    G = dev(p.G)
+    assert G.dtype == torch.float64
+    csc_spmm(A, v, X).backward(G)
+    torch.cuda.synchronize()
+    st, R = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+    Xh = oracle.widen(X.detach().cpu())
+    dXr, dvr, SdX, Sdv = oracle.spmm_backward(R, p.G, Xh)
+    assert v.grad.dtype == torch.float64 and X.grad.dtype == torch.float32
+    assert_close(v.grad, dvr, Sdv, p.k, torch.float64, what="dval")
+    assert_close(X.grad, dXr, SdX, np.diff(R.col_ptr), torch.float32, what="dX")

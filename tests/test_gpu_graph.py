@@ -97,7 +97,7 @@ def test_graph_trace_and_triplet_grad():
             ws.numel(), stream) == _lib.OK
         assert lib.spm_coo_triplet_grad(
             p.n_rows, p.n_cols, p.nnz_in, 32, row.data_ptr(), col.data_ptr(), _lib.F64,
-            G.data_ptr(), 32, X.data_ptr(), 32, _lib.F64, dv.data_ptr(), _lib.F64,
+            G.data_ptr(), 32, _lib.F64, X.data_ptr(), 32, _lib.F64, dv.data_ptr(), _lib.F64,
             stream) == _lib.OK
 
     s = torch.cuda.Stream(device=DEV)

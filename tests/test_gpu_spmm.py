@@ -32,12 +32,13 @@ def _check_plan(A_gpu, R):
     assert np.array_equal(perm[:n].cpu().numpy(), order)
 
 
-def _run(p, value_dtype, x_dtype, check_bitwise_f32=True, acc_f32=False):
+def _run(p, value_dtype, x_dtype, check_bitwise_f32=True, acc_f32=False, g_dtype=None):
+    """g_dtype: G's own element type (default: X's); G is never converted to X's type."""
     R = _ref(p)
     A = assemble_gpu(p, val_dtype=None)
     vals = A.values_buf if value_dtype is None else A.values_buf.to(value_dtype)
     X = dev(p.X).to(x_dtype)
-    Gm = dev(p.G).to(x_dtype)
+    Gm = dev(p.G).to(x_dtype if g_dtype is None else g_dtype)
     Y = ops.spmm(A, X, values=vals)
     dX, dval = ops.spmm_backward(A, Gm, X, values=vals)
     torch.cuda.synchronize()
@@ -52,7 +53,8 @@ def _run(p, value_dtype, x_dtype, check_bitwise_f32=True, acc_f32=False):
     assert_close(dX, dXr, SdX, colcnt, dX.dtype, acc_f32, "dX")
     assert_close(dval, dvr, Sdv, p.k, dval.dtype, acc_f32, "dval")
     if check_bitwise_f32 and out_t == torch.float32 and not acc_f32 and \
-            vals.dtype == torch.float32 and x_dtype == torch.float32:
+            vals.dtype == torch.float32 and x_dtype == torch.float32 and \
+            Gm.dtype == torch.float32:
         # binary32 operands, binary64 accumulation in the oracle's order: the products are
         # exact, so Y and dX round to exactly the oracle's values
         assert np.array_equal(Y.cpu().numpy(), Yr.astype(np.float32))
@@ -142,10 +144,34 @@ def test_widths_f64(k):
 
 
 def test_mixed_f64_values_f32_dense():
+    """Binary64 values, binary32 X: Y is binary64, so G arrives in binary64 and is read as
+    such; dvalues (binary64) meet the binary64 bound with the unrounded G."""
     p = synth.random_coo(71, 800, 800, 16_000, dup_frac=0.05, dtype=np.float64, k=64)
     p.X = p.X.astype(np.float32)
-    p.G = p.G.astype(np.float32)
-    _run(p, None, torch.float32)
+    _run(p, None, torch.float32, g_dtype=torch.float64)
+
+
+@pytest.mark.parametrize("k", [5, 64, 128])
+def test_g_f64_x_f32_values_f32(k):
+    """Binary32 values and X with a binary64 G (a caller whose loss is in binary64)."""
+    p = synth.random_coo(73 + k, 900, 700, 18_000, dup_frac=0.05, dtype=np.float32,
+                         dist="normal", k=k)
+    _run(p, None, torch.float32, g_dtype=torch.float64)
+
+
+def test_g_f32_x_bf16():
+    """A bfloat16 X gives a binary32 Y, so G arrives in binary32: read as binary32 (binary32
+    accumulation, as for any bfloat16 operand)."""
+    p = synth.random_coo(74, 1000, 1200, 30_000, dup_frac=0.1, dtype=np.float32, dist="normal",
+                         k=32)
+    _run(p, None, torch.bfloat16, acc_f32=True, g_dtype=torch.float32)
+
+
+def test_g_f64_x_bf16_f64_accumulation():
+    """A binary64 G with a bfloat16 X: binary64 takes part, so the sums run in binary64."""
+    p = synth.random_coo(75, 600, 500, 9_000, dup_frac=0.1, dtype=np.float32, dist="normal",
+                         k=64)
+    _run(p, None, torch.bfloat16, g_dtype=torch.float64)
 
 
 def test_bf16_dense_f32_accumulation():
@@ -160,10 +186,11 @@ def test_uniform_1e5_f32_k64():
 
 
 def test_uniform_1e5_f64_values():
+    """The 1e5 workload with binary64 values: X binary32, G N(0,1) in the output type
+    (binary64), unrounded; binary64 dvalues within 1e-12 relative plus the a-priori slack."""
     p = synth.uniform_1e5(value_dtype=np.float64, k=64)
-    # values f64, X f32, G f64 in the workload; the kernels take G and X in one type
-    p.G = p.G.astype(np.float32)
-    _run(p, None, torch.float32)
+    assert p.G.dtype == np.float64
+    _run(p, None, torch.float32, g_dtype=torch.float64)
 
 
 def test_deterministic_and_empty_rows():

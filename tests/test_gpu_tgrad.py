@@ -13,14 +13,17 @@ from gpu_util import DEV, assert_close, dev
 pytestmark = pytest.mark.gpu
 
 
-def _case(p, G, X, val_dtype, x_dtype, out_dtype=None, what=""):
-    print("case %s %dx%d nnz_in=%d k=%d x=%s" % (p.name, p.n_rows, p.n_cols, p.nnz_in,
-                                                 X.shape[1], x_dtype), flush=True)
-    Gd, Xd = dev(G, x_dtype), dev(X, x_dtype)
+def _case(p, G, X, val_dtype, x_dtype, out_dtype=None, what="", g_dtype=None):
+    """g_dtype: G's own element type (default: X's)."""
+    g_dtype = x_dtype if g_dtype is None else g_dtype
+    print("case %s %dx%d nnz_in=%d k=%d x=%s g=%s" % (p.name, p.n_rows, p.n_cols, p.nnz_in,
+                                                      X.shape[1], x_dtype, g_dtype), flush=True)
+    Gd, Xd = dev(G, g_dtype), dev(X, x_dtype)
     dv = ops.triplet_grad(dev(p.row), dev(p.col), Gd, Xd, (p.n_rows, p.n_cols),
                           val_dtype=val_dtype, out_dtype=out_dtype)
     want, S = oracle.triplet_grad(p.n_rows, p.n_cols, p.row, p.col, Gd.cpu(), Xd.cpu())
-    acc_f32 = x_dtype == torch.bfloat16 and val_dtype != torch.float64
+    dense = (g_dtype, x_dtype)
+    acc_f32 = torch.bfloat16 in dense and torch.float64 not in dense + (val_dtype,)
     assert_close(dv, want, S, X.shape[1], dv.dtype, acc_f32=acc_f32, what=what)
     return dv, want
 
@@ -54,6 +57,17 @@ def test_triplet_grad_random(k):
 def test_triplet_grad_dtypes(val_dtype, x_dtype, out_dtype):
     p, G, X = _with_specials(2200, 1200, 1000, 30_000, 32)
     _case(p, G, X, val_dtype, x_dtype, out_dtype, what=str(x_dtype))
+
+
+@pytest.mark.parametrize("val_dtype,g_dtype,x_dtype", [
+    (torch.float64, torch.float64, torch.float32), (torch.float32, torch.float64, torch.float32),
+    (torch.float32, torch.float32, torch.bfloat16), (torch.float64, torch.float64,
+                                                     torch.bfloat16)])
+def test_triplet_grad_g_own_dtype(val_dtype, g_dtype, x_dtype):
+    """G in an element type of its own (Y's type), read as such."""
+    p, G, X = _with_specials(2250, 1100, 900, 25_000, 64)
+    _case(p, G, X, val_dtype, x_dtype, torch.float64 if torch.float64 in (val_dtype, g_dtype)
+          else None, what="g=%s x=%s" % (g_dtype, x_dtype), g_dtype=g_dtype)
 
 
 def test_triplet_grad_uniform_1e5():
@@ -92,12 +106,13 @@ def test_triplet_grad_empty_and_arguments():
     lib = _lib.load()
     r = torch.zeros(2, dtype=torch.int32, device=DEV)
     dv = torch.zeros(2, dtype=torch.float64, device=DEV)
-    args = [4, 3, 2, 8, r.data_ptr(), r.data_ptr(), _lib.F64, G.data_ptr(), 8, X.data_ptr(), 8,
-            _lib.F64, dv.data_ptr(), _lib.F64, None]
-    for i, val, want in ((3, 0, _lib.EINVAL), (8, 7, _lib.EINVAL), (10, 7, _lib.EINVAL),
-                         (6, _lib.BF16, _lib.EDTYPE), (13, _lib.BF16, _lib.EDTYPE),
-                         (11, 9, _lib.EDTYPE), (4, None, _lib.EINVAL), (12, None, _lib.EINVAL),
-                         (2, 2 ** 31, _lib.EOVERFLOW), (0, -1, _lib.EINVAL)):
+    args = [4, 3, 2, 8, r.data_ptr(), r.data_ptr(), _lib.F64, G.data_ptr(), 8, _lib.F64,
+            X.data_ptr(), 8, _lib.F64, dv.data_ptr(), _lib.F64, None]
+    for i, val, want in ((3, 0, _lib.EINVAL), (8, 7, _lib.EINVAL), (11, 7, _lib.EINVAL),
+                         (6, _lib.BF16, _lib.EDTYPE), (14, _lib.BF16, _lib.EDTYPE),
+                         (12, 9, _lib.EDTYPE), (9, 9, _lib.EDTYPE), (4, None, _lib.EINVAL),
+                         (13, None, _lib.EINVAL), (2, 2 ** 31, _lib.EOVERFLOW),
+                         (0, -1, _lib.EINVAL)):
         bad = list(args)
         bad[i] = val
         assert lib.spm_coo_triplet_grad(*bad) == want, i
@@ -119,6 +134,27 @@ def test_coo_spmm_autograd():
     dX, _, SdX, _ = oracle.spmm_backward(A, G, X)
     m = np.diff(A.col_ptr)
     assert_close(Xd.grad, dX, SdX, m, torch.float64, what="dX")
+
+
+def test_coo_spmm_autograd_f64_values_f32_x():
+    """Binary64 triplet values with a binary32 X: Y and G are binary64; the per-triplet
+    gradients (binary64) come from the binary64 G, unrounded, within the binary64 bound."""
+    p, G, X = _with_specials(2450, 600, 500, 9000, 32)
+    inside = (p.row >= 0) & (p.row < p.n_rows) & (p.col >= 0) & (p.col < p.n_cols)
+    q = synth.COOProblem("inside", p.n_rows, p.n_cols, p.row[inside], p.col[inside],
+                         p.val[inside])
+    val = dev(q.val).requires_grad_(True)
+    Xd = dev(X, torch.float32).requires_grad_(True)
+    Y = autograd.coo_spmm(dev(q.row), dev(q.col), val, Xd, (q.n_rows, q.n_cols))
+    assert Y.dtype == torch.float64
+    Y.backward(dev(G))
+    Xh = oracle.widen(Xd.detach().cpu())
+    want_v, S = oracle.triplet_grad(q.n_rows, q.n_cols, q.row, q.col, G, Xh)
+    assert val.grad.dtype == torch.float64
+    assert_close(val.grad, want_v, S, 32, torch.float64, what="dval")
+    st, A = oracle.coo_to_csc(q.n_rows, q.n_cols, q.row, q.col, q.val)
+    dX, _, SdX, _ = oracle.spmm_backward(A, G, Xh)
+    assert_close(Xd.grad, dX, SdX, np.diff(A.col_ptr), torch.float32, what="dX")
 
 
 def test_coo_spmm_gradcheck():
