@@ -12,6 +12,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -25,7 +26,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed-FP32 instructions off: ordinary float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -44,18 +44,35 @@ def sources():
             os.path.join(CSRC, "spm_tgrad.hip")]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + \
-        sources() + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libspm.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed: %s" % " ".join(cmd[-3:]))
+
+
+def build(verbose: bool = False) -> str:
+    """Each translation unit compiles to an object of its own (in parallel; no device code
+    crosses units), then one link makes the shared library."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(LIBDIR, os.path.basename(src) + ".%s.o" % tag) for src in sources()]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cmds = [[hipcc()] + HIPCC_FLAGS + inc + ["-c", src, "-o", obj]
+            for src, obj in zip(sources(), objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp%s" % tag
+        _run([hipcc()] + HIPCC_FLAGS + ["-shared"] + objs + ["-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 
