@@ -33,3 +33,25 @@ def test_more_than_one_gpu_exits_with_message():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_model_bytes_g_in_its_own_type():
+    """A binary64 G (binary64 values, binary32 X) is read at 8 bytes per element."""
+    n, nnz_in, nnz, k = 1000, 5000, 4000, 16
+    b4 = bench.model_bytes(n, n, nnz_in, nnz, k, 8, 8, 4, 8, 4)
+    b8 = bench.model_bytes(n, n, nnz_in, nnz, k, 8, 8, 4, 8, 4, s_g=8)
+    assert b4 == b8  # G defaults to Y's element size
+    b_g4 = bench.model_bytes(n, n, nnz_in, nnz, k, 8, 8, 4, 8, 4, s_g=4)
+    assert b8["backward"] - b_g4["backward"] == n * k * 4
+    assert b8["forward"] == b_g4["forward"]
+
+
+def test_workload_table():
+    """Every workload names a generator that exists; the headline is the largest one."""
+    from paper_1805_03380_amd import synth
+    assert set(bench.SIDE_ORDER) == set(bench.WORKLOADS)
+    for name, (ctor, kw, label) in bench.WORKLOADS.items():
+        assert callable(getattr(synth, ctor)), name
+        assert label and " " not in label
+    p, label = bench.make_problem("tiny")
+    assert label == bench.WORKLOADS["tiny"][2] and p.nnz_in == 10_000 and p.k == 1
