@@ -165,6 +165,28 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
                                size_t plan_bytes, void *val_plan, int32_t *plan_info, void *ws,
                                size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): spm_coo_to_csc_plan with the workspace taken from a
+ * fixed array inside the library instead of the caller.
+ *   The array is SPM_NOALLOC_SCRATCH_BYTES (64 MiB) of device memory that every GPU the
+ *   library runs this call on holds from the first such call until the process ends.  Sizes
+ *   whose workspace (spm_coo_to_csc_plan_size) exceeds it return SPM_EWORKSPACE before
+ *   anything is enqueued (about 1.2e6 triplets at the default tuning).  The call allocates
+ *   nothing; the caller still passes every input and output as for spm_coo_to_csc_plan,
+ *   with the same results bit for bit.
+ *   All calls on one GPU share that GPU's array: calls that overlap in time on one GPU (on
+ *   different streams, or from several host threads without ordering) race on it and their
+ *   results are unspecified.  Calls in one stream are ordered and safe.  The array keeps the
+ *   last call's contents; every call clears what it needs itself.
+ *   SPM_EHIP if the array's device address cannot be obtained. */
+#define SPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+spm_status spm_coo_to_csc_plan_noalloc(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                       const int32_t *row, const int32_t *col, const void *val,
+                                       spm_dtype val_type, int32_t *col_ptr, int32_t *row_idx,
+                                       void *val_out, spm_dtype out_type, int32_t *info,
+                                       void *plan, size_t plan_bytes, void *val_plan,
+                                       int32_t *plan_info, void *stream);
+
 /* ------------------------------------------------------------------------------------------
  * Batch insertion into an existing CSC (Section 3.1: the elements to be inserted are sorted
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a

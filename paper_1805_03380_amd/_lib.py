@@ -17,6 +17,8 @@ OK, EINVAL, EBOUNDS, EOVERFLOW, EWORKSPACE, EDTYPE, EHIP = range(7)
 F64, F32, BF16 = 0, 1, 2
 # spm_val_order
 ORDER_CSC, ORDER_PLAN = 0, 1
+# SPM_NOALLOC_SCRATCH_BYTES
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -83,6 +85,9 @@ SIGNATURES = {
                                            c_p, c_p, c_p, ctypes.c_int, c_p, c_p,
                                            ctypes.c_size_t, c_p, c_p, c_p, ctypes.c_size_t,
                                            c_p]),
+    "spm_coo_to_csc_plan_noalloc": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p,
+                                                   ctypes.c_int, c_p, c_p, c_p, ctypes.c_int,
+                                                   c_p, c_p, ctypes.c_size_t, c_p, c_p, c_p]),
     "spm_csc_transpose_workspace": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p]),
     "spm_csc_transpose": (ctypes.c_int, [c_i64, c_i64, c_i64, c_p, c_p, c_p, ctypes.c_int, c_p,
                                          c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),

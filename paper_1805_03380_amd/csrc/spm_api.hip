@@ -1439,3 +1439,56 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
 }
 
 }  // extern "C"
+
+// ============================================================================================
+// Assembly and plan without allocation: the workspace is a fixed device array of the library.
+// ============================================================================================
+namespace {
+
+constexpr size_t kNoallocScratchBytes = SPM_NOALLOC_SCRATCH_BYTES;
+
+// The scratch array.  In host code its name is only a stand-in for the symbol: the device
+// address comes from hipGetSymbolAddress, once per device (each GPU holds its own copy).
+static __device__ __align__(256) unsigned char spm_noalloc_scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up on first use.
+spm_status noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPM_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(spm_noalloc_scratch)) != hipSuccess || !p)
+      return SPM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spm_status spm_coo_to_csc_plan_noalloc(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
+                                       const int32_t* row, const int32_t* col, const void* val,
+                                       spm_dtype val_type, int32_t* col_ptr, int32_t* row_idx,
+                                       void* val_out, spm_dtype out_type, int32_t* info,
+                                       void* plan, size_t plan_bytes, void* val_plan,
+                                       int32_t* plan_info, void* stream) {
+  spm_status st = check_dims(n_rows, n_cols, nnz_in);
+  if (st != SPM_OK) return st;
+  if (fuse_layout(n_rows, n_cols, nnz_in).total > kNoallocScratchBytes) return SPM_EWORKSPACE;
+  void* ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st != SPM_OK) return st;
+  return spm_coo_to_csc_plan(n_rows, n_cols, nnz_in, row, col, val, val_type, col_ptr, row_idx,
+                             val_out, out_type, info, plan, plan_bytes, val_plan, plan_info, ws,
+                             kNoallocScratchBytes, stream);
+}
+
+}  // extern "C"

@@ -188,6 +188,14 @@ def test_host_validation_rejects_before_launch():
     assert ta(info=None) == _lib.EINVAL
     assert ta(w=ctypes.c_void_p(0x1010)) == _lib.EINVAL
     assert ta(wsb=16) == _lib.EWORKSPACE
+    # the allocation-free assembly + plan: sizes whose workspace exceeds the fixed scratch
+    # array are rejected on the host, before anything touches the device
+    assert lib.spm_coo_to_csc_plan_noalloc(200_000, 200_000, 5_000_000, fake, fake, fake,
+                                           _lib.F32, fake, fake, fake, _lib.F32, fake, fake,
+                                           1 << 30, None, fake, None) == _lib.EWORKSPACE
+    assert lib.spm_coo_to_csc_plan_noalloc(-1, 4, 4, fake, fake, fake, _lib.F32, fake, fake,
+                                           fake, _lib.F32, fake, fake, 1 << 30, None, fake,
+                                           None) == _lib.EINVAL
     # more columns than one launch of 16-lane groups covers (2^32 lanes): rejected on the host
     assert ta(n_cols=2 ** 28 + 16, wsb=1 << 40) == _lib.EOVERFLOW
     # sum of two CSCs
