@@ -178,7 +178,7 @@ struct AsmLayout {
   // shared
   size_t bucket, scratch;
   // partition path
-  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, boff, flags;
+  size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, boff, flags, big;
   size_t total;
   int64_t fold_tiles;
 };
@@ -214,6 +214,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.bkept = c.take(sizeof(uint32_t) * (size_t)cb);
   L.boff = c.take(sizeof(int32_t) * (size_t)(cb > kEmitReduceMax ? cb + 1 : 0));
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? L.pp.ntiles : 0));
+  L.big = c.take(sizeof(uint32_t) * (size_t)(cb + 1));  // big-bucket list (count, buckets)
   L.total = c.off;
   return L;
 }
@@ -221,7 +222,7 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
 struct PlanLayout {
   PartParams pp;
   size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
-  size_t colarr, table, rowoff, btot, bstart, brec, bvhi, flags, total;
+  size_t colarr, table, rowoff, btot, bstart, brec, bvhi, flags, big, total;
   int64_t sort_tiles;
 };
 
@@ -256,6 +257,7 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_cap) {
   L.bvhi = c.take(sizeof(uint32_t) * (size_t)nP);  // high words of float64 values
   // status flags: one per k_expand_columns workgroup, then one per k_part_hist tile
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) + L.pp.ntiles : 0));
+  L.big = c.take(sizeof(uint32_t) * (size_t)(cb + 1));  // big-bucket list (count, buckets)
   L.total = c.off;
   return L;
 }
@@ -288,7 +290,7 @@ struct FuseLayout {
   AsmLayout A;
   PartParams Q;  // plan partition by row (capacity nnz_in)
   bool fused;
-  size_t table2, rowoff2, btot2, bstart2, total;
+  size_t table2, rowoff2, btot2, bstart2, big2, total;
 };
 
 FuseLayout fuse_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_in) {
@@ -298,7 +300,7 @@ FuseLayout fuse_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_in) {
   F.fused = F.A.pp.ok && F.Q.ok && nnz_in > 0 && F.Q.CB <= kFuseMaxRowBuckets &&
             (int64_t)F.Q.CB * F.A.pp.CB <= kFuseMaxTable;
   if (!F.fused) {
-    F.table2 = F.rowoff2 = F.btot2 = F.bstart2 = 0;
+    F.table2 = F.rowoff2 = F.btot2 = F.bstart2 = F.big2 = 0;
     F.total = std::max(F.A.total, plan_ws_layout(n_rows, n_cols, nnz_in).total);
     return F;
   }
@@ -309,6 +311,7 @@ FuseLayout fuse_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_in) {
   F.rowoff2 = c.take(sizeof(uint32_t) * tab);
   F.btot2 = c.take(sizeof(uint32_t) * (size_t)F.Q.CB);
   F.bstart2 = c.take(sizeof(int32_t) * ((size_t)F.Q.CB + 1));
+  F.big2 = c.take(sizeof(uint32_t) * ((size_t)F.Q.CB + 1));
   F.total = c.off;
   return F;
 }
@@ -322,6 +325,37 @@ struct FuseCtx {
   void* val_plan;  // optional, of the output type
   int32_t* plan_info;
 };
+
+// Level 2 over every bucket.  Buckets of at most kPartCap elements go through the first launch,
+// one workgroup each (small LDS, four per CU).  When the device's LDS allows, buckets above
+// that (listed by k_rows_scan in big) go through a second, persistent launch with an in-LDS
+// capacity of kPartBigCap and 512 threads, so that power-law buckets of up to twice the usual
+// size stay off the staged path.  big == nullptr: one launch, larger buckets staged.
+constexpr int kPartBigNT = 512;
+constexpr int kPartBigCap = 4096;
+
+bool level2_big_ok(int b) {
+  return part_level2_lds_bytes(b, kPartBigCap) + 2048 <= (size_t)max_lds_per_block();
+}
+
+template <bool PLAN, typename VT>
+void launch_level2(int b, int32_t CB, int64_t nseg, const int32_t* bstart, const uint4* brec,
+                   const uint32_t* bvhi, uint64_t* bucket, uint64_t* scratch, int32_t* row_ptr,
+                   int32_t* col_t, int32_t* perm, const VT* val, VT* val_plan, int32_t* col_rel,
+                   uint32_t* trow, double* tval, uint32_t* bkept, int rshift,
+                   const L2RowCount& rc, const uint32_t* big, hipStream_t s) {
+  k_part_level2<kNT, kPartCap, PLAN, VT>
+      <<<dim3((unsigned)CB), dim3(kNT), part_level2_lds_bytes(b, kPartCap), s>>>(
+          b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
+          col_rel, trow, tval, bkept, rshift, rc, big);
+  if (big) {
+    const int grid = (int)std::min<int64_t>(CB, (int64_t)cu_count() * 2);
+    k_part_level2_big<kPartBigNT, kPartBigCap, PLAN, VT>
+        <<<dim3((unsigned)grid), dim3(kPartBigNT), part_level2_lds_bytes(b, kPartBigCap), s>>>(
+            b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
+            col_rel, trow, tval, bkept, rshift, rc, big, CB);
+  }
+}
 
 spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
                          const int32_t* col, const void* val, spm_dtype val_type,
@@ -531,12 +565,15 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
+    uint32_t* big = level2_big_ok(P.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
+    uint32_t* big2 = (fz && level2_big_ok(fz->F->Q.b))
+                         ? reinterpret_cast<uint32_t*>(w + fz->F->big2) : nullptr;
     k_part_hist<kPartNT, PartSrcCoo>
         <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-            src, P.b, P.CB, P.ntiles, P.T1, table, flags);
+            src, P.b, P.CB, P.ntiles, P.T1, table, flags, big, big2);
     k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
-        (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info);
-    const size_t lds = part_level2_lds_bytes(P.b, kPartCap);
+        (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info,
+        (uint32_t)kPartCap, big);
     // fused plan: level 2 also counts the survivors per (row bucket, column bucket)
     const L2RowCount rc = fz ? L2RowCount{reinterpret_cast<uint32_t*>(w + fz->F->table2),
                                           fz->F->Q.b, fz->F->Q.CB, P.CB}
@@ -547,11 +584,11 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(                      \
           src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,      \
           bstart, brec, static_cast<const VT*>(val), bvhi);                                    \
-  k_part_level2<kNT, kPartCap, false, VT><<<dim3((unsigned)P.CB), dim3(kNT), lds, s>>>(        \
-      P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi, bucket,  \
-      scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,                        \
-      static_cast<const VT*>(val), (VT*)nullptr, col_ptr, trow, tval, bkept,                   \
-      sub_shift(n_rows, P.b), rc);                                                             \
+  launch_level2<false, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,     \
+                           (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,          \
+                           (int32_t*)nullptr, (int32_t*)nullptr, static_cast<const VT*>(val),  \
+                           (VT*)nullptr, col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b),   \
+                           rc, big, s);                                                        \
   } while (0)
     if (val_type == SPM_F64) SPM_L2(double);
     else if (val_type == SPM_F32) SPM_L2(float);
@@ -575,7 +612,7 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
       // the column buckets are the tiles of the plan's level 1; no status flags to fold
       k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
           (const uint32_t*)table2, (int64_t)P.CB, rowoff2, btot2, (const uint32_t*)nullptr,
-          (int64_t)0, fz->plan_info);
+          (int64_t)0, fz->plan_info, (uint32_t)kPartCap, big2);
       ep = EmitPlan{Q.b, Q.CB, rowoff2, btot2, bstart2, brec, bvhi, fz->plan_info};
       emit_lds = 4 * ((size_t)Q.CB + ((size_t)1 << P.b) + 1);
     }
@@ -591,13 +628,12 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
       int32_t* perm = reinterpret_cast<int32_t*>(fz->plan + PP.perm);
       const int32_t* bstart2 = reinterpret_cast<const int32_t*>(w + fz->F->bstart2);
 #define SPM_PL2(VT)                                                                            \
-  k_part_level2<kNT, kPartCap, true, VT>                                                       \
-      <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(          \
-          Q.b, n_rows, bstart2, (const uint4*)brec, (const uint32_t*)bvhi, bucket, scratch,    \
-          row_ptr, col_t, perm, static_cast<const VT*>(val_out),                               \
-          static_cast<VT*>(fz->val_plan), (int32_t*)nullptr, (uint32_t*)nullptr,               \
-          (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b),                        \
-          L2RowCount{nullptr, 0, 0, 0})
+  launch_level2<true, VT>(Q.b, Q.CB, n_rows, bstart2, (const uint4*)brec,                      \
+                          (const uint32_t*)bvhi, bucket, scratch, row_ptr, col_t, perm,        \
+                          static_cast<const VT*>(val_out), static_cast<VT*>(fz->val_plan),     \
+                          (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,             \
+                          (uint32_t*)nullptr, sub_shift(n_cols, Q.b),                          \
+                          L2RowCount{nullptr, 0, 0, 0}, big2, s)
       if (out_type == SPM_F64) SPM_PL2(double);
       else SPM_PL2(float);
 #undef SPM_PL2
@@ -672,22 +708,23 @@ void plan_build_into(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int3
     k_expand_columns<kNT><<<dim3(expand_grid(n_cols)), dim3(kNT), 0, s>>>(
         col_ptr, n_cols, nnz_cap, colarr, info, flags);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
+    uint32_t* big = level2_big_ok(Q.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
     k_part_hist<kPartNT, PartSrcCsc>
         <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
-            src, Q.b, Q.CB, Q.ntiles, Q.T1, table, flags + expand_grid(n_cols));
+            src, Q.b, Q.CB, Q.ntiles, Q.T1, table, flags + expand_grid(n_cols), big,
+            (uint32_t*)nullptr);
     k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
         (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
-        (int64_t)expand_grid(n_cols) + Q.ntiles, info);
+        (int64_t)expand_grid(n_cols) + Q.ntiles, info, (uint32_t)kPartCap, big);
     k_part_scatter<kPartNT, PartSrcCsc, VT>
         <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
             src, Q.b, Q.CB, Q.ntiles, Q.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
             bstart, brec, val_plan ? val : (const VT*)nullptr, bvhi);
-    k_part_level2<kNT, kPartCap, true, VT>
-        <<<dim3((unsigned)Q.CB), dim3(kNT), part_level2_lds_bytes(Q.b, kPartCap), s>>>(
-            Q.b, n_rows, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi,
-            bucket, scratch, row_ptr, col_t, perm, val, val_plan, (int32_t*)nullptr,
-            (uint32_t*)nullptr, (double*)nullptr, (uint32_t*)nullptr, sub_shift(n_cols, Q.b),
-            L2RowCount{nullptr, 0, 0, 0});
+    launch_level2<true, VT>(Q.b, Q.CB, n_rows, (const int32_t*)bstart, (const uint4*)brec,
+                            (const uint32_t*)bvhi, bucket, scratch, row_ptr, col_t, perm, val,
+                            val_plan, (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
+                            (uint32_t*)nullptr, sub_shift(n_cols, Q.b),
+                            L2RowCount{nullptr, 0, 0, 0}, big, s);
   } else {
     k_zero2<<<dim3(grid_for((int64_t)(L.zero_bytes / 4), kNT * 4, cap)), dim3(kNT), 0, s>>>(
         reinterpret_cast<uint32_t*>(w), (int64_t)(L.zero_bytes / 4),
@@ -797,22 +834,22 @@ void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_co
   }
   PartSrcMerge src{a_row_idx, colarr, a_col_ptr, row, col, (int32_t)n_rows, (int32_t)n_cols,
                    cap_a, nnz_t, t_col_ptr};
+  uint32_t* big = level2_big_ok(P.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
   k_part_hist<kPartNT, PartSrcMerge>
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg);
+          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg, big, (uint32_t*)nullptr);
   k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
       (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
-      (int64_t)eg + P.ntiles, info);
+      (int64_t)eg + P.ntiles, info, (uint32_t)kPartCap, big);
   k_part_scatter<kPartNT, PartSrcMerge, VT>
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
           src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
           bstart, brec, (const VT*)vcat, bvhi);
-  k_part_level2<kNT, kPartCap, false, VT>
-      <<<dim3((unsigned)P.CB), dim3(kNT), part_level2_lds_bytes(P.b, kPartCap), s>>>(
-          P.b, n_cols, (const int32_t*)bstart, (const uint4*)brec, (const uint32_t*)bvhi,
-          bucket, scratch, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-          (const VT*)vcat, (VT*)nullptr, col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b),
-          L2RowCount{nullptr, 0, 0, 0});
+  launch_level2<false, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,
+                           (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,
+                           (int32_t*)nullptr, (int32_t*)nullptr, (const VT*)vcat, (VT*)nullptr,
+                           col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b),
+                           L2RowCount{nullptr, 0, 0, 0}, big, s);
   int32_t* boff = nullptr;
   if (P.CB > kEmitReduceMax) {
     boff = reinterpret_cast<int32_t*>(w + L.boff);

@@ -200,12 +200,20 @@ __global__ __launch_bounds__(NT) void k_expand_columns(const int32_t* __restrict
 }
 
 // Level 1a: per-tile coarse-bucket counts -> table[cb * ntiles + t].
+// zero0 / zero1 (nullable): the counts of the big-bucket lists that k_rows_scan fills next;
+// workgroup 0 clears them.
 template <int NT, typename SRC>
 __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, int64_t ntiles,
                                                   int64_t T1, uint32_t* __restrict__ table,
-                                                  uint32_t* __restrict__ flags) {
+                                                  uint32_t* __restrict__ flags,
+                                                  uint32_t* __restrict__ zero0,
+                                                  uint32_t* __restrict__ zero1) {
   __shared__ uint32_t s_flag;
   extern __shared__ uint32_t h[];  // CB counters (dynamic LDS, 4*CB bytes)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (zero0) *zero0 = 0;
+    if (zero1) *zero1 = 0;
+  }
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = src.count();
   for (int i = threadIdx.x; i < CB; i += NT) h[i] = 0;
@@ -383,12 +391,16 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
 // Per-bucket exclusive scan of one row of the (bucket x tile) table: rowoff[cb][t] = number of
 // bucket-cb elements in tiles before t; btot[cb] = the bucket's total.  One workgroup per row.
 // Workgroup 0 also folds the nflags status flags of the checking kernel into info[1].
+// big (nullable): a bucket of more than big_cap elements is appended to the list
+// big[1 .. 1 + big[0]) (big[0] cleared by k_part_hist); level 2 takes those in a launch of
+// their own.  The list's order is arbitrary; every bucket's result is independent of it.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ table,
                                                   int64_t ntiles, uint32_t* __restrict__ rowoff,
                                                   uint32_t* __restrict__ btot,
                                                   const uint32_t* __restrict__ flags,
-                                                  int64_t nflags, int32_t* __restrict__ info) {
+                                                  int64_t nflags, int32_t* __restrict__ info,
+                                                  uint32_t big_cap, uint32_t* __restrict__ big) {
   __shared__ uint32_t s_w[NT / kWave + 1];
   __shared__ uint32_t s_flag;
   if (blockIdx.x == 0) {
@@ -425,7 +437,10 @@ __global__ __launch_bounds__(NT) void k_rows_scan(const uint32_t* __restrict__ t
     }
     carry += tot;
   }
-  if (threadIdx.x == 0) btot[cb] = carry;
+  if (threadIdx.x == 0) {
+    btot[cb] = carry;
+    if (big && carry > big_cap) big[1 + atomicAdd(&big[0], 1u)] = (uint32_t)cb;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -842,22 +857,19 @@ __device__ __forceinline__ void l2_slow(const L2Bucket& B, const L2Lds<CAP>& L, 
   }
 }
 
+// Level 2 of bucket cb: the in-LDS path when it holds at most CAP elements, else the staged
+// path.
 template <int NT, int CAP, bool PLAN, typename VT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_part_level2(
-    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
-    const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
-    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
-    int32_t* __restrict__ perm, const VT* __restrict__ val, VT* __restrict__ val_plan,
-    int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
-    uint32_t* __restrict__ bkept, int rshift, L2RowCount rc) {
-  static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
-  static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_w[NT / kWave + 1];
-  __shared__ int64_t s_b[3];
-  const L2Lds<CAP> L(smem, b);
+__device__ __forceinline__ void l2_bucket(
+    int64_t cb, int b, int64_t nseg, const int32_t* __restrict__ bstarts,
+    const uint4* __restrict__ brec, const uint32_t* __restrict__ bvhi,
+    uint64_t* __restrict__ gkeys, uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr,
+    int32_t* __restrict__ col_t, int32_t* __restrict__ perm, const VT* __restrict__ val,
+    VT* __restrict__ val_plan, int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow,
+    double* __restrict__ tval, uint32_t* __restrict__ bkept, int rshift, const L2RowCount& rc,
+    const L2Lds<CAP>& L, uint32_t* s_w, int64_t* s_b) {
   L2Bucket B;
-  B.cb = xcd_tile(blockIdx.x, gridDim.x);
+  B.cb = cb;
   B.bstart = bstarts[B.cb];
   B.bend = bstarts[B.cb + 1];
   B.m = B.bend - B.bstart;
@@ -872,6 +884,57 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   else
     l2_slow<NT, CAP, PLAN, VT>(B, L, s_w, s_b, brec, gkeys, scratch, row_ptr, col_t, perm,
                                val, val_plan, col_rel, trow, tval, bkept, rc);
+}
+
+// One workgroup per bucket.  big_skip != nullptr: buckets of more than CAP elements are left
+// to k_part_level2_big (listed by k_rows_scan).
+template <int NT, int CAP, bool PLAN, typename VT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_part_level2(
+    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
+    const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
+    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
+    int32_t* __restrict__ perm, const VT* __restrict__ val, VT* __restrict__ val_plan,
+    int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
+    uint32_t* __restrict__ bkept, int rshift, L2RowCount rc,
+    const uint32_t* __restrict__ big_skip) {
+  static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
+  static_assert((CAP + 1) * 4 <= CAP * 8, "s_pre must fit in s_key");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_b[3];
+  const L2Lds<CAP> L(smem, b);
+  const int64_t cb = xcd_tile(blockIdx.x, gridDim.x);
+  if (big_skip && bstarts[cb + 1] - bstarts[cb] > CAP) return;
+  l2_bucket<NT, CAP, PLAN, VT>(cb, b, nseg, bstarts, brec, bvhi, gkeys, scratch, row_ptr,
+                               col_t, perm, val, val_plan, col_rel, trow, tval, bkept, rshift,
+                               rc, L, s_w, s_b);
+}
+
+// The listed big buckets (big[1 .. 1 + big[0]), k_rows_scan), persistent workgroups each
+// taking every gridDim-th entry, with the larger in-LDS capacity CAP (staged path beyond).
+template <int NT, int CAP, bool PLAN, typename VT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_part_level2_big(
+    int b, int64_t nseg, const int32_t* __restrict__ bstarts, const uint4* __restrict__ brec,
+    const uint32_t* __restrict__ bvhi, uint64_t* __restrict__ gkeys,
+    uint64_t* __restrict__ scratch, int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_t,
+    int32_t* __restrict__ perm, const VT* __restrict__ val, VT* __restrict__ val_plan,
+    int32_t* __restrict__ col_rel, uint32_t* __restrict__ trow, double* __restrict__ tval,
+    uint32_t* __restrict__ bkept, int rshift, L2RowCount rc, const uint32_t* __restrict__ big,
+    int32_t CB) {
+  static_assert((CAP / NT) * NT == CAP, "CAP must be a multiple of the workgroup size");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_b[3];
+  const L2Lds<CAP> L(smem, b);
+  const uint32_t nbig = min(big[0], (uint32_t)CB);
+  for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const uint32_t cb = big[1 + i];
+    __syncthreads();  // the previous bucket is done with the LDS
+    if (cb >= (uint32_t)CB) continue;
+    l2_bucket<NT, CAP, PLAN, VT>(cb, b, nseg, bstarts, brec, bvhi, gkeys, scratch, row_ptr,
+                                 col_t, perm, val, val_plan, col_rel, trow, tval, bkept,
+                                 rshift, rc, L, s_w, s_b);
+  }
 }
 
 // Values in plan order for the plans built without the partition: val_plan[q] =
