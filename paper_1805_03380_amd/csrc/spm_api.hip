@@ -142,9 +142,10 @@ PartParams part_params(int64_t nseg, int64_t n) {
   PartParams P{false, 0, 0, 1, 1024};
   if (nseg <= 0) return P;
   const spm_tuning tu = tuning();
-  // level-1 kernels keep one LDS counter per bucket (plus under 1 KB of static LDS)
-  const int64_t max_buckets =
-      std::min<int64_t>(kPartMaxBuckets, ((int64_t)max_lds_per_block() - 1024) / 4);
+  // level-1 kernels keep one LDS counter per bucket (plus under 1 KB of static LDS, and the
+  // histogram's sub-tile counters)
+  const int64_t max_buckets = std::min<int64_t>(
+      kPartMaxBuckets, ((int64_t)max_lds_per_block() - 1024 - 4 * kSubMax * 128) / 4);
   const int bmin = ceil_log2(ceil_div(nseg, max_buckets));
   // floor_log2 puts the expected bucket size in (target/2, target]; keep it at most 3/4 of
   // the in-LDS capacity so that ordinary fluctuations stay on the in-LDS path
@@ -165,6 +166,46 @@ PartParams part_params(int64_t nseg, int64_t n) {
   return P;
 }
 
+// Level 1 in two passes (spm_partition.h) once there are this many buckets: a tile then
+// holds only a few elements per bucket, and the single scatter's records would each go to a
+// line of their own.  Super-buckets of 2^kSuperLog2 buckets; pass-B workgroups take K
+// consecutive tiles' slices of a super-bucket, about one LDS chunk each.
+constexpr int32_t kSplitMinBuckets = 4096;
+constexpr int kSuperLog2 = 7;
+static_assert((1 << kSuperLog2) <= kSuperMax, "buckets per super-bucket");
+static_assert(kPartMaxBuckets <= kSuperMax << kSuperLog2, "super-buckets per partition");
+constexpr int kSplitNT = 512;  // threads of a pass-A / pass-B workgroup
+constexpr int kSplitU = 4;     // elements per thread of a chunk
+
+struct SplitParams {
+  bool on;
+  int g;
+  int32_t SB;
+  int SH;           // pass-A sub-tiles per tile
+  int64_t K, nq;    // pass B: tiles per slice, slices per super-bucket
+  int64_t nchunk;   // k_super_offsets: workgroups per super-bucket (64 tiles each)
+};
+
+SplitParams split_params(const PartParams& P) {
+  SplitParams S{false, kSuperLog2, 0, 0, 1, 1, 1};
+  if (!P.ok || P.CB < kSplitMinBuckets) return S;
+  if (staged_lds_bytes(kSplitNT, kSplitU, true) + 2048 > (size_t)max_lds_per_block()) return S;
+  S.on = true;
+  S.SB = (int32_t)ceil_div(P.CB, (int64_t)1 << S.g);
+  const int64_t chunk = (int64_t)kSplitNT * kSplitU;
+  // pass A: enough workgroups to fill the chip several times over, each at least a chunk
+  S.SH = 1;
+  while (S.SH < kSubMax && P.ntiles * S.SH < 4 * (int64_t)cu_count() &&
+         P.T1 / (2 * S.SH) >= chunk)
+    S.SH *= 2;
+  // pass B: a slice of about 85 % of a chunk, so that one chunk nearly always covers it
+  const int64_t K = (chunk * S.SB * 85) / (100 * P.T1);
+  S.K = std::min<int64_t>(std::max<int64_t>(K, 1), P.ntiles);
+  S.nq = ceil_div(P.ntiles, S.K);
+  S.nchunk = ceil_div(P.ntiles + 1, (int64_t)kWave);
+  return S;
+}
+
 // ------------------------------------------------------------------------------------------
 // Assembly workspace layout.  The first region (counters, look-back states, tickets) is
 // zeroed by one kernel at the start of every call.
@@ -179,6 +220,8 @@ struct AsmLayout {
   size_t bucket, scratch;
   // partition path
   size_t table, rowoff, btot, bstart, brec, bvhi, trow, tval, bkept, boff, flags, big;
+  size_t sbro, subcnt;  // two-pass level 1 (its records go to bucket + scratch)
+  SplitParams sp;
   size_t total;
   int64_t fold_tiles;
 };
@@ -215,6 +258,10 @@ AsmLayout asm_layout(int64_t n_cols, int64_t nnz_in) {
   L.boff = c.take(sizeof(int32_t) * (size_t)(cb > kEmitReduceMax ? cb + 1 : 0));
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? L.pp.ntiles : 0));
   L.big = c.take(sizeof(uint32_t) * (size_t)(cb + 1));  // big-bucket list (count, buckets)
+  L.sp = split_params(L.pp);
+  L.sbro = c.take(sizeof(uint32_t) * (size_t)(L.sp.on ? L.sp.SB * (L.pp.ntiles + 1) : 0));
+  L.subcnt = c.take(sizeof(uint32_t) *
+                    (size_t)(L.sp.on ? L.sp.SB * L.sp.SH * L.pp.ntiles : 0));
   L.total = c.off;
   return L;
 }
@@ -223,6 +270,8 @@ struct PlanLayout {
   PartParams pp;
   size_t rowcnt, scan_state, tickets, zero_bytes, first, bucket, scratch;
   size_t colarr, table, rowoff, btot, bstart, brec, bvhi, flags, big, total;
+  size_t sbro, subcnt, ivhi;  // two-pass level 1 (records in bucket + scratch)
+  SplitParams sp;
   int64_t sort_tiles;
 };
 
@@ -258,6 +307,11 @@ PlanLayout plan_ws_layout(int64_t n_rows, int64_t n_cols, int64_t nnz_cap) {
   // status flags: one per k_expand_columns workgroup, then one per k_part_hist tile
   L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? expand_grid(n_cols) + L.pp.ntiles : 0));
   L.big = c.take(sizeof(uint32_t) * (size_t)(cb + 1));  // big-bucket list (count, buckets)
+  L.sp = split_params(L.pp);
+  L.sbro = c.take(sizeof(uint32_t) * (size_t)(L.sp.on ? L.sp.SB * (L.pp.ntiles + 1) : 0));
+  L.subcnt = c.take(sizeof(uint32_t) *
+                    (size_t)(L.sp.on ? L.sp.SB * L.sp.SH * L.pp.ntiles : 0));
+  L.ivhi = c.take(sizeof(uint32_t) * (size_t)(L.sp.on ? nP : 0));
   L.total = c.off;
   return L;
 }
@@ -355,6 +409,36 @@ void launch_level2(int b, int32_t CB, int64_t nseg, const int32_t* bstart, const
             b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
             col_rel, trow, tval, bkept, rshift, rc, big, CB);
   }
+}
+
+// Level 1's scatter into the buckets' records (brec, bvhi) and bstart: one pass, or the two
+// passes of spm_partition.h through irec / ivhi (16 and 4 bytes per element) and sbro.
+template <typename SRC, typename VT>
+void launch_scatter(const SRC& src, const PartParams& P, const SplitParams& S,
+                    const uint32_t* rowoff, const uint32_t* btot, int32_t* bstart, uint4* brec,
+                    const VT* vin, uint32_t* bvhi, uint4* irec, uint32_t* ivhi, uint32_t* sbro,
+                    const uint32_t* subcnt, hipStream_t s) {
+  if (!S.on) {
+    k_part_scatter<kPartNT, SRC, VT>
+        <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
+            src, P.b, P.CB, P.ntiles, P.T1, rowoff, btot, bstart, brec, vin, bvhi);
+    return;
+  }
+  k_super_offsets<kNT><<<dim3((unsigned)(S.SB * S.nchunk)), dim3(kNT), 0, s>>>(
+      btot, rowoff, P.CB, S.g, P.ntiles, S.nchunk, bstart, sbro);
+  const size_t lds = staged_lds_bytes(kSplitNT, kSplitU, ValWords<VT>::kHi);
+  k_part_scatter_a<kSplitNT, SRC, VT>
+      <<<dim3((unsigned)(P.ntiles * S.SH)), dim3(kSplitNT), lds, s>>>(
+          src, P.b, S.g, S.SB, P.ntiles, P.T1, S.SH, sbro, subcnt, irec, vin, ivhi);
+  k_part_scatter_b<kSplitNT, VT>
+      <<<dim3((unsigned)(S.SB * S.nq)), dim3(kSplitNT), lds, s>>>(
+          P.b, S.g, P.CB, P.ntiles, S.K, S.nq, sbro, rowoff, bstart, irec, ivhi, brec, bvhi);
+}
+
+// The histogram's sub-tile counts for the two-pass level 1 (none when it is off).
+SubCounts sub_counts(const SplitParams& S, char* w, size_t off) {
+  return S.on ? SubCounts{reinterpret_cast<uint32_t*>(w + off), S.g, S.SH, S.SB}
+              : SubCounts{nullptr, 0, 0, 0};
 }
 
 spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const int32_t* row,
@@ -570,7 +654,8 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
                          ? reinterpret_cast<uint32_t*>(w + fz->F->big2) : nullptr;
     k_part_hist<kPartNT, PartSrcCoo>
         <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-            src, P.b, P.CB, P.ntiles, P.T1, table, flags, big, big2);
+            src, P.b, P.CB, P.ntiles, P.T1, table, flags, big, big2,
+            sub_counts(L.sp, w, L.subcnt));
     k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
         (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info,
         (uint32_t)kPartCap, big);
@@ -580,10 +665,11 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
                              : L2RowCount{nullptr, 0, 0, 0};
 #define SPM_L2(VT)                                                                             \
   do {                                                                                         \
-  k_part_scatter<kPartNT, PartSrcCoo, VT>                                                      \
-      <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(                      \
-          src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,      \
-          bstart, brec, static_cast<const VT*>(val), bvhi);                                    \
+  launch_scatter<PartSrcCoo, VT>(src, P, L.sp, rowoff, btot, bstart, brec,                    \
+                                 static_cast<const VT*>(val), bvhi,                            \
+                                 reinterpret_cast<uint4*>(bucket), trow,                       \
+                                 reinterpret_cast<uint32_t*>(w + L.sbro),                      \
+                                 reinterpret_cast<const uint32_t*>(w + L.subcnt), s);          \
   launch_level2<false, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,     \
                            (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,          \
                            (int32_t*)nullptr, (int32_t*)nullptr, static_cast<const VT*>(val),  \
@@ -712,14 +798,16 @@ void plan_build_into(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int3
     k_part_hist<kPartNT, PartSrcCsc>
         <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
             src, Q.b, Q.CB, Q.ntiles, Q.T1, table, flags + expand_grid(n_cols), big,
-            (uint32_t*)nullptr);
+            (uint32_t*)nullptr, sub_counts(L.sp, w, L.subcnt));
     k_rows_scan<kNT><<<dim3((unsigned)Q.CB), dim3(kNT), 0, s>>>(
         (const uint32_t*)table, Q.ntiles, rowoff, btot, (const uint32_t*)flags,
         (int64_t)expand_grid(n_cols) + Q.ntiles, info, (uint32_t)kPartCap, big);
-    k_part_scatter<kPartNT, PartSrcCsc, VT>
-        <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
-            src, Q.b, Q.CB, Q.ntiles, Q.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
-            bstart, brec, val_plan ? val : (const VT*)nullptr, bvhi);
+    launch_scatter<PartSrcCsc, VT>(src, Q, L.sp, rowoff, btot, bstart, brec,
+                                   val_plan ? val : (const VT*)nullptr, bvhi,
+                                   reinterpret_cast<uint4*>(bucket),
+                                   reinterpret_cast<uint32_t*>(w + L.ivhi),
+                                   reinterpret_cast<uint32_t*>(w + L.sbro),
+                                   reinterpret_cast<const uint32_t*>(w + L.subcnt), s);
     launch_level2<true, VT>(Q.b, Q.CB, n_rows, (const int32_t*)bstart, (const uint4*)brec,
                             (const uint32_t*)bvhi, bucket, scratch, row_ptr, col_t, perm, val,
                             val_plan, (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
@@ -837,14 +925,15 @@ void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_co
   uint32_t* big = level2_big_ok(P.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
   k_part_hist<kPartNT, PartSrcMerge>
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg, big, (uint32_t*)nullptr);
+          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg, big, (uint32_t*)nullptr,
+          sub_counts(L.sp, w, L.subcnt));
   k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
       (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
       (int64_t)eg + P.ntiles, info, (uint32_t)kPartCap, big);
-  k_part_scatter<kPartNT, PartSrcMerge, VT>
-      <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-          src, P.b, P.CB, P.ntiles, P.T1, (const uint32_t*)rowoff, (const uint32_t*)btot,
-          bstart, brec, (const VT*)vcat, bvhi);
+  launch_scatter<PartSrcMerge, VT>(src, P, L.sp, rowoff, btot, bstart, brec, (const VT*)vcat,
+                                   bvhi, reinterpret_cast<uint4*>(bucket), trow,
+                                   reinterpret_cast<uint32_t*>(w + L.sbro),
+                                   reinterpret_cast<const uint32_t*>(w + L.subcnt), s);
   launch_level2<false, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,
                            (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,
                            (int32_t*)nullptr, (int32_t*)nullptr, (const VT*)vcat, (VT*)nullptr,

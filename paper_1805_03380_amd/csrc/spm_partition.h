@@ -202,13 +202,24 @@ __global__ __launch_bounds__(NT) void k_expand_columns(const int32_t* __restrict
 // Level 1a: per-tile coarse-bucket counts -> table[cb * ntiles + t].
 // zero0 / zero1 (nullable): the counts of the big-bucket lists that k_rows_scan fills next;
 // workgroup 0 clears them.
+// Two-pass level 1 (below): the tile's counts per super-bucket (buckets >> sg) for each of its
+// SH equal sub-tiles, subcnt[(t * SH + h) * SB + s]; SH == 0 for none.
+struct SubCounts {
+  uint32_t* subcnt;
+  int sg;     // log2(buckets per super-bucket)
+  int SH;     // sub-tiles per tile (a power of two), 0: not counted
+  int32_t SB;
+};
+constexpr int kSubMax = 8;  // sub-tiles per tile at most
+
 template <int NT, typename SRC>
 __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, int64_t ntiles,
                                                   int64_t T1, uint32_t* __restrict__ table,
                                                   uint32_t* __restrict__ flags,
                                                   uint32_t* __restrict__ zero0,
-                                                  uint32_t* __restrict__ zero1) {
+                                                  uint32_t* __restrict__ zero1, SubCounts sc) {
   __shared__ uint32_t s_flag;
+  __shared__ uint32_t s_sub[kSubMax * 128];
   extern __shared__ uint32_t h[];  // CB counters (dynamic LDS, 4*CB bytes)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (zero0) *zero0 = 0;
@@ -217,6 +228,9 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = src.count();
   for (int i = threadIdx.x; i < CB; i += NT) h[i] = 0;
+  const int nsub = sc.SH * sc.SB;
+  for (int i = threadIdx.x; i < nsub; i += NT) s_sub[i] = 0;
+  const int sub_shift = sc.SH > 0 ? 63 - __clzll((unsigned long long)(T1 / sc.SH)) : 0;
   if (threadIdx.x == 0) s_flag = 0;
   __syncthreads();
   bool bad = false;
@@ -238,12 +252,21 @@ __global__ __launch_bounds__(NT) void k_part_hist(SRC src, int b, int32_t CB, in
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (ok[u]) atomicAdd(&h[seg[u] >> b], 1u);
+    for (int u = 0; u < U; ++u) {
+      if (ok[u]) {
+        atomicAdd(&h[seg[u] >> b], 1u);
+        if (nsub) {
+          const int64_t e = e0 + (int64_t)u * NT;
+          const int hh = (int)((e - base) >> sub_shift);
+          atomicAdd(&s_sub[hh * sc.SB + (seg[u] >> (b + sc.sg))], 1u);
+        }
+      }
+    }
   }
   if (bad) s_flag = kFlagIndex;
   __syncthreads();
   for (int i = threadIdx.x; i < CB; i += NT) table[(int64_t)i * ntiles + t] = h[i];
+  for (int i = threadIdx.x; i < nsub; i += NT) sc.subcnt[t * nsub + i] = s_sub[i];
   if (flags && threadIdx.x == 0) flags[t] = s_flag;
 }
 
@@ -385,6 +408,236 @@ __global__ __launch_bounds__(NT) void k_part_scatter(SRC src, int b, int32_t CB,
         if (ValWords<VT>::kHi && carry) bvhi[pos] = ValWords<VT>::hi(v[u]);
       }
     }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Level 1 in two passes, for many buckets.  With CB in the thousands a tile holds only a few
+// elements of each bucket, so the single scatter above writes every record to a line of its
+// own.  Instead the buckets are taken in super-buckets of 2^g consecutive buckets:
+//   k_super_offsets  bstart of every bucket, and for every super-bucket s and tile t the
+//                    offset sbro[s][t] = bstart[s 2^g] + sum of rowoff over s's buckets (the
+//                    start of tile t's elements of s in super-bucket order; sbro[s][ntiles]
+//                    is the end of s);
+//   k_part_scatter_a each tile sorts chunks of its elements by super-bucket in LDS and
+//                    writes them out as runs at sbro[s][t] onwards (irec);
+//   k_part_scatter_b each (super-bucket, group of K tiles) reads its slice of irec, sorts
+//                    chunks by bucket in LDS and writes runs at bstart[cb] + rowoff[cb][first
+//                    tile of the group] onwards (brec, the same layout as the single scatter).
+// Every bucket receives exactly its elements; their order inside a bucket differs from the
+// single scatter's, which level 2 does not see (it sorts by the unique key).
+// ------------------------------------------------------------------------------------------
+constexpr int kSuperMax = 128;       // super-buckets (and buckets per super-bucket) at most
+constexpr uint32_t kNoGroup = 0xffffffffu;
+
+// One chunk of NT*U elements (element u of thread i; grp == kNoGroup for none) goes out in
+// runs: a counting sort by group in LDS (stage, stage_g, and stage_hi for HI), then every
+// staged record is written to cur[its group] + its position among the group's records, so
+// neighbouring lanes write neighbouring addresses; cur advances by the group counts.
+template <int NT, int U, bool HI>
+__device__ __forceinline__ void staged_runs(const uint32_t (&grp)[U], const uint4 (&rec)[U],
+                                            const uint32_t (&hi)[U], int ng, uint32_t* cnt,
+                                            uint32_t* cur, uint4* stage, uint32_t* stage_hi,
+                                            uint8_t* stage_g, uint4* __restrict__ out,
+                                            uint32_t* __restrict__ out_hi) {
+  static_assert(kSuperMax <= 2 * kWave, "one wave scans the group counts");
+  for (int i = threadIdx.x; i <= ng; i += NT) cnt[i] = 0;
+  __syncthreads();
+  uint32_t rank[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) rank[u] = grp[u] != kNoGroup ? atomicAdd(&cnt[grp[u]], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < kWave) {  // cnt[g] = end of group g in the chunk (ng <= 2 * kWave)
+    const int l = threadIdx.x;
+    const uint32_t a = 2 * l < ng ? cnt[2 * l] : 0u;
+    const uint32_t c = 2 * l + 1 < ng ? cnt[2 * l + 1] : 0u;
+    const uint32_t incl = wave_incl_scan(a + c);
+    if (2 * l < ng) cnt[2 * l] = incl - c;
+    if (2 * l + 1 < ng) cnt[2 * l + 1] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (grp[u] != kNoGroup) {
+      const uint32_t slot = (grp[u] ? cnt[grp[u] - 1] : 0u) + rank[u];
+      stage[slot] = rec[u];
+      stage_g[slot] = (uint8_t)grp[u];
+      if (HI) stage_hi[slot] = hi[u];
+    }
+  }
+  __syncthreads();
+  const uint32_t m = ng > 0 ? cnt[ng - 1] : 0u;
+  for (uint32_t i = threadIdx.x; i < m; i += NT) {
+    const uint32_t gi = stage_g[i];
+    const uint32_t dst = cur[gi] + (i - (gi ? cnt[gi - 1] : 0u));
+    out[dst] = stage[i];
+    if (HI) out_hi[dst] = stage_hi[i];
+  }
+  __syncthreads();
+  for (int gi = threadIdx.x; gi < ng; gi += NT) cur[gi] += cnt[gi] - (gi ? cnt[gi - 1] : 0u);
+  __syncthreads();
+}
+
+__host__ __device__ inline size_t staged_lds_bytes(int nt, int u, bool hi) {
+  const size_t c = (size_t)nt * u;
+  return c * 16 + (hi ? c * 4 : 0) + c;
+}
+
+// bstart of every bucket and the super-bucket offsets sbro[s][t] (t = 0 .. ntiles).  Workgroup
+// (s, c) takes super-bucket s of G = 2^g buckets and tiles [64 c, 64 c + 64): each of its four
+// waves sums a quarter of the buckets' rowoff entries for its lane's tile (independent loads,
+// eight in flight), LDS adds the quarters.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_super_offsets(const uint32_t* __restrict__ btot,
+                                                      const uint32_t* __restrict__ rowoff,
+                                                      int32_t CB, int g, int64_t ntiles,
+                                                      int64_t nchunk,
+                                                      int32_t* __restrict__ bstart,
+                                                      uint32_t* __restrict__ sbro) {
+  static_assert(NT == 4 * kWave && NT >= kSuperMax, "four waves; one thread per bucket");
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ uint32_t s_part[4][kWave];
+  const int64_t s = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
+  const int64_t cb0 = s << g;
+  const int64_t ng = min((int64_t)1 << g, (int64_t)CB - cb0);
+  uint32_t part = 0;
+  for (int64_t i = threadIdx.x; i < cb0; i += NT) part += btot[i];
+  uint32_t base;
+  (void)wg_excl_scan<NT>(part, s_w, &base);
+  const uint32_t v = threadIdx.x < ng ? btot[cb0 + threadIdx.x] : 0u;
+  uint32_t tot;
+  const uint32_t ex = wg_excl_scan<NT>(v, s_w, &tot);
+  if (c == 0) {
+    if (threadIdx.x < ng) bstart[cb0 + threadIdx.x] = (int32_t)(base + ex);
+    if (cb0 + ng == CB && threadIdx.x == 0) bstart[CB] = (int32_t)(base + tot);
+  }
+  const int64_t t = c * kWave + lane_id();
+  const int q = wave_id();
+  const int64_t j0 = (ng * q) / 4, j1 = (ng * (q + 1)) / 4;
+  uint32_t sum = 0;
+  if (t < ntiles) {
+    int64_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      uint32_t r[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) r[k] = rowoff[(cb0 + j + k) * ntiles + t];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sum += r[k];
+    }
+    for (; j < j1; ++j) sum += rowoff[(cb0 + j) * ntiles + t];
+  }
+  s_part[q][lane_id()] = sum;
+  __syncthreads();
+  if (q == 0 && t <= ntiles) {
+    const uint32_t all = s_part[0][lane_id()] + s_part[1][lane_id()] + s_part[2][lane_id()] +
+                         s_part[3][lane_id()];
+    sbro[s * (ntiles + 1) + t] = base + (t < ntiles ? all : tot);
+  }
+}
+
+// Pass A: tile t's elements into super-bucket order (record z = segment within the
+// super-bucket: bucket within it above bit b, segment within the bucket below).
+// Workgroup (t, h) takes sub-tile h of tile t (SH sub-tiles per tile); its cursor for
+// super-bucket s starts after the s-elements of the sub-tiles before it (subcnt).
+template <int NT, typename SRC, typename VT>
+__global__ __launch_bounds__(NT) void k_part_scatter_a(SRC src, int b, int g, int32_t SB,
+                                                       int64_t ntiles, int64_t T1, int SH,
+                                                       const uint32_t* __restrict__ sbro,
+                                                       const uint32_t* __restrict__ subcnt,
+                                                       uint4* __restrict__ irec,
+                                                       const VT* __restrict__ vin,
+                                                       uint32_t* __restrict__ ivhi) {
+  constexpr int U = 4;
+  constexpr bool HI = ValWords<VT>::kHi;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint4* stage = reinterpret_cast<uint4*>(smem);
+  uint32_t* stage_hi = reinterpret_cast<uint32_t*>(smem + (size_t)NT * U * 16);
+  uint8_t* stage_g = smem + (size_t)NT * U * (HI ? 20 : 16);
+  __shared__ uint32_t cnt[kSuperMax + 1], cur[kSuperMax];
+  const int64_t th = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t t = th / SH, hh = th % SH;
+  const int64_t n = src.count();
+  for (int i = threadIdx.x; i < SB; i += NT) {
+    uint32_t c = sbro[(int64_t)i * (ntiles + 1) + t];
+    for (int64_t k = 0; k < hh; ++k) c += subcnt[(t * SH + k) * SB + i];
+    cur[i] = c;
+  }
+  __syncthreads();
+  const bool carry = vin != nullptr;
+  const uint32_t zmask = (1u << (b + g)) - 1u;
+  const int64_t sub = T1 / SH;
+  const int64_t base = t * T1 + hh * sub;
+  const int64_t end = (base + sub < n) ? base + sub : n;
+  for (int64_t e0 = base; e0 < end; e0 += (int64_t)NT * U) {
+    uint32_t grp[U], hi[U];
+    uint4 rec[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * NT + threadIdx.x;
+      uint32_t seg;
+      uint64_t key;
+      grp[u] = kNoGroup;
+      hi[u] = 0u;
+      rec[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < end && (int)src.elem(e, seg, key) == kElemOk) {
+        const VT v = carry ? vin[e] : VT(0);
+        grp[u] = seg >> (b + g);
+        rec[u] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), seg & zmask,
+                            carry ? ValWords<VT>::lo(v) : 0u);
+        if (HI && carry) hi[u] = ValWords<VT>::hi(v);
+      }
+    }
+    staged_runs<NT, U, HI>(grp, rec, hi, SB, cnt, cur, stage, stage_hi, stage_g, irec, ivhi);
+  }
+}
+
+// Pass B: the slice of super-bucket s that tiles [q K, q K + K) wrote, into its buckets.
+template <int NT, typename VT>
+__global__ __launch_bounds__(NT) void k_part_scatter_b(int b, int g, int32_t CB,
+                                                       int64_t ntiles, int64_t K, int64_t nq,
+                                                       const uint32_t* __restrict__ sbro,
+                                                       const uint32_t* __restrict__ rowoff,
+                                                       const int32_t* __restrict__ bstart,
+                                                       const uint4* __restrict__ irec,
+                                                       const uint32_t* __restrict__ ivhi,
+                                                       uint4* __restrict__ brec,
+                                                       uint32_t* __restrict__ bvhi) {
+  constexpr int U = 4;
+  constexpr bool HI = ValWords<VT>::kHi;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint4* stage = reinterpret_cast<uint4*>(smem);
+  uint32_t* stage_hi = reinterpret_cast<uint32_t*>(smem + (size_t)NT * U * 16);
+  uint8_t* stage_g = smem + (size_t)NT * U * (HI ? 20 : 16);
+  __shared__ uint32_t cnt[kSuperMax + 1], cur[kSuperMax];
+  const int64_t idx = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s = idx / nq, q = idx % nq;
+  const int64_t t0 = q * K;
+  const int64_t t1 = t0 + K < ntiles ? t0 + K : ntiles;
+  const int64_t cb0 = s << g;
+  const int ng = (int)min((int64_t)1 << g, (int64_t)CB - cb0);
+  const uint32_t lo = sbro[s * (ntiles + 1) + t0], hi_end = sbro[s * (ntiles + 1) + t1];
+  for (int j = threadIdx.x; j < ng; j += NT)
+    cur[j] = (uint32_t)bstart[cb0 + j] + rowoff[(cb0 + j) * ntiles + t0];
+  __syncthreads();
+  const uint32_t wmask = (1u << b) - 1u;
+  for (int64_t e0 = lo; e0 < (int64_t)hi_end; e0 += (int64_t)NT * U) {
+    uint32_t grp[U], hi[U];
+    uint4 rec[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * NT + threadIdx.x;
+      grp[u] = kNoGroup;
+      hi[u] = 0u;
+      rec[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < (int64_t)hi_end) {
+        rec[u] = irec[e];
+        grp[u] = rec[u].z >> b;
+        if (grp[u] >= (uint32_t)ng) grp[u] = kNoGroup;  // never, for records pass A wrote
+        rec[u].z &= wmask;
+        if (HI) hi[u] = ivhi[e];
+      }
+    }
+    staged_runs<NT, U, HI>(grp, rec, hi, ng, cnt, cur, stage, stage_hi, stage_g, brec, bvhi);
   }
 }
 
