@@ -23,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.json")
 
 SPMM_SPACE = {"spmm_block": [64, 128, 256], "spmm_blocks_per_cu": [8, 16, 32, 64]}
-PART_SPACE = {"part_bucket_target": [512, 1024, 2048], "part_max_tiles": [64, 128, 256, 512]}
+PART_SPACE = {"part_bucket_target": [512, 1024, 2048],
+              "part_max_tiles": [64, 128, 256, 512, 1024]}
 BATCH_SPACE = {"batch_wg_per_cu": [1, 2, 3, 4], "batch_spmm_wg_per_cu": [4, 8, 16]}
 
 
@@ -118,7 +119,7 @@ def tune_pipeline(p, reps: int = 10):
     col = torch.from_numpy(p.col).to(dev)
     val = torch.from_numpy(p.val).to(dev)
     X = torch.from_numpy(p.X).to(dev)
-    G = torch.from_numpy(p.G).to(dev).to(X.dtype)
+    G = torch.from_numpy(p.G).to(dev)  # in Y's element type, as a loss hands it over
     result = {}
 
     def make():  # the workspace sizes follow the grouping parameters
@@ -161,24 +162,49 @@ def tune_batch(problems, reps: int = 3):
     return best, {"batch_ms": ms, "batch_log": log}
 
 
-def main():
+# workload name -> (synth constructor, keyword arguments)
+PIPELINE_WORKLOADS = {
+    "uniform": ("uniform_1e5", {"value_dtype": "float32"}),
+    "uniform_f64": ("uniform_1e5", {"value_dtype": "float64"}),
+    "powerlaw": ("powerlaw_1e6", {}),
+    "diff": ("diff_2e5", {}),
+}
+
+
+def pipeline_signature(p) -> str:
+    return signature("pipeline", p.n_rows, p.n_cols, p.nnz_in, p.k, p.val.dtype.name,
+                     p.X.dtype.name)
+
+
+def main(argv=None):
+    import argparse
     import numpy as np
     from . import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workloads", default=",".join(list(PIPELINE_WORKLOADS) + ["batch"]),
+                    help="comma-separated: %s, batch" % ", ".join(PIPELINE_WORKLOADS))
+    args = ap.parse_args(argv)
     table = load_table()
     dev = device_key()
     entries = table.setdefault(dev, {})
     t0 = time.time()
-    p = synth.uniform_1e5(value_dtype=np.float32, k=64)
-    tu, info = tune_pipeline(p)
-    sig = signature("pipeline", p.n_rows, p.n_cols, p.nnz_in, p.k, "float32", "float32")
-    entries[sig] = {"tuning": tu, "ms": {"spmm": info["spmm_ms"],
-                                          "assemble_plan": info["assemble_plan_ms"]}}
-    print(sig, tu, info["spmm_ms"], info["assemble_plan_ms"], flush=True)
-    bt = synth.batch_problems()
-    tb, infob = tune_batch(bt.problems)
-    sigb = signature("batch", 8192, 8192, 131072, 32, "float32", "float32")
-    entries[sigb] = {"tuning": tb, "ms": {"batch": infob["batch_ms"]}}
-    print(sigb, tb, infob["batch_ms"], flush=True)
+    for name in args.workloads.split(","):
+        if name == "batch":
+            bt = synth.batch_problems()
+            tb, infob = tune_batch(bt.problems)
+            sigb = signature("batch", 8192, 8192, 131072, 32, "float32", "float32")
+            entries[sigb] = {"tuning": tb, "ms": {"batch": infob["batch_ms"]}}
+            print(sigb, tb, infob["batch_ms"], flush=True)
+            continue
+        ctor, kw = PIPELINE_WORKLOADS[name]
+        kw = {k: (np.dtype(v).type if k == "value_dtype" else v) for k, v in kw.items()}
+        p = getattr(synth, ctor)(**kw)
+        tu, info = tune_pipeline(p)
+        sig = pipeline_signature(p)
+        entries[sig] = {"tuning": tu, "ms": {"spmm": info["spmm_ms"],
+                                              "assemble_plan": info["assemble_plan_ms"]}}
+        print(sig, tu, info["spmm_ms"], info["assemble_plan_ms"], flush=True)
+        del p
     print("saved", save_table(table), "in %.1f s" % (time.time() - t0), flush=True)
 
 
