@@ -50,7 +50,16 @@
 extern "C" {
 #endif
 
-typedef enum spm_status {
+/* Under C++ the enumerations have int as their underlying type, so every int a C caller
+ * passes is a value of the type (an unknown one is then rejected by the checks below); in C an
+ * enumeration is an int already. */
+#ifdef __cplusplus
+#define SPM_ENUM_INT : int
+#else
+#define SPM_ENUM_INT
+#endif
+
+typedef enum spm_status SPM_ENUM_INT {
   SPM_OK = 0,
   SPM_EINVAL = 1,     /* null pointer, negative size, k < 1, bad leading dimension, bad CSC */
   SPM_EBOUNDS = 2,    /* (device) a triplet's row or column is outside the matrix */
@@ -60,7 +69,7 @@ typedef enum spm_status {
   SPM_EHIP = 6        /* a HIP runtime call or kernel launch failed */
 } spm_status;
 
-typedef enum spm_dtype {
+typedef enum spm_dtype SPM_ENUM_INT {
   SPM_F64 = 0,  /* IEEE binary64 */
   SPM_F32 = 1,  /* IEEE binary32 */
   SPM_BF16 = 2  /* bfloat16, stored as uint16 */
@@ -72,7 +81,7 @@ typedef enum spm_dtype {
  *                   spm_csc_plan_build with values); the product reads val[q] contiguously.
  * Plan-order values are a copy: after the CSC values change they must be rebuilt (or the
  * CSC order used). */
-typedef enum spm_val_order { SPM_ORDER_CSC = 0, SPM_ORDER_PLAN = 1 } spm_val_order;
+typedef enum spm_val_order SPM_ENUM_INT { SPM_ORDER_CSC = 0, SPM_ORDER_PLAN = 1 } spm_val_order;
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *spm_status_string(int status);
