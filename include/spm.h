@@ -129,6 +129,10 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
 spm_status spm_csc_plan_size(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                              size_t *plan_bytes, size_t *ws_bytes);
 
+/* Host only.  The plan size alone (the plan_bytes of spm_csc_plan_size). */
+spm_status spm_csc_plan_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                              size_t *plan_bytes);
+
 /* Build the plan of the CSC pattern (col_ptr[n_cols+1], row_idx[nnz]) where nnz =
  * col_ptr[n_cols] is read on the device and must not exceed nnz_cap.
  *   val, val_plan  optional (both NULL, or both given): the CSC values (val_type F64 or F32,
@@ -434,13 +438,26 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item *items,
                          float *dval, int32_t *info, int64_t max_dim, int64_t max_nnz_in,
                          int32_t workers, void *ws, size_t ws_bytes, void *stream);
 
+/* spm_batch_run with the named tuning tune_key (spm_tuning_register) in effect for this call
+ * only (NULL: the tuning already in effect; SPM_EINVAL for an unknown key, nothing enqueued). */
+spm_status spm_batch_coo_to_csc_spmm(int32_t batch, int64_t k, const spm_batch_item *items,
+                                     const int32_t *order, const int32_t *row,
+                                     const int32_t *col, const void *val, spm_dtype val_type,
+                                     const void *X, const void *G, spm_dtype x_type,
+                                     int32_t *col_ptr, int32_t *row_idx, float *val_out,
+                                     int32_t *row_ptr, int32_t *col_t, int32_t *perm, float *Y,
+                                     float *dX, float *dval, int32_t *info, int64_t max_dim,
+                                     int64_t max_nnz_in, int32_t workers, void *ws,
+                                     size_t ws_bytes, const char *tune_key, void *stream);
+
 /* ------------------------------------------------------------------------------------------
  * Tuning.  Launch-shape parameters that never change results (see Numerics above): they
  * decide how work is cut into workgroups, never the order in which any output is summed.
- * The values are process-wide; spm_tuning_set validates and copies them (host only).  The
- * grouping parameters change the workspace sizes that spm_coo_to_csc_workspace and
- * spm_csc_plan_size report: ask for sizes after setting the tuning (a call made with a smaller
- * workspace fails with SPM_EWORKSPACE, it never overruns).
+ * spm_tuning_set validates and copies process-wide values (host only); named tunings below
+ * give a thread or a call values of its own.  The grouping parameters change the workspace
+ * sizes that spm_coo_to_csc_workspace and spm_csc_plan_size report: ask for sizes after
+ * setting the tuning (a call made with a smaller workspace fails with SPM_EWORKSPACE, it never
+ * overruns).
  * ------------------------------------------------------------------------------------------ */
 typedef struct spm_tuning {
   int32_t spmm_block;          /* threads per workgroup of the forward / backward kernels:
@@ -459,8 +476,18 @@ typedef struct spm_tuning {
   int32_t reserved;
 } spm_tuning;
 
+/* The tuning in effect for the calling thread (its selection, else the process-wide values). */
 spm_status spm_tuning_get(spm_tuning *out);
+/* Set the process-wide values (SPM_EINVAL for a value outside the ranges above). */
 spm_status spm_tuning_set(const spm_tuning *in);
+
+/* Named tunings ("tune keys"), so that callers with different shapes in one process do not
+ * share one mutable setting: spm_tuning_register stores a validated copy under key (replacing
+ * an earlier one); spm_tuning_select makes it the calling thread's tuning for every later call
+ * from that thread (NULL: back to the process-wide values; SPM_EINVAL for an unknown key).
+ * Workspace sizes follow the tuning in effect, as above. */
+spm_status spm_tuning_register(const char *key, const spm_tuning *in);
+spm_status spm_tuning_select(const char *key);
 
 #ifdef __cplusplus
 }

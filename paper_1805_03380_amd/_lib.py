@@ -69,6 +69,21 @@ def set_tuning(**kw) -> Tuning:
     return old
 
 
+def register_tuning(key: str, **kw) -> None:
+    """Store a named tuning (spm_tuning_register): the current values with `kw` changed."""
+    t = Tuning.from_buffer_copy(get_tuning())
+    for k, v in kw.items():
+        if k not in Tuning.FIELDS:
+            raise KeyError(k)
+        setattr(t, k, int(v))
+    check(load().spm_tuning_register(key.encode(), ctypes.byref(t)), "spm_tuning_register")
+
+
+def select_tuning(key: str | None) -> None:
+    """Make a named tuning the calling thread's (spm_tuning_select); None: process values."""
+    check(load().spm_tuning_select(None if key is None else key.encode()), "spm_tuning_select")
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "spm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -121,8 +136,16 @@ SIGNATURES = {
     "spm_batch_run": (ctypes.c_int, [c_i32, c_i64, c_p, c_p, c_p, c_p, c_p, ctypes.c_int, c_p,
                                      c_p, ctypes.c_int, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                      c_p, c_p, c_i64, c_i64, c_i32, c_p, ctypes.c_size_t, c_p]),
+    "spm_batch_coo_to_csc_spmm": (ctypes.c_int, [c_i32, c_i64, c_p, c_p, c_p, c_p, c_p,
+                                                 ctypes.c_int, c_p, c_p, ctypes.c_int, c_p, c_p,
+                                                 c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_i64,
+                                                 c_i64, c_i32, c_p, ctypes.c_size_t,
+                                                 ctypes.c_char_p, c_p]),
+    "spm_csc_plan_bytes": (ctypes.c_int, [c_i64, c_i64, c_i64, c_size_p]),
     "spm_tuning_get": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "spm_tuning_set": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+    "spm_tuning_register": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+    "spm_tuning_select": (ctypes.c_int, [ctypes.c_char_p]),
 }
 
 

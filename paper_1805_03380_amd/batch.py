@@ -114,20 +114,33 @@ class PackedBatch:
         if ws.value > self.ws.numel():
             self.ws = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
 
-    def run_batched(self, out=None, stream=None):
-        """All matrices: the grouping launch, then the product launches (spm_batch_run)."""
-        self._ensure_workspace()
+    def run_batched(self, out=None, stream=None, tune_key: str | None = None):
+        """All matrices: the grouping launch, then the product launches (spm_batch_run; with a
+        named tuning, spm_batch_coo_to_csc_spmm with that key for this call)."""
+        if tune_key is not None:  # the workspace follows the tuning the call will run with
+            _lib.select_tuning(tune_key)
+            try:
+                self._ensure_workspace()
+            finally:
+                _lib.select_tuning(None)
+        else:
+            self._ensure_workspace()
         o = self.out if out is None else out
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        st = self.lib.spm_batch_run(
-            self.B, self.k, self.items.data_ptr(), self.order.data_ptr(), self.row.data_ptr(),
-            self.col.data_ptr(), self.val.data_ptr(), _DT[self.val_dtype], self.X.data_ptr(),
-            self.G.data_ptr(), _DT[self.x_dtype], o["col_ptr"].data_ptr(),
-            o["row_idx"].data_ptr(), o["val_out"].data_ptr(), o["row_ptr"].data_ptr(),
-            o["col_t"].data_ptr(), o["perm"].data_ptr(), o["Y"].data_ptr(), o["dX"].data_ptr(),
-            o["dval"].data_ptr(), o["info"].data_ptr(), self.max_dim, self.max_nnz,
-            self.workers, self.ws.data_ptr(), self.ws.numel(), s.cuda_stream)
-        _lib.check(st, "spm_batch_run")
+        args = [self.B, self.k, self.items.data_ptr(), self.order.data_ptr(), self.row.data_ptr(),
+                self.col.data_ptr(), self.val.data_ptr(), _DT[self.val_dtype],
+                self.X.data_ptr(), self.G.data_ptr(), _DT[self.x_dtype],
+                o["col_ptr"].data_ptr(), o["row_idx"].data_ptr(), o["val_out"].data_ptr(),
+                o["row_ptr"].data_ptr(), o["col_t"].data_ptr(), o["perm"].data_ptr(),
+                o["Y"].data_ptr(), o["dX"].data_ptr(), o["dval"].data_ptr(),
+                o["info"].data_ptr(), self.max_dim, self.max_nnz, self.workers,
+                self.ws.data_ptr(), self.ws.numel()]
+        if tune_key is None:
+            st = self.lib.spm_batch_run(*args, s.cuda_stream)
+            _lib.check(st, "spm_batch_run")
+        else:
+            st = self.lib.spm_batch_coo_to_csc_spmm(*args, tune_key.encode(), s.cuda_stream)
+            _lib.check(st, "spm_batch_coo_to_csc_spmm")
         return o
 
     def run_single(self, out=None, stream=None, keep_plan: bool = True):

@@ -5,7 +5,9 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "spm.h"
@@ -45,10 +47,16 @@ struct Carve {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Tuning in effect for a call: the calling thread's selection (spm_tuning_select) if it made
+// one, else the process-wide values (spm_tuning_set).  Named tunings live in a registry.
 spm_tuning g_tuning = {256, 64, 2, 2048, 512, 0, 0, 0};
 std::mutex g_tuning_mu;
+std::map<std::string, spm_tuning> g_tuning_named;
+thread_local bool t_tuning_on = false;
+thread_local spm_tuning t_tuning;
 
 spm_tuning tuning() {
+  if (t_tuning_on) return t_tuning;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   return g_tuning;
 }
@@ -1365,7 +1373,7 @@ spm_status spm_tuning_get(spm_tuning* out) {
   return SPM_OK;
 }
 
-spm_status spm_tuning_set(const spm_tuning* in) {
+static spm_status tuning_valid(const spm_tuning* in) {
   if (!in) return SPM_EINVAL;
   auto pow2 = [](int32_t x) { return x > 0 && (x & (x - 1)) == 0; };
   if (in->spmm_block != 64 && in->spmm_block != 128 && in->spmm_block != 256) return SPM_EINVAL;
@@ -1380,9 +1388,44 @@ spm_status spm_tuning_set(const spm_tuning* in) {
     return SPM_EINVAL;
   if (!pow2(in->part_max_tiles) || in->part_max_tiles < 64 || in->part_max_tiles > 4096)
     return SPM_EINVAL;
+  return SPM_OK;
+}
+
+spm_status spm_tuning_set(const spm_tuning* in) {
+  const spm_status st = tuning_valid(in);
+  if (st != SPM_OK) return st;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning = *in;
   return SPM_OK;
+}
+
+spm_status spm_tuning_register(const char* key, const spm_tuning* in) {
+  if (!key || !*key) return SPM_EINVAL;
+  const spm_status st = tuning_valid(in);
+  if (st != SPM_OK) return st;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning_named[key] = *in;
+  return SPM_OK;
+}
+
+spm_status spm_tuning_select(const char* key) {
+  if (!key) {
+    t_tuning_on = false;
+    return SPM_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  const auto it = g_tuning_named.find(key);
+  if (it == g_tuning_named.end()) return SPM_EINVAL;
+  t_tuning = it->second;
+  t_tuning_on = true;
+  return SPM_OK;
+}
+
+spm_status spm_csc_plan_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+                              size_t* plan_bytes) {
+  if (!plan_bytes) return SPM_EINVAL;
+  size_t ws = 0;
+  return spm_csc_plan_size(n_rows, n_cols, nnz_cap, plan_bytes, &ws);
 }
 
 }  // extern "C"
@@ -1562,6 +1605,31 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
   launch_batch_nt<256>(a, val_type, x_type, w, batch_spmm_workers(batch), (size_t)w * stride,
                        s);
   return launch_status();
+}
+
+spm_status spm_batch_coo_to_csc_spmm(int32_t batch, int64_t k, const spm_batch_item* items,
+                                     const int32_t* order, const int32_t* row,
+                                     const int32_t* col, const void* val, spm_dtype val_type,
+                                     const void* X, const void* Gm, spm_dtype x_type,
+                                     int32_t* col_ptr, int32_t* row_idx, float* val_out,
+                                     int32_t* row_ptr, int32_t* col_t, int32_t* perm, float* Y,
+                                     float* dX, float* dval, int32_t* info, int64_t max_dim,
+                                     int64_t max_nnz_in, int32_t workers, void* ws,
+                                     size_t ws_bytes, const char* tune_key, void* stream) {
+  // the named tuning for this call only: the thread's own selection is restored afterwards
+  const bool had = t_tuning_on;
+  const spm_tuning saved = t_tuning;
+  if (tune_key) {
+    const spm_status st = spm_tuning_select(tune_key);
+    if (st != SPM_OK) return st;
+  }
+  const spm_status st = spm_batch_run(batch, k, items, order, row, col, val, val_type, X, Gm,
+                                      x_type, col_ptr, row_idx, val_out, row_ptr, col_t, perm,
+                                      Y, dX, dval, info, max_dim, max_nnz_in, workers, ws,
+                                      ws_bytes, stream);
+  t_tuning_on = had;
+  t_tuning = saved;
+  return st;
 }
 
 }  // extern "C"

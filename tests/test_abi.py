@@ -278,3 +278,50 @@ def test_tuning_roundtrip():
     lib.spm_tuning_get(ctypes.byref(chk))
     assert chk.spmm_block == 128 and chk.part_bucket_target == 1024
     assert lib.spm_tuning_set(ctypes.byref(saved)) == _lib.OK
+
+
+def test_named_tunings_per_thread():
+    """A named tuning selected by one thread is that thread's alone; NULL goes back to the
+    process values; unknown keys and invalid values are refused."""
+    import threading
+    lib = _lib_or_build()
+    base = _lib.get_tuning().as_dict()
+    _lib.register_tuning("narrow", spmm_block=64, spmm_blocks_per_cu=4)
+    _lib.register_tuning("wide", spmm_block=256, spmm_blocks_per_cu=64)
+    seen = {}
+
+    def worker(key):
+        _lib.select_tuning(key)
+        seen[key] = _lib.get_tuning().as_dict()
+        _lib.select_tuning(None)
+        seen[key + "/after"] = _lib.get_tuning().as_dict()
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in ("narrow", "wide")]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert seen["narrow"]["spmm_block"] == 64 and seen["narrow"]["spmm_blocks_per_cu"] == 4
+    assert seen["wide"]["spmm_block"] == 256 and seen["wide"]["spmm_blocks_per_cu"] == 64
+    assert seen["narrow/after"] == base and seen["wide/after"] == base
+    assert _lib.get_tuning().as_dict() == base  # this thread never selected one
+    assert lib.spm_tuning_select(b"no such key") == _lib.EINVAL
+    bad = _lib.Tuning.from_buffer_copy(_lib.get_tuning())
+    bad.spmm_block = 100
+    assert lib.spm_tuning_register(b"bad", ctypes.byref(bad)) == _lib.EINVAL
+    assert lib.spm_tuning_register(None, ctypes.byref(bad)) == _lib.EINVAL
+
+
+def test_plan_bytes_alias_and_batch_key_checks():
+    lib = _lib_or_build()
+    pb, wb, pb2 = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+    for shape in ((10, 10, 100), (100_000, 100_000, 1_000_000)):
+        assert lib.spm_csc_plan_size(*shape, ctypes.byref(pb), ctypes.byref(wb)) == _lib.OK
+        assert lib.spm_csc_plan_bytes(*shape, ctypes.byref(pb2)) == _lib.OK
+        assert pb.value == pb2.value
+    assert lib.spm_csc_plan_bytes(-1, 1, 1, ctypes.byref(pb2)) == _lib.EINVAL
+    fake = 0x1000
+    args = [4, 32] + [fake] * 5 + [_lib.F32, fake, fake, _lib.F32] + [fake] * 10 + \
+        [64, 1024, 0, 0x100000, 1 << 30]
+    # an unknown key is refused before anything is enqueued
+    assert lib.spm_batch_coo_to_csc_spmm(*args, b"never registered", None) == _lib.EINVAL

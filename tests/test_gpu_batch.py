@@ -119,6 +119,50 @@ def test_full_batch_workload_bitwise_and_sampled_oracle(full_batch, dtype):
     order = pb.order_host
     for b in [int(order[0]), int(order[-1]), 0, 1234, 4095]:
         _oracle_check(pb, o_b, bt.problems, b, acc_f32=(dtype == torch.bfloat16))
+    if dtype == torch.float32:
+        _all_structures_match_oracle(pb, o_b, bt.problems)
+
+
+def _all_structures_match_oracle(pb, out, problems):
+    """Every matrix of the batch: col_ptr, row_idx and the stored values bit for bit against
+    the oracle (host threads; the oracle's C code runs without the interpreter lock)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    cp_all = out["col_ptr"].cpu().numpy()
+    ri_all = out["row_idx"].cpu().numpy()
+    vo_all = out["val_out"].cpu().numpy()
+    info = out["info"].cpu().numpy().reshape(-1, 2)
+    co = pb.colptr_off
+
+    def one(b):
+        p = problems[b]
+        st, R = oracle.coo_to_csc(p.n_rows, p.n_cols, p.row, p.col, p.val)
+        to = int(pb.trip_off[b])
+        c0 = int(co[b])
+        n = int(info[b, 0])
+        ok = st == oracle.OK and info[b, 1] == 0 and n == R.nnz
+        ok = ok and np.array_equal(cp_all[c0:c0 + p.n_cols + 1], R.col_ptr)
+        ok = ok and np.array_equal(ri_all[to:to + n], R.row_idx)
+        ok = ok and np.array_equal(vo_all[to:to + n], R.values.astype(np.float32))
+        return b, ok
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        bad = [b for b, ok in ex.map(one, range(pb.B)) if not ok]
+    assert not bad, "matrices differing from the oracle: %s" % bad[:10]
+
+
+def test_batch_with_named_tuning_equals_default():
+    """spm_batch_coo_to_csc_spmm with a registered tune key: bitwise the same outputs as
+    spm_batch_run under the process tuning (tuning never changes results)."""
+    from paper_1805_03380_amd import _lib
+    bt = _small_batch(2009, 300, 40, 3000)
+    pb = PackedBatch(bt.problems)
+    o_d = pb.run_batched(out=pb.new_outputs())
+    _lib.register_tuning("test-batch-narrow", batch_wg_per_cu=1, batch_spmm_wg_per_cu=2)
+    o_k = pb.run_batched(out=pb.new_outputs(), tune_key="test-batch-narrow")
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_d, o_k)
 
 
 def test_deterministic_rerun():
