@@ -779,6 +779,8 @@ def main():
         "roofline": head["roofline"],
     }
     out["headline"] = head
+    if args.workload == "uniform":  # the operations around the hot path use this CSC
+        out.update(legs_on_csc(p, head_state, args))
     side_problems = []
     if not args.no_side:
         configs = {}

@@ -205,7 +205,10 @@ spm_status spm_coo_to_csc_plan_noalloc(int64_t n_rows, int64_t n_cols, int64_t n
  * and then merged with the existing arrays), accumulating like X(r,c) += v of Fig. 1: at a
  * location the existing value comes first, then the new values in input order, folded in
  * binary64 and rounded once to out_type; a location whose result compares equal to 0.0 is
- * not stored.  The result is a new CSC (outputs must not overlap the existing arrays).
+ * not stored.  The result is a new CSC (outputs must not overlap the existing arrays).  Only
+ * the new triplets are sorted (by column, row and input position); the existing arrays are
+ * read once by a merge that cuts the work by position in the merged sequence (merge path),
+ * so long columns are shared by many threads.
  * ------------------------------------------------------------------------------------------ */
 
 /* Host only.  Workspace of spm_csc_insert for an existing CSC of capacity cap_a and nnz_t new
@@ -221,7 +224,9 @@ spm_status spm_csc_insert_workspace(int64_t n_rows, int64_t n_cols, int64_t cap_
  *              capacity cap_a + nnz_t, the first nnz_out entries are written.
  *   info       int32[2]: info[0] = nnz_out, info[1] = 0, SPM_EBOUNDS (a new triplet, or an
  *              existing row index, outside the matrix; skipped) or SPM_EINVAL (a_col_ptr not
- *              monotone, a_col_ptr[0] != 0 or more than cap_a elements).
+ *              monotone, a_col_ptr[0] != 0 or more than cap_a elements, or existing rows not
+ *              increasing down a column: then the outputs hold unspecified values, written
+ *              only within their capacity).
  *   ws         at least spm_csc_insert_workspace() bytes, 256-byte aligned.
  * The existing rows must increase strictly within each column (a valid CSC).  n_cols >= 1;
  * shapes the assembly's partition does not cover return SPM_EINVAL.  cap_a + nnz_t must fit
@@ -287,10 +292,11 @@ spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, 
  *   info       int32[2]: info[0] = nnz of the sum, info[1] = 0, SPM_EINVAL (a malformed
  *              CSC) or SPM_EBOUNDS (a stored row outside the matrix).
  *   ws         at least spm_csc_add_workspace() bytes, 256-byte aligned.
- * n_cols must be at least 1 (SPM_EINVAL otherwise, as for spm_csc_insert).
- * With short columns (capacities at most 64 per column on average) the columns are merged
- * directly, and rows not increasing down a column are also reported as SPM_EINVAL; otherwise
- * B's elements go through the insertion path.  Both give the same bits. */
+ * n_cols must be at least 1 (SPM_EINVAL otherwise, as for spm_csc_insert).  The two CSCs are
+ * merged by merge path (as in spm_csc_insert, with B in place of the sorted new triplets);
+ * rows not increasing down a column of A or B are also reported as SPM_EINVAL, after which
+ * the outputs hold unspecified values, written only within their capacity; with SPM_EBOUNDS
+ * the locations outside the matrix are skipped. */
 spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t *a_col_ptr,
                        const int32_t *a_row_idx, const void *a_val, int64_t b_cap,
                        const int32_t *b_col_ptr, const int32_t *b_row_idx, const void *b_val,

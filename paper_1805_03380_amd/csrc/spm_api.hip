@@ -14,7 +14,7 @@
 #include "spm_assemble.h"
 #include "spm_spmm.h"
 #include "spm_batch.h"
-#include "spm_merge.h"
+#include "spm_mergepath.h"
 #include <algorithm>
 #include <vector>
 
@@ -396,8 +396,13 @@ struct FuseCtx {
 constexpr int kPartBigNT = 512;
 constexpr int kPartBigCap = 4096;
 
-bool level2_big_ok(int b) {
-  return part_level2_lds_bytes(b, kPartBigCap) + 2048 <= (size_t)max_lds_per_block();
+// Partitions of fewer buckets keep the one launch (a big bucket is rare there, and the second
+// launch would cost more than staging it).
+constexpr int32_t kBigMinBuckets = 2048;
+
+bool level2_big_ok(int b, int32_t CB) {
+  return CB >= kBigMinBuckets &&
+         part_level2_lds_bytes(b, kPartBigCap) + 2048 <= (size_t)max_lds_per_block();
 }
 
 template <bool PLAN, typename VT>
@@ -657,8 +662,8 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
     uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
     PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_in};
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
-    uint32_t* big = level2_big_ok(P.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
-    uint32_t* big2 = (fz && level2_big_ok(fz->F->Q.b))
+    uint32_t* big = level2_big_ok(P.b, P.CB) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
+    uint32_t* big2 = (fz && level2_big_ok(fz->F->Q.b, fz->F->Q.CB))
                          ? reinterpret_cast<uint32_t*>(w + fz->F->big2) : nullptr;
     k_part_hist<kPartNT, PartSrcCoo>
         <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
@@ -802,7 +807,7 @@ void plan_build_into(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, const int3
     k_expand_columns<kNT><<<dim3(expand_grid(n_cols)), dim3(kNT), 0, s>>>(
         col_ptr, n_cols, nnz_cap, colarr, info, flags);
     PartSrcCsc src{row_idx, colarr, col_ptr, n_rows, n_cols, nnz_cap};
-    uint32_t* big = level2_big_ok(Q.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
+    uint32_t* big = level2_big_ok(Q.b, Q.CB) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
     k_part_hist<kPartNT, PartSrcCsc>
         <<<dim3((unsigned)Q.ntiles), dim3(kPartNT), 4 * (size_t)Q.CB, s>>>(
             src, Q.b, Q.CB, Q.ntiles, Q.T1, table, flags + expand_grid(n_cols), big,
@@ -867,96 +872,150 @@ size_t transpose_ws_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, size_
   return c.off;
 }
 
-// Batch insertion: the assembly's layout over the cap_a + nnz_t positions of the virtual
-// input, plus the existing elements' columns, the virtual values (8 bytes each, for either
-// value type) and the status flags (column expansion, then level-1 tiles).
-struct InsertLayout {
-  AsmLayout A;
-  size_t colarr, tcolarr, vcat, flags, total;
+// Merge path (spm_mergepath.h): one look-back state per workgroup tile of kNT * kMergeE merged
+// positions, the column of each tile's start (and of position M), the tile ticket.  k_merge_cols
+// writes the columns and clears the rest at the start of every call.
+struct MpLayout {
+  size_t scan_state, tile_col, ticket, end;
+  int64_t ntiles;
 };
 
-// sum: the new elements are a second CSC's nnz_t slots, whose columns are expanded too
-InsertLayout insert_layout(int64_t n_cols, int64_t cap_a, int64_t nnz_t, bool sum = false) {
+void mp_carve(Carve& c, int64_t m_cap, MpLayout& M) {
+  M.ntiles = std::max<int64_t>(1, ceil_div(m_cap, (int64_t)kNT * kMergeE));
+  M.scan_state = c.take(sizeof(uint64_t) * (size_t)M.ntiles);
+  M.tile_col = c.take(sizeof(int32_t) * (size_t)(M.ntiles + 1));
+  M.ticket = c.take(sizeof(uint32_t) * 4);
+  M.end = c.off;
+}
+
+// Workgroups of kernel k (kNT threads each) that fit on the current device at once, 0 if
+// unknown (cached per device; one cache per kernel type).
+template <typename K>
+int64_t resident_blocks(K k) {
+  static int64_t cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
+                                                     kNT, 0) != hipSuccess)
+      per_cu = 0;
+    cached[dev] = per_cu > 0 ? (int64_t)per_cu * cu_count() : -1;
+  }
+  return cached[dev] > 0 ? cached[dev] : 0;
+}
+
+// The merge of the two lists into (col_ptr, row_idx, val_out).  info_clear: info when nothing
+// was reported before in this call (its info[1] is cleared), else null (info[1] keeps the
+// earlier report unless the merge finds worse).
+template <typename VA, typename VB>
+void mp_run(const MergeLists& ML, const VA* a_v, const VB* b_v, int32_t* col_ptr,
+            int32_t* row_idx, void* val_out, int out_f64, int64_t out_cap, int32_t* info,
+            int32_t* info_clear, char* w, const MpLayout& M, hipStream_t s) {
+  uint64_t* state = reinterpret_cast<uint64_t*>(w + M.scan_state);
+  int32_t* tile_col = reinterpret_cast<int32_t*>(w + M.tile_col);
+  uint32_t* ticket = reinterpret_cast<uint32_t*>(w + M.ticket);
+  const int64_t seg = (int64_t)kNT * kMergeE;
+  const int64_t cblocks = std::min<int64_t>(ceil_div(ML.n_cols + 1, (int64_t)kNT), 1 << 16);
+  k_merge_cols<kNT><<<dim3((unsigned)cblocks), dim3(kNT), 0, s>>>(ML, seg, M.ntiles, tile_col,
+                                                                   state, ticket, info_clear);
+  const int by_ticket = M.ntiles > resident_blocks(k_merge<kNT, VA, VB>) ? 1 : 0;
+  k_merge<kNT, VA, VB><<<dim3((unsigned)M.ntiles), dim3(kNT), 0, s>>>(
+      ML, a_v, b_v, (const int32_t*)tile_col, col_ptr, row_idx, val_out, out_f64, out_cap,
+      state, ticket, by_ticket, info, (int32_t)SPM_EINVAL, (int32_t)SPM_EBOUNDS);
+}
+
+// Batch insertion (Section 3.1: the new elements sorted, then merged with the existing
+// arrays): the new triplets alone go through the partition by column, with level 2 in its
+// sorting form (no fold): per column their rows in increasing order, equal rows in input
+// order, with their values (b_cp, b_ri, b_v; b_perm is the input position, unused); then the
+// merge path folds every location, the existing value first.
+struct InsertLayout {
+  PartParams pp;
+  SplitParams sp;
+  size_t table, rowoff, btot, bstart, brec, bvhi, flags, big, bucket, scratch, ivhi, sbro,
+      subcnt;
+  size_t b_cp, b_ri, b_perm, b_v;
+  MpLayout mp;
+  size_t total;
+};
+
+InsertLayout insert_layout(int64_t n_cols, int64_t cap_a, int64_t nnz_t) {
   InsertLayout L;
-  L.A = asm_layout(n_cols, cap_a + nnz_t);
   Carve c;
-  c.off = L.A.total;
-  L.colarr = c.take(sizeof(int32_t) * (size_t)cap_a);
-  L.tcolarr = c.take(sizeof(int32_t) * (size_t)(sum ? nnz_t : 0));
-  L.vcat = c.take(sizeof(double) * (size_t)(cap_a + nnz_t));
-  L.flags = c.take(sizeof(uint32_t) * (size_t)((sum ? 2 : 1) * expand_grid(n_cols) +
-                                               (L.A.pp.ok ? L.A.pp.ntiles : 0)));
+  L.pp = part_params(n_cols, nnz_t);
+  L.sp = split_params(L.pp);
+  const bool ok = L.pp.ok;
+  const int64_t tab = ok ? (int64_t)L.pp.CB * L.pp.ntiles : 0;
+  const int64_t cb = ok ? L.pp.CB : 0;
+  const size_t nt = (size_t)nnz_t;
+  mp_carve(c, cap_a + nnz_t, L.mp);
+  L.table = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.rowoff = c.take(sizeof(uint32_t) * (size_t)tab);
+  L.btot = c.take(sizeof(uint32_t) * (size_t)cb);
+  L.bstart = c.take(sizeof(int32_t) * (size_t)(cb + 1));
+  L.brec = c.take(16 * nt);
+  L.bvhi = c.take(sizeof(uint32_t) * nt);
+  L.flags = c.take(sizeof(uint32_t) * (size_t)(ok ? L.pp.ntiles : 0));
+  L.big = c.take(sizeof(uint32_t) * (size_t)(cb + 1));
+  L.bucket = c.take(sizeof(uint64_t) * nt);  // bucket and scratch back to back: also the
+  L.scratch = c.take(sizeof(uint64_t) * nt);  // two-pass level 1's records
+  L.ivhi = c.take(sizeof(uint32_t) * (L.sp.on ? nt : 0));
+  L.sbro = c.take(sizeof(uint32_t) * (size_t)(L.sp.on ? L.sp.SB * (L.pp.ntiles + 1) : 0));
+  L.subcnt = c.take(sizeof(uint32_t) *
+                    (size_t)(L.sp.on ? L.sp.SB * L.sp.SH * L.pp.ntiles : 0));
+  L.b_cp = c.take(sizeof(int32_t) * (size_t)(n_cols + 1));
+  L.b_ri = c.take(sizeof(int32_t) * nt);
+  L.b_perm = c.take(sizeof(int32_t) * nt);
+  L.b_v = c.take(sizeof(double) * nt);
   L.total = c.off;
   return L;
 }
 
-// The merge as the assembly of the virtual input (PartSrcMerge), on the partition path.
 template <typename VT>
 void insert_t(int64_t n_rows, int64_t n_cols, int64_t cap_a, const int32_t* a_col_ptr,
               const int32_t* a_row_idx, const VT* a_val, int64_t nnz_t, const int32_t* row,
               const int32_t* col, const VT* val, int32_t* col_ptr, int32_t* row_idx,
-              void* val_out, int out_f64, int32_t* info, char* w, const InsertLayout& IL,
-              hipStream_t s, const int32_t* t_col_ptr = nullptr) {
-  const AsmLayout& L = IL.A;
+              void* val_out, int out_f64, int32_t* info, char* w, const InsertLayout& L,
+              hipStream_t s) {
   const PartParams& P = L.pp;
-  int32_t* colarr = reinterpret_cast<int32_t*>(w + IL.colarr);
-  VT* vcat = reinterpret_cast<VT*>(w + IL.vcat);
-  uint32_t* flags = reinterpret_cast<uint32_t*>(w + IL.flags);
-  uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
-  uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
   uint32_t* table = reinterpret_cast<uint32_t*>(w + L.table);
   uint32_t* rowoff = reinterpret_cast<uint32_t*>(w + L.rowoff);
   uint32_t* btot = reinterpret_cast<uint32_t*>(w + L.btot);
   int32_t* bstart = reinterpret_cast<int32_t*>(w + L.bstart);
   uint4* brec = reinterpret_cast<uint4*>(w + L.brec);
   uint32_t* bvhi = reinterpret_cast<uint32_t*>(w + L.bvhi);
-  uint32_t* trow = reinterpret_cast<uint32_t*>(w + L.trow);
-  double* tval = reinterpret_cast<double*>(w + L.tval);
-  uint32_t* bkept = reinterpret_cast<uint32_t*>(w + L.bkept);
-  const int cap = cu_count() * 16;
-  const int64_t n = cap_a + nnz_t;
-  if (n > 0)
-    k_concat_values<kNT, VT><<<dim3(grid_for(n, kNT * 4, cap)), dim3(kNT), 0, s>>>(
-        a_val, cap_a, val, nnz_t, vcat);
-  int eg = expand_grid(n_cols);
-  k_expand_columns<kNT><<<dim3(eg), dim3(kNT), 0, s>>>(a_col_ptr, n_cols, cap_a, colarr, info,
-                                                       flags);
-  if (t_col_ptr) {  // the second CSC's columns, checked like the first's
-    int32_t* tcolarr = reinterpret_cast<int32_t*>(w + IL.tcolarr);
-    k_expand_columns<kNT><<<dim3(eg), dim3(kNT), 0, s>>>(t_col_ptr, n_cols, nnz_t, tcolarr,
-                                                         info, flags + eg);
-    col = tcolarr;
-    eg *= 2;  // both expansions' flags come before the tiles'
-  }
-  PartSrcMerge src{a_row_idx, colarr, a_col_ptr, row, col, (int32_t)n_rows, (int32_t)n_cols,
-                   cap_a, nnz_t, t_col_ptr};
-  uint32_t* big = level2_big_ok(P.b) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
-  k_part_hist<kPartNT, PartSrcMerge>
+  uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(w + L.bucket);
+  uint64_t* scratch = reinterpret_cast<uint64_t*>(w + L.scratch);
+  int32_t* b_cp = reinterpret_cast<int32_t*>(w + L.b_cp);
+  int32_t* b_ri = reinterpret_cast<int32_t*>(w + L.b_ri);
+  int32_t* b_perm = reinterpret_cast<int32_t*>(w + L.b_perm);
+  VT* b_v = reinterpret_cast<VT*>(w + L.b_v);
+  uint32_t* big = level2_big_ok(P.b, P.CB) ? reinterpret_cast<uint32_t*>(w + L.big) : nullptr;
+  // the new triplets sorted by (column, row, input position); out-of-range ones are skipped
+  // and reported in info[1] (k_rows_scan)
+  PartSrcCoo src{row, col, (int32_t)n_rows, (int32_t)n_cols, nnz_t};
+  k_part_hist<kPartNT, PartSrcCoo>
       <<<dim3((unsigned)P.ntiles), dim3(kPartNT), 4 * (size_t)P.CB, s>>>(
-          src, P.b, P.CB, P.ntiles, P.T1, table, flags + eg, big, (uint32_t*)nullptr,
+          src, P.b, P.CB, P.ntiles, P.T1, table, flags, big, (uint32_t*)nullptr,
           sub_counts(L.sp, w, L.subcnt));
   k_rows_scan<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
-      (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags,
-      (int64_t)eg + P.ntiles, info, (uint32_t)kPartCap, big);
-  launch_scatter<PartSrcMerge, VT>(src, P, L.sp, rowoff, btot, bstart, brec, (const VT*)vcat,
-                                   bvhi, reinterpret_cast<uint4*>(bucket), trow,
-                                   reinterpret_cast<uint32_t*>(w + L.sbro),
-                                   reinterpret_cast<const uint32_t*>(w + L.subcnt), s);
-  launch_level2<false, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,
-                           (const uint32_t*)bvhi, bucket, scratch, (int32_t*)nullptr,
-                           (int32_t*)nullptr, (int32_t*)nullptr, (const VT*)vcat, (VT*)nullptr,
-                           col_ptr, trow, tval, bkept, sub_shift(n_rows, P.b),
-                           L2RowCount{nullptr, 0, 0, 0}, big, s);
-  int32_t* boff = nullptr;
-  if (P.CB > kEmitReduceMax) {
-    boff = reinterpret_cast<int32_t*>(w + L.boff);
-    k_small_scan<kNT><<<dim3(1), dim3(kNT), 0, s>>>((const uint32_t*)bkept, (int64_t)P.CB,
-                                                    boff);
-  }
-  k_part_emit<kNT><<<dim3((unsigned)P.CB), dim3(kNT), 0, s>>>(
-      P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint32_t*)bkept, (const int32_t*)boff,
-      (const uint32_t*)trow, (const double*)tval, col_ptr, row_idx, val_out, out_f64, info,
-      EmitPlan{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+      (const uint32_t*)table, P.ntiles, rowoff, btot, (const uint32_t*)flags, P.ntiles, info,
+      (uint32_t)kPartCap, big);
+  launch_scatter<PartSrcCoo, VT>(src, P, L.sp, rowoff, btot, bstart, brec, val, bvhi,
+                                 reinterpret_cast<uint4*>(bucket),
+                                 reinterpret_cast<uint32_t*>(w + L.ivhi),
+                                 reinterpret_cast<uint32_t*>(w + L.sbro),
+                                 reinterpret_cast<const uint32_t*>(w + L.subcnt), s);
+  launch_level2<true, VT>(P.b, P.CB, n_cols, (const int32_t*)bstart, (const uint4*)brec,
+                          (const uint32_t*)bvhi, bucket, scratch, b_cp, b_ri, b_perm, val, b_v,
+                          (int32_t*)nullptr, (uint32_t*)nullptr, (double*)nullptr,
+                          (uint32_t*)nullptr, sub_shift(n_rows, P.b),
+                          L2RowCount{nullptr, 0, 0, 0}, big, s);
+  const MergeLists ML{a_col_ptr, a_row_idx, cap_a, b_cp, b_ri, nnz_t, n_rows, n_cols, false};
+  mp_run<VT, VT>(ML, a_val, b_v, col_ptr, row_idx, val_out, out_f64, cap_a + nnz_t, info,
+                 (int32_t*)nullptr, w, L.mp, s);
 }
 
 }  // namespace
@@ -1113,7 +1172,7 @@ spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
   if (cap_a + nnz_t > 0 && (!row_idx || !val_out)) return SPM_EINVAL;
   if (!aligned(ws, 256)) return SPM_EINVAL;
   const InsertLayout L = insert_layout(n_cols, cap_a, nnz_t);
-  if (!L.A.pp.ok) return SPM_EINVAL;  // no columns, or more than the partition covers
+  if (!L.pp.ok) return SPM_EINVAL;  // no columns, or more than the partition covers
   if (ws_bytes < L.total) return SPM_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
@@ -1133,61 +1192,6 @@ spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
 
 }  // extern "C"
 
-namespace {
-
-// A + B by the direct column merge (spm_merge.h) when the columns are short: at most
-// kAddMergeMaxAvg stored elements per column on average (from the capacities); longer columns
-// take the insertion path, whose work does not grow with the column length.
-constexpr int64_t kAddMergeMaxAvg = 64;
-
-bool add_uses_merge(int64_t n_cols, int64_t a_cap, int64_t b_cap) {
-  return n_cols > 0 && a_cap + b_cap <= kAddMergeMaxAvg * n_cols;
-}
-
-struct MergeLayout {
-  size_t scan_state, ticket, flag, zero_bytes, counts, total;
-};
-
-// The first region (look-back states, the scan ticket, the status flag) is zeroed by one
-// kernel at the start of every call.
-MergeLayout merge_layout(int64_t n_cols) {
-  MergeLayout L;
-  Carve c;
-  L.scan_state = c.take(sizeof(uint64_t) * (size_t)ceil_div(n_cols > 0 ? n_cols : 1, kScanTile));
-  L.ticket = c.take(sizeof(uint32_t) * 4);
-  L.flag = c.take(sizeof(uint32_t) * 4);
-  L.zero_bytes = c.off;
-  L.counts = c.take(sizeof(uint32_t) * (size_t)(n_cols > 0 ? n_cols : 1));
-  L.total = c.off;
-  return L;
-}
-
-template <typename VT>
-void add_merge_t(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int32_t* a_cp,
-                 const int32_t* a_ri, const VT* a_v, int64_t b_cap, const int32_t* b_cp,
-                 const int32_t* b_ri, const VT* b_v, int32_t* col_ptr, int32_t* row_idx,
-                 void* val_out, int out_f64, int32_t* info, char* w, const MergeLayout& L,
-                 hipStream_t s) {
-  uint64_t* state = reinterpret_cast<uint64_t*>(w + L.scan_state);
-  uint32_t* ticket = reinterpret_cast<uint32_t*>(w + L.ticket);
-  uint32_t* flag = reinterpret_cast<uint32_t*>(w + L.flag);
-  uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
-  const int cap = cu_count() * 16;
-  k_zero2<<<dim3(1), dim3(kNT), 0, s>>>(reinterpret_cast<uint32_t*>(w),
-                                         (int64_t)(L.zero_bytes / 4), nullptr, 0);
-  const int grid = grid_for(n_cols, kNT, cap);
-  k_add_count<kNT, VT><<<dim3(grid), dim3(kNT), 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, a_v,
-                                                        b_cap, b_cp, b_ri, b_v, counts, flag);
-  launch_scan<kNT, kScanIPT>(counts, n_cols, col_ptr, state, ticket, s);
-  k_add_write<kNT, VT><<<dim3(grid), dim3(kNT), 0, s>>>(n_rows, n_cols, a_cap, a_cp, a_ri, a_v,
-                                                        b_cap, b_cp, b_ri, b_v, col_ptr,
-                                                        row_idx, val_out, out_f64,
-                                                        a_cap + b_cap);
-  k_add_finish<<<dim3(1), dim3(64), 0, s>>>(n_cols, col_ptr, flag, info, (int32_t)SPM_EINVAL,
-                                            (int32_t)SPM_EBOUNDS);
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -1197,9 +1201,10 @@ spm_status spm_csc_add_workspace(int64_t n_rows, int64_t n_cols, int64_t a_cap, 
   spm_status st = check_dims(n_rows, n_cols, a_cap);
   if (st != SPM_OK) return st;
   if (!fits_i32(b_cap) || !fits_i32(a_cap + b_cap)) return SPM_EOVERFLOW;
-  *ws_bytes = add_uses_merge(n_cols, a_cap, b_cap)
-                  ? merge_layout(n_cols).total
-                  : insert_layout(n_cols, a_cap, b_cap, true).total;
+  Carve c;
+  MpLayout M;
+  mp_carve(c, a_cap + b_cap, M);
+  *ws_bytes = c.off;
   return SPM_OK;
 }
 
@@ -1221,39 +1226,24 @@ spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int3
   if (a_cap + b_cap > 0 && (!row_idx || !val_out)) return SPM_EINVAL;
   if (!aligned(ws, 256)) return SPM_EINVAL;
   if (n_cols == 0) return SPM_EINVAL;  // as for the insertion
+  Carve c;
+  MpLayout M;
+  mp_carve(c, a_cap + b_cap, M);
+  if (ws_bytes < c.off) return SPM_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int out_f64 = out_type == SPM_F64 ? 1 : 0;
-  if (add_uses_merge(n_cols, a_cap, b_cap)) {
-    const MergeLayout M = merge_layout(n_cols);
-    if (ws_bytes < M.total) return SPM_EWORKSPACE;
-    (void)hipGetLastError();
-    if (val_type == SPM_F64)
-      add_merge_t<double>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
-                          static_cast<const double*>(a_val), b_cap, b_col_ptr, b_row_idx,
-                          static_cast<const double*>(b_val), col_ptr, row_idx, val_out, out_f64,
-                          info, static_cast<char*>(ws), M, s);
-    else
-      add_merge_t<float>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
-                         static_cast<const float*>(a_val), b_cap, b_col_ptr, b_row_idx,
-                         static_cast<const float*>(b_val), col_ptr, row_idx, val_out, out_f64,
-                         info, static_cast<char*>(ws), M, s);
-    return launch_status();
-  }
-  const InsertLayout L = insert_layout(n_cols, a_cap, b_cap, true);
-  if (!L.A.pp.ok) return SPM_EINVAL;  // more than the partition covers
-  if (ws_bytes < L.total) return SPM_EWORKSPACE;
+  char* w = static_cast<char*>(ws);
   (void)hipGetLastError();
-  // B's slots are the new elements (rows b_row_idx, columns expanded from b_col_ptr)
+  const MergeLists ML{a_col_ptr, a_row_idx, a_cap, b_col_ptr, b_row_idx, b_cap,
+                      n_rows,    n_cols,    true};
   if (val_type == SPM_F64)
-    insert_t<double>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
-                     static_cast<const double*>(a_val), b_cap, b_row_idx, nullptr,
-                     static_cast<const double*>(b_val), col_ptr, row_idx, val_out, out_f64,
-                     info, static_cast<char*>(ws), L, s, b_col_ptr);
+    mp_run<double, double>(ML, static_cast<const double*>(a_val),
+                           static_cast<const double*>(b_val), col_ptr, row_idx, val_out,
+                           out_f64, a_cap + b_cap, info, info, w, M, s);
   else
-    insert_t<float>(n_rows, n_cols, a_cap, a_col_ptr, a_row_idx,
-                    static_cast<const float*>(a_val), b_cap, b_row_idx, nullptr,
-                    static_cast<const float*>(b_val), col_ptr, row_idx, val_out, out_f64, info,
-                    static_cast<char*>(ws), L, s, b_col_ptr);
+    mp_run<float, float>(ML, static_cast<const float*>(a_val), static_cast<const float*>(b_val),
+                         col_ptr, row_idx, val_out, out_f64, a_cap + b_cap, info, info, w, M,
+                         s);
   return launch_status();
 }
 

@@ -122,6 +122,12 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
   return x;
 }
 
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
+
 // Exclusive scan of one value per thread across the workgroup (NT threads).  `lds` needs
 // NT/64 + 1 words.  Returns the exclusive prefix; *total receives the workgroup sum.
 template <int NT>
@@ -200,10 +206,15 @@ __device__ __forceinline__ uint64_t lb_read(const uint64_t* p) {
 // (256 predecessors): device-coherent reads cross the XCD fabric, so fewer, wider passes
 // shorten the chain.  Lane l holds the states of tiles base - 4l - q, q = 0..3 (q = 0 is the
 // closest); the window is summed up to and including the closest inclusive prefix.
+// With FB > 0 the top FB bits of a value are flags: those are OR-ed instead of summed (the
+// count lives in the low 62 - FB bits).
+template <int FB = 0>
 __device__ inline uint64_t lookback_exclusive(const uint64_t* state, int64_t tile) {
   constexpr int Q = 4;
+  constexpr int CB = 62 - FB;
+  constexpr uint64_t kCnt = (1ull << CB) - 1;
   const int lane = lane_id();
-  uint64_t excl = 0;
+  uint64_t excl = 0, fl = 0;
   int64_t base = tile - 1;
   while (base >= 0) {
     uint64_t v[Q];
@@ -230,18 +241,22 @@ __device__ inline uint64_t lookback_exclusive(const uint64_t* state, int64_t til
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    uint64_t mine = 0;
+    uint64_t mine = 0, mf = 0;
     if (relevant) {
       const int qmax = (lane == first_lane) ? firstp_q : Q - 1;
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        if (q <= qmax) mine += v[q] & kLbVal;
+        if (q <= qmax) {
+          mine += v[q] & kCnt;
+          if (FB > 0) mf |= (v[q] & kLbVal) >> CB;
+        }
     }
     excl += wave_sum_u64(mine);
+    if (FB > 0) fl |= wave_or_u64(mf);
     if (pm) break;
     base -= (int64_t)kWave * Q;
   }
-  return excl;
+  return FB > 0 ? (excl | (fl << CB)) : excl;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -79,62 +79,6 @@ struct PartSrcCsc {  // plan: segment = row, key = column << 32 | CSC slot
   }
 };
 
-// Batch insertion into an existing CSC (and the sum of two CSCs): the existing stored
-// elements take the positions 0 .. cap_a of one virtual input (slot p; slots at or past a_col_ptr[n_cols] are unused and
-// skipped silently), the new triplets follow at cap_a + t.  Keys carry the position, so at a
-// location the existing element folds first, then the new triplets in input order; the
-// assembly of this virtual input is the merge.
-struct PartSrcMerge {
-  const int32_t* a_row;      // existing row indices, by CSC slot
-  const int32_t* a_colarr;   // column of every existing slot (k_expand_columns)
-  const int32_t* a_col_ptr;  // a_col_ptr[n_cols] = number of existing elements
-  const int32_t* row;        // new triplets
-  const int32_t* col;
-  int32_t n_rows, n_cols;
-  int64_t cap_a, n_t;
-  // non-null: the new elements are the n_t slots of a second CSC (the sum A + B), col its
-  // k_expand_columns; slots at or past t_col_ptr[n_cols] are unused and skipped silently
-  const int32_t* t_col_ptr;
-  __device__ __forceinline__ int64_t count() const { return cap_a + n_t; }
-  __device__ __forceinline__ int elem(int64_t e, uint32_t& seg, uint64_t& key) const {
-    int32_t r, c;
-    if (e < cap_a) {
-      const int64_t raw = a_col_ptr[n_cols];
-      const int64_t nnz_a = raw < 0 ? 0 : (raw > cap_a ? cap_a : raw);
-      if (e >= nnz_a) return kElemSkip;
-      r = a_row[e];
-      c = a_colarr[e];
-    } else {
-      if (t_col_ptr) {
-        const int64_t raw = t_col_ptr[n_cols];
-        const int64_t nnz_t = raw < 0 ? 0 : (raw > n_t ? n_t : raw);
-        if (e - cap_a >= nnz_t) return kElemSkip;
-      }
-      r = row[e - cap_a];
-      c = col[e - cap_a];
-    }
-    if ((uint32_t)r < (uint32_t)n_rows && (uint32_t)c < (uint32_t)n_cols) {
-      seg = (uint32_t)c;
-      key = ((uint64_t)(uint32_t)r << 32) | (uint32_t)e;
-      return kElemOk;
-    }
-    return kElemBad;
-  }
-};
-
-// Values of the virtual input of a batch insertion: vcat[e] = a_val[e] for e < cap_a (slots
-// past the existing elements are copied but never read), val[e - cap_a] after.
-template <int NT, typename VT>
-__global__ __launch_bounds__(NT) void k_concat_values(const VT* __restrict__ a_val,
-                                                      int64_t cap_a,
-                                                      const VT* __restrict__ val, int64_t n_t,
-                                                      VT* __restrict__ vcat) {
-  const int64_t n = cap_a + n_t;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * NT)
-    vcat[e] = e < cap_a ? a_val[e] : val[e - cap_a];
-}
-
 // Status without a cleared word: every workgroup of a checking kernel writes its own flag
 // word (kFlagShape | kFlagIndex bits, 0 if clean) and k_rows_scan folds them into info[1],
 // an invalid shape taking precedence over an out-of-range index.

@@ -105,6 +105,19 @@ def _with_capacity(A, cap):
     return ops.CSCMatrix(A.n_rows, A.n_cols, A.col_ptr.clone(), ri, v, A.info)
 
 
+def test_add_tile_order_by_ticket_and_by_index_agree():
+    """Spare capacity of 10^6 per operand makes the merge grid larger than what fits on the
+    device at once, so tiles number themselves by ticket; without it the workgroup index
+    serves.  Both give the same bits."""
+    pa = synth.random_coo(3109, 30_000, 20_000, 400_000, dup_frac=0.1, dist="normal")
+    pb = synth.random_coo(3110, 30_000, 20_000, 300_000, dup_frac=0.1, dist="normal")
+    A, B = assemble_gpu(pa), assemble_gpu(pb)
+    C1 = _add_case(A, B)
+    C2 = _add_case(_with_capacity(A, 1_000_000), _with_capacity(B, 1_000_000))
+    assert torch.equal(C1.col_ptr, C2.col_ptr) and torch.equal(C1.row_idx, C2.row_idx)
+    assert torch.equal(C1.values.view(torch.int64), C2.values.view(torch.int64))
+
+
 def test_add_merge_and_insertion_paths_agree():
     """Short columns take the direct merge, long ones (by capacity) the insertion path: both
     give the same bits, and both match the oracle."""

@@ -15,13 +15,14 @@ pytestmark = pytest.mark.gpu
 
 
 def _heavy(seed, dtype=np.float64):
-    """50,000 x 4,096 with 2e6 uniform triplets (column buckets of 2 columns, about 1,000
-    elements; row buckets of 32 rows, about 1,300), plus heavy columns and rows: column 100
+    """65,536 x 4,096 with 2e6 uniform triplets (2,048 column buckets of 2 columns, about 1,000
+    elements; 2,048 row buckets of 32 rows, about 1,000, so both partitions take the second
+    level-2 launch and the fused call still applies), plus heavy columns and rows: column 100
     +4,000 (its bucket above 4,096), columns 200, 201 +700 each and column 300 +1,200 (buckets
     between 2,048 and 4,096), row 7 with 3,500 distinct columns (its row bucket above 4,096)
     and row 1,000 with 1,800 (between).  Duplicates in the heavy columns."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    n_rows, n_cols, n = 50_000, 4096, 2_000_000
+    n_rows, n_cols, n = 65_536, 4096, 2_000_000
     rows = [rng.integers(0, n_rows, n)]
     cols = [rng.integers(0, n_cols, n)]
     for c, extra in ((100, 4000), (200, 700), (201, 700), (300, 1200)):

@@ -103,3 +103,56 @@ def test_insert_statuses():
         ops.csc_insert(bad, dev(row[:1]), dev(col[:1]), dev(val[:1]))
     with pytest.raises(ValueError):
         ops.csc_insert(A, dev(row[:1]), dev(col[:1]), dev(val[:1].astype(np.float32)))
+
+
+def test_insert_long_runs_and_columns():
+    """Work is cut by position in the merged sequence: a column longer than many threads'
+    ranges, a location with 5,000 new values (one run across many ranges, folded by the thread
+    owning its start, existing value first), new triplets in empty columns, all bit for bit."""
+    rng = np.random.Generator(np.random.PCG64(88))
+    n_rows, n_cols = 30_000, 500
+    m = 40_000
+    row = np.concatenate([rng.integers(0, n_rows, m), rng.permutation(n_rows)[:20_000]])
+    col = np.concatenate([rng.integers(0, 400, m), np.full(20_000, 7)])  # column 7: 20k rows
+    p = synth.COOProblem("long", n_rows, n_cols, row.astype(np.int32), col.astype(np.int32),
+                         rng.standard_normal(row.size))
+    r2 = np.concatenate([np.full(5000, 11), rng.integers(0, n_rows, 30_000),
+                         rng.integers(0, n_rows, 3000)])
+    c2 = np.concatenate([np.full(5000, 7), rng.integers(0, n_cols, 30_000),
+                         rng.integers(450, n_cols, 3000)])  # columns 450.. hold no existing
+    q = synth.COOProblem("runs", n_rows, n_cols, r2.astype(np.int32), c2.astype(np.int32),
+                         rng.standard_normal(r2.size))
+    _insert_case(p, q)
+    _insert_case(p, q, np.float32)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_insert_random_small_shapes(seed):
+    """Small shapes around the per-thread range (8 merged positions): empty columns,
+    single-column and single-row matrices, duplicates of existing locations."""
+    rng = np.random.Generator(np.random.PCG64(890 + seed))
+    n_rows, n_cols = [(1, 1), (1, 17), (19, 1), (5, 7), (40, 3), (3, 40)][seed]
+
+    def iid(name, n):  # i.i.d. locations: duplicates as they fall
+        return synth.COOProblem(name, n_rows, n_cols,
+                                rng.integers(0, n_rows, n).astype(np.int32),
+                                rng.integers(0, n_cols, n).astype(np.int32),
+                                rng.choice([-1.0, 1.0, 0.5, 2.0], n))
+    p = iid("small_a", int(rng.integers(0, 3 * n_rows * n_cols + 1)))
+    q = iid("small_t", int(rng.integers(0, 4 * n_rows * n_cols + 1)))
+    _insert_case(p, q)
+
+
+def test_insert_existing_rows_out_of_order():
+    """Existing rows that do not increase down a column are reported as SPM_EINVAL."""
+    p = synth.random_coo(91, 60, 40, 900, dup_frac=0.0)
+    A = assemble_gpu(p)
+    ri = A.row_idx_buf.clone()
+    cp = A.col_ptr.cpu().numpy()
+    c = int(np.argmax(np.diff(cp) >= 2))
+    a, b = int(cp[c]), int(cp[c] + 1)
+    ri[a], ri[b] = A.row_idx_buf[b], A.row_idx_buf[a]  # swap two rows of one column
+    bad = ops.CSCMatrix(60, 40, A.col_ptr, ri, A.values_buf, A.info)
+    with pytest.raises(ValueError):
+        ops.csc_insert(bad, dev(np.array([1], np.int32)), dev(np.array([2], np.int32)),
+                       dev(np.array([1.0])))
