@@ -1466,13 +1466,16 @@ void launch_batch_spmm(const BatchArgs& a, int workers, hipStream_t s) {
 
 // Flat products: the forward over all rows, then the adjoint over all columns.
 template <int NT, typename XT, typename ACC>
-void launch_batch_flat(const BatchArgs& a, const int64_t* rpre, const int64_t* cpre, int grid,
+void launch_batch_flat(const BatchArgs& a, const int64_t* rpre, const int64_t* cpre,
+                       const int32_t* rtab, const int32_t* ctab, uint32_t* xcd_next, int grid,
                        hipStream_t s) {
   const bool full = a.k == 4 * (int64_t)a.G && a.xal && a.yal;
 #define SPM_CALL_F(GW, F)                                                                      \
   do {                                                                                         \
-    k_batch_flat<NT, XT, ACC, GW, F, true><<<dim3(grid), dim3(NT), 0, s>>>(a, rpre);           \
-    k_batch_flat<NT, XT, ACC, GW, F, false><<<dim3(grid), dim3(NT), 0, s>>>(a, cpre);          \
+    k_batch_flat<NT, XT, ACC, GW, F, true><<<dim3(grid), dim3(NT), 0, s>>>(a, rpre, rtab,      \
+                                                                           xcd_next);          \
+    k_batch_flat<NT, XT, ACC, GW, F, false><<<dim3(grid), dim3(NT), 0, s>>>(a, cpre, ctab,     \
+                                                                            xcd_next + kXcds); \
   } while (0)
 #define SPM_CALL(GW) SPM_CALL_F(GW, false)
   if (full && a.G == 8) SPM_CALL_F(8, true);
@@ -1490,17 +1493,31 @@ void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers
                      int spmm_workers, size_t slices_bytes, hipStream_t s) {
   if (vt == SPM_F32) k_batch<NT, float><<<dim3(workers), dim3(NT), 0, s>>>(a);
   else k_batch<NT, bf16_t><<<dim3(workers), dim3(NT), 0, s>>>(a);
+  // the flat products need the two prefixes and a chunk table per prefix (one entry per
+  // chunk of NT / G rows or columns; at most batch * max_dim of those) in the freed slices
+  const int64_t chunk = (int64_t)kBatchFlatPerGroup * (NT / (a.G > 0 ? a.G : 1));
+  const int64_t tab_cap = ((int64_t)a.batch * a.max_dim + chunk - 1) / chunk + 1;
   const size_t pre_bytes = 2 * sizeof(int64_t) * ((size_t)a.batch + 1);
-  if (slices_bytes >= pre_bytes) {
+  const size_t tab_bytes = sizeof(int32_t) * (size_t)tab_cap;
+  const size_t ctr_bytes = sizeof(uint32_t) * 2 * kXcds;
+  if (a.batch > 0 && slices_bytes >= pre_bytes + 2 * tab_bytes + ctr_bytes) {
     int64_t* rpre = reinterpret_cast<int64_t*>(a.ws);
     int64_t* cpre = rpre + a.batch + 1;
+    int32_t* rtab = reinterpret_cast<int32_t*>(cpre + a.batch + 1);
+    int32_t* ctab = rtab + tab_cap;
+    uint32_t* xcd_next = reinterpret_cast<uint32_t*>(ctab + tab_cap);
     k_batch_prefix<NT><<<dim3(1), dim3(NT), 0, s>>>(a, rpre, cpre);
+    const int64_t tab_blocks = ceil_div(std::max<int64_t>((int64_t)a.batch, 2 * kXcds), (int64_t)NT);
+    k_batch_tab<NT><<<dim3((unsigned)tab_blocks), dim3(NT), 0, s>>>(a, rpre, cpre, chunk, tab_cap,
+                                                                    rtab, ctab, xcd_next);
     const int grid = cu_count() * (tuning().batch_spmm_wg_per_cu > 0
                                        ? tuning().batch_spmm_wg_per_cu
                                        : kBatchSpmmDefaultWgPerCu);
     // values are assembled into binary32; bfloat16 dense operands accumulate in binary32
-    if (xt == SPM_F32) launch_batch_flat<NT, float, double>(a, rpre, cpre, grid, s);
-    else launch_batch_flat<NT, bf16_t, float>(a, rpre, cpre, grid, s);
+    if (xt == SPM_F32)
+      launch_batch_flat<NT, float, double>(a, rpre, cpre, rtab, ctab, xcd_next, grid, s);
+    else
+      launch_batch_flat<NT, bf16_t, float>(a, rpre, cpre, rtab, ctab, xcd_next, grid, s);
     return;
   }
   if (xt == SPM_F32) launch_batch_spmm<NT, float, double>(a, spmm_workers, s);

@@ -216,7 +216,7 @@ __device__ void chunk_sort(uint64_t* __restrict__ keys, const ST* starts, int64_
   const int64_t e0 = starts[a];
   const int cnt = (int)((int64_t)starts[b] - e0);
   if (threadIdx.x == 0) s_nlong = 0;
-  constexpr int U = 4;
+  constexpr int U = (CAP + NT - 1) / NT < 8 ? (CAP + NT - 1) / NT : 8;  // one pass for CAP <= 8 NT
   for (int i0 = threadIdx.x; i0 < cnt; i0 += NT * U) {
     uint64_t kv[U];
 #pragma unroll

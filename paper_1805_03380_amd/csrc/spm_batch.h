@@ -63,9 +63,14 @@ template <int NT, typename VIN>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
   constexpr int T = NT * kBatchFoldIPT;
+  static_assert(T == 8 * NT, "the column scan of a fold block takes 8 entries per thread");
+  constexpr int U = 8;  // elements per thread whose loads are issued together
   __shared__ uint32_t s_cnt[kBatchMaxLdsDim + 1];
   __shared__ uint64_t s_key[kBatchCap];
   __shared__ uint32_t s_pre[T + 1];
+  __shared__ int32_t s_col[T];  // column of each element of a fold block
+  __shared__ float s_val[T];    // value of each element of a fold block (exact: f32 or bf16)
+  __shared__ uint64_t s_prev;   // the key before the fold block
   __shared__ uint32_t s_w[NT / kWave + 1];
   __shared__ int64_t s_b[4];
   __shared__ int32_t s_item;
@@ -113,16 +118,28 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     int32_t* ri = a.row_idx + to;
     float* vo = a.val_out + to;
     int32_t* rp = a.row_ptr + it.rowptr_off;
+    int32_t* slot_col = a.col_t + to;  // column of each CSC slot, until the plan overwrites it
     uint32_t* cnt = (n_r <= kBatchMaxLdsDim && n_c <= kBatchMaxLdsDim) ? s_cnt : gcnt;
 
     // ---- 1. column histogram (bounds-checked) -------------------------------------------
     for (int64_t i = threadIdx.x; i <= n_c; i += NT) cnt[i] = 0;
     __syncthreads();
     bool bad = false;
-    for (int64_t t = threadIdx.x; t < nnz_in; t += NT) {
-      const int32_t r = trow[t], c = tcol[t];
-      if (r >= 0 && r < n_r && c >= 0 && c < n_c) atomicAdd(&cnt[c], 1u);
-      else bad = true;
+    for (int64_t t0 = threadIdx.x; t0 < nnz_in; t0 += (int64_t)NT * U) {
+      int32_t r[U], c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = t0 + (int64_t)u * NT;
+        r[u] = t < nnz_in ? trow[t] : 0;
+        c[u] = t < nnz_in ? tcol[t] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (t0 + (int64_t)u * NT < nnz_in) {
+          if (r[u] >= 0 && r[u] < n_r && c[u] >= 0 && c[u] < n_c) atomicAdd(&cnt[c[u]], 1u);
+          else bad = true;
+        }
+      }
     }
     if (bad) s_bad = 1;
     // ---- 2. inclusive scan: cnt[c] = end of column c -------------------------------------
@@ -131,11 +148,21 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     if (threadIdx.x == 0) cnt[n_c] = n_c > 0 ? cnt[n_c - 1] : 0u;
     __syncthreads();
     // ---- 3. scatter keys (row << 32 | position); counters end as column starts ------------
-    for (int64_t t = threadIdx.x; t < nnz_in; t += NT) {
-      const int32_t r = trow[t], c = tcol[t];
-      if (r >= 0 && r < n_r && c >= 0 && c < n_c) {
-        const uint32_t pos = atomicSub(&cnt[c], 1u) - 1u;
-        bucket[pos] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)t;
+    for (int64_t t0 = threadIdx.x; t0 < nnz_in; t0 += (int64_t)NT * U) {
+      int32_t r[U], c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = t0 + (int64_t)u * NT;
+        r[u] = t < nnz_in ? trow[t] : -1;
+        c[u] = t < nnz_in ? tcol[t] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = t0 + (int64_t)u * NT;
+        if (t < nnz_in && r[u] >= 0 && r[u] < n_r && c[u] >= 0 && c[u] < n_c) {
+          const uint32_t pos = atomicSub(&cnt[c[u]], 1u) - 1u;
+          bucket[pos] = ((uint64_t)(uint32_t)r[u] << 32) | (uint32_t)t;
+        }
       }
     }
     __syncthreads();
@@ -145,15 +172,84 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
                                         (int32_t*)nullptr, s_key, s_pre, &s_b[0]);
     __syncthreads();
     // ---- 5. fold, drop zeros, compact, column offsets --------------------------------------
+    // (the column of each element comes from a max-scan over the column starts in the block)
     uint32_t running = 0;
     for (int64_t base = 0; base < N || base == 0; base += T) {
       const int cntb = (int)((N - base) < T ? (N - base) : T);
-      for (int li = threadIdx.x; li < cntb; li += NT) s_key[li] = bucket[base + li];
+      {
+        uint64_t kv[kBatchFoldIPT];
+#pragma unroll
+        for (int u = 0; u < kBatchFoldIPT; ++u) {
+          const int li = u * NT + threadIdx.x;
+          kv[u] = li < cntb ? bucket[base + li] : 0ull;
+        }
+        // the values of the block's elements, gathered at once
+        float vv[kBatchFoldIPT];
+#pragma unroll
+        for (int u = 0; u < kBatchFoldIPT; ++u) {
+          const int li = u * NT + threadIdx.x;
+          vv[u] = li < cntb ? to_acc<float>(tval[(uint32_t)kv[u]]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatchFoldIPT; ++u) {
+          const int li = u * NT + threadIdx.x;
+          if (li < cntb) {
+            s_key[li] = kv[u];
+            s_val[li] = vv[u];
+          }
+          s_col[li] = -1;
+        }
+        if (threadIdx.x == 0) s_prev = base > 0 ? bucket[base - 1] : 0ull;
+      }
+      if (threadIdx.x == 0) {
+        const bool last = base + T >= N;
+        s_b[1] = lower_bound(cnt, n_c + 1, base);
+        s_b[2] = last ? n_c + 1 : lower_bound(cnt, n_c + 1, base + T);
+      }
       __syncthreads();
+      for (int64_t c = s_b[1] + threadIdx.x; c < s_b[2] && c < n_c; c += NT) {
+        const int64_t p = (int64_t)cnt[c] - base;
+        if (p >= 0 && p < cntb) atomicMax(&s_col[p], (int32_t)c);
+      }
+      __syncthreads();
+      wg_max_scan8<NT>(s_col, (int32_t)(s_b[1] > 0 ? s_b[1] - 1 : 0),
+                       reinterpret_cast<int32_t*>(s_w));
+      __syncthreads();
+      // fold: a run starts at a column's first key or where the row changes; its head sums
+      // the run left to right in binary64 (from LDS, then from memory past the block)
       uint32_t rows[kBatchFoldIPT];
       double sums[kBatchFoldIPT];
-      const uint32_t mask = fold_tile<NT, kBatchFoldIPT, VIN>(bucket, s_key, base, cntb, N, tval,
-                                                               rows, sums);
+      uint32_t mask = 0;
+#pragma unroll
+      for (int s = 0; s < kBatchFoldIPT; ++s) {
+        const int li = threadIdx.x * kBatchFoldIPT + s;
+        rows[s] = 0;
+        sums[s] = 0.0;
+        if (li < cntb) {
+          const uint64_t key = s_key[li];
+          const uint32_t row = key_row(key);
+          const uint64_t pk = li > 0 ? s_key[li - 1] : s_prev;
+          rows[s] = row;
+          if ((key & kSegHead) || key_row(pk) != row) {
+            double acc = (double)s_val[li];
+            int j = li + 1;
+            for (; j < cntb; ++j) {
+              const uint64_t k2 = s_key[j];
+              if ((k2 & kSegHead) || key_row(k2) != row) break;
+              acc += (double)s_val[j];
+            }
+            if (j == cntb) {
+              for (int64_t g = base + cntb; g < N; ++g) {
+                const uint64_t k2 = bucket[g];
+                if ((k2 & kSegHead) || key_row(k2) != row) break;
+                acc += to_acc<double>(tval[(uint32_t)k2]);
+              }
+            }
+            sums[s] = acc;
+            if (acc != 0.0) mask |= 1u << s;
+          }
+        }
+      }
       uint32_t blk_kept;
       const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk_kept);
       {
@@ -164,12 +260,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
           if (li < cntb) s_pre[li] = run;
           run += (mask >> s) & 1u;
         }
-        if (threadIdx.x == 0) {
-          s_pre[cntb] = blk_kept;
-          const bool last = base + T >= N;
-          s_b[1] = lower_bound(cnt, n_c + 1, base);
-          s_b[2] = last ? n_c + 1 : lower_bound(cnt, n_c + 1, base + T);
-        }
+        if (threadIdx.x == 0) s_pre[cntb] = blk_kept;
       }
       __syncthreads();
       {
@@ -179,6 +270,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
           if ((mask >> s) & 1u) {
             ri[o] = (int32_t)rows[s];
             vo[o] = (float)sums[s];
+            slot_col[o] = s_col[threadIdx.x * kBatchFoldIPT + s];
             ++o;
           }
         }
@@ -201,19 +293,36 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     // ---- 6. plan: row counts, row starts, (col << 32 | slot) keys sorted per row -----------
     for (int64_t i = threadIdx.x; i <= n_r; i += NT) cnt[i] = 0;
     __syncthreads();
-    for (int64_t p = threadIdx.x; p < nnz; p += NT) atomicAdd(&cnt[ri[p]], 1u);
+    for (int64_t p0 = threadIdx.x; p0 < nnz; p0 += (int64_t)NT * U) {
+      int32_t r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = p0 + (int64_t)u * NT;
+        r[u] = p < nnz ? ri[p] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (p0 + (int64_t)u * NT < nnz) atomicAdd(&cnt[r[u]], 1u);
+    }
     __syncthreads();
     wg_inclusive_scan_inplace<NT>(cnt, n_r, s_w);
     if (threadIdx.x == 0) cnt[n_r] = n_r > 0 ? cnt[n_r - 1] : 0u;
     __syncthreads();
-    for (int64_t p0 = (int64_t)threadIdx.x * 4; p0 < nnz; p0 += (int64_t)NT * 4) {
-      int64_t c = upper_bound(cp, n_c + 1, p0) - 1;
-      const int64_t p1 = (p0 + 4 < nnz) ? p0 + 4 : nnz;
-      for (int64_t p = p0; p < p1; ++p) {
-        while (c + 1 < n_c && (int64_t)cp[c + 1] <= p) ++c;
-        const int32_t r = ri[p];
-        const uint32_t pos = atomicSub(&cnt[r], 1u) - 1u;
-        bucket[pos] = ((uint64_t)c << 32) | (uint32_t)p;
+    for (int64_t p0 = threadIdx.x; p0 < nnz; p0 += (int64_t)NT * U) {
+      int32_t r[U], c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = p0 + (int64_t)u * NT;
+        r[u] = p < nnz ? ri[p] : 0;
+        c[u] = p < nnz ? slot_col[p] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = p0 + (int64_t)u * NT;
+        if (p < nnz) {
+          const uint32_t pos = atomicSub(&cnt[r[u]], 1u) - 1u;
+          bucket[pos] = ((uint64_t)(uint32_t)c[u] << 32) | (uint32_t)p;
+        }
       }
     }
     __syncthreads();
@@ -365,41 +474,64 @@ __global__ __launch_bounds__(NT) void k_batch_prefix(BatchArgs a, int64_t* __res
   }
 }
 
+// tab[t] = the schedule slot q whose rows (columns) hold the start of chunk t, that is
+// pre[q] <= t * chunk < pre[q + 1], for both prefixes.  One thread per slot.
+// Also clears the per-XCD chunk counters of the two product launches (2 * kXcds words).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_tab(BatchArgs a, const int64_t* __restrict__ rpre,
+                                                  const int64_t* __restrict__ cpre,
+                                                  int64_t chunk, int64_t cap,
+                                                  int32_t* __restrict__ rtab,
+                                                  int32_t* __restrict__ ctab,
+                                                  uint32_t* __restrict__ xcd_next) {
+  const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (q < 2 * kXcds) xcd_next[q] = 0;
+  if (q >= a.batch) return;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t* pre = side == 0 ? rpre : cpre;
+    int32_t* tab = side == 0 ? rtab : ctab;
+    const int64_t t0 = (pre[q] + chunk - 1) / chunk, t1 = (pre[q + 1] + chunk - 1) / chunk;
+    for (int64_t t = t0; t < t1 && t < cap; ++t) tab[t] = (int32_t)q;
+  }
+}
+
 // FWD: rows of all matrices (pre = rpre), forward product.  !FWD: columns (pre = cpre),
-// adjoint.  Each group takes kPerGroup rows (columns) of a chunk, kGroups apart.
+// adjoint.  A chunk is kPerGroup rows (columns) per group.  The chunks are cut into one
+// contiguous range per XCD (workgroup b runs on XCD b mod 8), and the workgroups of an XCD
+// take its chunks in order from a counter of its own: each XCD then has about (its
+// workgroups x chunk) consecutive rows in flight, a few matrices whose dense rows stay in its
+// L2.
+constexpr int kBatchFlatPerGroup = 2;
 template <int NT, typename XT, typename ACC, int GW, bool FULL, bool FWD>
-__global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* __restrict__ pre) {
+__global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* __restrict__ pre,
+                                                   const int32_t* __restrict__ tab,
+                                                   uint32_t* __restrict__ xcd_next) {
   constexpr int64_t kGroups = NT / GW;
-  constexpr int kPerGroup = 8;
-  constexpr int64_t kChunk = kGroups * kPerGroup;
-  __shared__ int32_t s_q;
+  constexpr int64_t kChunk = kGroups * kBatchFlatPerGroup;
+  __shared__ int64_t s_chunk;
   const XT* Xa = static_cast<const XT*>(a.X);
   const XT* Ga = static_cast<const XT*>(a.Gm);
   const int lg = threadIdx.x & (GW - 1);
   const int64_t gid = threadIdx.x / GW;
   const int64_t total = pre[a.batch];
   const int64_t nchunks = (total + kChunk - 1) / kChunk;
-  for (int64_t round = 0; round < nchunks; round += gridDim.x) {
-    const int64_t chunk = round + xcd_tile(blockIdx.x, gridDim.x);
-    if (chunk >= nchunks) break;  // the same for every thread of the workgroup
-    const int64_t g0 = chunk * kChunk;
-    if (threadIdx.x == 0) s_q = (int32_t)(upper_bound(pre, (int64_t)a.batch + 1, g0) - 1);
+  const int64_t x = blockIdx.x % kXcds;
+  const int64_t c_lo = nchunks * x / kXcds, c_hi = nchunks * (x + 1) / kXcds;
+  while (true) {
+    if (threadIdx.x == 0) s_chunk = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
     __syncthreads();
-    int64_t q = s_q;
-    __syncthreads();  // s_q is read before thread 0 rewrites it
-    int64_t qb = -1;  // schedule slot whose item is loaded below
-    spm_batch_item it{};
-    int64_t nnz = 0;
-    for (int j = 0; j < kPerGroup; ++j) {
-      const int64_t g = g0 + (int64_t)j * kGroups + gid;
+    const int64_t chunk = s_chunk;
+    __syncthreads();  // s_chunk is read before thread 0 rewrites it
+    if (chunk >= c_hi) break;  // the same for every thread of the workgroup
+    int64_t q = tab[chunk];
+    q = q < 0 ? 0 : (q >= a.batch ? a.batch - 1 : q);
+    for (int j = 0; j < kBatchFlatPerGroup; ++j) {
+      const int64_t g = chunk * kChunk + (int64_t)j * kGroups + gid;
       if (g >= total) break;
-      while (pre[q + 1] <= g) ++q;  // q < batch: g < total = pre[batch]
-      if (q != qb) {
-        qb = q;
-        it = a.items[a.order[q]];
-        nnz = a.info[2 * (int64_t)a.order[q]];
-        nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
-      }
+      while (q + 1 < a.batch && pre[q + 1] <= g) ++q;  // g < total = pre[batch]
+      const spm_batch_item it = a.items[a.order[q]];
+      int64_t nnz = a.info[2 * (int64_t)a.order[q]];
+      nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
       const int64_t e = g - pre[q];  // row (column) within the matrix
       const int64_t to = it.trip_off;
       const int64_t n_r = it.n_rows, n_c = it.n_cols;

@@ -153,6 +153,36 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t x, uint32_t* lds, uint
   return excl;
 }
 
+// In-place inclusive max-scan of a[0 .. 8 NT) seeded with `init` (8 consecutive entries per
+// thread).  `s_w` needs NT/64 words.
+template <int NT>
+__device__ __forceinline__ void wg_max_scan8(int32_t* a, int32_t init, int32_t* s_w) {
+  int32_t v[8];
+  int32_t m = init;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = a[threadIdx.x * 8 + k];
+    m = max(m, v[k]);
+  }
+  int32_t inc = m;  // inclusive over the wave
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t y = __shfl_up(inc, d, kWave);
+    if (lane_id() >= d) inc = max(inc, y);
+  }
+  if (lane_id() == kWave - 1) s_w[wave_id()] = inc;
+  __syncthreads();
+  int32_t e = init;  // earlier waves, then earlier lanes
+  for (int w = 0; w < wave_id(); ++w) e = max(e, s_w[w]);
+  const int32_t p = __shfl_up(inc, 1, kWave);
+  if (lane_id() > 0) e = max(e, p);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e = max(e, v[k]);
+    a[threadIdx.x * 8 + k] = e;
+  }
+}
+
 // In-place inclusive scan of a[0..n) by the whole workgroup (blocked chunks with a carry).
 template <int NT>
 __device__ void wg_inclusive_scan_inplace(uint32_t* a, int64_t n, uint32_t* s_w) {
