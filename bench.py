@@ -77,7 +77,34 @@ def parse():
                     help="assembly and plan as two calls (default: spm_coo_to_csc_plan)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--batch-only", choices=("float32", "bfloat16"), default=None,
+                    help="only run the batched path of the 4096-matrix workload in this dtype, "
+                         "--warmup then --steps calls (for profiling its kernels)")
     return ap.parse_args()
+
+
+def batch_only(dtype_name, steps, warmup):
+    """The batched entry point alone on the 4096-matrix workload: one JSON line with its
+    average time per call."""
+    import torch
+    from paper_1805_03380_amd import autotune, synth
+    from paper_1805_03380_amd.batch import PackedBatch
+    autotune.apply(autotune.load_table(),
+                   autotune.signature("batch", 8192, 8192, 131072, 32, "float32", "float32"))
+    dt = torch.bfloat16 if dtype_name == "bfloat16" else torch.float32
+    pb = PackedBatch(synth.batch_problems().problems, val_dtype=dt, x_dtype=dt)
+    for _ in range(max(1, warmup)):
+        pb.run_batched()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pb.run_batched()
+    e1.record()
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": batch_workload_label(dtype_name), "steps": steps,
+                      "batched_ms": e0.elapsed_time(e1) / max(1, steps)}), flush=True)
 
 
 def make_problem(name):
@@ -735,6 +762,9 @@ def main():
     args = parse()
     if args.copy_calib_mib:
         copy_calibration(args.copy_calib_mib)
+        return
+    if args.batch_only:
+        batch_only(args.batch_only, args.steps, args.warmup)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: it measures the single-GPU kernels "

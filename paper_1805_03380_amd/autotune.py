@@ -42,9 +42,13 @@ def signature(kind: str, n_rows: int, n_cols: int, nnz_in: int, k: int, val_dtyp
 
 
 def device_key() -> str:
+    """The device by architecture and compute-unit count (the marketing name that the runtime
+    reports can differ between processes on one machine), plus the library version."""
     import torch
     lib = _lib.load()
-    return "%s|%s" % (torch.cuda.get_device_name(0), lib.spm_version().decode())
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    return "%s:%dcu|%s" % (arch, props.multi_processor_count, lib.spm_version().decode())
 
 
 def load_table(path: str | None = None) -> dict:
