@@ -59,6 +59,240 @@ __device__ __forceinline__ bool batch_item_ok(const BatchArgs& a, const spm_batc
            it.n_cols > a.max_dim || it.nnz_in > a.max_nnz);
 }
 
+// Columns [ca, cb) of one matrix, their keys (row << 32 | input position) at
+// bucket[cnt[ca] .. cnt[cb]), at most kBatchCap of them: each column sorted by rank in LDS,
+// then each run (one row of one column) folded left to right in binary64 from LDS; the
+// survivors go to ri / vo (and their columns to slot_col) from `running` on, and the columns'
+// offsets to cp.  Runs never leave the chunk: it holds whole columns.
+template <int NT, typename VIN>
+__device__ void batch_fold_chunk(int64_t ca, int64_t cb, const uint32_t* cnt,
+                                 const uint64_t* __restrict__ bucket,
+                                 const VIN* __restrict__ tval, int32_t* __restrict__ ri,
+                                 float* __restrict__ vo, int32_t* __restrict__ slot_col,
+                                 int32_t* __restrict__ cp, uint32_t& running, uint64_t* s_key,
+                                 float* s_val, int32_t* s_col, uint32_t* s_pre, uint32_t* s_w) {
+  constexpr int IPT = kBatchCap / NT;
+  constexpr int kLong = 64;  // longer columns get their bounds from the whole workgroup
+  __shared__ int32_t s_long[kBatchCap / kLong + 1];
+  __shared__ int32_t s_nlong;
+  uint32_t* s_lohi = s_pre;  // bounds first, then the compaction prefix
+  const int64_t e0 = cnt[ca];
+  const int n = (int)((int64_t)cnt[cb] - e0);
+  if (threadIdx.x == 0) s_nlong = 0;
+  // keys and values, every load issued before the first use
+  uint64_t kv[IPT];
+  float vv[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int i = u * NT + threadIdx.x;
+    kv[u] = i < n ? bucket[e0 + i] : 0ull;
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int i = u * NT + threadIdx.x;
+    vv[u] = i < n ? to_acc<float>(tval[(uint32_t)kv[u]]) : 0.0f;
+    if (i < n) s_key[i] = kv[u];
+  }
+  __syncthreads();
+  // bounds (lo | hi << 16, chunk-relative) and column of every element
+  for (int64_t c = ca + threadIdx.x; c < cb; c += NT) {
+    const int lo = (int)((int64_t)cnt[c] - e0), hi = (int)((int64_t)cnt[c + 1] - e0);
+    if (hi - lo <= kLong) {
+      for (int i = lo; i < hi; ++i) {
+        s_lohi[i] = (uint32_t)lo | ((uint32_t)hi << 16);
+        s_col[i] = (int32_t)c;
+      }
+    } else {
+      s_long[atomicAdd(&s_nlong, 1)] = (int32_t)(c - ca);
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < s_nlong; ++q) {
+    const int64_t c = ca + s_long[q];
+    const int lo = (int)((int64_t)cnt[c] - e0), hi = (int)((int64_t)cnt[c + 1] - e0);
+    for (int i = lo + threadIdx.x; i < hi; i += NT) {
+      s_lohi[i] = (uint32_t)lo | ((uint32_t)hi << 16);
+      s_col[i] = (int32_t)c;
+    }
+  }
+  __syncthreads();
+  // rank of each key in its column (keys are unique): its sorted slot
+  int dst[IPT];
+  int32_t dcol[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int i = u * NT + threadIdx.x;
+    dst[u] = -1;
+    dcol[u] = 0;
+    if (i < n) {
+      const uint32_t lh = s_lohi[i];
+      const int lo = (int)(lh & 0xffffu), hi = (int)(lh >> 16);
+      int r = 0, j = lo;
+      for (; j + 4 <= hi; j += 4) {
+        const uint64_t k0 = s_key[j], k1 = s_key[j + 1], k2 = s_key[j + 2], k3 = s_key[j + 3];
+        r += (int)(k0 < kv[u]) + (int)(k1 < kv[u]) + (int)(k2 < kv[u]) + (int)(k3 < kv[u]);
+      }
+      for (; j < hi; ++j) r += (int)(s_key[j] < kv[u]);
+      dst[u] = lo + r;
+      dcol[u] = s_col[i];
+      if (r == 0) kv[u] |= kSegHead;
+    }
+  }
+  __syncthreads();  // every read of the unsorted chunk is done
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    if (dst[u] >= 0) {
+      s_key[dst[u]] = kv[u];
+      s_val[dst[u]] = vv[u];
+      s_col[dst[u]] = dcol[u];
+    }
+  }
+  __syncthreads();
+  // fold: a run starts at a column's first key or where the row changes
+  uint32_t rows[IPT];
+  double sums[IPT];
+  uint32_t mask = 0;
+#pragma unroll
+  for (int s = 0; s < IPT; ++s) {
+    const int li = threadIdx.x * IPT + s;
+    rows[s] = 0;
+    sums[s] = 0.0;
+    if (li < n) {
+      const uint64_t key = s_key[li];
+      const uint32_t row = key_row(key);
+      rows[s] = row;
+      if ((key & kSegHead) || li == 0 || key_row(s_key[li - 1]) != row) {
+        double acc = (double)s_val[li];
+        for (int j = li + 1; j < n; ++j) {
+          const uint64_t k2 = s_key[j];
+          if ((k2 & kSegHead) || key_row(k2) != row) break;
+          acc += (double)s_val[j];
+        }
+        sums[s] = acc;
+        if (acc != 0.0) mask |= 1u << s;
+      }
+    }
+  }
+  int32_t cols[IPT];
+#pragma unroll
+  for (int s = 0; s < IPT; ++s) {
+    const int li = threadIdx.x * IPT + s;
+    cols[s] = s_col[li < n ? li : 0];
+  }
+  uint32_t blk_kept;
+  const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk_kept);
+  {
+    uint32_t run = excl;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int li = threadIdx.x * IPT + s;
+      if (li < n) s_pre[li] = run;
+      run += (mask >> s) & 1u;
+    }
+    if (threadIdx.x == 0) s_pre[n] = blk_kept;
+  }
+  __syncthreads();
+  {
+    int64_t o = (int64_t)running + excl;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      if ((mask >> s) & 1u) {
+        ri[o] = (int32_t)rows[s];
+        vo[o] = (float)sums[s];
+        slot_col[o] = cols[s];
+        ++o;
+      }
+    }
+  }
+  for (int64_t c = ca + threadIdx.x; c < cb; c += NT)
+    cp[c] = (int32_t)(running + s_pre[(int64_t)cnt[c] - e0]);
+  running += blk_kept;
+  __syncthreads();
+}
+
+// One column c longer than kBatchCap: merge-sorted in global memory, then folded in blocks of
+// kBatchCap keys (a run may continue past a block: read from memory).
+template <int NT, typename VIN>
+__device__ void batch_giant_column(int64_t c, const uint32_t* cnt, uint64_t* __restrict__ bucket,
+                                   uint64_t* __restrict__ scratch, const VIN* __restrict__ tval,
+                                   int32_t* __restrict__ ri, float* __restrict__ vo,
+                                   int32_t* __restrict__ slot_col, int32_t* __restrict__ cp,
+                                   uint32_t& running, uint64_t* s_key, float* s_val,
+                                   uint32_t* s_pre, uint32_t* s_w) {
+  constexpr int IPT = kBatchCap / NT;
+  constexpr int T = kBatchCap;
+  const int64_t e0 = cnt[c], e1 = cnt[c + 1];
+  giant_sort<NT, false>(bucket + e0, e1 - e0, scratch + e0, e0, (int32_t*)nullptr,
+                        (int32_t*)nullptr, s_key);
+  if (threadIdx.x == 0) cp[c] = (int32_t)running;
+  for (int64_t base = e0; base < e1; base += T) {
+    const int m = (int)((e1 - base) < T ? (e1 - base) : T);
+    uint64_t kv[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int i = u * NT + threadIdx.x;
+      kv[u] = i < m ? bucket[base + i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int i = u * NT + threadIdx.x;
+      if (i < m) {
+        s_key[i] = kv[u];
+        s_val[i] = to_acc<float>(tval[(uint32_t)kv[u]]);
+      }
+    }
+    __syncthreads();
+    uint32_t rows[IPT];
+    double sums[IPT];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      const int li = threadIdx.x * IPT + s;
+      rows[s] = 0;
+      sums[s] = 0.0;
+      if (li < m) {
+        const uint64_t key = s_key[li];
+        const uint32_t row = key_row(key);
+        const uint64_t pk = li > 0 ? s_key[li - 1] : (base > e0 ? bucket[base - 1] : 0ull);
+        rows[s] = row;
+        if ((key & kSegHead) || key_row(pk) != row) {
+          double acc = (double)s_val[li];
+          int j = li + 1;
+          for (; j < m; ++j) {
+            const uint64_t k2 = s_key[j];
+            if (key_row(k2) != row) break;
+            acc += (double)s_val[j];
+          }
+          if (j == m) {
+            for (int64_t g = base + m; g < e1; ++g) {
+              const uint64_t k2 = bucket[g];
+              if (key_row(k2) != row) break;
+              acc += to_acc<double>(tval[(uint32_t)k2]);
+            }
+          }
+          sums[s] = acc;
+          if (acc != 0.0) mask |= 1u << s;
+        }
+      }
+    }
+    uint32_t blk_kept;
+    const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk_kept);
+    int64_t o = (int64_t)running + excl;
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+      if ((mask >> s) & 1u) {
+        ri[o] = (int32_t)rows[s];
+        vo[o] = (float)sums[s];
+        slot_col[o] = (int32_t)c;
+        ++o;
+      }
+    }
+    running += blk_kept;
+    __syncthreads();
+  }
+  (void)s_pre;
+}
+
 template <int NT, typename VIN>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
@@ -68,9 +302,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   __shared__ uint32_t s_cnt[kBatchMaxLdsDim + 1];
   __shared__ uint64_t s_key[kBatchCap];
   __shared__ uint32_t s_pre[T + 1];
-  __shared__ int32_t s_col[T];  // column of each element of a fold block
-  __shared__ float s_val[T];    // value of each element of a fold block (exact: f32 or bf16)
-  __shared__ uint64_t s_prev;   // the key before the fold block
+  __shared__ int32_t s_col[T];  // column of each element of a fold chunk
+  __shared__ float s_val[T];    // value of each element of a fold chunk (exact: f32 or bf16)
   __shared__ uint32_t s_w[NT / kWave + 1];
   __shared__ int64_t s_b[4];
   __shared__ int32_t s_item;
@@ -167,123 +400,27 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     }
     __syncthreads();
     const int64_t N = cnt[n_c];
-    // ---- 4. sort each column's keys --------------------------------------------------------
-    sort_segments<NT, kBatchCap, false>(bucket, cnt, 0, n_c, scratch, (int32_t*)nullptr,
-                                        (int32_t*)nullptr, s_key, s_pre, &s_b[0]);
-    __syncthreads();
-    // ---- 5. fold, drop zeros, compact, column offsets --------------------------------------
-    // (the column of each element comes from a max-scan over the column starts in the block)
+    // ---- 4 + 5. per chunk of whole columns (at most kBatchCap keys): sort each column in
+    // LDS, fold each run in binary64 from LDS, drop zeros, compact, column offsets.  A
+    // column longer than kBatchCap is merge-sorted in global memory and folded in blocks.
     uint32_t running = 0;
-    for (int64_t base = 0; base < N || base == 0; base += T) {
-      const int cntb = (int)((N - base) < T ? (N - base) : T);
-      {
-        uint64_t kv[kBatchFoldIPT];
-#pragma unroll
-        for (int u = 0; u < kBatchFoldIPT; ++u) {
-          const int li = u * NT + threadIdx.x;
-          kv[u] = li < cntb ? bucket[base + li] : 0ull;
-        }
-        // the values of the block's elements, gathered at once
-        float vv[kBatchFoldIPT];
-#pragma unroll
-        for (int u = 0; u < kBatchFoldIPT; ++u) {
-          const int li = u * NT + threadIdx.x;
-          vv[u] = li < cntb ? to_acc<float>(tval[(uint32_t)kv[u]]) : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kBatchFoldIPT; ++u) {
-          const int li = u * NT + threadIdx.x;
-          if (li < cntb) {
-            s_key[li] = kv[u];
-            s_val[li] = vv[u];
-          }
-          s_col[li] = -1;
-        }
-        if (threadIdx.x == 0) s_prev = base > 0 ? bucket[base - 1] : 0ull;
-      }
-      if (threadIdx.x == 0) {
-        const bool last = base + T >= N;
-        s_b[1] = lower_bound(cnt, n_c + 1, base);
-        s_b[2] = last ? n_c + 1 : lower_bound(cnt, n_c + 1, base + T);
-      }
+    for (int64_t ca = 0; ca < n_c;) {
+      if (threadIdx.x == 0) s_b[0] = ca + upper_bound(cnt + ca, n_c - ca + 1,
+                                                       (int64_t)cnt[ca] + kBatchCap) - 1;
       __syncthreads();
-      for (int64_t c = s_b[1] + threadIdx.x; c < s_b[2] && c < n_c; c += NT) {
-        const int64_t p = (int64_t)cnt[c] - base;
-        if (p >= 0 && p < cntb) atomicMax(&s_col[p], (int32_t)c);
-      }
+      const int64_t cb = s_b[0];
       __syncthreads();
-      wg_max_scan8<NT>(s_col, (int32_t)(s_b[1] > 0 ? s_b[1] - 1 : 0),
-                       reinterpret_cast<int32_t*>(s_w));
-      __syncthreads();
-      // fold: a run starts at a column's first key or where the row changes; its head sums
-      // the run left to right in binary64 (from LDS, then from memory past the block)
-      uint32_t rows[kBatchFoldIPT];
-      double sums[kBatchFoldIPT];
-      uint32_t mask = 0;
-#pragma unroll
-      for (int s = 0; s < kBatchFoldIPT; ++s) {
-        const int li = threadIdx.x * kBatchFoldIPT + s;
-        rows[s] = 0;
-        sums[s] = 0.0;
-        if (li < cntb) {
-          const uint64_t key = s_key[li];
-          const uint32_t row = key_row(key);
-          const uint64_t pk = li > 0 ? s_key[li - 1] : s_prev;
-          rows[s] = row;
-          if ((key & kSegHead) || key_row(pk) != row) {
-            double acc = (double)s_val[li];
-            int j = li + 1;
-            for (; j < cntb; ++j) {
-              const uint64_t k2 = s_key[j];
-              if ((k2 & kSegHead) || key_row(k2) != row) break;
-              acc += (double)s_val[j];
-            }
-            if (j == cntb) {
-              for (int64_t g = base + cntb; g < N; ++g) {
-                const uint64_t k2 = bucket[g];
-                if ((k2 & kSegHead) || key_row(k2) != row) break;
-                acc += to_acc<double>(tval[(uint32_t)k2]);
-              }
-            }
-            sums[s] = acc;
-            if (acc != 0.0) mask |= 1u << s;
-          }
-        }
+      if (cb == ca) {  // one giant column
+        batch_giant_column<NT, VIN>(ca, cnt, bucket, scratch, tval, ri, vo, slot_col, cp,
+                                    running, s_key, s_val, s_pre, s_w);
+        ca += 1;
+      } else {
+        batch_fold_chunk<NT, VIN>(ca, cb, cnt, bucket, tval, ri, vo, slot_col, cp, running,
+                                  s_key, s_val, s_col, s_pre, s_w);
+        ca = cb;
       }
-      uint32_t blk_kept;
-      const uint32_t excl = wg_excl_scan<NT>((uint32_t)__popc(mask), s_w, &blk_kept);
-      {
-        uint32_t run = excl;
-#pragma unroll
-        for (int s = 0; s < kBatchFoldIPT; ++s) {
-          const int li = threadIdx.x * kBatchFoldIPT + s;
-          if (li < cntb) s_pre[li] = run;
-          run += (mask >> s) & 1u;
-        }
-        if (threadIdx.x == 0) s_pre[cntb] = blk_kept;
-      }
-      __syncthreads();
-      {
-        int64_t o = (int64_t)running + excl;
-#pragma unroll
-        for (int s = 0; s < kBatchFoldIPT; ++s) {
-          if ((mask >> s) & 1u) {
-            ri[o] = (int32_t)rows[s];
-            vo[o] = (float)sums[s];
-            slot_col[o] = s_col[threadIdx.x * kBatchFoldIPT + s];
-            ++o;
-          }
-        }
-      }
-      for (int64_t c = s_b[1] + threadIdx.x; c < s_b[2]; c += NT) {
-        int64_t p = (int64_t)cnt[c] - base;
-        if (p > cntb) p = cntb;
-        cp[c] = (int32_t)(running + s_pre[p]);
-      }
-      running += blk_kept;
-      __syncthreads();
-      if (base + T >= N) break;
     }
+    if (threadIdx.x == 0) cp[n_c] = (int32_t)running;
     const int64_t nnz = running;
     if (threadIdx.x == 0) {
       a.info[2 * (int64_t)b] = (int32_t)nnz;
