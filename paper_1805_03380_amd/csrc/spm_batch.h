@@ -59,13 +59,38 @@ __device__ __forceinline__ bool batch_item_ok(const BatchArgs& a, const spm_batc
            it.n_cols > a.max_dim || it.nnz_in > a.max_nnz);
 }
 
+// Packed keys.  When a matrix's row and input position fit in 31 bits together, the key is
+// (row << tb | position) << 32 | the value's bits: the sort orders it exactly as
+// row << 32 | position (positions are unique), and the fold reads the value from the key
+// instead of gathering it.  bit 63 stays free for kSegHead.
+struct BatchKey {
+  int tb;       // bits of the input position; -1: plain keys, values gathered by position
+  __device__ __forceinline__ uint32_t row(uint64_t k) const {
+    const uint32_t hi = (uint32_t)(k >> 32) & 0x7fffffffu;
+    return tb < 0 ? hi : hi >> tb;
+  }
+};
+__device__ __forceinline__ uint32_t vin_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t vin_bits(bf16_t v) { return (uint32_t)v; }
+template <typename VIN> __device__ __forceinline__ float vin_value(uint32_t b);
+template <> __device__ __forceinline__ float vin_value<float>(uint32_t b) { return __uint_as_float(b); }
+template <> __device__ __forceinline__ float vin_value<bf16_t>(uint32_t b) {
+  return to_acc<float>((bf16_t)(b & 0xffffu));
+}
+// The value of an element, binary32 (exact for f32 and bf16 input).
+template <typename VIN>
+__device__ __forceinline__ float batch_value(const BatchKey& bk, uint64_t k,
+                                             const VIN* __restrict__ tval) {
+  return bk.tb < 0 ? to_acc<float>(tval[(uint32_t)k]) : vin_value<VIN>((uint32_t)k);
+}
+
 // Columns [ca, cb) of one matrix, their keys (row << 32 | input position) at
 // bucket[cnt[ca] .. cnt[cb]), at most kBatchCap of them: each column sorted by rank in LDS,
 // then each run (one row of one column) folded left to right in binary64 from LDS; the
 // survivors go to ri / vo (and their columns to slot_col) from `running` on, and the columns'
 // offsets to cp.  Runs never leave the chunk: it holds whole columns.
 template <int NT, typename VIN>
-__device__ void batch_fold_chunk(int64_t ca, int64_t cb, const uint32_t* cnt,
+__device__ void batch_fold_chunk(const BatchKey bk, int64_t ca, int64_t cb, const uint32_t* cnt,
                                  const uint64_t* __restrict__ bucket,
                                  const VIN* __restrict__ tval, int32_t* __restrict__ ri,
                                  float* __restrict__ vo, int32_t* __restrict__ slot_col,
@@ -90,7 +115,7 @@ __device__ void batch_fold_chunk(int64_t ca, int64_t cb, const uint32_t* cnt,
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     const int i = u * NT + threadIdx.x;
-    vv[u] = i < n ? to_acc<float>(tval[(uint32_t)kv[u]]) : 0.0f;
+    vv[u] = i < n ? batch_value<VIN>(bk, kv[u], tval) : 0.0f;
     if (i < n) s_key[i] = kv[u];
   }
   __syncthreads();
@@ -159,13 +184,13 @@ __device__ void batch_fold_chunk(int64_t ca, int64_t cb, const uint32_t* cnt,
     sums[s] = 0.0;
     if (li < n) {
       const uint64_t key = s_key[li];
-      const uint32_t row = key_row(key);
+      const uint32_t row = bk.row(key);
       rows[s] = row;
-      if ((key & kSegHead) || li == 0 || key_row(s_key[li - 1]) != row) {
+      if ((key & kSegHead) || li == 0 || bk.row(s_key[li - 1]) != row) {
         double acc = (double)s_val[li];
         for (int j = li + 1; j < n; ++j) {
           const uint64_t k2 = s_key[j];
-          if ((k2 & kSegHead) || key_row(k2) != row) break;
+          if ((k2 & kSegHead) || bk.row(k2) != row) break;
           acc += (double)s_val[j];
         }
         sums[s] = acc;
@@ -213,7 +238,8 @@ __device__ void batch_fold_chunk(int64_t ca, int64_t cb, const uint32_t* cnt,
 // One column c longer than kBatchCap: merge-sorted in global memory, then folded in blocks of
 // kBatchCap keys (a run may continue past a block: read from memory).
 template <int NT, typename VIN>
-__device__ void batch_giant_column(int64_t c, const uint32_t* cnt, uint64_t* __restrict__ bucket,
+__device__ void batch_giant_column(const BatchKey bk, int64_t c, const uint32_t* cnt,
+                                   uint64_t* __restrict__ bucket,
                                    uint64_t* __restrict__ scratch, const VIN* __restrict__ tval,
                                    int32_t* __restrict__ ri, float* __restrict__ vo,
                                    int32_t* __restrict__ slot_col, int32_t* __restrict__ cp,
@@ -238,7 +264,7 @@ __device__ void batch_giant_column(int64_t c, const uint32_t* cnt, uint64_t* __r
       const int i = u * NT + threadIdx.x;
       if (i < m) {
         s_key[i] = kv[u];
-        s_val[i] = to_acc<float>(tval[(uint32_t)kv[u]]);
+        s_val[i] = batch_value<VIN>(bk, kv[u], tval);
       }
     }
     __syncthreads();
@@ -252,22 +278,22 @@ __device__ void batch_giant_column(int64_t c, const uint32_t* cnt, uint64_t* __r
       sums[s] = 0.0;
       if (li < m) {
         const uint64_t key = s_key[li];
-        const uint32_t row = key_row(key);
+        const uint32_t row = bk.row(key);
         const uint64_t pk = li > 0 ? s_key[li - 1] : (base > e0 ? bucket[base - 1] : 0ull);
         rows[s] = row;
-        if ((key & kSegHead) || key_row(pk) != row) {
+        if ((key & kSegHead) || bk.row(pk) != row) {
           double acc = (double)s_val[li];
           int j = li + 1;
           for (; j < m; ++j) {
             const uint64_t k2 = s_key[j];
-            if (key_row(k2) != row) break;
+            if (bk.row(k2) != row) break;
             acc += (double)s_val[j];
           }
           if (j == m) {
             for (int64_t g = base + m; g < e1; ++g) {
               const uint64_t k2 = bucket[g];
-              if (key_row(k2) != row) break;
-              acc += to_acc<double>(tval[(uint32_t)k2]);
+              if (bk.row(k2) != row) break;
+              acc += (double)batch_value<VIN>(bk, k2, tval);
             }
           }
           sums[s] = acc;
@@ -352,6 +378,13 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     float* vo = a.val_out + to;
     int32_t* rp = a.row_ptr + it.rowptr_off;
     int32_t* slot_col = a.col_t + to;  // column of each CSC slot, until the plan overwrites it
+    BatchKey bk{-1};
+    {
+      int rb = 0, tb = 0;
+      while (((int64_t)1 << rb) < n_r) ++rb;
+      while (((int64_t)1 << tb) < nnz_in) ++tb;
+      if (rb + tb <= 31) bk.tb = tb;
+    }
     uint32_t* cnt = (n_r <= kBatchMaxLdsDim && n_c <= kBatchMaxLdsDim) ? s_cnt : gcnt;
 
     // ---- 1. column histogram (bounds-checked) -------------------------------------------
@@ -383,18 +416,22 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
     // ---- 3. scatter keys (row << 32 | position); counters end as column starts ------------
     for (int64_t t0 = threadIdx.x; t0 < nnz_in; t0 += (int64_t)NT * U) {
       int32_t r[U], c[U];
+      uint32_t vb[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t t = t0 + (int64_t)u * NT;
         r[u] = t < nnz_in ? trow[t] : -1;
         c[u] = t < nnz_in ? tcol[t] : -1;
+        vb[u] = (bk.tb >= 0 && t < nnz_in) ? vin_bits(tval[t]) : 0u;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t t = t0 + (int64_t)u * NT;
         if (t < nnz_in && r[u] >= 0 && r[u] < n_r && c[u] >= 0 && c[u] < n_c) {
           const uint32_t pos = atomicSub(&cnt[c[u]], 1u) - 1u;
-          bucket[pos] = ((uint64_t)(uint32_t)r[u] << 32) | (uint32_t)t;
+          bucket[pos] = bk.tb >= 0
+                            ? ((uint64_t)(((uint32_t)r[u] << bk.tb) | (uint32_t)t) << 32) | vb[u]
+                            : ((uint64_t)(uint32_t)r[u] << 32) | (uint32_t)t;
         }
       }
     }
@@ -411,11 +448,11 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
       const int64_t cb = s_b[0];
       __syncthreads();
       if (cb == ca) {  // one giant column
-        batch_giant_column<NT, VIN>(ca, cnt, bucket, scratch, tval, ri, vo, slot_col, cp,
+        batch_giant_column<NT, VIN>(bk, ca, cnt, bucket, scratch, tval, ri, vo, slot_col, cp,
                                     running, s_key, s_val, s_pre, s_w);
         ca += 1;
       } else {
-        batch_fold_chunk<NT, VIN>(ca, cb, cnt, bucket, tval, ri, vo, slot_col, cp, running,
+        batch_fold_chunk<NT, VIN>(bk, ca, cb, cnt, bucket, tval, ri, vo, slot_col, cp, running,
                                   s_key, s_val, s_col, s_pre, s_w);
         ca = cb;
       }

@@ -69,7 +69,8 @@ def test_small_batch_equals_single_and_oracle(x_dtype):
 
 def test_large_dims_global_counters_and_giant_column():
     """One matrix larger than the LDS counter capacity, one with a column longer than an LDS
-    sort chunk, one with an out-of-range triplet (its own status only)."""
+    sort chunk, one with an out-of-range triplet (its own status only), an empty one, and one
+    whose row and input position do not fit the packed key (values gathered by position)."""
     rng = np.random.Generator(np.random.PCG64(31))
     probs = []
     n = 12_000
@@ -87,16 +88,20 @@ def test_large_dims_global_counters_and_giant_column():
     bad.row[10] = 100  # out of range
     probs.append(bad)
     probs.append(synth.random_coo(34, 50, 70, 0, dtype=np.float32, k=32))  # empty
+    # row and input position need 16 + 17 bits: plain keys, values gathered by position
+    probs.append(synth.random_coo(35, 65_536, 64, 70_000, dup_frac=0.1, dtype=np.float32,
+                                  dist="normal", k=32))
     pb = PackedBatch(probs)
     o_b = pb.run_batched()
     o_s = pb.run_single(out=pb.new_outputs())
     torch.cuda.synchronize()
     info = o_b["info"].cpu().numpy().reshape(-1, 2)
     assert info[2, 1] == 2 and info[0, 1] == 0 and info[1, 1] == 0 and info[3, 1] == 0
-    assert info[3, 0] == 0
+    assert info[3, 0] == 0 and info[4, 1] == 0
     _bitwise_equal(pb, o_b, o_s)
     _oracle_check(pb, o_b, probs, 0)
     _oracle_check(pb, o_b, probs, 1)
+    _oracle_check(pb, o_b, probs, 4)
 
 
 @pytest.fixture(scope="module")
