@@ -682,7 +682,7 @@ __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* _
                                                    uint32_t* __restrict__ xcd_next) {
   constexpr int64_t kGroups = NT / GW;
   constexpr int64_t kChunk = kGroups * kBatchFlatPerGroup;
-  __shared__ int64_t s_chunk;
+  __shared__ int64_t s_chunk, s_next;
   const XT* Xa = static_cast<const XT*>(a.X);
   const XT* Ga = static_cast<const XT*>(a.Gm);
   const int lg = threadIdx.x & (GW - 1);
@@ -691,12 +691,13 @@ __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* _
   const int64_t nchunks = (total + kChunk - 1) / kChunk;
   const int64_t x = blockIdx.x % kXcds;
   const int64_t c_lo = nchunks * x / kXcds, c_hi = nchunks * (x + 1) / kXcds;
-  while (true) {
-    if (threadIdx.x == 0) s_chunk = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
-    __syncthreads();
-    const int64_t chunk = s_chunk;
-    __syncthreads();  // s_chunk is read before thread 0 rewrites it
-    if (chunk >= c_hi) break;  // the same for every thread of the workgroup
+  // the next chunk is requested while the current one is computed
+  if (threadIdx.x == 0) s_chunk = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
+  __syncthreads();
+  int64_t chunk = s_chunk;
+  while (chunk < c_hi) {  // the same for every thread of the workgroup
+    __syncthreads();  // s_next is read before thread 0 rewrites it
+    if (threadIdx.x == 0) s_next = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
     int64_t q = tab[chunk];
     q = q < 0 ? 0 : (q >= a.batch ? a.batch - 1 : q);
     for (int j = 0; j < kBatchFlatPerGroup; ++j) {
@@ -736,6 +737,8 @@ __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* _
                                                   a.dval + to, false);
       }
     }
+    __syncthreads();
+    chunk = s_next;
   }
 }
 
