@@ -184,3 +184,10 @@ def test_add_overlapping_offsets_stay_in_bounds():
         assert int(info[1]) == _lib.EINVAL
         assert torch.all(row_idx[out_cap:] == -77)
         assert torch.all(val_out[out_cap:] == 1234.5)
+
+
+def test_add_hypersparse():
+    """200,000 columns for a few thousand elements (tiles over many empty columns)."""
+    pa = synth.random_coo(3111, 50_000, 200_000, 3000, dup_frac=0.0, dist="normal")
+    pb = synth.random_coo(3112, 50_000, 200_000, 2500, dup_frac=0.0, dist="normal")
+    _add_case(assemble_gpu(pa), assemble_gpu(pb))

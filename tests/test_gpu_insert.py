@@ -156,3 +156,20 @@ def test_insert_existing_rows_out_of_order():
     with pytest.raises(ValueError):
         ops.csc_insert(bad, dev(np.array([1], np.int32)), dev(np.array([2], np.int32)),
                        dev(np.array([1.0])))
+
+
+def test_insert_hypersparse():
+    """200,000 columns for a few thousand elements: every merge tile spans tens of thousands
+    of mostly empty columns, and most columns start at the very end or share one start."""
+    rng = np.random.Generator(np.random.PCG64(93))
+    n_rows, n_cols = 50_000, 200_000
+
+    def iid(name, n, lo=0, hi=n_cols):
+        return synth.COOProblem(name, n_rows, n_cols,
+                                rng.integers(0, n_rows, n).astype(np.int32),
+                                rng.integers(lo, hi, n).astype(np.int32),
+                                rng.standard_normal(n))
+    p = iid("hyper_a", 3000)
+    q = iid("hyper_t", 2500, 0, 150_000)  # the last 50,000 columns stay empty
+    _insert_case(p, q)
+    _insert_case(p, q, np.float32)
