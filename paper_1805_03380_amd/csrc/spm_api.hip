@@ -1467,15 +1467,15 @@ void launch_batch_spmm(const BatchArgs& a, int workers, hipStream_t s) {
 // Flat products: the forward over all rows, then the adjoint over all columns.
 template <int NT, typename XT, typename ACC>
 void launch_batch_flat(const BatchArgs& a, const int64_t* rpre, const int64_t* cpre,
-                       const int32_t* rtab, const int32_t* ctab, uint32_t* xcd_next, int grid,
-                       hipStream_t s) {
+                       const int32_t* rtab, const int32_t* ctab, uint32_t* xcd_next,
+                       const BatchSlot* rslot, const BatchSlot* cslot, int grid, hipStream_t s) {
   const bool full = a.k == 4 * (int64_t)a.G && a.xal && a.yal;
 #define SPM_CALL_F(GW, F)                                                                      \
   do {                                                                                         \
     k_batch_flat<NT, XT, ACC, GW, F, true><<<dim3(grid), dim3(NT), 0, s>>>(a, rpre, rtab,      \
-                                                                           xcd_next);          \
-    k_batch_flat<NT, XT, ACC, GW, F, false><<<dim3(grid), dim3(NT), 0, s>>>(a, cpre, ctab,     \
-                                                                            xcd_next + kXcds); \
+                                                                           xcd_next, rslot);   \
+    k_batch_flat<NT, XT, ACC, GW, F, false><<<dim3(grid), dim3(NT), 0, s>>>(                   \
+        a, cpre, ctab, xcd_next + kXcds, cslot);                                               \
   } while (0)
 #define SPM_CALL(GW) SPM_CALL_F(GW, false)
   if (full && a.G == 8) SPM_CALL_F(8, true);
@@ -1500,24 +1500,32 @@ void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers
   const size_t pre_bytes = 2 * sizeof(int64_t) * ((size_t)a.batch + 1);
   const size_t tab_bytes = sizeof(int32_t) * (size_t)tab_cap;
   const size_t ctr_bytes = sizeof(uint32_t) * 2 * kXcds;
-  if (a.batch > 0 && slices_bytes >= pre_bytes + 2 * tab_bytes + ctr_bytes) {
+  const size_t slot_bytes = sizeof(BatchSlot) * (size_t)a.batch;
+  const size_t need = pre_bytes + 2 * tab_bytes + ctr_bytes + 64 + 2 * slot_bytes;
+  if (a.batch > 0 && slices_bytes >= need) {
     int64_t* rpre = reinterpret_cast<int64_t*>(a.ws);
     int64_t* cpre = rpre + a.batch + 1;
     int32_t* rtab = reinterpret_cast<int32_t*>(cpre + a.batch + 1);
     int32_t* ctab = rtab + tab_cap;
     uint32_t* xcd_next = reinterpret_cast<uint32_t*>(ctab + tab_cap);
+    const size_t slot_at = (pre_bytes + 2 * tab_bytes + ctr_bytes + 63) & ~(size_t)63;
+    BatchSlot* rslot = reinterpret_cast<BatchSlot*>(a.ws + slot_at);
+    BatchSlot* cslot = rslot + a.batch;
     k_batch_prefix<NT><<<dim3(1), dim3(NT), 0, s>>>(a, rpre, cpre);
     const int64_t tab_blocks = ceil_div(std::max<int64_t>((int64_t)a.batch, 2 * kXcds), (int64_t)NT);
     k_batch_tab<NT><<<dim3((unsigned)tab_blocks), dim3(NT), 0, s>>>(a, rpre, cpre, chunk, tab_cap,
-                                                                    rtab, ctab, xcd_next);
+                                                                    rtab, ctab, xcd_next, rslot,
+                                                                    cslot);
     const int grid = cu_count() * (tuning().batch_spmm_wg_per_cu > 0
                                        ? tuning().batch_spmm_wg_per_cu
                                        : kBatchSpmmDefaultWgPerCu);
     // values are assembled into binary32; bfloat16 dense operands accumulate in binary32
     if (xt == SPM_F32)
-      launch_batch_flat<NT, float, double>(a, rpre, cpre, rtab, ctab, xcd_next, grid, s);
+      launch_batch_flat<NT, float, double>(a, rpre, cpre, rtab, ctab, xcd_next, rslot, cslot,
+                                           grid, s);
     else
-      launch_batch_flat<NT, bf16_t, float>(a, rpre, cpre, rtab, ctab, xcd_next, grid, s);
+      launch_batch_flat<NT, bf16_t, float>(a, rpre, cpre, rtab, ctab, xcd_next, rslot, cslot,
+                                           grid, s);
     return;
   }
   if (xt == SPM_F32) launch_batch_spmm<NT, float, double>(a, spmm_workers, s);

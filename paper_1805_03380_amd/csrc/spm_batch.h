@@ -650,17 +650,54 @@ __global__ __launch_bounds__(NT) void k_batch_prefix(BatchArgs a, int64_t* __res
 
 // tab[t] = the schedule slot q whose rows (columns) hold the start of chunk t, that is
 // pre[q] <= t * chunk < pre[q + 1], for both prefixes.  One thread per slot.
-// Also clears the per-XCD chunk counters of the two product launches (2 * kXcds words).
+// What the products need of schedule slot q, in one 64-byte record per direction: the rows
+// (forward) or columns (adjoint) of the schedule before it and through it, the matrix's
+// offsets and sizes, and its nnz from the grouping launch.
+struct BatchSlot {
+  int64_t lo, hi;
+  int64_t trip_off, ptr_off, x_off, g_off;
+  int32_t n_r, n_c, nnz, q;
+};
+static_assert(sizeof(BatchSlot) == 64, "one record per 64 bytes");
+
+// Also writes the slot records (rslot: rows and row_ptr, cslot: columns and col_ptr) and
+// clears the per-XCD chunk counters of the two product launches (2 * kXcds words).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch_tab(BatchArgs a, const int64_t* __restrict__ rpre,
                                                   const int64_t* __restrict__ cpre,
                                                   int64_t chunk, int64_t cap,
                                                   int32_t* __restrict__ rtab,
                                                   int32_t* __restrict__ ctab,
-                                                  uint32_t* __restrict__ xcd_next) {
+                                                  uint32_t* __restrict__ xcd_next,
+                                                  BatchSlot* __restrict__ rslot,
+                                                  BatchSlot* __restrict__ cslot) {
   const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (q < 2 * kXcds) xcd_next[q] = 0;
   if (q >= a.batch) return;
+  {
+    BatchSlot r{}, c{};
+    const int32_t m = a.order[q];
+    if (m >= 0 && m < a.batch) {
+      const spm_batch_item it = a.items[m];
+      int64_t nnz = a.info[2 * (int64_t)m];
+      nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
+      r.trip_off = c.trip_off = it.trip_off;
+      r.x_off = c.x_off = it.x_off;
+      r.g_off = c.g_off = it.g_off;
+      r.n_r = c.n_r = it.n_rows;
+      r.n_c = c.n_c = it.n_cols;
+      r.nnz = c.nnz = (int32_t)nnz;
+      r.ptr_off = it.rowptr_off;
+      c.ptr_off = it.colptr_off;
+    }
+    r.lo = rpre[q];
+    r.hi = rpre[q + 1];
+    c.lo = cpre[q];
+    c.hi = cpre[q + 1];
+    r.q = c.q = (int32_t)q;
+    rslot[q] = r;
+    cslot[q] = c;
+  }
   for (int side = 0; side < 2; ++side) {
     const int64_t* pre = side == 0 ? rpre : cpre;
     int32_t* tab = side == 0 ? rtab : ctab;
@@ -679,10 +716,12 @@ constexpr int kBatchFlatPerGroup = 2;
 template <int NT, typename XT, typename ACC, int GW, bool FULL, bool FWD>
 __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* __restrict__ pre,
                                                    const int32_t* __restrict__ tab,
-                                                   uint32_t* __restrict__ xcd_next) {
+                                                   uint32_t* __restrict__ xcd_next,
+                                                   const BatchSlot* __restrict__ slots) {
   constexpr int64_t kGroups = NT / GW;
   constexpr int64_t kChunk = kGroups * kBatchFlatPerGroup;
-  __shared__ int64_t s_chunk, s_next;
+  __shared__ int64_t s_next;
+  __shared__ BatchSlot s_slot[2];  // the record of the current chunk's start, and the next's
   const XT* Xa = static_cast<const XT*>(a.X);
   const XT* Ga = static_cast<const XT*>(a.Gm);
   const int lg = threadIdx.x & (GW - 1);
@@ -691,54 +730,63 @@ __global__ __launch_bounds__(NT) void k_batch_flat(BatchArgs a, const int64_t* _
   const int64_t nchunks = (total + kChunk - 1) / kChunk;
   const int64_t x = blockIdx.x % kXcds;
   const int64_t c_lo = nchunks * x / kXcds, c_hi = nchunks * (x + 1) / kXcds;
-  // the next chunk is requested while the current one is computed
-  if (threadIdx.x == 0) s_chunk = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
+  // thread 0 takes the next chunk and loads its slot record while the current one is computed
+  auto fetch = [&](int buf) {
+    const int64_t ch = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
+    s_next = ch;
+    if (ch < c_hi) {
+      int64_t q = tab[ch];
+      q = q < 0 ? 0 : (q >= a.batch ? a.batch - 1 : q);
+      s_slot[buf] = slots[q];
+    }
+  };
+  if (threadIdx.x == 0) fetch(0);
   __syncthreads();
-  int64_t chunk = s_chunk;
+  int64_t chunk = s_next;
+  int buf = 0;
   while (chunk < c_hi) {  // the same for every thread of the workgroup
-    __syncthreads();  // s_next is read before thread 0 rewrites it
-    if (threadIdx.x == 0) s_next = c_lo + (int64_t)atomicAdd(&xcd_next[x], 1u);
-    int64_t q = tab[chunk];
-    q = q < 0 ? 0 : (q >= a.batch ? a.batch - 1 : q);
+    __syncthreads();  // s_next and the other record were read before thread 0 rewrites them
+    if (threadIdx.x == 0) fetch(buf ^ 1);
     for (int j = 0; j < kBatchFlatPerGroup; ++j) {
       const int64_t g = chunk * kChunk + (int64_t)j * kGroups + gid;
       if (g >= total) break;
-      while (q + 1 < a.batch && pre[q + 1] <= g) ++q;  // g < total = pre[batch]
-      const spm_batch_item it = a.items[a.order[q]];
-      int64_t nnz = a.info[2 * (int64_t)a.order[q]];
-      nnz = nnz < 0 ? 0 : (nnz > it.nnz_in ? it.nnz_in : nnz);
-      const int64_t e = g - pre[q];  // row (column) within the matrix
-      const int64_t to = it.trip_off;
-      const int64_t n_r = it.n_rows, n_c = it.n_cols;
+      BatchSlot S = s_slot[buf];
+      // a row past the record's matrix (the chunk runs into later ones): walk the records
+      for (int64_t q = (int64_t)S.q + 1; g >= S.hi && q < a.batch; ++q) S = slots[q];
+      if (g < S.lo || g >= S.hi) continue;  // (only for malformed schedules)
+      const int64_t e = g - S.lo;  // row (column) within the matrix
+      const int64_t to = S.trip_off;
+      const int64_t nnz = S.nnz;
       const float* vo = a.val_out + to;
-      const XT* Xb = Xa + it.x_off;
+      const XT* Xb = Xa + S.x_off;
       if constexpr (FWD) {
-        const int32_t* rp = a.row_ptr + it.rowptr_off;
+        const int32_t* rp = a.row_ptr + S.ptr_off;
         if constexpr (FULL)
-          spmm_row_full<float, XT, ACC, GW>(e, lg, n_c, nnz, rp, a.col_t + to, a.perm + to, vo,
-                                            Xb, a.k, a.Y + it.g_off, a.k, false);
+          spmm_row_full<float, XT, ACC, GW>(e, lg, S.n_c, nnz, rp, a.col_t + to, a.perm + to,
+                                            vo, Xb, a.k, a.Y + S.g_off, a.k, false);
         else
-          spmm_row<float, XT, ACC, GW, false>(e, lg, a.k, n_c, nnz, rp, a.col_t + to,
+          spmm_row<float, XT, ACC, GW, false>(e, lg, a.k, S.n_c, nnz, rp, a.col_t + to,
                                               a.perm + to, vo, Xb, a.k, a.xal != 0,
-                                              a.Y + it.g_off, a.k, false, a.yal != 0);
+                                              a.Y + S.g_off, a.k, false, a.yal != 0);
       } else {
-        const int32_t* cp = a.col_ptr + it.colptr_off;
+        const int32_t* cp = a.col_ptr + S.ptr_off;
         const int32_t* ri = a.row_idx + to;
-        const XT* Gb = Ga + it.g_off;
+        const XT* Gb = Ga + S.g_off;
         const int64_t p0 = cp[e], p1 = cp[e + 1];
         if constexpr (FULL)
-          spmm_col_bwd_full<float, XT, XT, ACC, GW>(e, p0, p1, lg, n_r, ri, vo, Gb, a.k, Xb, a.k,
-                                                a.dX + it.x_off, a.k, false, a.dval + to,
+          spmm_col_bwd_full<float, XT, XT, ACC, GW>(e, p0, p1, lg, S.n_r, ri, vo, Gb, a.k, Xb,
+                                                a.k, a.dX + S.x_off, a.k, false, a.dval + to,
                                                 false);
         else
-          spmm_col_bwd<float, XT, XT, ACC, GW, false>(e, p0, p1, lg, a.k, n_r, ri, vo, Gb, a.k,
-                                                  a.xal != 0, Xb, a.k, a.xal != 0,
-                                                  a.dX + it.x_off, a.k, false, a.yal != 0,
+          spmm_col_bwd<float, XT, XT, ACC, GW, false>(e, p0, p1, lg, a.k, S.n_r, ri, vo, Gb,
+                                                  a.k, a.xal != 0, Xb, a.k, a.xal != 0,
+                                                  a.dX + S.x_off, a.k, false, a.yal != 0,
                                                   a.dval + to, false);
       }
     }
     __syncthreads();
     chunk = s_next;
+    buf ^= 1;
   }
 }
 
