@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "spm.h"
+#include "spm_range.h"
 #include "spm_assemble.h"
 #include "spm_spmm.h"
 #include "spm_batch.h"
@@ -602,6 +603,7 @@ spm_status spm_coo_to_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const 
                           const int32_t* col, const void* val, spm_dtype val_type,
                           int32_t* col_ptr, int32_t* row_idx, void* val_out, spm_dtype out_type,
                           int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  SPM_RANGE("spm_coo_to_csc");
   spm_status st = check_dims(n_rows, n_cols, nnz_in);
   if (st != SPM_OK) return st;
   if (val_type != SPM_F64 && val_type != SPM_F32 && val_type != SPM_BF16) return SPM_EDTYPE;
@@ -1027,6 +1029,7 @@ spm_status spm_csc_plan_build(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                               spm_dtype val_type, void* plan, size_t plan_bytes,
                               void* val_plan, int32_t* info, void* ws, size_t ws_bytes,
                               void* stream) {
+  SPM_RANGE("spm_csc_plan_build");
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (!col_ptr || !plan || !info || !ws) return SPM_EINVAL;
@@ -1066,6 +1069,7 @@ spm_status spm_coo_to_csc_plan(int64_t n_rows, int64_t n_cols, int64_t nnz_in,
                                void* val_out, spm_dtype out_type, int32_t* info, void* plan,
                                size_t plan_bytes, void* val_plan, int32_t* plan_info, void* ws,
                                size_t ws_bytes, void* stream) {
+  SPM_RANGE("spm_coo_to_csc_plan");
   spm_status st = check_dims(n_rows, n_cols, nnz_in);
   if (st != SPM_OK) return st;
   if (val_type != SPM_F64 && val_type != SPM_F32 && val_type != SPM_BF16) return SPM_EDTYPE;
@@ -1115,6 +1119,7 @@ spm_status spm_csc_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                              spm_dtype val_type, int32_t* t_col_ptr, int32_t* t_row_idx,
                              void* t_val, int32_t* info, void* ws, size_t ws_bytes,
                              void* stream) {
+  SPM_RANGE("spm_csc_transpose");
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (val_type != SPM_F64 && val_type != SPM_F32) return SPM_EDTYPE;
@@ -1160,6 +1165,7 @@ spm_status spm_csc_insert(int64_t n_rows, int64_t n_cols, int64_t cap_a,
                           const void* val, spm_dtype val_type, int32_t* col_ptr,
                           int32_t* row_idx, void* val_out, spm_dtype out_type, int32_t* info,
                           void* ws, size_t ws_bytes, void* stream) {
+  SPM_RANGE("spm_csc_insert");
   if (cap_a < 0 || nnz_t < 0) return SPM_EINVAL;
   spm_status st = check_dims(n_rows, n_cols, cap_a);
   if (st != SPM_OK) return st;
@@ -1214,6 +1220,7 @@ spm_status spm_csc_add(int64_t n_rows, int64_t n_cols, int64_t a_cap, const int3
                        spm_dtype val_type, int32_t* col_ptr, int32_t* row_idx, void* val_out,
                        spm_dtype out_type, int32_t* info, void* ws, size_t ws_bytes,
                        void* stream) {
+  SPM_RANGE("spm_csc_add");
   if (a_cap < 0 || b_cap < 0) return SPM_EINVAL;
   spm_status st = check_dims(n_rows, n_cols, a_cap);
   if (st != SPM_OK) return st;
@@ -1251,6 +1258,7 @@ spm_status spm_csc_spmm(int64_t n_rows, int64_t n_cols, int64_t nnz_cap, int64_t
                         const void* plan, const void* val, spm_dtype val_type,
                         spm_val_order val_order, const void* X, int64_t ldx, spm_dtype x_type,
                         void* Y, int64_t ldy, spm_dtype y_type, void* stream) {
+  SPM_RANGE("spm_csc_spmm");
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (k < 1 || ldx < k || ldy < k) return SPM_EINVAL;
@@ -1306,6 +1314,7 @@ spm_status spm_csc_spmm_backward(int64_t n_rows, int64_t n_cols, int64_t nnz_cap
                                  spm_dtype g_type, const void* X, int64_t ldx, spm_dtype x_type,
                                  void* dX, int64_t lddx, spm_dtype dx_type, void* dval,
                                  spm_dtype dval_type, void* stream) {
+  SPM_RANGE("spm_csc_spmm_backward");
   spm_status st = check_dims(n_rows, n_cols, nnz_cap);
   if (st != SPM_OK) return st;
   if (k < 1 || ldg < k || ldx < k || (dX && lddx < k)) return SPM_EINVAL;
@@ -1571,6 +1580,7 @@ spm_status spm_batch_run(int32_t batch, int64_t k, const spm_batch_item* items,
                          int32_t* row_ptr, int32_t* col_t, int32_t* perm, float* Y, float* dX,
                          float* dval, int32_t* info, int64_t max_dim, int64_t max_nnz_in,
                          int32_t workers, void* ws, size_t ws_bytes, void* stream) {
+  SPM_RANGE("spm_batch_run");
   if (batch < 0 || k < 1 || max_dim < 0 || max_nnz_in < 0 || workers < 0) return SPM_EINVAL;
   if (!fits_i32(k) || !fits_i32(max_dim) || !fits_i32(max_nnz_in) || max_dim == INT32_MAX)
     return SPM_EOVERFLOW;
@@ -1631,6 +1641,7 @@ spm_status spm_batch_coo_to_csc_spmm(int32_t batch, int64_t k, const spm_batch_i
                                      float* dX, float* dval, int32_t* info, int64_t max_dim,
                                      int64_t max_nnz_in, int32_t workers, void* ws,
                                      size_t ws_bytes, const char* tune_key, void* stream) {
+  SPM_RANGE("spm_batch_coo_to_csc_spmm");
   // the named tuning for this call only: the thread's own selection is restored afterwards
   const bool had = t_tuning_on;
   const spm_tuning saved = t_tuning;
@@ -1689,6 +1700,7 @@ spm_status spm_coo_to_csc_plan_noalloc(int64_t n_rows, int64_t n_cols, int64_t n
                                        void* val_out, spm_dtype out_type, int32_t* info,
                                        void* plan, size_t plan_bytes, void* val_plan,
                                        int32_t* plan_info, void* stream) {
+  SPM_RANGE("spm_coo_to_csc_plan_noalloc");
   spm_status st = check_dims(n_rows, n_cols, nnz_in);
   if (st != SPM_OK) return st;
   if (fuse_layout(n_rows, n_cols, nnz_in).total > kNoallocScratchBytes) return SPM_EWORKSPACE;

@@ -16,6 +16,7 @@
 #include <cstdint>
 
 #include "spm.h"
+#include "spm_range.h"
 #include "spm_spmm.h"
 
 namespace spm {
@@ -286,6 +287,7 @@ spm_status spm_coo_triplet_grad(int64_t n_rows, int64_t n_cols, int64_t nnz_in, 
                                 const void* Gm, int64_t ldg, spm_dtype g_type, const void* X,
                                 int64_t ldx, spm_dtype x_type, void* dv, spm_dtype dv_type,
                                 void* stream) {
+  SPM_RANGE("spm_coo_triplet_grad");
   if (n_rows < 0 || n_cols < 0 || nnz_in < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz_in) || n_rows == INT32_MAX ||
       n_cols == INT32_MAX)
@@ -318,6 +320,7 @@ spm_status spm_coo_triplet_grad_csc(int64_t n_rows, int64_t n_cols, int64_t nnz_
                                     const void* Gm, int64_t ldg, spm_dtype g_type,
                                     const void* X, int64_t ldx, spm_dtype x_type, void* dv,
                                     spm_dtype dv_type, void* stream) {
+  SPM_RANGE("spm_coo_triplet_grad_csc");
   if (n_rows < 0 || n_cols < 0 || nnz_in < 0 || nnz_cap < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(nnz_in) || !fits_i32(nnz_cap) ||
       n_rows == INT32_MAX || n_cols == INT32_MAX)

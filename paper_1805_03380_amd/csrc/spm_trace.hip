@@ -23,6 +23,7 @@
 #include <cstdint>
 
 #include "spm.h"
+#include "spm_range.h"
 
 namespace spm {
 
@@ -425,6 +426,7 @@ spm_status spm_csc_trace_atb(int64_t n_rows, int64_t n_cols, int64_t a_cap,
                              const int32_t* b_row_idx, const void* b_val, spm_dtype val_type,
                              double* out, int32_t* info, void* ws, size_t ws_bytes,
                              void* stream) {
+  SPM_RANGE("spm_csc_trace_atb");
   if (n_rows < 0 || n_cols < 0 || a_cap < 0 || b_cap < 0) return SPM_EINVAL;
   if (!fits_i32(n_rows) || !fits_i32(n_cols) || !fits_i32(a_cap) || !fits_i32(b_cap) ||
       n_rows == INT32_MAX || n_cols == INT32_MAX)

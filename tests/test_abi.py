@@ -325,3 +325,25 @@ def test_plan_bytes_alias_and_batch_key_checks():
         [64, 1024, 0, 0x100000, 1 << 30]
     # an unknown key is refused before anything is enqueued
     assert lib.spm_batch_coo_to_csc_spmm(*args, b"never registered", None) == _lib.EINVAL
+
+
+def test_roctx_ranges_are_optional():
+    """With SPM_ROCTX=1 the compute entry points push and pop a roctx range (roctx found by
+    dlopen); rejected calls still return their status, with or without the variable.  Each
+    setting runs in a process of its own (the lookup happens once per process)."""
+    import subprocess
+    import sys
+    _lib_or_build()
+    code = ("import ctypes, sys; sys.path.insert(0, %r); "
+            "from paper_1805_03380_amd import _lib; lib = _lib.load(); f = 0x1000; "
+            "st = [lib.spm_coo_to_csc(-1, 4, 8, f, f, f, _lib.F64, f, f, f, _lib.F64, f, "
+            "ctypes.c_void_p(0x100000), 1 << 30, None) for _ in range(3)]; "
+            "st.append(lib.spm_csc_spmm(4, 4, 8, 0, f, f, _lib.F32, _lib.ORDER_CSC, f, 4, "
+            "_lib.F32, f, 4, _lib.F32, None)); "
+            "print(st)") % ROOT
+    for value in ("1", "0", ""):
+        env = dict(os.environ, SPM_ROCTX=value)
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=120)
+        assert out.returncode == 0, out.stderr
+        assert out.stdout.strip() == str([_lib.EINVAL] * 4), (value, out.stdout)
