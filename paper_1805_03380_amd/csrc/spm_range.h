@@ -2,13 +2,14 @@
 // environment variable SPM_ROCTX set to a non-empty value other than "0", every such call is
 // pushed as a range named after the entry point, so a rocprofv3 run with --marker-trace shows
 // which call each kernel belongs to.  roctx is looked up with dlopen on the first call: the
-// library does not depend on it, and without the variable (or without libroctx64) a range
-// costs one branch.
+// library does not depend on it, and without the variable (or without a roctx library) a
+// range costs one branch.
 #pragma once
 
 #include <dlfcn.h>
 
 #include <cstdlib>
+#include <initializer_list>
 
 namespace spm {
 
@@ -22,8 +23,14 @@ inline const RoctxFns& roctx_fns() {
     RoctxFns r{nullptr, nullptr};
     const char* e = std::getenv("SPM_ROCTX");
     if (!e || !*e || (e[0] == '0' && e[1] == '\0')) return r;
-    void* h = dlopen("libroctx64.so", RTLD_NOW | RTLD_LOCAL);
-    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    // the profiler SDK's roctx first (rocprofv3 --marker-trace records its ranges), then the
+    // older library of the same interface
+    void* h = nullptr;
+    for (const char* lib : {"librocprofiler-sdk-roctx.so", "librocprofiler-sdk-roctx.so.1",
+                            "libroctx64.so", "libroctx64.so.4"}) {
+      h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+      if (h) break;
+    }
     if (!h) return r;
     r.push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
     r.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
