@@ -1446,6 +1446,10 @@ int batch_workers(int32_t workers, int32_t batch) {
   return w < 1 ? 1 : w;
 }
 
+// Threads of a grouping workgroup (its LDS, not its thread count, bounds the workgroups per
+// CU, so more threads per workgroup mean more waves in flight).
+constexpr int kBatchNT = 512;
+
 // Persistent workgroups of the products launch: it holds no LDS and few registers, so
 // several times the grouping launch's workgroups fit a CU.
 constexpr int kBatchSpmmDefaultWgPerCu = 8;
@@ -1500,8 +1504,8 @@ void launch_batch_flat(const BatchArgs& a, const int64_t* rpre, const int64_t* c
 template <int NT>
 void launch_batch_nt(const BatchArgs& a, spm_dtype vt, spm_dtype xt, int workers,
                      int spmm_workers, size_t slices_bytes, hipStream_t s) {
-  if (vt == SPM_F32) k_batch<NT, float><<<dim3(workers), dim3(NT), 0, s>>>(a);
-  else k_batch<NT, bf16_t><<<dim3(workers), dim3(NT), 0, s>>>(a);
+  if (vt == SPM_F32) k_batch<kBatchNT, float><<<dim3(workers), dim3(kBatchNT), 0, s>>>(a);
+  else k_batch<kBatchNT, bf16_t><<<dim3(workers), dim3(kBatchNT), 0, s>>>(a);
   // the flat products need the two prefixes and a chunk table per prefix (one entry per
   // chunk of NT / G rows or columns; at most batch * max_dim of those) in the freed slices
   const int64_t chunk = (int64_t)kBatchFlatPerGroup * (NT / (a.G > 0 ? a.G : 1));

@@ -320,10 +320,9 @@ __device__ void batch_giant_column(const BatchKey bk, int64_t c, const uint32_t*
 }
 
 template <int NT, typename VIN>
-__global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs a) {
   constexpr int kBatchFoldIPT = kBatchCap / NT;  // fold block = the sort chunk buffer
   constexpr int T = NT * kBatchFoldIPT;
-  static_assert(T == 8 * NT, "the column scan of a fold block takes 8 entries per thread");
   constexpr int U = 8;  // elements per thread whose loads are issued together
   __shared__ uint32_t s_cnt[kBatchMaxLdsDim + 1];
   __shared__ uint64_t s_key[kBatchCap];
