@@ -406,16 +406,27 @@ bool level2_big_ok(int b, int32_t CB) {
          part_level2_lds_bytes(b, kPartBigCap) + 2048 <= (size_t)max_lds_per_block();
 }
 
+constexpr int kL2WideMinBucketsPerCu = 16;
+
 template <bool PLAN, typename VT>
 void launch_level2(int b, int32_t CB, int64_t nseg, const int32_t* bstart, const uint4* brec,
                    const uint32_t* bvhi, uint64_t* bucket, uint64_t* scratch, int32_t* row_ptr,
                    int32_t* col_t, int32_t* perm, const VT* val, VT* val_plan, int32_t* col_rel,
                    uint32_t* trow, double* tval, uint32_t* bkept, int rshift,
                    const L2RowCount& rc, const uint32_t* big, hipStream_t s) {
-  k_part_level2<kNT, kPartCap, PLAN, VT>
-      <<<dim3((unsigned)CB), dim3(kNT), part_level2_lds_bytes(b, kPartCap), s>>>(
-          b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
-          col_rel, trow, tval, bkept, rshift, rc, big);
+  // With many buckets (several rounds of workgroups) 512-thread workgroups put more waves on
+  // each CU than LDS allows 256-thread ones (each thread's share of a bucket halves, and so do
+  // its registers); with one round, four buckets per CU at a time finish sooner.
+  if ((int64_t)CB > (int64_t)cu_count() * kL2WideMinBucketsPerCu)
+    k_part_level2<2 * kNT, kPartCap, PLAN, VT>
+        <<<dim3((unsigned)CB), dim3(2 * kNT), part_level2_lds_bytes(b, kPartCap), s>>>(
+            b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
+            col_rel, trow, tval, bkept, rshift, rc, big);
+  else
+    k_part_level2<kNT, kPartCap, PLAN, VT>
+        <<<dim3((unsigned)CB), dim3(kNT), part_level2_lds_bytes(b, kPartCap), s>>>(
+            b, nseg, bstart, brec, bvhi, bucket, scratch, row_ptr, col_t, perm, val, val_plan,
+            col_rel, trow, tval, bkept, rshift, rc, big);
   if (big) {
     const int grid = (int)std::min<int64_t>(CB, (int64_t)cu_count() * 2);
     k_part_level2_big<kPartBigNT, kPartBigCap, PLAN, VT>
