@@ -1,16 +1,22 @@
 // Batched path: launches that assemble, plan, multiply forward and backward many
 // independent matrices.
-//   k_batch       assembly and plan: a persistent workgroup takes whole matrices from a
-//                 device queue (in the order the caller gives, largest first) and keeps the
-//                 matrix's per-column / per-row counters in LDS and its keys in a
-//                 per-workgroup slice of the workspace;
-//   k_batch_prefix, k_batch_flat
+//   k_batch       assembly and plan: persistent workgroups take whole matrices from a device
+//                 queue (in the order the caller gives, largest first), keep the matrix's
+//                 per-column / per-row counters in LDS and its keys in a per-workgroup slice
+//                 of the workspace; each chunk of whole columns is sorted and folded in LDS
+//                 in one pass, and values travel inside the keys when row and input position
+//                 leave room for them;
+//   k_batch_prefix, k_batch_tab, k_batch_flat
 //                 forward over all rows and adjoint over all columns of all matrices, one
-//                 grid each, at the occupancy of the single-matrix kernels;
+//                 grid each: the prefixes lay the rows (columns) out in schedule order, a
+//                 table maps every chunk to the matrix holding its start, one record per
+//                 matrix and direction carries what the products need, and every XCD takes a
+//                 contiguous range of chunks in order, so its L2 holds a few matrices at a time;
 //   k_batch_spmm  the same products one workgroup per matrix, when the workspace cannot hold
-//                 the prefixes the flat launches need.
-// The phases call the same device functions as the per-matrix kernels (segment sort, fold,
-// spmm_row, spmm_col_bwd), so the results are bitwise equal to the per-matrix entry points.
+//                 the prefixes and tables the flat launches need.
+// Every output is summed in the same order as by the per-matrix entry points (the same key
+// order and binary64 fold, the same spmm_row / spmm_col_bwd device functions), so the results
+// are bitwise equal to theirs.
 #pragma once
 
 #include "spm_partition.h"

@@ -8,26 +8,25 @@
 // existing value first), and a fold that compares equal to 0.0 is not stored.
 //
 // Work is cut by position in the merged sequence, not by column, so a long column is shared
-// by many threads: thread g owns the positions [g E, g E + E).  Position d lies in the column
-// c with mcp(c) <= d < mcp(c + 1), mcp(c) = acp(c) + bcp(c) (the columns' merged starts);
-// inside the column a binary search on the diagonal (merge path) gives how many of the first
-// d - mcp(c) merged elements come from A.  A thread folds every run whose first element it
-// owns (reading past its range when the run continues) and skips the tail of a run it starts
-// inside; its at most E results stay in registers.
+// by many workgroups.  Position d lies in the column c with mcp(c) <= d < mcp(c + 1),
+// mcp(c) = acp(c) + bcp(c) (the columns' merged starts); inside the column a binary search on
+// the diagonal (merge path) gives how many of the first d - mcp(c) merged elements are A's.
 // k_merge_cols (one thread per column) records for every workgroup tile the column of its
-// first position, and clears the per-call state.  k_merge: a workgroup takes the merge-path
-// splits at its two ends (one wave each), stages its slices of A and B and the offsets of its
-// columns in LDS, walks, scans its results and takes its output offset by decoupled look-back
-// over the workgroups before it, writes the results and the offsets of the columns that start
-// in its range; the last workgroup also writes nnz, the status and the offsets of the columns
-// that start at the very end.
+// first position, and clears the per-call state.  k_merge, one workgroup per tile of
+// NT * kMergeE positions: the merge-path splits at the tile's two ends (one wave each) give
+// its slices of A and B; every element gets the key (column, row), its column from a max-scan
+// over the column starts inside the slices; a merge-path split per thread over the keys and
+// a serial merge of kMergeE steps give the tile's merged order; runs fold from their first
+// position (a run continues into later threads' positions, and past the tile into B's next
+// elements); the kept results take their offsets from a workgroup scan and a decoupled
+// look-back over the tiles before, and go out in position order with the offsets of the
+// columns that start in the tile.  The last tile also writes nnz, the status and the offsets
+// of the columns that start at the very end (the status flags travel in the look-back words).
 // The offsets of both lists are checked on the way (start at 0, non-decreasing, end within
-// capacity; else SPM_EINVAL).  The walk reads offsets through clamped views and every loop is
-// bounded by a column's range or the column count, and every store is checked against the
-// output capacity, so malformed offsets give a wrong result, never an access out of range.
+// capacity; else SPM_EINVAL).  Every read goes through clamped offsets and bounded indices,
+// and every store is checked against the output capacity, so malformed offsets give a wrong
+// result, never an access out of range.
 #pragma once
-
-#include <type_traits>
 
 #include "spm_device.h"
 
