@@ -514,8 +514,13 @@ __global__ __launch_bounds__(256) void k_spmm_fwd(int64_t n_rows, int64_t n_cols
                                        ldx, xal != 0, Y, ldy, y_f64 != 0, yal != 0);
 }
 
+// Waves per SIMD asked of the compiler for the adjoint (1: no request).  At 32 lanes per
+// column (k = 128) six waves, with a few spilled registers, measured faster than the five the
+// compiler picks on its own (power-law workload: 1.64 against 1.67 ms; seven and eight waves
+// spill more and took 2.9 and 3.8 ms).  At 16 lanes a request lost (66 against 52 µs).
+template <int GW> constexpr int kBwdWaves = GW == 32 ? 6 : 1;
 template <typename VT, typename GT, typename XT, typename ACC, int GW, bool FULL>
-__global__ __launch_bounds__(256) void k_spmm_bwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdWaves<GW>))) void k_spmm_bwd(int64_t n_rows, int64_t n_cols, int64_t nnz_cap,
                                                   int64_t k, const int32_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ row_idx,
                                                   const VT* __restrict__ val,
