@@ -89,8 +89,7 @@ def batch_only(dtype_name, steps, warmup):
     import torch
     from paper_1805_03380_amd import autotune, synth
     from paper_1805_03380_amd.batch import PackedBatch
-    autotune.apply(autotune.load_table(),
-                   autotune.signature("batch", 8192, 8192, 131072, 32, "float32", "float32"))
+    autotune.apply(autotune.load_table(), autotune.batch_signature(dtype_name))
     dt = torch.bfloat16 if dtype_name == "bfloat16" else torch.float32
     pb = PackedBatch(synth.batch_problems().problems, val_dtype=dt, x_dtype=dt)
     for _ in range(max(1, warmup)):
@@ -197,8 +196,7 @@ def batched_vs_single(bt, dtype_name="float32", reps_batched=5, reps_single=3):
     import torch
     from paper_1805_03380_amd.batch import PackedBatch
     from paper_1805_03380_amd import autotune
-    autotune.apply(autotune.load_table(),
-                   autotune.signature("batch", 8192, 8192, 131072, 32, "float32", "float32"))
+    autotune.apply(autotune.load_table(), autotune.batch_signature(dtype_name))
     dt = torch.bfloat16 if dtype_name == "bfloat16" else torch.float32
     t0 = time.perf_counter()
     pb = PackedBatch(bt.problems, val_dtype=dt, x_dtype=dt)

@@ -159,11 +159,22 @@ def tune_pipeline(p, reps: int = 10):
                     "spmm_log": log_s, "part_log": log_p}
 
 
-def tune_batch(problems, reps: int = 3):
+def tune_batch(problems, dtype_name: str = "float32", reps: int = 3):
+    """Tune the batched path on `problems` with values, X and G in dtype_name."""
+    import torch
     from .batch import PackedBatch
-    pb = PackedBatch(problems)
+    dt = torch.bfloat16 if dtype_name == "bfloat16" else torch.float32
+    pb = PackedBatch(problems, val_dtype=dt, x_dtype=dt)
     best, ms, log = _sweep(BATCH_SPACE, lambda: pb.run_batched(), reps)
     return best, {"batch_ms": ms, "batch_log": log}
+
+
+def batch_signature(dtype_name: str = "float32") -> str:
+    """The 4096-matrix batch class (n up to 8192, up to 16 n triplets, k = 32)."""
+    return signature("batch", 8192, 8192, 131072, 32, dtype_name, dtype_name)
+
+
+BATCH_WORKLOADS = {"batch": "float32", "batch_bf16": "bfloat16"}
 
 
 # workload name -> (synth constructor, keyword arguments)
@@ -185,18 +196,21 @@ def main(argv=None):
     import numpy as np
     from . import synth
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", default=",".join(list(PIPELINE_WORKLOADS) + ["batch"]),
-                    help="comma-separated: %s, batch" % ", ".join(PIPELINE_WORKLOADS))
+    ap.add_argument("--workloads",
+                    default=",".join(list(PIPELINE_WORKLOADS) + list(BATCH_WORKLOADS)),
+                    help="comma-separated: %s" % ", ".join(list(PIPELINE_WORKLOADS) +
+                                                         list(BATCH_WORKLOADS)))
     args = ap.parse_args(argv)
     table = load_table()
     dev = device_key()
     entries = table.setdefault(dev, {})
     t0 = time.time()
+    bt = None
     for name in args.workloads.split(","):
-        if name == "batch":
-            bt = synth.batch_problems()
-            tb, infob = tune_batch(bt.problems)
-            sigb = signature("batch", 8192, 8192, 131072, 32, "float32", "float32")
+        if name in BATCH_WORKLOADS:
+            bt = bt or synth.batch_problems()
+            tb, infob = tune_batch(bt.problems, BATCH_WORKLOADS[name])
+            sigb = batch_signature(BATCH_WORKLOADS[name])
             entries[sigb] = {"tuning": tb, "ms": {"batch": infob["batch_ms"]}}
             print(sigb, tb, infob["batch_ms"], flush=True)
             continue
