@@ -179,6 +179,7 @@ BATCH_WORKLOADS = {"batch": "float32", "batch_bf16": "bfloat16"}
 
 # workload name -> (synth constructor, keyword arguments)
 PIPELINE_WORKLOADS = {
+    "tiny": ("tiny_spmv", {}),
     "uniform": ("uniform_1e5", {"value_dtype": "float32"}),
     "uniform_f64": ("uniform_1e5", {"value_dtype": "float64"}),
     "powerlaw": ("powerlaw_1e6", {}),
