@@ -104,6 +104,33 @@ def test_large_dims_global_counters_and_giant_column():
     _oracle_check(pb, o_b, probs, 4)
 
 
+def test_giant_row_in_the_plan():
+    """A matrix with one row longer than an LDS sort chunk (5000 stored elements in row 5), so
+    the per-row sort of the plan takes its global merge-sort path, beside ordinary ones."""
+    rng = np.random.Generator(np.random.PCG64(36))
+    n = 6000
+    cols = rng.permutation(n)[:5000].astype(np.int32)
+    row = np.concatenate([np.full(5000, 5, np.int32), rng.integers(0, n, 20_000).astype(np.int32)])
+    col = np.concatenate([cols, rng.integers(0, n, 20_000).astype(np.int32)])
+    perm = rng.permutation(row.size)
+    g = synth.COOProblem("giant_row", n, n, row[perm], col[perm],
+                         rng.standard_normal(row.size).astype(np.float32),
+                         rng.standard_normal((n, 32)).astype(np.float32),
+                         rng.standard_normal((n, 32)).astype(np.float32))
+    probs = [g, synth.random_coo(37, 700, 500, 8000, dup_frac=0.1, dtype=np.float32,
+                                 dist="normal", k=32)]
+    pb = PackedBatch(probs)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_b, o_s)
+    r0 = int(pb.rowptr_off[0])
+    rp = o_b["row_ptr"][r0: r0 + n + 1].cpu().numpy()
+    assert int(rp[6] - rp[5]) >= 5000
+    _oracle_check(pb, o_b, probs, 0)
+    _oracle_check(pb, o_b, probs, 1)
+
+
 @pytest.fixture(scope="module")
 def full_batch():
     return synth.batch_problems()
