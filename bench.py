@@ -544,6 +544,16 @@ def legs_on_csc(p, st, args):
                              dtype=np.float64 if pipe.values.dtype == torch.float64
                              else np.float32)
         qr, qc, qv = (torch.from_numpy(a).to(dev) for a in (q.row, q.col, q.val))
+        # the insertion's own tuned grouping parameters (for this leg only)
+        from paper_1805_03380_amd import autotune
+        saved_tuning = _lib.get_tuning().as_dict()
+        _lib.set_tuning(**DEFAULT_TUNING)
+        ins_sig = autotune.insert_signature(p.n_rows, p.n_cols, q.nnz_in,
+                                            str(qv.dtype).replace("torch.", ""))
+        ins_tuned = autotune.apply(autotune.load_table(), ins_sig)
+        if not ins_tuned:
+            _lib.set_tuning(**saved_tuning)
+        ins_tuning = _lib.get_tuning().as_dict()
         B = ops.csc_insert(A, qr, qc, qv)  # warm-up, and the workspace for the timed calls
         o = (B.col_ptr, B.row_idx_buf, B.values_buf, B.info)
         cap_a = A.nnz_cap
@@ -558,6 +568,7 @@ def legs_on_csc(p, st, args):
                                    ops._dtype_code(o[2].dtype), o[3].data_ptr(),
                                    B._ws.data_ptr(), B._ws.numel(), stream.cuda_stream)
         i_ms = timed(run_insert)
+        _lib.set_tuning(**saved_tuning)
         nnz_out, st_i = (int(x) for x in o[3].cpu())
         if st_i:
             raise RuntimeError("spm_csc_insert reported status %d" % st_i)
@@ -573,6 +584,8 @@ def legs_on_csc(p, st, args):
                "workload": "10^5 new triplets (5 percent duplicates, seed 1006) into the "
                            "assembled 1e5 x 1e5 CSC", "existing": nnz, "new": q.nnz_in,
                "nnz_out": nnz_out, "ms": i_ms,
+               "tuning": {k: v for k, v in ins_tuning.items() if k.startswith("part_")},
+               "tuning_from_table": bool(ins_tuned),
                "elements_per_s": (nnz + q.nnz_in) / (i_ms * 1e-3),
                "new_triplets_per_s": q.nnz_in / (i_ms * 1e-3),
                "compulsory_bytes": i_bytes,

@@ -177,6 +177,25 @@ def batch_signature(dtype_name: str = "float32") -> str:
 BATCH_WORKLOADS = {"batch": "float32", "batch_bf16": "bfloat16"}
 
 
+def insert_signature(n_rows: int, n_cols: int, nnz_new: int, dtype_name: str) -> str:
+    """Batch insertion of nnz_new triplets into an n_rows x n_cols CSC (the grouping
+    parameters sort the new triplets)."""
+    return signature("insert", n_rows, n_cols, nnz_new, 0, dtype_name, dtype_name)
+
+
+def tune_insert(p, q, reps: int = 20):
+    """Tune the grouping parameters of batch insertion of q's triplets into p assembled."""
+    import torch
+    from . import ops
+    dev = torch.device("cuda:0")
+    A = ops.coo_to_csc(*(torch.from_numpy(a).to(dev) for a in (p.row, p.col, p.val)),
+                       (p.n_rows, p.n_cols))
+    qr, qc, qv = (torch.from_numpy(a).to(dev) for a in (q.row, q.col, q.val))
+    ops.csc_insert(A, qr, qc, qv)
+    best, ms, log = _sweep(PART_SPACE, lambda: ops.csc_insert(A, qr, qc, qv, sync=False), reps)
+    return best, {"insert_ms": ms, "insert_log": log}
+
+
 # workload name -> (synth constructor, keyword arguments)
 PIPELINE_WORKLOADS = {
     "tiny": ("tiny_spmv", {}),
@@ -197,10 +216,9 @@ def main(argv=None):
     import numpy as np
     from . import synth
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads",
-                    default=",".join(list(PIPELINE_WORKLOADS) + list(BATCH_WORKLOADS)),
-                    help="comma-separated: %s" % ", ".join(list(PIPELINE_WORKLOADS) +
-                                                         list(BATCH_WORKLOADS)))
+    names = list(PIPELINE_WORKLOADS) + list(BATCH_WORKLOADS) + ["insert"]
+    ap.add_argument("--workloads", default=",".join(names),
+                    help="comma-separated: %s" % ", ".join(names))
     args = ap.parse_args(argv)
     table = load_table()
     dev = device_key()
@@ -208,6 +226,16 @@ def main(argv=None):
     t0 = time.time()
     bt = None
     for name in args.workloads.split(","):
+        if name == "insert":  # 10^5 new triplets into the uniform 1e5 x 1e5 CSC
+            p = synth.uniform_1e5(value_dtype=np.float32, k=0)
+            q = synth.random_coo(1006, p.n_rows, p.n_cols, 100_000, dup_frac=0.05,
+                                 dtype=np.float32)
+            ti, infoi = tune_insert(p, q)
+            sigi = insert_signature(p.n_rows, p.n_cols, q.nnz_in, "float32")
+            entries[sigi] = {"tuning": ti, "ms": {"insert": infoi["insert_ms"]}}
+            print(sigi, ti, infoi["insert_ms"], flush=True)
+            del p, q
+            continue
         if name in BATCH_WORKLOADS:
             bt = bt or synth.batch_problems()
             tb, infob = tune_batch(bt.problems, BATCH_WORKLOADS[name])
