@@ -220,6 +220,9 @@ def main(argv=None):
     ap.add_argument("--workloads", default=",".join(names),
                     help="comma-separated: %s" % ", ".join(names))
     args = ap.parse_args(argv)
+    unknown = [n for n in args.workloads.split(",") if n not in names]
+    if unknown:
+        ap.error("unknown workloads: %s" % ", ".join(unknown))
     table = load_table()
     dev = device_key()
     entries = table.setdefault(dev, {})
@@ -237,7 +240,8 @@ def main(argv=None):
             del p, q
             continue
         if name in BATCH_WORKLOADS:
-            bt = bt or synth.batch_problems()
+            if bt is None:
+                bt = synth.batch_problems()
             tb, infob = tune_batch(bt.problems, BATCH_WORKLOADS[name])
             sigb = batch_signature(BATCH_WORKLOADS[name])
             entries[sigb] = {"tuning": tb, "ms": {"batch": infob["batch_ms"]}}
