@@ -67,6 +67,23 @@ def test_small_batch_equals_single_and_oracle(x_dtype):
         _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
 
 
+@pytest.mark.parametrize("k,x_dtype", [(1, torch.float32), (5, torch.float32),
+                                         (20, torch.float32), (64, torch.float32),
+                                         (130, torch.float32), (20, torch.bfloat16)])
+def test_other_k_general_products(k, x_dtype):
+    """k other than 32: group widths 1 to 64 and the general product path (k not 4 lanes' worth
+    per lane, pieces beyond one per lane, rows not 4-aligned), bitwise equal to the per-matrix
+    calls and within the bound against the oracle."""
+    bt = _small_batch(2010 + k, 40, 16, 700, k=k)
+    pb = PackedBatch(bt.problems, val_dtype=x_dtype, x_dtype=x_dtype)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_b, o_s)
+    for b in (0, 17, 39):
+        _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
+
+
 def test_large_dims_global_counters_and_giant_column():
     """One matrix larger than the LDS counter capacity, one with a column longer than an LDS
     sort chunk, one with an out-of-range triplet (its own status only), an empty one, and one
