@@ -223,13 +223,15 @@ def test_deterministic_rerun():
     _bitwise_equal(pb, o1, o2)
 
 
-def test_flat_and_per_matrix_products_agree():
+@pytest.mark.parametrize("k", [32, 5])
+def test_flat_and_per_matrix_products_agree(k):
     """The products run flat over all rows / columns when the grouping workspace can hold the
     batch's row and column prefixes (16 bytes per matrix), else one workgroup per matrix.
     Many tiny matrices with one grouping workgroup per CU take the per-matrix form, the
-    default tuning the flat one; both are bitwise equal to the per-matrix calls."""
+    default tuning the flat one; both are bitwise equal to the per-matrix calls (k = 32: the
+    full-width path; k = 5: the general one)."""
     from paper_1805_03380_amd import _lib
-    bt = _small_batch(2008, 5000, 2, 6, per_col=2)
+    bt = _small_batch(2008, 5000, 2, 6, per_col=2, k=k)
     pb = PackedBatch(bt.problems)
     o_s = pb.run_single(out=pb.new_outputs())
     torch.cuda.synchronize()
