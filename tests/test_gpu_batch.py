@@ -84,6 +84,21 @@ def test_other_k_general_products(k, x_dtype):
         _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
 
 
+@pytest.mark.parametrize("val_dtype,x_dtype", [(torch.bfloat16, torch.float32),
+                                               (torch.float32, torch.bfloat16)])
+def test_mixed_value_and_dense_types(val_dtype, x_dtype):
+    """Values and dense operands of different types (bfloat16 values with binary32 X and G,
+    and the reverse): bitwise equal to the per-matrix calls, within the bound of the oracle."""
+    bt = _small_batch(2020, 48, 24, 900)
+    pb = PackedBatch(bt.problems, val_dtype=val_dtype, x_dtype=x_dtype)
+    o_b = pb.run_batched()
+    o_s = pb.run_single(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    _bitwise_equal(pb, o_b, o_s)
+    for b in (0, 23, 47):
+        _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
+
+
 def test_large_dims_global_counters_and_giant_column():
     """One matrix larger than the LDS counter capacity, one with a column longer than an LDS
     sort chunk, one with an out-of-range triplet (its own status only), an empty one, and one
