@@ -99,6 +99,25 @@ def test_mixed_value_and_dense_types(val_dtype, x_dtype):
         _oracle_check(pb, o_b, bt.problems, b, acc_f32=(x_dtype == torch.bfloat16))
 
 
+def test_items_beyond_the_limits_are_refused_alone():
+    """A call whose max_dim is below one matrix's rows: that matrix alone gets SPM_EINVAL and
+    no output; every other matrix is assembled and multiplied as usual."""
+    from paper_1805_03380_amd import _lib
+    bt = _small_batch(2030, 12, 30, 400)
+    big = synth.random_coo(2031, 1000, 900, 9000, dtype=np.float32, dist="normal", k=32)
+    probs = bt.problems + [big]
+    pb = PackedBatch(probs)
+    assert pb.max_dim == 1000
+    pb.max_dim = 999
+    o = pb.run_batched(out=pb.new_outputs())
+    torch.cuda.synchronize()
+    info = o["info"].cpu().numpy().reshape(-1, 2)
+    assert info[-1, 1] == _lib.EINVAL and info[-1, 0] == 0
+    assert (info[:-1, 1] == 0).all()
+    for b in (0, 5, 11):
+        _oracle_check(pb, o, probs, b)
+
+
 def test_large_dims_global_counters_and_giant_column():
     """One matrix larger than the LDS counter capacity, one with a column longer than an LDS
     sort chunk, one with an out-of-range triplet (its own status only), an empty one, and one
