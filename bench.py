@@ -525,6 +525,18 @@ def measure_step(p, label, args, steps, warmup, graph, cold_steps, separate=Fals
     return rec, state
 
 
+def leg_tuning(sig):
+    """The table's tuning for one side operation (signature `sig`), over the defaults; without
+    an entry the tuning in effect stays.  Returns (previous tuning, applied or None, in effect)."""
+    from paper_1805_03380_amd import _lib, autotune
+    saved = _lib.get_tuning().as_dict()
+    _lib.set_tuning(**DEFAULT_TUNING)
+    applied = autotune.apply(autotune.load_table(), sig)
+    if not applied:
+        _lib.set_tuning(**saved)
+    return saved, applied, _lib.get_tuning().as_dict()
+
+
 def legs_on_csc(p, st, args):
     """Batch insertion, the sum A + B, the transpose and row-vector product, the gradient per
     input triplet and trace(A^T B), timed with the step's CSC (uniform workload)."""
@@ -546,14 +558,8 @@ def legs_on_csc(p, st, args):
         qr, qc, qv = (torch.from_numpy(a).to(dev) for a in (q.row, q.col, q.val))
         # the insertion's own tuned grouping parameters (for this leg only)
         from paper_1805_03380_amd import autotune
-        saved_tuning = _lib.get_tuning().as_dict()
-        _lib.set_tuning(**DEFAULT_TUNING)
-        ins_sig = autotune.insert_signature(p.n_rows, p.n_cols, q.nnz_in,
-                                            str(qv.dtype).replace("torch.", ""))
-        ins_tuned = autotune.apply(autotune.load_table(), ins_sig)
-        if not ins_tuned:
-            _lib.set_tuning(**saved_tuning)
-        ins_tuning = _lib.get_tuning().as_dict()
+        saved_tuning, ins_tuned, ins_tuning = leg_tuning(autotune.insert_signature(
+            p.n_rows, p.n_cols, q.nnz_in, str(qv.dtype).replace("torch.", "")))
         B = ops.csc_insert(A, qr, qc, qv)  # warm-up, and the workspace for the timed calls
         o = (B.col_ptr, B.row_idx_buf, B.values_buf, B.info)
         cap_a = A.nnz_cap
@@ -626,6 +632,9 @@ def legs_on_csc(p, st, args):
 
     if not args.no_transpose:
         A = pipe.csc()
+        from paper_1805_03380_amd import autotune
+        saved_tuning, tr_tuned, tr_tuning = leg_tuning(autotune.transpose_signature(
+            p.n_rows, p.n_cols, nnz, str(A.values_buf.dtype).replace("torch.", "")))
         T = ops.csc_transpose(A)  # warm-up, and the buffers for the timed calls
         t_info = T.info
 
@@ -638,6 +647,7 @@ def legs_on_csc(p, st, args):
                                       t_info.data_ptr(), T._ws.data_ptr(), T._ws.numel(),
                                       stream.cuda_stream)
         t_ms = timed(run_transpose)
+        _lib.set_tuning(**saved_tuning)
         if int(t_info[1].item()):
             raise RuntimeError("spm_csc_transpose reported status %d" % int(t_info[1]))
         sv = A.values_buf.element_size()
@@ -658,6 +668,9 @@ def legs_on_csc(p, st, args):
         out["transpose"] = {"cpu_oracle_ms": cpu_ms,
                             "workload": "transpose of the assembled 1e5 x 1e5 CSC", "nnz": nnz,
                             "ms": t_ms, "elements_per_s": nnz / (t_ms * 1e-3),
+                            "tuning": {k: v for k, v in tr_tuning.items()
+                                       if k.startswith("part_")},
+                            "tuning_from_table": bool(tr_tuned),
                             "compulsory_bytes": t_bytes,
                             "compulsory_GBps": t_bytes / (t_ms * 1e-3) / 1e9,
                             "rowvec_ms": r_ms, "rowvec_elements_per_s": nnz / (r_ms * 1e-3)}

@@ -183,6 +183,24 @@ def insert_signature(n_rows: int, n_cols: int, nnz_new: int, dtype_name: str) ->
     return signature("insert", n_rows, n_cols, nnz_new, 0, dtype_name, dtype_name)
 
 
+def transpose_signature(n_rows: int, n_cols: int, nnz: int, dtype_name: str) -> str:
+    """Transpose of an n_rows x n_cols CSC holding nnz elements (the grouping parameters
+    partition its elements by row)."""
+    return signature("transpose", n_rows, n_cols, nnz, 0, dtype_name, dtype_name)
+
+
+def tune_transpose(p, reps: int = 20):
+    """Tune the grouping parameters of the transpose of p assembled."""
+    import torch
+    from . import ops
+    dev = torch.device("cuda:0")
+    A = ops.coo_to_csc(*(torch.from_numpy(a).to(dev) for a in (p.row, p.col, p.val)),
+                       (p.n_rows, p.n_cols))
+    ops.csc_transpose(A)
+    best, ms, log = _sweep(PART_SPACE, lambda: ops.csc_transpose(A, sync=False), reps)
+    return best, {"transpose_ms": ms, "transpose_log": log, "nnz": A.nnz}
+
+
 def tune_insert(p, q, reps: int = 20):
     """Tune the grouping parameters of batch insertion of q's triplets into p assembled."""
     import torch
@@ -216,7 +234,7 @@ def main(argv=None):
     import numpy as np
     from . import synth
     ap = argparse.ArgumentParser()
-    names = list(PIPELINE_WORKLOADS) + list(BATCH_WORKLOADS) + ["insert"]
+    names = list(PIPELINE_WORKLOADS) + list(BATCH_WORKLOADS) + ["insert", "transpose"]
     ap.add_argument("--workloads", default=",".join(names),
                     help="comma-separated: %s" % ", ".join(names))
     args = ap.parse_args(argv)
@@ -238,6 +256,14 @@ def main(argv=None):
             entries[sigi] = {"tuning": ti, "ms": {"insert": infoi["insert_ms"]}}
             print(sigi, ti, infoi["insert_ms"], flush=True)
             del p, q
+            continue
+        if name == "transpose":  # the uniform 1e5 x 1e5 CSC
+            p = synth.uniform_1e5(value_dtype=np.float32, k=0)
+            tt, infot = tune_transpose(p)
+            sigt = transpose_signature(p.n_rows, p.n_cols, infot["nnz"], "float32")
+            entries[sigt] = {"tuning": tt, "ms": {"transpose": infot["transpose_ms"]}}
+            print(sigt, tt, infot["transpose_ms"], flush=True)
+            del p
             continue
         if name in BATCH_WORKLOADS:
             if bt is None:

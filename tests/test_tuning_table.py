@@ -1,6 +1,6 @@
 """The committed tuning table: well formed, every entry accepted by the library's own
 validation (spm_tuning_set, host only), and one signature per problem class and element
-type, so a float32 and a bfloat16 batch never share an entry (kinds: pipeline, batch, insert)."""
+type, so a float32 and a bfloat16 batch never share an entry (kinds: pipeline, batch, insert, transpose)."""
 import json
 import os
 
@@ -27,7 +27,7 @@ def test_table_entries_are_valid_tunings():
             assert ver, dev
             for sig, entry in entries.items():
                 kind = sig.split(":")[0]
-                assert kind in ("pipeline", "batch", "insert"), sig
+                assert kind in ("pipeline", "batch", "insert", "transpose"), sig
                 assert entry["tuning"] and all(ms > 0 for ms in entry["ms"].values()), sig
                 _lib.set_tuning(**entry["tuning"])  # raises on a value the library refuses
                 got = _lib.get_tuning().as_dict()
