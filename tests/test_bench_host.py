@@ -1,5 +1,6 @@
 """Host-side pieces of bench.py (no GPU): the exit for more than one GPU, the algorithmic
-byte model and the workload labels that go into its JSON line."""
+byte model, the workload labels that go into its JSON line, and the tuning of the side
+operations."""
 import os
 import subprocess
 import sys
@@ -55,3 +56,31 @@ def test_workload_table():
         assert label and " " not in label
     p, label = bench.make_problem("tiny")
     assert label == bench.WORKLOADS["tiny"][2] and p.nnz_in == 10_000 and p.k == 1
+
+
+def test_leg_tuning_applies_the_table_and_falls_back(monkeypatch):
+    """bench.leg_tuning: a side operation with a table entry runs under it (over the defaults);
+    one without keeps the tuning in effect; the caller gets the previous tuning back."""
+    import json
+    from paper_1805_03380_amd import _lib, autotune
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1805_03380_amd import build
+        build.build()
+    _lib.load()
+    with open(autotune.DEFAULT_TABLE) as f:
+        table = json.load(f)
+    dev = next(iter(table))
+    monkeypatch.setattr(autotune, "device_key", lambda: dev)
+    start = _lib.get_tuning().as_dict()
+    monkeypatch.setattr(bench, "DEFAULT_TUNING", dict(start))
+    sig = autotune.insert_signature(100_000, 100_000, 100_000, "float32")
+    want = table[dev][sig]["tuning"]
+    try:
+        saved, applied, in_effect = bench.leg_tuning(sig)
+        assert saved == start and applied == want
+        assert all(in_effect[k] == v for k, v in want.items())
+        _lib.set_tuning(**saved)
+        saved2, applied2, in_effect2 = bench.leg_tuning("insert:r1:c1:n1:k0:float32:float32")
+        assert applied2 is None and in_effect2 == saved2 == start
+    finally:
+        _lib.set_tuning(**start)
