@@ -118,6 +118,10 @@ constexpr int kPartCap = 2048;  // bucket size kept entirely in LDS by the fused
 // Up to this many buckets k_part_emit reduces the survivor counts of the buckets before it
 // per workgroup; beyond it one k_small_scan launch computes them.
 constexpr int kEmitReduceMax = 1024;
+// k_small_scan's shape: one round of loads for up to kPartMaxBuckets counts
+constexpr int kSmallScanNT = 1024;
+constexpr int kSmallScanIPT = 16;
+static_assert(kSmallScanNT * kSmallScanIPT >= kPartMaxBuckets, "one round of the small scan");
 
 // Level 2 splits each segment into R = 2^l2_sub_log2(b) sub-ranges of the key's high word
 // (values in [0, key_range)): the shift that maps that range onto [0, R).
@@ -709,7 +713,7 @@ spm_status assemble_impl(int64_t n_rows, int64_t n_cols, int64_t nnz_in, const i
     int32_t* boff = nullptr;
     if (P.CB > kEmitReduceMax) {
       boff = reinterpret_cast<int32_t*>(w + L.boff);
-      k_small_scan<kNT><<<dim3(1), dim3(kNT), 0, s>>>(
+      k_small_scan<kSmallScanNT, kSmallScanIPT><<<dim3(1), dim3(kSmallScanNT), 0, s>>>(
           (const uint32_t*)bkept, (int64_t)P.CB, boff);
     }
     EmitPlan ep{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

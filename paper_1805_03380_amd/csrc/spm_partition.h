@@ -1158,29 +1158,39 @@ __global__ __launch_bounds__(NT) void k_plan_values(const int32_t* __restrict__ 
 
 // Exclusive scan of n counts by ONE workgroup: out[i] = sum in[0..i), out[n] = total.  Used
 // for the survivor offsets when there are too many buckets for k_part_emit to reduce them
-// per workgroup.
-template <int NT>
+// per workgroup.  Each wave scans a segment of 64 * IPT counts in coalesced slices of 64;
+// with NT * IPT >= n (the launch takes 1024 x 16 for up to 16384 buckets) the scan is one
+// round of loads.
+template <int NT, int IPT>
 __global__ __launch_bounds__(NT) void k_small_scan(const uint32_t* __restrict__ in, int64_t n,
                                                    int32_t* __restrict__ out) {
   __shared__ uint32_t s_w[NT / kWave + 1];
-  constexpr int IPT = 8;
+  constexpr int64_t kSeg = (int64_t)kWave * IPT;  // counts per wave and round
   uint32_t carry = 0;
   for (int64_t base = 0; base < n; base += (int64_t)NT * IPT) {
+    // wave w scans its segment in coalesced slices of 64, carrying the slice totals
+    const int64_t seg = base + (int64_t)wave_id() * kSeg;
     uint32_t v[IPT];
-    uint32_t sum = 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
+      const int64_t i = seg + (int64_t)q * kWave + lane_id();
       v[q] = i < n ? in[i] : 0u;
-      sum += v[q];
+    }
+    uint32_t wsum = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const uint32_t incl = wave_incl_scan(v[q]);
+      const uint32_t x = v[q];
+      v[q] = wsum + incl - x;  // exclusive within the wave's segment
+      wsum += __shfl(incl, kWave - 1, kWave);
     }
     uint32_t tot;
-    uint32_t run = carry + wg_excl_scan<NT>(sum, s_w, &tot);
+    const uint32_t wpre = wg_excl_scan<NT>(lane_id() == 0 ? wsum : 0u, s_w, &tot);
+    const uint32_t woff = carry + __shfl(wpre, 0, kWave);  // the waves before this one
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      const int64_t i = base + (int64_t)threadIdx.x * IPT + q;
-      if (i < n) out[i] = (int32_t)run;
-      run += v[q];
+      const int64_t i = seg + (int64_t)q * kWave + lane_id();
+      if (i < n) out[i] = (int32_t)(woff + v[q]);
     }
     carry += tot;
   }
