@@ -444,8 +444,20 @@ __global__ __launch_bounds__(NT) void k_super_offsets(const uint32_t* __restrict
   const int64_t s = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
   const int64_t cb0 = s << g;
   const int64_t ng = min((int64_t)1 << g, (int64_t)CB - cb0);
+  // the totals of the buckets before this super-bucket, eight loads in flight per thread
   uint32_t part = 0;
-  for (int64_t i = threadIdx.x; i < cb0; i += NT) part += btot[i];
+  {
+    constexpr int U = 8;
+    int64_t i = threadIdx.x;
+    for (; i + (int64_t)(U - 1) * NT < cb0; i += (int64_t)NT * U) {
+      uint32_t r[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) r[k] = btot[i + (int64_t)k * NT];
+#pragma unroll
+      for (int k = 0; k < U; ++k) part += r[k];
+    }
+    for (; i < cb0; i += NT) part += btot[i];
+  }
   uint32_t base;
   (void)wg_excl_scan<NT>(part, s_w, &base);
   const uint32_t v = threadIdx.x < ng ? btot[cb0 + threadIdx.x] : 0u;
