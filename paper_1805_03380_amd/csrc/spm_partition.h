@@ -1255,7 +1255,7 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
   const int64_t seg0 = cb << b;
   const int64_t rem = nseg - seg0;
   const int64_t nW = rem < ((int64_t)1 << b) ? rem : ((int64_t)1 << b);
-  constexpr int U = 4;  // elements in flight per thread (fused branch)
+  constexpr int U = 4;  // elements in flight per thread
   uint32_t r[U];
   double v[U];
   auto load = [&](int64_t i0) {
@@ -1332,10 +1332,17 @@ __global__ __launch_bounds__(NT) void k_part_emit(int b, int32_t CB, int64_t nse
       }
     }
   } else {
-    for (int64_t i = threadIdx.x; i < kept; i += NT) {
-      row_idx[dst0 + i] = (int32_t)trow[src0 + i];
-      if (out_f64) static_cast<double*>(val_out)[dst0 + i] = tval[src0 + i];
-      else static_cast<float*>(val_out)[dst0 + i] = (float)tval[src0 + i];
+    for (int64_t i0 = threadIdx.x; i0 < kept; i0 += (int64_t)NT * U) {
+      load(i0);  // U elements' loads in flight before any store
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i < kept) {
+          row_idx[dst0 + i] = (int32_t)r[u];
+          if (out_f64) static_cast<double*>(val_out)[dst0 + i] = v[u];
+          else static_cast<float*>(val_out)[dst0 + i] = (float)v[u];
+        }
+      }
     }
   }
   // (the fused branch copied the bucket-relative offsets to LDS behind a barrier)
